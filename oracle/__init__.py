@@ -1,0 +1,167 @@
+"""CPU oracle of the complex Krylov solvers -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never imports it,
+and it never imports the product library.
+
+It wraps ``ccg_oracle.c`` (plain sequential complex128 C, built with gcc and
+``-ffp-contract=off``) through ctypes.  The C file documents what each routine
+follows in the paper (Introduction: the problem A x = y; section 2.1: the
+bicgstab and cgnr methods of the PIM90 set; Usage: matvec / cmatvec kept apart
+from the iteration, tolerance epsilon_err and budget maxit).
+
+Parity status: pinned for every routine (see tests/test_oracle_*.py: dense LU,
+closed forms, finite termination, exact integer products, invariants, third
+party cross-check, planted-mistake detection).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ccg_oracle.c")
+BUILD_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(BUILD_DIR, "liboracle.so")
+
+X0_ZERO = 1
+
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Werror=implicit-function-declaration",
+          "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(src: str = SRC, out: str = LIB) -> str:
+    """Compile the oracle with gcc into ``out`` (always recompiles)."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, src, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, out)
+    return out
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("confirms", ctypes.c_int32),
+                ("relres_rec", ctypes.c_double),
+                ("relres_true", ctypes.c_double)]
+
+
+HIST_FIELDS = ("alpha_re", "alpha_im", "omega_re", "omega_im", "beta_re",
+               "beta_im", "res_half", "res_full")
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    info: int
+    iters: int
+    matvecs: int
+    confirms: int
+    relres_rec: float
+    relres_true: float
+    hist: np.ndarray  # (maxit, 8) float64, columns HIST_FIELDS
+
+    def alpha(self):
+        return self.hist[:, 0] + 1j * self.hist[:, 1]
+
+    def omega(self):
+        return self.hist[:, 2] + 1j * self.hist[:, 3]
+
+    def beta(self):
+        return self.hist[:, 4] + 1j * self.hist[:, 5]
+
+
+class Oracle:
+    """ctypes handle on one built copy of the oracle library."""
+
+    def __init__(self, path: str | None = None):
+        if path is None:
+            path = LIB
+            if not os.path.exists(path) or (
+                    os.path.getmtime(path) < os.path.getmtime(SRC)):
+                build()
+        self.path = path
+        self.lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        for name in ("oracle_matvec", "oracle_matvec_h"):
+            f = getattr(self.lib, name)
+            f.argtypes = [I64, P, I64, P, P]
+            f.restype = None
+        for name in ("oracle_bicgstab", "oracle_cgnr", "oracle_cg"):
+            f = getattr(self.lib, name)
+            f.argtypes = [I64, P, I64, P, P, ctypes.c_double, ctypes.c_int32,
+                          ctypes.c_uint32, ctypes.POINTER(_Stats), P]
+            f.restype = ctypes.c_int
+
+    # -- products ---------------------------------------------------------
+    @staticmethod
+    def _mat(A):
+        A = np.asarray(A)
+        if A.dtype != np.complex128 or A.ndim != 2 or A.shape[0] != A.shape[1]:
+            raise TypeError("A must be a square complex128 matrix")
+        if A.shape[0] == 0:
+            return A, 1
+        if A.strides[1] != 16:
+            raise TypeError("A must have unit column stride (row-major)")
+        return A, A.strides[0] // 16
+
+    def matvec(self, A, x):
+        A, lda = self._mat(A)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.empty(A.shape[0], dtype=np.complex128)
+        self.lib.oracle_matvec(A.shape[0], A.ctypes.data, lda, x.ctypes.data,
+                               y.ctypes.data)
+        return y
+
+    def matvec_h(self, A, x):
+        A, lda = self._mat(A)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.empty(A.shape[0], dtype=np.complex128)
+        self.lib.oracle_matvec_h(A.shape[0], A.ctypes.data, lda, x.ctypes.data,
+                                 y.ctypes.data)
+        return y
+
+    # -- solvers ----------------------------------------------------------
+    def _solve(self, fn, A, y, x0, tol, maxit, flags):
+        A, lda = self._mat(A)
+        n = A.shape[0]
+        y = np.ascontiguousarray(y, dtype=np.complex128)
+        if x0 is None:
+            x = np.zeros(n, dtype=np.complex128)
+            flags |= X0_ZERO
+        else:
+            x = np.array(x0, dtype=np.complex128, copy=True)
+        hist = np.full((max(maxit, 0), 8), np.nan)
+        st = _Stats()
+        rc = fn(n, A.ctypes.data, lda, y.ctypes.data, x.ctypes.data,
+                float(tol), int(maxit), int(flags), ctypes.byref(st),
+                hist.ctypes.data if maxit > 0 else None)
+        if rc != 0:
+            raise ValueError("oracle argument error %d" % rc)
+        return Result(x, st.info, st.iters, st.matvecs, st.confirms,
+                      st.relres_rec, st.relres_true, hist)
+
+    def bicgstab(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
+        return self._solve(self.lib.oracle_bicgstab, A, y, x0, tol, maxit,
+                           flags)
+
+    def cgnr(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
+        return self._solve(self.lib.oracle_cgnr, A, y, x0, tol, maxit, flags)
+
+    def cg(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
+        return self._solve(self.lib.oracle_cg, A, y, x0, tol, maxit, flags)
+
+
+_default: Oracle | None = None
+
+
+def get() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default

@@ -1,0 +1,583 @@
+/*
+ * ccg_oracle.c -- CPU oracle of the complex Krylov solvers.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg are the only code that may load this library.
+ * The product library never links, calls or falls back to it, and this file
+ * shares no code, header or constant table with it.
+ *
+ * What is computed.  CCGPAK solves A x = y for a complex square matrix A
+ * (Introduction, the problem statement "Ax = y"), with the matrix-vector
+ * product kept apart from the iteration (Abstract; Usage, the matvec and
+ * cmatvec routines).  Of the PIM90 set (Codes, section 2.1) this oracle
+ * provides bicgstab and cgnr.  The paper names these methods but prints no
+ * algorithm, so the steps follow the published methods it points to:
+ *   - BiCGSTAB: van der Vorst (1992), as presented in the Templates book that
+ *     the Introduction recommends; complex, unpreconditioned.
+ *   - CGNR: conjugate gradients applied to the normal equations
+ *     A^H A x = A^H y, which minimises ||y - A x||_2 over a growing Krylov
+ *     space (PIM90 set, section 2.1; Templates).
+ *   - CG: Hestenes-Stiefel conjugate gradients for Hermitian positive-definite
+ *     A.  Not in the paper's list; kept only as a pinned reference that other
+ *     tests compare CGNR and BiCGSTAB against.
+ *
+ * Conventions (readings of what the paper leaves open):
+ *   - A is row-major: element (i, j) is A[i*lda + j].
+ *   - The inner product conjugates its first argument: <a, b> = sum conj(a_i) b_i
+ *     (what Fortran's dot_product does for complex arguments, the intrinsic
+ *     the Introduction and section 2.1 say replaced the BLAS calls).
+ *   - The iteration stops when ||r||_2 <= tol * ||y||_2 on the recursive
+ *     residual; a true residual y - A x then confirms it, and when the
+ *     confirmation fails the true residual replaces r and the method restarts
+ *     inside the same iteration budget (tolerance epsilon_err and budget maxit
+ *     of the cgmodule structure, Usage section).
+ *   - info: 0 converged, 1 iteration budget spent, 2 breakdown of rho or sigma
+ *     (BiCGSTAB) or of ||w|| or ||A^H r|| (CGNR), 3 breakdown of omega or
+ *     t^H t (BiCGSTAB), 4 non-finite value met.
+ *
+ * Arithmetic: C11 double complex, one thread, every sum a left-to-right loop.
+ * Build with -ffp-contract=off so that no multiply-add is fused.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex zc;
+
+#define ORACLE_X0_ZERO 1u /* caller says x holds zero on entry: skip y - A x */
+
+typedef struct {
+    int32_t info;     /* 0..4, meaning above */
+    int32_t iters;    /* completed iterations (a half-step exit counts) */
+    int32_t matvecs;  /* applications of A or A^H */
+    int32_t confirms; /* true-residual checks made */
+    double relres_rec;  /* last recursive ||r|| / ||y|| */
+    double relres_true; /* last true ||y - A x|| / ||y|| */
+} oracle_stats;
+
+/* One record per iteration; fields a method does not use stay NaN. */
+typedef struct {
+    double alpha_re, alpha_im;
+    double omega_re, omega_im;
+    double beta_re, beta_im;
+    double res_half; /* BiCGSTAB: ||s|| / ||y|| */
+    double res_full; /* ||r|| / ||y|| after the iteration */
+} oracle_hist;
+
+/* ---------------------------------------------------------------- helpers */
+
+static double norm2sq(int64_t n, const zc* v)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += creal(v[i]) * creal(v[i]) + cimag(v[i]) * cimag(v[i]);
+    return s;
+}
+
+/* <a, b> = sum_i conj(a_i) * b_i */
+static zc dotc(int64_t n, const zc* a, const zc* b)
+{
+    zc s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += conj(a[i]) * b[i];
+    return s;
+}
+
+/* a / b written out as a * conj(b) / |b|^2 */
+static zc zdiv(zc a, zc b)
+{
+    double d = creal(b) * creal(b) + cimag(b) * cimag(b);
+    zc q = a * conj(b);
+    return CMPLX(creal(q) / d, cimag(q) / d);
+}
+
+static double abs2(zc z) { return creal(z) * creal(z) + cimag(z) * cimag(z); }
+
+static int zfinite(zc z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
+
+static void zcopy(int64_t n, const zc* src, zc* dst)
+{
+    for (int64_t i = 0; i < n; ++i)
+        dst[i] = src[i];
+}
+
+static void zzero(int64_t n, zc* v)
+{
+    for (int64_t i = 0; i < n; ++i)
+        v[i] = 0.0;
+}
+
+/* -------------------------------------------------------- matrix products */
+
+/* y = A x : y_i = sum_j A_ij x_j  (the user matvec of the Usage section) */
+void oracle_matvec(int64_t n, const zc* A, int64_t lda, const zc* x, zc* y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        zc s = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            s += A[i * lda + j] * x[j];
+        y[i] = s;
+    }
+}
+
+/* y = A^H x : y_j = sum_i conj(A_ij) x_i, summed over i in increasing order
+ * (the cmatvec of the Usage section, read as the conjugate transpose that
+ * CGNR needs). */
+void oracle_matvec_h(int64_t n, const zc* A, int64_t lda, const zc* x, zc* y)
+{
+    for (int64_t j = 0; j < n; ++j)
+        y[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        zc xi = x[i];
+        for (int64_t j = 0; j < n; ++j)
+            y[j] += conj(A[i * lda + j]) * xi;
+    }
+}
+
+/* rt = y - A x */
+static void residual(int64_t n, const zc* A, int64_t lda, const zc* y,
+                     const zc* x, zc* rt)
+{
+    oracle_matvec(n, A, lda, x, rt);
+    for (int64_t i = 0; i < n; ++i)
+        rt[i] = y[i] - rt[i];
+}
+
+static int bad_args(int64_t n, int64_t lda, double tol, int32_t maxit)
+{
+    if (n < 0) return -1;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (!(tol > 0.0) || !isfinite(tol)) return -6;
+    if (maxit < 0) return -7;
+    return 0;
+}
+
+static void stats_init(oracle_stats* st)
+{
+    memset(st, 0, sizeof *st);
+    st->relres_rec = NAN;
+    st->relres_true = NAN;
+}
+
+static void hist_init(oracle_hist* h, int32_t maxit)
+{
+    if (!h) return;
+    for (int32_t k = 0; k < maxit; ++k) {
+        h[k].alpha_re = h[k].alpha_im = NAN;
+        h[k].omega_re = h[k].omega_im = NAN;
+        h[k].beta_re = h[k].beta_im = NAN;
+        h[k].res_half = h[k].res_full = NAN;
+    }
+}
+
+/* Shared set-up of both solvers: the quick exits and r = y - A x.
+ * Returns 1 when the solve is already finished (st->info is set). */
+static int setup(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+                 uint32_t flags, zc* r, double* ny2_out, double* rr_out,
+                 oracle_stats* st)
+{
+    if (n == 0) {
+        st->info = 0;
+        return 1;
+    }
+    double ny2 = norm2sq(n, y);
+    if (!isfinite(ny2)) {
+        st->info = 4;
+        return 1;
+    }
+    if (ny2 == 0.0) { /* y = 0: the solution is x = 0 */
+        zzero(n, x);
+        st->info = 0;
+        st->relres_rec = st->relres_true = 0.0;
+        return 1;
+    }
+    if (flags & ORACLE_X0_ZERO) {
+        zzero(n, x);
+        zcopy(n, y, r);
+    } else {
+        residual(n, A, lda, y, x, r);
+        st->matvecs++;
+    }
+    double rr = norm2sq(n, r);
+    if (!isfinite(rr)) {
+        st->info = 4;
+        return 1;
+    }
+    st->relres_rec = sqrt(rr / ny2);
+    *ny2_out = ny2;
+    *rr_out = rr;
+    return 0;
+}
+
+/* Confirm a converged recursive residual with the true one.  Returns 1 when
+ * the solve is finished (info set), 0 when r has been replaced by the true
+ * residual and the method must restart. */
+static int confirm(int64_t n, const zc* A, int64_t lda, const zc* y,
+                   const zc* x, zc* r, zc* work, double ny2, double thr2,
+                   int32_t k, int32_t maxit, double* rr, oracle_stats* st)
+{
+    residual(n, A, lda, y, x, work);
+    st->matvecs++;
+    st->confirms++;
+    double rtt = norm2sq(n, work);
+    st->relres_true = sqrt(rtt / ny2);
+    if (!isfinite(rtt)) {
+        st->info = 4;
+        return 1;
+    }
+    if (rtt <= thr2) {
+        st->info = 0;
+        return 1;
+    }
+    zcopy(n, work, r);
+    *rr = rtt;
+    st->relres_rec = sqrt(rtt / ny2);
+    if (k >= maxit) {
+        st->info = 1;
+        return 1;
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------------- BiCGSTAB */
+
+int oracle_bicgstab(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+                    double tol, int32_t maxit, uint32_t flags,
+                    oracle_stats* st, oracle_hist* hist)
+{
+    stats_init(st);
+    int bad = bad_args(n, lda, tol, maxit);
+    if (bad) return bad;
+    hist_init(hist, maxit);
+
+    zc* work = (zc*)malloc(sizeof(zc) * (size_t)(7 * (n > 0 ? n : 1)));
+    if (!work) return -100;
+    zc *r = work, *rh = r + n, *p = rh + n, *v = p + n, *s = v + n,
+       *t = s + n, *tmp = t + n;
+
+    double ny2 = 0.0, rr = 0.0;
+    if (setup(n, A, lda, y, x, flags, r, &ny2, &rr, st)) {
+        free(work);
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    int32_t k = 0;
+    int need_confirm = rr <= thr2;
+    int restart = 1, first = 1;
+    double rh2 = 0.0;
+    zc rho = 0.0, rho_old = 1.0, alpha = 1.0, omega = 1.0;
+
+    for (;;) {
+        if (need_confirm) {
+            need_confirm = 0;
+            if (confirm(n, A, lda, y, x, r, tmp, ny2, thr2, k, maxit, &rr, st))
+                break;
+            restart = 1;
+        }
+        if (restart) { /* shadow residual: fixed to the current residual */
+            zcopy(n, r, rh);
+            rh2 = rr;
+            first = 1;
+            restart = 0;
+        }
+        if (k >= maxit) {
+            st->info = 1;
+            break;
+        }
+        rho = dotc(n, rh, r);
+        if (!zfinite(rho)) {
+            st->info = 4;
+            break;
+        }
+        if (abs2(rho) <= 1e-28 * rh2 * rr) {
+            st->info = 2;
+            break;
+        }
+        if (first) {
+            zcopy(n, r, p);
+            first = 0;
+        } else {
+            zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);
+            if (!zfinite(beta)) {
+                st->info = 4;
+                break;
+            }
+            if (hist) {
+                hist[k].beta_re = creal(beta);
+                hist[k].beta_im = cimag(beta);
+            }
+            for (int64_t i = 0; i < n; ++i)
+                p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+
+        oracle_matvec(n, A, lda, p, v);
+        st->matvecs++;
+        zc sigma = dotc(n, rh, v);
+        double vv = norm2sq(n, v);
+        if (!zfinite(sigma) || !isfinite(vv)) {
+            st->info = 4;
+            break;
+        }
+        if (abs2(sigma) <= 1e-28 * rh2 * vv) {
+            st->info = 2;
+            break;
+        }
+        alpha = zdiv(rho, sigma);
+        if (!zfinite(alpha)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) {
+            hist[k].alpha_re = creal(alpha);
+            hist[k].alpha_im = cimag(alpha);
+        }
+
+        for (int64_t i = 0; i < n; ++i)
+            s[i] = r[i] - alpha * v[i];
+        double ss = norm2sq(n, s);
+        if (!isfinite(ss)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) hist[k].res_half = sqrt(ss / ny2);
+        if (ss <= thr2) { /* converged half-way through the iteration */
+            for (int64_t i = 0; i < n; ++i)
+                x[i] = x[i] + alpha * p[i];
+            k++;
+            st->relres_rec = sqrt(ss / ny2);
+            need_confirm = 1;
+            continue;
+        }
+
+        oracle_matvec(n, A, lda, s, t);
+        st->matvecs++;
+        double tt = norm2sq(n, t);
+        zc ts = dotc(n, t, s);
+        if (!isfinite(tt) || !zfinite(ts)) {
+            st->info = 4;
+            break;
+        }
+        if (tt == 0.0) {
+            st->info = 3;
+            break;
+        }
+        omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);
+        if (omega == 0.0) {
+            st->info = 3;
+            break;
+        }
+        if (hist) {
+            hist[k].omega_re = creal(omega);
+            hist[k].omega_im = cimag(omega);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        rr = norm2sq(n, r);
+        k++;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) hist[k - 1].res_full = sqrt(rr / ny2);
+        st->relres_rec = sqrt(rr / ny2);
+        rho_old = rho;
+        if (rr <= thr2) need_confirm = 1;
+    }
+    st->iters = k;
+    free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------- CGNR */
+
+int oracle_cgnr(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+                double tol, int32_t maxit, uint32_t flags, oracle_stats* st,
+                oracle_hist* hist)
+{
+    stats_init(st);
+    int bad = bad_args(n, lda, tol, maxit);
+    if (bad) return bad;
+    hist_init(hist, maxit);
+
+    zc* work = (zc*)malloc(sizeof(zc) * (size_t)(5 * (n > 0 ? n : 1)));
+    if (!work) return -100;
+    zc *r = work, *z = r + n, *p = z + n, *w = p + n, *tmp = w + n;
+
+    double ny2 = 0.0, rr = 0.0;
+    if (setup(n, A, lda, y, x, flags, r, &ny2, &rr, st)) {
+        free(work);
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    int32_t k = 0;
+    int need_confirm = rr <= thr2;
+    int restart = 1;
+    double gamma = 0.0;
+
+    for (;;) {
+        if (need_confirm) {
+            need_confirm = 0;
+            if (confirm(n, A, lda, y, x, r, tmp, ny2, thr2, k, maxit, &rr, st))
+                break;
+            restart = 1;
+        }
+        if (restart) { /* z = A^H r, p = z */
+            oracle_matvec_h(n, A, lda, r, z);
+            st->matvecs++;
+            gamma = norm2sq(n, z);
+            if (!isfinite(gamma)) {
+                st->info = 4;
+                break;
+            }
+            if (gamma == 0.0) {
+                st->info = 2;
+                break;
+            }
+            zcopy(n, z, p);
+            restart = 0;
+        }
+        if (k >= maxit) {
+            st->info = 1;
+            break;
+        }
+
+        oracle_matvec(n, A, lda, p, w);
+        st->matvecs++;
+        double ww = norm2sq(n, w);
+        if (!isfinite(ww)) {
+            st->info = 4;
+            break;
+        }
+        if (ww == 0.0) {
+            st->info = 2;
+            break;
+        }
+        double alpha = gamma / ww;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * w[i];
+        }
+        rr = norm2sq(n, r);
+        k++;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) {
+            hist[k - 1].alpha_re = alpha;
+            hist[k - 1].alpha_im = 0.0;
+            hist[k - 1].res_full = sqrt(rr / ny2);
+        }
+        st->relres_rec = sqrt(rr / ny2);
+        if (rr <= thr2) {
+            need_confirm = 1;
+            continue;
+        }
+
+        oracle_matvec_h(n, A, lda, r, z);
+        st->matvecs++;
+        double gamma_new = norm2sq(n, z);
+        if (!isfinite(gamma_new)) {
+            st->info = 4;
+            break;
+        }
+        if (gamma_new == 0.0) {
+            st->info = 2;
+            break;
+        }
+        double beta = gamma_new / gamma;
+        if (hist) {
+            hist[k - 1].beta_re = beta;
+            hist[k - 1].beta_im = 0.0;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = z[i] + beta * p[i];
+        gamma = gamma_new;
+    }
+    st->iters = k;
+    free(work);
+    return 0;
+}
+
+/* --------------------------------------------------------------------- CG */
+
+/* Hestenes-Stiefel CG for Hermitian positive-definite A.  Stops on the
+ * recursive residual ||r|| <= tol ||y||; reports the true residual too. */
+int oracle_cg(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+              double tol, int32_t maxit, uint32_t flags, oracle_stats* st,
+              oracle_hist* hist)
+{
+    stats_init(st);
+    int bad = bad_args(n, lda, tol, maxit);
+    if (bad) return bad;
+    hist_init(hist, maxit);
+
+    zc* work = (zc*)malloc(sizeof(zc) * (size_t)(4 * (n > 0 ? n : 1)));
+    if (!work) return -100;
+    zc *r = work, *p = r + n, *q = p + n, *tmp = q + n;
+
+    double ny2 = 0.0, rr = 0.0;
+    if (setup(n, A, lda, y, x, flags, r, &ny2, &rr, st)) {
+        free(work);
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    int32_t k = 0;
+    st->info = 1;
+    if (rr <= thr2) {
+        st->info = 0;
+    } else {
+        zcopy(n, r, p);
+        while (k < maxit) {
+            oracle_matvec(n, A, lda, p, q);
+            st->matvecs++;
+            double pq = creal(dotc(n, p, q));
+            if (!isfinite(pq)) {
+                st->info = 4;
+                break;
+            }
+            if (pq <= 0.0) { /* not positive definite along p */
+                st->info = 2;
+                break;
+            }
+            double alpha = rr / pq;
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * q[i];
+            }
+            double rr_new = norm2sq(n, r);
+            k++;
+            if (hist) {
+                hist[k - 1].alpha_re = alpha;
+                hist[k - 1].alpha_im = 0.0;
+                hist[k - 1].res_full = sqrt(rr_new / ny2);
+            }
+            st->relres_rec = sqrt(rr_new / ny2);
+            if (!isfinite(rr_new)) {
+                st->info = 4;
+                break;
+            }
+            if (rr_new <= thr2) {
+                st->info = 0;
+                break;
+            }
+            double beta = rr_new / rr;
+            if (hist) {
+                hist[k - 1].beta_re = beta;
+                hist[k - 1].beta_im = 0.0;
+            }
+            for (int64_t i = 0; i < n; ++i)
+                p[i] = r[i] + beta * p[i];
+            rr = rr_new;
+        }
+    }
+    residual(n, A, lda, y, x, tmp);
+    st->relres_true = sqrt(norm2sq(n, tmp) / ny2);
+    st->iters = k;
+    free(work);
+    return 0;
+}

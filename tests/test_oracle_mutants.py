@@ -1,0 +1,89 @@
+"""Planted mistakes: each mutant copies the oracle's C source, changes one
+thing a careless implementation could get wrong, builds it on the CPU and
+runs the whole pin battery in a child process.  Some pin must fail for every
+mutant; a mutant that passes every pin would mean the pins cannot tell that
+mistake from the right arithmetic."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# (name, text in ccg_oracle.c, replacement, expected number of occurrences)
+MUTANTS = [
+    ("beta_drops_alpha_over_omega",
+     "zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);",
+     "zc beta = zdiv(rho, rho_old);", 1),
+    ("omega_conjugated",
+     "omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);",
+     "omega = CMPLX(creal(ts) / tt, -cimag(ts) / tt);", 1),
+    ("p_update_sign",
+     "p[i] = r[i] + beta * (p[i] - omega * v[i]);",
+     "p[i] = r[i] + beta * (p[i] + omega * v[i]);", 1),
+    ("s_update_sign",
+     "s[i] = r[i] - alpha * v[i];", "s[i] = r[i] + alpha * v[i];", 1),
+    ("adjoint_without_conj",
+     "y[j] += conj(A[i * lda + j]) * xi;", "y[j] += A[i * lda + j] * xi;", 1),
+    ("cgnr_beta_inverted",
+     "double beta = gamma_new / gamma;", "double beta = gamma / gamma_new;", 1),
+    ("matvec_transposed",
+     "s += A[i * lda + j] * x[j];", "s += A[j * lda + i] * x[j];", 1),
+    ("dot_unconjugated",
+     "s += conj(a[i]) * b[i];", "s += a[i] * b[i];", 1),
+    ("stop_test_not_squared",
+     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 3),
+    ("residual_sign",
+     "rt[i] = y[i] - rt[i];", "rt[i] = y[i] + rt[i];", 1),
+    ("division_without_conj",
+     "zc q = a * conj(b);", "zc q = a * b;", 1),
+    ("x_update_drops_omega_s",
+     "x[i] = x[i] + alpha * p[i] + omega * s[i];", "x[i] = x[i] + alpha * p[i];",
+     1),
+    ("r_update_wrong_vector",
+     "r[i] = s[i] - omega * t[i];", "r[i] = s[i] - omega * s[i];", 1),
+    ("cgnr_p_update_drops_beta",
+     "p[i] = z[i] + beta * p[i];", "p[i] = z[i];", 1),
+    ("rho_without_shadow",
+     "rho = dotc(n, rh, r);", "rho = dotc(n, r, r);", 1),
+    ("sigma_without_shadow",
+     "zc sigma = dotc(n, rh, v);", "zc sigma = dotc(n, r, v);", 1),
+    ("ts_operands_swapped",
+     "zc ts = dotc(n, t, s);", "zc ts = dotc(n, s, t);", 1),
+    ("norm_drops_imaginary",
+     "s += creal(v[i]) * creal(v[i]) + cimag(v[i]) * cimag(v[i]);",
+     "s += creal(v[i]) * creal(v[i]);", 1),
+    ("cgnr_alpha_halved",
+     "double alpha = gamma / ww;", "double alpha = 0.5 * gamma / ww;", 1),
+    ("half_step_forgets_x",
+     "x[i] = x[i] + alpha * p[i];\n            k++;",
+     "(void)p;\n            k++;", 1),
+    ("cgnr_r_update_sign",
+     "r[i] = r[i] - alpha * w[i];", "r[i] = r[i] + alpha * w[i];", 1),
+]
+
+
+@pytest.mark.parametrize("name,old,new,count", MUTANTS,
+                         ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new, count):
+    src = open(oracle.SRC).read()
+    assert src.count(old) == count, "mutation site moved: %s" % name
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new))
+    lib = oracle.build(str(mutated), str(tmp_path / "libmutant.so"))
+    proc = subprocess.run([sys.executable, os.path.join(HERE, "mutant_runner.py"),
+                           lib], capture_output=True, text=True, timeout=300)
+    failed = [ln for ln in proc.stdout.splitlines() if ln.startswith("FAILED")]
+    crashed = proc.returncode != 0
+    assert failed or crashed, "no pin caught mutant %s" % name
+
+
+def test_pins_pass_on_unmutated_copy(tmp_path):
+    lib = oracle.build(oracle.SRC, str(tmp_path / "libcopy.so"))
+    proc = subprocess.run([sys.executable, os.path.join(HERE, "mutant_runner.py"),
+                           lib], capture_output=True, text=True, timeout=300)
+    assert proc.returncode == 0, proc.stderr
+    assert "FAILED" not in proc.stdout, proc.stdout
