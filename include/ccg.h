@@ -1,0 +1,156 @@
+/*
+ * ccg.h -- C ABI of the MI355X (gfx950) complex Krylov solvers.
+ *
+ * Problem: solve A x = y for a dense complex square matrix A (Introduction,
+ * the problem statement "Ax = y").  The matrix-vector product is an entry
+ * point of its own, apart from the iterations (Abstract; Usage section: the
+ * matvec and cmatvec routines), and the solvers are two of the PIM90 set
+ * (Codes, section 2.1): bicgstab (BiCGSTAB) and cgnr (CG on the normal
+ * equations).  The tolerance and iteration budget play the part of the
+ * cgmodule structure's epsilon_err and maxit (Usage section).
+ *
+ * Types and layout
+ *   ccg_z      one complex128, real part first (16 bytes).  Bit-compatible with
+ *              C99 double _Complex, std::complex<double> and torch.complex128.
+ *   A          n x n, row-major: element (i, j) at A[i*lda + j], lda >= n.
+ *   vectors    contiguous (stride 1), n elements.
+ *   stream     a hipStream_t passed as void*; NULL means the null stream.
+ *
+ * Ownership
+ *   A, x, y, work and hist are device pointers owned by the caller.  The
+ *   library keeps no pointer after a call returns.  info and res are host
+ *   pointers.  A and y are only read; x is read (initial guess) and written
+ *   (solution).
+ *
+ * Return value of every entry point
+ *   0 on success; -k when argument k (1-based) is illegal, in which case no
+ *   work is enqueued; a positive hipError_t when the HIP runtime fails.
+ *
+ * Solver status (*info, res->info)
+ *   0  converged: ||y - A x||_2 <= tol * ||y||_2, checked on the true residual
+ *   1  iteration budget maxit spent
+ *   2  breakdown: rho or sigma (BiCGSTAB); ||A p|| or ||A^H r|| zero (CGNR)
+ *   3  breakdown: t^H t or omega zero (BiCGSTAB)
+ *   4  a non-finite value was met (x is left at the last finite iterate)
+ *   n == 0 is a no-op with info 0; y == 0 gives x = 0 with info 0.
+ *
+ * Concurrency: calls on different streams with different workspaces are
+ * independent.  The solvers wait on their stream before they return; the
+ * matrix-vector products do not wait.
+ */
+#ifndef CCG_H
+#define CCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double re, im;
+} ccg_z;
+
+/* Outcome of a solve (host struct). */
+typedef struct {
+    int32_t info;       /* status, codes above */
+    int32_t iters;      /* completed iterations; a half-step exit counts */
+    int32_t matvecs;    /* applications of A or A^H, confirmations included */
+    int32_t confirms;   /* true-residual checks made */
+    double relres_rec;  /* last recursive ||r|| / ||y|| */
+    double relres_true; /* last true ||y - A x|| / ||y|| */
+} ccg_result;
+
+/* Per-iteration record (device array of maxit entries, optional).  Fields a
+ * method does not produce are left as they were (callers fill with NaN).
+ * BiCGSTAB: alpha, omega, beta (the beta used to form this iteration's
+ * direction), res_half = ||s||/||y||, res_full = ||r||/||y||.
+ * CGNR: alpha (real), beta (real, formed at the end of the iteration),
+ * res_full = ||r||/||y||. */
+typedef struct {
+    double alpha_re, alpha_im;
+    double omega_re, omega_im;
+    double beta_re, beta_im;
+    double res_half, res_full;
+} ccg_hist;
+
+enum { CCG_OP_N = 0, CCG_OP_C = 1 };
+
+/* Method ids for ccg_workspace_bytes. */
+enum {
+    CCG_WS_MATVEC_C = 1, /* scratch of ccg_matvec_ex with op = CCG_OP_C */
+    CCG_WS_BICGSTAB = 2,
+    CCG_WS_CGNR = 3
+};
+
+/* Flags of the _ex solvers. */
+#define CCG_X0_ZERO 1u /* x holds no guess: start from x = 0, skip y - A x */
+
+/*
+ * y = op(A) x, op(A) = A (op = CCG_OP_N) or A^H (op = CCG_OP_C).
+ * The user matvec / cmatvec of the Usage section; cmatvec is read as the
+ * conjugate transpose, which CGNR needs.  Sums are in FP64 with a fixed order
+ * (results are bitwise reproducible from run to run).  x and y must not
+ * overlap.  Enqueued on stream, no wait.  CCG_OP_C takes a stream-ordered
+ * scratch of ccg_workspace_bytes(CCG_WS_MATVEC_C, n, 1) bytes from the HIP
+ * stream-ordered allocator; ccg_matvec_ex takes it from the caller instead.
+ * Arguments: 1 op, 2 n >= 0, 3 A, 4 lda >= max(1,n), 5 x, 6 y, 7 stream.
+ */
+int ccg_matvec(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
+               ccg_z* y, void* stream);
+
+/* As ccg_matvec, with caller scratch (8: work, 9: work_bytes; unused for
+ * CCG_OP_N, may be NULL/0 there). Argument 10 is the stream. */
+int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda,
+                  const ccg_z* x, ccg_z* y, void* work, size_t work_bytes,
+                  void* stream);
+
+/* Bytes of device workspace the _ex entry points need (256-byte aligned
+ * start required).  nrhs is 1 for the single right-hand-side solvers. */
+size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs);
+
+/*
+ * BiCGSTAB (section 2.1, bicgstab; van der Vorst's method, unpreconditioned,
+ * shadow residual fixed to the starting residual).  x holds the initial
+ * guess.  Stops on ||r|| <= tol ||y|| (at the half step s or at r), confirms
+ * with the true residual, and on a failed confirmation restarts from it
+ * within the same budget.  Allocates its workspace, waits on stream, writes
+ * *info.
+ * Arguments: 1 n, 2 A, 3 lda, 4 y, 5 x, 6 tol (> 0, finite), 7 maxit >= 0,
+ * 8 info (host, not NULL), 9 stream.
+ */
+int ccg_bicgstab(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
+                 ccg_z* x, double tol, int32_t maxit, int32_t* info,
+                 void* stream);
+
+/*
+ * CGNR (section 2.1, cgnr): conjugate gradients on A^H A x = A^H y, one
+ * product with A and one with A^H per iteration.  Same stop rule,
+ * confirmation, arguments and waiting as ccg_bicgstab.
+ */
+int ccg_cgnr(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
+             double tol, int32_t maxit, int32_t* info, void* stream);
+
+/*
+ * Extended forms: caller workspace, flags, outcome and per-iteration record.
+ * Arguments: 1 n, 2 A, 3 lda, 4 y, 5 x, 6 tol, 7 maxit, 8 flags (CCG_X0_ZERO
+ * or 0), 9 work (device, 256-byte aligned), 10 work_bytes (>= the
+ * ccg_workspace_bytes figure), 11 res (host, not NULL), 12 hist (device array
+ * of maxit ccg_hist, or NULL), 13 stream.  Wait on stream before returning.
+ */
+int ccg_bicgstab_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
+                    ccg_z* x, double tol, int32_t maxit, uint32_t flags,
+                    void* work, size_t work_bytes, ccg_result* res,
+                    ccg_hist* hist, void* stream);
+
+int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
+                ccg_z* x, double tol, int32_t maxit, uint32_t flags,
+                void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCG_H */

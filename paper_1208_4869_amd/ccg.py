@@ -1,0 +1,228 @@
+"""ctypes binding of ``libccg.so`` (the C ABI of include/ccg.h).
+
+Argument marshalling only: every function here checks that the tensors are
+complex128 device tensors of the right shape, passes their data pointers and
+the current HIP stream to the entry point of the same name, and turns a
+negative or HIP error return into an exception.  All arithmetic runs in the
+library's HIP kernels.  There is no fallback: when the library is missing the
+call fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+OP_N = 0
+OP_C = 1
+WS_MATVEC_C = 1
+WS_BICGSTAB = 2
+WS_CGNR = 3
+X0_ZERO = 1
+
+INFO_TEXT = {0: "converged", 1: "iteration budget spent",
+             2: "breakdown (rho/sigma or |Ap|/|A^H r| zero)",
+             3: "breakdown (omega or t^H t zero)", 4: "non-finite value"}
+
+
+class CcgError(RuntimeError):
+    pass
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("confirms", ctypes.c_int32),
+                ("relres_rec", ctypes.c_double),
+                ("relres_true", ctypes.c_double)]
+
+
+@dataclass
+class Result:
+    info: int
+    iters: int
+    matvecs: int
+    confirms: int
+    relres_rec: float
+    relres_true: float
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime (same soname); load it first so that the
+    # library binds to the runtime that owns torch's memory and streams
+    _torch()
+    path = lib_path()
+    if not os.path.exists(path):
+        raise CcgError("%s is not built; run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, I64, I32, U32, D = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                           ctypes.c_uint32, ctypes.c_double)
+    S = ctypes.c_size_t
+    lib.ccg_matvec.argtypes = [ctypes.c_int, I64, P, I64, P, P, P]
+    lib.ccg_matvec_ex.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, S, P]
+    lib.ccg_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
+    lib.ccg_workspace_bytes.restype = S
+    for name in ("ccg_bicgstab", "ccg_cgnr"):
+        getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32,
+                                       ctypes.POINTER(I32), P]
+    for name in ("ccg_bicgstab_ex", "ccg_cgnr_ex"):
+        getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32, U32, P, S,
+                                       ctypes.POINTER(_Result), P, P]
+    for name in ("ccg_matvec", "ccg_matvec_ex", "ccg_bicgstab", "ccg_cgnr",
+                 "ccg_bicgstab_ex", "ccg_cgnr_ex"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, name: str):
+    if rc < 0:
+        raise ValueError("%s: illegal argument %d" % (name, -rc))
+    if rc > 0:
+        raise CcgError("%s: HIP error %d" % (name, rc))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mat(A):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.complex128 or \
+            A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_cuda:
+        raise TypeError("A must be a square complex128 CUDA tensor")
+    n = A.shape[0]
+    if n > 0 and A.stride(1) != 1:
+        raise TypeError("A must be row-major (unit column stride)")
+    lda = max(A.stride(0), 1) if n > 0 else 1
+    return n, lda
+
+
+def _vec(v, n, what):
+    torch = _torch()
+    if not isinstance(v, torch.Tensor) or v.dtype != torch.complex128 or \
+            not v.is_cuda or v.numel() != n or (n > 0 and not v.is_contiguous()):
+        raise TypeError("%s must be a contiguous complex128 CUDA tensor of %d "
+                        "elements" % (what, n))
+    return v
+
+
+def ccg_workspace_bytes(method: int, n: int, nrhs: int = 1) -> int:
+    return int(load().ccg_workspace_bytes(method, n, nrhs))
+
+
+def ccg_matvec(op: int, A, x, y=None, stream=None):
+    """y = A x (op = OP_N) or A^H x (op = OP_C); returns y."""
+    n, lda = _mat(A)
+    _vec(x, n, "x")
+    if y is None:
+        y = _torch().empty_like(x)
+    _vec(y, n, "y")
+    _check(load().ccg_matvec(op, n, A.data_ptr(), lda, x.data_ptr(),
+                             y.data_ptr(), _stream(stream)), "ccg_matvec")
+    return y
+
+
+def ccg_matvec_ex(op: int, A, x, y, work, stream=None):
+    n, lda = _mat(A)
+    _vec(x, n, "x")
+    _vec(y, n, "y")
+    wp = work.data_ptr() if work is not None else None
+    wb = work.numel() * work.element_size() if work is not None else 0
+    _check(load().ccg_matvec_ex(op, n, A.data_ptr(), lda, x.data_ptr(),
+                                y.data_ptr(), wp, wb, _stream(stream)),
+           "ccg_matvec_ex")
+    return y
+
+
+def _short(name, A, y, x, tol, maxit, stream):
+    n, lda = _mat(A)
+    _vec(y, n, "y")
+    _vec(x, n, "x")
+    info = ctypes.c_int32(-1)
+    _check(getattr(load(), name)(n, A.data_ptr(), lda, y.data_ptr(),
+                                 x.data_ptr(), float(tol), int(maxit),
+                                 ctypes.byref(info), _stream(stream)), name)
+    return int(info.value)
+
+
+def ccg_bicgstab(A, y, x, tol=1e-10, maxit=1000, stream=None) -> int:
+    """BiCGSTAB on A x = y, x in/out; returns info."""
+    return _short("ccg_bicgstab", A, y, x, tol, maxit, stream)
+
+
+def ccg_cgnr(A, y, x, tol=1e-10, maxit=1000, stream=None) -> int:
+    """CGNR on A x = y, x in/out; returns info."""
+    return _short("ccg_cgnr", A, y, x, tol, maxit, stream)
+
+
+def workspace(method: int, n: int, device=None):
+    """Device workspace tensor (uint8) of the size the method needs."""
+    torch = _torch()
+    nbytes = max(ccg_workspace_bytes(method, n), 256)
+    return torch.empty(nbytes, dtype=torch.uint8,
+                       device=device or torch.device("cuda"))
+
+
+def new_hist(maxit: int, device=None):
+    """Per-iteration record (maxit x 8 float64 on the device, NaN-filled);
+    columns alpha re/im, omega re/im, beta re/im, res_half, res_full."""
+    torch = _torch()
+    return torch.full((max(maxit, 1), 8), float("nan"), dtype=torch.float64,
+                      device=device or torch.device("cuda"))
+
+
+def _ex(name, method, A, y, x, tol, maxit, flags, work, hist, stream):
+    n, lda = _mat(A)
+    _vec(y, n, "y")
+    _vec(x, n, "x")
+    if work is None:
+        work = workspace(method, n, A.device)
+    res = _Result()
+    _check(getattr(load(), name)(
+        n, A.data_ptr(), lda, y.data_ptr(), x.data_ptr(), float(tol),
+        int(maxit), int(flags), work.data_ptr(),
+        work.numel() * work.element_size(), ctypes.byref(res),
+        hist.data_ptr() if hist is not None else None, _stream(stream)), name)
+    return Result(res.info, res.iters, res.matvecs, res.confirms,
+                  res.relres_rec, res.relres_true)
+
+
+def ccg_bicgstab_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
+                    hist=None, stream=None) -> Result:
+    return _ex("ccg_bicgstab_ex", WS_BICGSTAB, A, y, x, tol, maxit, flags,
+               work, hist, stream)
+
+
+def ccg_cgnr_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
+                hist=None, stream=None) -> Result:
+    return _ex("ccg_cgnr_ex", WS_CGNR, A, y, x, tol, maxit, flags, work, hist,
+               stream)
+
+
+def hist_numpy(hist) -> np.ndarray:
+    return hist.detach().cpu().numpy()

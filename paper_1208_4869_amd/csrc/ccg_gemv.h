@@ -1,0 +1,145 @@
+// ccg_gemv.h -- dense complex128 matrix-vector products on gfx950.
+//
+// y = A x (row-major A): each 64-lane wavefront owns R consecutive rows and
+// streams them left to right, one 16-byte element per lane per load, U
+// column chunks of 64 elements per step (R*U loads of A in flight per lane).
+// A is read with nontemporal loads so that it streams through the caches
+// without evicting x, which every wavefront re-reads from L2.  Each lane
+// accumulates a strided partial sum in FP64 with fused multiply-adds; a
+// 64-lane butterfly then gives every lane the row totals.
+//
+// y = A^H x on the same row-major A: a block owns a tile of 64 columns and a
+// band of rows; lane j of each wavefront walks down column j (coalesced 1 KB
+// row segments per wavefront), accumulating conj(A_ij) x_i.  The four
+// wavefronts of a block split the band into four sub-bands and add their
+// sums in a fixed order; a second pass adds the band partials in band order.
+// Both products use only fixed summation orders: results are reproducible
+// bit for bit from run to run.
+#pragma once
+
+#include "ccg_device.h"
+
+namespace ccg {
+
+// Row sums of R rows starting at row0 for the calling wavefront.  Rows past
+// n - 1 are clamped to n - 1 (their sums are discarded by the caller).  On
+// return every lane holds all R totals.
+template <int R, int U>
+__device__ __forceinline__ void gemv_n_wave(const d2* __restrict__ A, int64_t lda, int n,
+                                            const d2* __restrict__ x, int row0, d2 (&acc)[R])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const d2* Ar[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = row0 + r < n ? row0 + r : n - 1;
+        Ar[r] = A + (int64_t)row * lda + lane;
+        acc[r] = d2{0.0, 0.0};
+    }
+    const d2* xl = x + lane;
+    int jb = 0;
+    for (; jb + kWave * U <= n; jb += kWave * U) {
+        d2 xv[U];
+        d2 a[R][U];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[r][u] = ldnt(Ar[r] + jb + kWave * u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = xl[jb + kWave * u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = cfma(a[r][u], xv[u], acc[r]);
+    }
+    for (int j = jb + lane; j < n; j += kWave) {
+        const d2 xv = x[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = cfma(ldnt(Ar[r] - lane + j), xv, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = wave_sum(acc[r]);
+}
+
+// Launch shape of the A x kernels for a given n.
+struct GemvNShape {
+    int rows_per_wave;
+    int blocks;
+};
+
+// Launch shape of the A^H x kernels.
+struct GemvCShape {
+    int ntiles;     // column tiles of 64
+    int nbands;     // row bands
+    int band_rows;  // rows per band (the last band may be shorter)
+    int blocks() const { return ntiles * nbands; }
+};
+
+inline GemvCShape gemv_c_shape(int64_t n)
+{
+    GemvCShape s;
+    s.ntiles = (int)((n + kWave - 1) / kWave);
+    int64_t want = (2048 + s.ntiles - 1) / s.ntiles;
+    int64_t cap = (n + 63) / 64;
+    int64_t nb = want < cap ? want : cap;
+    if (nb < 1) nb = 1;
+    s.band_rows = (int)((n + nb - 1) / nb);
+    if (s.band_rows < 1) s.band_rows = 1;
+    s.nbands = (int)((n + s.band_rows - 1) / s.band_rows);
+    if (s.nbands < 1) s.nbands = 1;
+    return s;
+}
+
+// Partial sums of conj(A_ij) x_i over one band of rows for one 64-column
+// tile, written to part[band * n + j].  Block = 4 wavefronts; wavefront w
+// takes the w-th quarter of the band.
+template <int U>
+__device__ __forceinline__ void gemv_c_band(const d2* __restrict__ A, int64_t lda, int n,
+                                            const d2* __restrict__ x, d2* __restrict__ part,
+                                            GemvCShape sh)
+{
+    __shared__ d2 red[kWavesPerBlock][kWave];
+    const int tile = blockIdx.x % sh.ntiles;
+    const int band = blockIdx.x / sh.ntiles;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int col = tile * kWave + lane;
+    const int colc = col < n ? col : n - 1;
+    const int rb0 = band * sh.band_rows;
+    const int rb1 = rb0 + sh.band_rows < n ? rb0 + sh.band_rows : n;
+    const int q = (sh.band_rows + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int i0 = rb0 + wave * q < rb1 ? rb0 + wave * q : rb1;
+    const int i1 = i0 + q < rb1 ? i0 + q : rb1;
+    const d2* Ac = A + colc;
+    d2 acc = d2{0.0, 0.0};
+    int i = i0;
+    for (; i + U <= i1; i += U) {
+        d2 a[U];
+        d2 xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = ldnt(Ac + (int64_t)(i + u) * lda);
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[i + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = cfma_conj(a[u], xv[u], acc);
+    }
+    for (; i < i1; ++i) acc = cfma_conj(ldnt(Ac + (int64_t)i * lda), x[i], acc);
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && col < n) {
+        d2 s = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += red[w][lane];
+        part[(int64_t)band * n + col] = s;
+    }
+}
+
+// z_j = sum over bands b (in order) of part[b * n + j].
+__device__ __forceinline__ d2 gemv_c_gather(const d2* __restrict__ part, int n, int nbands, int j)
+{
+    d2 s = part[j];
+    for (int b = 1; b < nbands; ++b) s += part[(int64_t)b * n + j];
+    return s;
+}
+
+}  // namespace ccg

@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every entry point include/ccg.h
+declares, and its host-side argument checks reject illegal arguments before
+any GPU work (these calls make no HIP call, so they run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccg.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccg_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1208_4869_amd import build, ccg
+    if not os.path.exists(build.LIB):
+        build.build()
+    return ccg.load()
+
+
+def test_header_declares_the_abi():
+    names = declared()
+    for want in ("ccg_matvec", "ccg_bicgstab", "ccg_cgnr", "ccg_bicgstab_ex",
+                 "ccg_cgnr_ex", "ccg_workspace_bytes", "ccg_matvec_ex"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_sizes(lib):
+    from paper_1208_4869_amd import ccg
+    for n in (1, 256, 8000, 17576):
+        b = ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB, n)
+        c = ccg.ccg_workspace_bytes(ccg.WS_CGNR, n)
+        assert b >= 6 * 16 * n and c >= 4 * 16 * n
+        assert ccg.ccg_workspace_bytes(ccg.WS_MATVEC_C, n) >= 16 * n
+    assert ccg.ccg_workspace_bytes(99, 10) == 0
+    assert ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB, -1) == 0
+
+
+def test_argument_errors_are_rejected_on_the_host(lib):
+    P = ctypes.c_void_p
+    dummy = P(256)  # never dereferenced: the checks fail first
+    info = ctypes.c_int32(-7)
+    for fn in (lib.ccg_bicgstab, lib.ccg_cgnr):
+        assert fn(-1, dummy, 1, dummy, dummy, 1e-10, 10, ctypes.byref(info), None) == -1
+        assert fn(4, None, 4, dummy, dummy, 1e-10, 10, ctypes.byref(info), None) == -2
+        assert fn(4, dummy, 3, dummy, dummy, 1e-10, 10, ctypes.byref(info), None) == -3
+        assert fn(4, dummy, 4, None, dummy, 1e-10, 10, ctypes.byref(info), None) == -4
+        assert fn(4, dummy, 4, dummy, None, 1e-10, 10, ctypes.byref(info), None) == -5
+        for tol in (0.0, -1.0, float("nan"), float("inf")):
+            assert fn(4, dummy, 4, dummy, dummy, tol, 10, ctypes.byref(info), None) == -6
+        assert fn(4, dummy, 4, dummy, dummy, 1e-10, -1, ctypes.byref(info), None) == -7
+        assert fn(4, dummy, 4, dummy, dummy, 1e-10, 10, None, None) == -8
+        # n = 0 is a no-op with info 0
+        assert fn(0, None, 1, None, None, 1e-10, 10, ctypes.byref(info), None) == 0
+        assert info.value == 0
+    from paper_1208_4869_amd.ccg import _Result
+    res = _Result()
+    for fn in (lib.ccg_bicgstab_ex, lib.ccg_cgnr_ex):
+        args = [4, dummy, 4, dummy, dummy, 1e-10, 10]
+        assert fn(*args, 2, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
+        assert fn(*args, 0, None, 1 << 20, ctypes.byref(res), None, None) == -9
+        assert fn(*args, 0, P(257), 1 << 20, ctypes.byref(res), None, None) == -9
+        assert fn(*args, 0, dummy, 16, ctypes.byref(res), None, None) == -10
+        assert fn(*args, 0, dummy, 1 << 20, None, None, None) == -11
+    for op, code in ((2, -1), (-1, -1)):
+        assert lib.ccg_matvec(op, 4, dummy, 4, dummy, P(4096), None) == code
+    assert lib.ccg_matvec(0, -3, dummy, 4, dummy, P(4096), None) == -2
+    assert lib.ccg_matvec(0, 4, None, 4, dummy, P(4096), None) == -3
+    assert lib.ccg_matvec(0, 4, dummy, 2, dummy, P(4096), None) == -4
+    assert lib.ccg_matvec(0, 4, dummy, 4, None, P(4096), None) == -5
+    assert lib.ccg_matvec(0, 4, dummy, 4, dummy, None, None) == -6
+    assert lib.ccg_matvec(0, 4, dummy, 4, dummy, P(256 + 16), None) == -6  # overlap
+    assert lib.ccg_matvec(1, 0, None, 1, None, None, None) == 0
+    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), None, 0, None) == -8
+    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), dummy, 8, None) == -9
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1208_4869_amd import ccg
+    monkeypatch.setattr(ccg, "_lib", None)
+    monkeypatch.setattr(ccg, "lib_path", lambda: str(tmp_path / "missing.so"))
+    with pytest.raises(ccg.CcgError):
+        ccg.load()
