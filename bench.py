@@ -1,0 +1,268 @@
+"""Benchmark of the complex Krylov hot path on one MI355X.
+
+Workload (the headline): the dipole-lattice system on a 20^3 cubic lattice,
+n = 8000, dense complex128 A (1.024 GB, resident in HBM before timing), x_true
+iid CN(0,1) from seed 1, y = A x_true, BiCGSTAB from x0 = 0 to a relative
+residual of 1e-10 (maxit 1000).  One step = one complete BiCGSTAB solve through
+the C ABI (set-up, iterations with their products, fused reductions and device
+scalar steps, confirmation), ending when the host holds info.
+
+Printed: one JSON line with solves/s, p50/p99 latency, the roofline of the
+dominant kernel (A x, HBM-bound: algorithmic bytes 16 n^2 + 32 n per launch over
+its average launch time from HIP events on the stream it runs on), CGNR on the
+same system, and the CPU oracle timed on a bounded sample on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --profile-kernels     # short kernel mix for rocprofv3
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "BiCGSTAB solves/s at 1e-10 residual; matvec HBM GB/s; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+LATTICE_M = 20
+X_SEED = 1
+TOL = 1e-10
+MAXIT = 1000
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lattice20.md")
+
+
+def measured_traffic():
+    """HBM bytes per A x launch from the committed FETCH_SIZE / WRITE_SIZE
+    record, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        line = [ln for ln in open(TRAFFIC_FILE) if ln.startswith("traffic-json:")][0]
+        rec = json.loads(line.split(":", 1)[1])
+        h = hashlib.sha256()
+        for p in rec["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        if h.hexdigest() != rec["kernel_sources_sha256"]:
+            return None
+        return rec
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=30)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="bound on the oracle's timed sample")
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="run a short mix of the kernels for rocprofv3 and exit")
+    return p.parse_args()
+
+
+def make_inputs():
+    from paper_1208_4869_amd import inputs
+    t = time.time()
+    A = inputs.lattice_matrix(LATTICE_M)
+    rng = np.random.default_rng(X_SEED)
+    x_true = inputs.cn01(rng, A.shape[0])
+    y = A @ x_true
+    log("built the %d^3 lattice system (n=%d) in %.1fs" % (LATTICE_M, A.shape[0],
+                                                         time.time() - t))
+    return A, x_true, y
+
+
+def time_solves(fn, A, y, x, work, steps, warmup, hist=None):
+    import torch
+    res = None
+    for _ in range(warmup):
+        res = fn(A, y, x, TOL, MAXIT, flags=1, work=work, hist=hist)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        res = fn(A, y, x, TOL, MAXIT, flags=1, work=work, hist=hist)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return total, np.array(lat), res
+
+
+def time_kernel(launch, reps):
+    """Average duration of one launch from HIP events recorded on torch's
+    current stream, the stream the library launches on."""
+    import torch
+    launch()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        launch()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / 1e3 / reps
+
+
+def cpu_baseline(A, y, budget_s):
+    import oracle
+    orc = oracle.get()
+    t0 = time.perf_counter()
+    k = 0
+    res = None
+    while True:
+        res = orc.bicgstab(A, y, tol=TOL, maxit=MAXIT)
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or k >= 50:
+            break
+    return {"value": k / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "%d complete BiCGSTAB solve(s) of the same 20^3 lattice "
+                      "system (n=8000) by the single-threaded C oracle, %.1f s"
+                      % (k, el),
+            "iters": res.iters, "relres_true": res.relres_true}
+
+
+def profile_kernels(A, y):
+    """A short, fixed mix for rocprofv3: a device copy of known size (the
+    reference for scaling the HBM byte counters), A x, A^H x, one BiCGSTAB and
+    one CGNR solve."""
+    import torch
+
+    from paper_1208_4869_amd import ccg
+    n = A.shape[0]
+    src = torch.empty(A.numel() * 2, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    x = torch.ones(n, dtype=torch.complex128, device="cuda")
+    for _ in range(5):
+        dst.copy_(src)
+        ccg.ccg_matvec(ccg.OP_N, A, x)
+        ccg.ccg_matvec(ccg.OP_C, A, x)
+    ccg.ccg_bicgstab_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
+    ccg.ccg_cgnr_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
+    torch.cuda.synchronize()
+    log("profile mix done: copy %d bytes x5, matvec N/C x5, 1 BiCGSTAB, 1 CGNR"
+        % (src.numel() * 8))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single "
+              "MI355X (--gpus 1); a system larger than one GPU would be "
+              "row-sharded as described in DESIGN.md, not measured here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1208_4869_amd import ccg
+    torch.cuda.set_device(0)
+    ccg.load()
+
+    A_h, x_true, y_h = make_inputs()
+    n = A_h.shape[0]
+    A = torch.from_numpy(A_h).cuda()
+    y = torch.from_numpy(y_h).cuda()
+    torch.cuda.synchronize()
+
+    if args.profile_kernels:
+        profile_kernels(A, y)
+        return
+
+    # --- headline: BiCGSTAB solves/s
+    x = torch.empty(n, dtype=torch.complex128, device="cuda")
+    work = ccg.workspace(ccg.WS_BICGSTAB, n)
+    log("timing %d BiCGSTAB solves (+%d warm-up)" % (args.steps, args.warmup))
+    total, lat, res = time_solves(ccg.ccg_bicgstab_ex, A, y, x, work, args.steps,
+                                  args.warmup)
+    xg = x.cpu().numpy()
+    relres = float(np.linalg.norm(y_h - A_h @ xg) / np.linalg.norm(y_h))
+    fwd = float(np.linalg.norm(xg - x_true) / np.linalg.norm(x_true))
+    if res.info != 0 or not relres <= 1.01 * TOL:
+        raise SystemExit("BiCGSTAB did not reach the tolerance: info %d relres %.3e"
+                         % (res.info, relres))
+
+    # --- CGNR on the same system
+    wc = ccg.workspace(ccg.WS_CGNR, n)
+    xc = torch.empty_like(x)
+    csteps = max(args.steps // 2, 1)
+    log("timing %d CGNR solves" % csteps)
+    ctot, clat, cres = time_solves(ccg.ccg_cgnr_ex, A, y, xc, wc, csteps, 1)
+    xcg = xc.cpu().numpy()
+    crel = float(np.linalg.norm(y_h - A_h @ xcg) / np.linalg.norm(y_h))
+
+    # --- dominant kernel: A x (and A^H x), timed with HIP events
+    xin = torch.from_numpy(x_true).cuda()
+    yout = torch.empty_like(xin)
+    wmv = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_C, n), dtype=torch.uint8,
+                      device="cuda")
+    reps = 50
+    tn = time_kernel(lambda: ccg.ccg_matvec(ccg.OP_N, A, xin, yout), reps)
+    tc = time_kernel(lambda: ccg.ccg_matvec_ex(ccg.OP_C, A, xin, yout, wmv), reps)
+    bytes_mv = 16.0 * n * n + 32.0 * n
+    trec = measured_traffic()
+    gbs_n = bytes_mv / tn / 1e9
+    gbs_c = bytes_mv / tc / 1e9
+    log("A x: %.1f us (%.0f GB/s); A^H x: %.1f us (%.0f GB/s)"
+        % (tn * 1e6, gbs_n, tc * 1e6, gbs_c))
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "dipole-lattice 20^3, n=8000, dense complex128 "
+                               "A resident in HBM, BiCGSTAB tol 1e-10 from x0=0",
+                   "n": n, "tol": TOL, "maxit": MAXIT, "method": "bicgstab",
+                   "x_seed": X_SEED},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "iters": res.iters,
+        "matvecs": res.matvecs,
+        "relres_true": relres,
+        "fwd_err": fwd,
+        "roofline": {"bound": "hbm", "kernel": "k_gemv_n (A x)",
+                     "achieved": gbs_n, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs_n / HBM_PEAK_GBS,
+                     "traffic": trec["k_gemv_n_traffic_bytes"] if trec else None,
+                     "launch_us": tn * 1e6, "bytes_per_launch": bytes_mv},
+        "matvec_h": {"kernel": "k_gemv_c_band + gather (A^H x)",
+                     "achieved_gbs": gbs_c, "frac": gbs_c / HBM_PEAK_GBS,
+                     "launch_us": tc * 1e6},
+        "cgnr": {"solves_per_s": csteps / ctot,
+                 "p50_ms": float(np.percentile(clat, 50) * 1e3),
+                 "iters": cres.iters, "matvecs": cres.matvecs, "info": cres.info,
+                 "relres_true": crel},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (bounded sample, ~%.0f s)" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A_h, y_h, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -14,6 +14,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxWaves = 16;  // largest block used: 1024 threads
 
 __device__ __forceinline__ d2 cz(double re, double im) { return d2{re, im}; }
 
@@ -69,69 +70,51 @@ __device__ __forceinline__ double wave_sum(double v)
 
 __device__ __forceinline__ d2 wave_sum(d2 v) { return d2{wave_sum(v.x), wave_sum(v.y)}; }
 
-// Block-wide fixed-order reduction of NV complex values, followed by a
-// last-block hand-off: every block writes its NV partial sums to
-// partials[blockIdx.x * NV + k], takes a ticket, and the block that takes the
-// last ticket sums all partials in index order.  Returns true (in every thread
-// of that block) in the last block only; `total` is then valid in thread 0.
-// The ticket is reset to zero for the next launch.  No float atomics: the
-// result is the same on every run.
-template <int NV>
-__device__ bool reduce_to_last_block(d2 (&v)[NV], d2* partials, unsigned* ticket,
-                                     d2 (&total)[NV])
+// Sum of one value per thread over the block, in a fixed order (64-lane
+// butterfly, then wavefronts in index order).  Valid in thread 0.  `lds` must
+// hold one entry per wavefront.
+__device__ __forceinline__ d2 block_sum(d2 v, d2* lds)
 {
-    __shared__ d2 lds[kWavesPerBlock][NV];
-    __shared__ bool last;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int nwaves = blockDim.x / kWave;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        d2 s = wave_sum(v[k]);
-        if (lane == 0) lds[wave][k] = s;
-    }
+    const d2 s = wave_sum(v);
+    __syncthreads();  // lds may still be read by a previous call
+    if (lane == 0) lds[wave] = s;
     __syncthreads();
+    d2 t = lds[0];
+    for (int w = 1; w < nwaves; ++w) t += lds[w];
+    return t;
+}
+
+// Per-block partial sums: block b writes its two block totals to
+// part[2b], part[2b + 1] with plain stores.  The kernel that runs next on the
+// stream adds them up (reduce_partials); the kernel boundary makes them
+// visible.  No atomics and no fences: every block of the consumer adds the
+// same values in the same order and gets the same bits.
+__device__ __forceinline__ void write_partials(d2 v0, d2 v1, d2* part, d2* lds)
+{
+    const d2 s0 = block_sum(v0, lds);
+    const d2 s1 = block_sum(v1, lds);
     if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            d2 s = lds[0][k];
-            for (int w = 1; w < nwaves; ++w) s += lds[w][k];
-            partials[blockIdx.x * NV + k] = s;
-        }
-        __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
+        part[2 * blockIdx.x] = s0;
+        part[2 * blockIdx.x + 1] = s1;
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    d2 acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = d2{0.0, 0.0};
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            d2 p = __builtin_nontemporal_load(&partials[b * NV + k]);
-            acc[k] += p;
-        }
+}
+
+// Totals of the nblocks partial pairs written by the previous kernel.  Every
+// thread of the block takes part in the loads; the totals are valid in
+// thread 0.  Thread t adds blocks t, t + blockDim.x, ... in increasing order.
+__device__ __forceinline__ void reduce_partials(const d2* part, int nblocks, d2* lds,
+                                                d2& t0, d2& t1)
+{
+    d2 a0 = d2{0.0, 0.0}, a1 = d2{0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        a0 += part[2 * b];
+        a1 += part[2 * b + 1];
     }
-    __syncthreads();  // lds reuse
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        d2 s = wave_sum(acc[k]);
-        if (lane == 0) lds[wave][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            d2 s = lds[0][k];
-            for (int w = 1; w < nwaves; ++w) s += lds[w][k];
-            total[k] = s;
-        }
-        *ticket = 0u;
-    }
-    return true;
+    t0 = block_sum(a0, lds);
+    t1 = block_sum(a1, lds);
 }
 
 }  // namespace ccg

@@ -1,12 +1,12 @@
 // ccg_gemv.h -- dense complex128 matrix-vector products on gfx950.
 //
-// y = A x (row-major A): each 64-lane wavefront owns R consecutive rows and
-// streams them left to right, one 16-byte element per lane per load, U
-// column chunks of 64 elements per step (R*U loads of A in flight per lane).
-// A is read with nontemporal loads so that it streams through the caches
-// without evicting x, which every wavefront re-reads from L2.  Each lane
-// accumulates a strided partial sum in FP64 with fused multiply-adds; a
-// 64-lane butterfly then gives every lane the row totals.
+// y = A x (row-major A): a block of W wavefronts owns R consecutive rows and
+// streams them left to right, the wavefronts interleaved over 64-element
+// column chunks, one 16-byte element per lane per load.  A is read with
+// nontemporal loads so that it streams through the caches without evicting
+// x, which is re-read from L2 once per block (R rows).  Each lane accumulates
+// a strided partial sum in FP64 with fused multiply-adds; a 64-lane butterfly
+// and a fixed-order sum over the block's wavefronts give the row totals.
 //
 // y = A^H x on the same row-major A: a block owns a tile of 64 columns and a
 // band of rows; lane j of each wavefront walks down column j (coalesced 1 KB
@@ -21,15 +21,23 @@
 
 namespace ccg {
 
-// Row sums of R rows starting at row0 for the calling wavefront.  Rows past
-// n - 1 are clamped to n - 1 (their sums are discarded by the caller).  On
-// return every lane holds all R totals.
-template <int R, int U>
-__device__ __forceinline__ void gemv_n_wave(const d2* __restrict__ A, int64_t lda, int n,
-                                            const d2* __restrict__ x, int row0, d2 (&acc)[R])
+// Row sums of R rows starting at row0, computed by a block of W wavefronts:
+// wavefront w takes the 64-column chunks w, w + W, w + 2W, ... of all R rows,
+// U chunks per step (R*U loads of A in flight per lane), so the W wavefronts
+// of a block read W adjacent 1 KB segments of the same rows at a time and
+// each x chunk is fetched once per block for R rows.  Rows past n - 1 are
+// clamped to n - 1 (their sums are discarded by the caller).  On return
+// red[w][r] holds wavefront w's sum for row row0 + r; the row total is
+// red[0][r] + red[1][r] + ... in wavefront order (gemv_n_row_total).
+template <int R, int U, int W>
+__device__ __forceinline__ void gemv_n_block(const d2* __restrict__ A, int64_t lda, int n,
+                                             const d2* __restrict__ x, int row0,
+                                             d2 (*red)[R])
 {
     const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
     const d2* Ar[R];
+    d2 acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = row0 + r < n ? row0 + r : n - 1;
@@ -37,28 +45,45 @@ __device__ __forceinline__ void gemv_n_wave(const d2* __restrict__ A, int64_t ld
         acc[r] = d2{0.0, 0.0};
     }
     const d2* xl = x + lane;
-    int jb = 0;
-    for (; jb + kWave * U <= n; jb += kWave * U) {
-        d2 xv[U];
+    const int nfull = n / kWave;  // chunks with 64 valid columns
+    int c = wave;
+    for (; c + (U - 1) * W < nfull; c += U * W) {
         d2 a[R][U];
+        d2 xv[U];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[r][u] = ldnt(Ar[r] + jb + kWave * u);
+            for (int u = 0; u < U; ++u) a[r][u] = ldnt(Ar[r] + (c + u * W) * kWave);
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = xl[jb + kWave * u];
+        for (int u = 0; u < U; ++u) xv[u] = xl[(c + u * W) * kWave];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = cfma(a[r][u], xv[u], acc[r]);
     }
-    for (int j = jb + lane; j < n; j += kWave) {
-        const d2 xv = x[j];
+    for (; c * kWave < n; c += W) {
+        if (c * kWave + lane < n) {
+            const d2 xv = xl[c * kWave];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = cfma(ldnt(Ar[r] - lane + j), xv, acc[r]);
+            for (int r = 0; r < R; ++r) acc[r] = cfma(ldnt(Ar[r] + c * kWave), xv, acc[r]);
+        }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = wave_sum(acc[r]);
+    for (int r = 0; r < R; ++r) {
+        const d2 s = wave_sum(acc[r]);
+        if (lane == 0) red[wave][r] = s;
+    }
+    __syncthreads();
+}
+
+// Total of row row0 + r from the per-wavefront sums, in wavefront order.
+template <int R, int W>
+__device__ __forceinline__ d2 gemv_n_row_total(const d2 (*red)[R], int r)
+{
+    d2 s = red[0][r];
+#pragma unroll
+    for (int w = 1; w < W; ++w) s += red[w][r];
+    return s;
 }
 
 // Launch shape of the A x kernels for a given n.
@@ -79,7 +104,9 @@ inline GemvCShape gemv_c_shape(int64_t n)
 {
     GemvCShape s;
     s.ntiles = (int)((n + kWave - 1) / kWave);
-    int64_t want = (2048 + s.ntiles - 1) / s.ntiles;
+    // about 1000 blocks: enough to fill 256 CUs, few enough that each block
+    // walks a long band (fewer partials, longer streams)
+    int64_t want = (1024 + s.ntiles - 1) / s.ntiles;
     int64_t cap = (n + 63) / 64;
     int64_t nb = want < cap ? want : cap;
     if (nb < 1) nb = 1;

@@ -47,161 +47,364 @@ enum Phase : int {
     PH_DONE = 5,
 };
 
-enum Ticket : int {
-    T_NORMY = 0, T_SETUP, T_V, T_S, T_T, T_XR, T_W, T_XR2, T_Z2, T_COUNT
+// Reduction left for the next kernel to finish, and the scalar step that
+// goes with it.
+enum Pending : int {
+    PK_NONE = 0,
+    PK_NORMY,      // ||y||^2
+    PK_SETUP_B0,   // BiCGSTAB set-up, r = y (x0 = 0): ||r||^2
+    PK_SETUP_B1,   // BiCGSTAB set-up, r = y - A x: ||r||^2
+    PK_SETUP_C0,   // CGNR set-up, r = y
+    PK_SETUP_C1,   // CGNR set-up, r = y - A x
+    PK_ZERO,       // y == 0: x has been zeroed
+    PK_V,          // r^H v, ||v||^2        -> alpha
+    PK_CONFIRM_B,  // ||y - A x||^2 (BiCGSTAB)
+    PK_CONFIRM_C,  // ||y - A x||^2 (CGNR)
+    PK_S,          // ||s||^2               -> half-step test
+    PK_T,          // t^H s, ||t||^2        -> omega
+    PK_XR,         // ||r||^2, r^H r        -> stop test, beta
+    PK_HALF,       // x += alpha p done after a half-step exit
+    PK_W,          // ||w||^2               -> alpha (CGNR)
+    PK_XR2,        // ||r||^2               -> stop test (CGNR)
+    PK_Z_RUN,      // ||z||^2               -> beta (CGNR)
+    PK_Z_RESTART,  // ||z||^2               -> gamma of a new direction (CGNR)
 };
 
+// The solver's scalars in device memory.  Two copies alternate: a launch
+// reads copy q and block 0 writes copy q ^ 1, so no block of a launch ever
+// reads what its own launch writes.
 struct alignas(16) SolverState {
     int phase, restart, info, iters;
-    int matvecs, confirms, maxit, pad0;
+    int matvecs, confirms, maxit, pending;
+    int pending_blocks, pad0, pad1, pad2;
     double ny2, thr2, rh2, rr;
-    double relres_rec, relres_true, gamma, pad1;
+    double relres_rec, relres_true, gamma, tol2;
     d2 rho, rho_old, alpha, omega, beta;
-    unsigned tickets[16];
 };
-static_assert(sizeof(SolverState) <= 1024, "state block");
+static_assert(sizeof(SolverState) <= 512, "state block");
 
 struct Args {
     const d2* A;
     int64_t lda;
     int n;
-    int nbands_c;
     GemvCShape csh;
     const d2* y;
     d2* x;
     d2 *r, *rh, *p, *v, *s, *t;  // BiCGSTAB vectors
     d2 *z, *w, *zpart;           // CGNR vectors and A^H band partials
-    d2* partials;
-    SolverState* st;
+    d2* part[2];                 // per-block partial sums, alternating
+    SolverState* st[2];          // state copies, alternating
     ccg_hist* hist;
-    double tol2;
 };
 
-constexpr int kR = 4;  // rows per wavefront in A x
-constexpr int kU = 2;  // 64-element column chunks per step in A x
-constexpr int kUC = 8; // rows per step in A^H x
+constexpr int kR = 4;   // rows per block in A x
+constexpr int kU = 1;   // 64-element column chunks per wavefront step in A x
+constexpr int kWN = 8;  // wavefronts per block in A x
+constexpr int kBlockN = kWN * kWave;
+constexpr int kUC = 4;  // rows per step in A^H x
 
-__device__ __forceinline__ int read_phase(const SolverState* st)
+__device__ __forceinline__ void finish(SolverState& L, int info)
 {
-    return __builtin_amdgcn_readfirstlane(*(volatile const int*)&st->phase);
-}
-
-__device__ __forceinline__ void finish(SolverState* st, int info)
-{
-    st->info = info;
-    st->phase = PH_DONE;
+    L.info = info;
+    L.phase = PH_DONE;
 }
 
 __device__ __forceinline__ double relres(double sq, double ny2) { return sqrt(sq / ny2); }
 
 // After r = y - A x (or r = y when x0 = 0) at set-up.
-__device__ void setup_scalar(SolverState* st, double rr, bool bicg)
+__device__ void setup_step(SolverState& L, double rr, bool bicg)
 {
-    if (!__builtin_isfinite(rr)) { finish(st, 4); return; }
-    st->rr = rr;
-    st->relres_rec = relres(rr, st->ny2);
-    if (rr <= st->thr2) { st->phase = PH_CONFIRM; return; }
-    st->restart = 1;
+    if (!__builtin_isfinite(rr)) { finish(L, 4); return; }
+    L.rr = rr;
+    L.relres_rec = relres(rr, L.ny2);
+    if (rr <= L.thr2) { L.phase = PH_CONFIRM; return; }
+    L.restart = 1;
     if (bicg) {
-        st->rh2 = rr;
-        st->rho = d2{rr, 0.0};
-        if (st->maxit <= 0) { finish(st, 1); return; }
-        st->phase = PH_RUN;
+        L.rh2 = rr;
+        L.rho = d2{rr, 0.0};
+        if (L.maxit <= 0) { finish(L, 1); return; }
+        L.phase = PH_RUN;
     } else {
-        st->phase = PH_RESTART;  // z = A^H r, p = z come next
+        L.phase = PH_RESTART;  // z = A^H r, p = z come next
     }
 }
 
 // After the true residual rt = y - A x of a confirmation.
-__device__ void confirm_scalar(SolverState* st, double rtt, bool bicg)
+__device__ void confirm_step(SolverState& L, double rtt, bool bicg)
 {
-    st->matvecs++;
-    st->confirms++;
-    st->relres_true = relres(rtt, st->ny2);
-    if (!__builtin_isfinite(rtt)) { finish(st, 4); return; }
-    if (rtt <= st->thr2) { finish(st, 0); return; }
-    st->rr = rtt;
-    st->relres_rec = relres(rtt, st->ny2);
-    if (st->iters >= st->maxit) { finish(st, 1); return; }
+    L.matvecs++;
+    L.confirms++;
+    L.relres_true = relres(rtt, L.ny2);
+    if (!__builtin_isfinite(rtt)) { finish(L, 4); return; }
+    if (rtt <= L.thr2) { finish(L, 0); return; }
+    L.rr = rtt;
+    L.relres_rec = relres(rtt, L.ny2);
+    if (L.iters >= L.maxit) { finish(L, 1); return; }
     if (bicg) {
-        st->rh2 = rtt;
-        st->rho = d2{rtt, 0.0};
-        st->restart = 1;
+        L.rh2 = rtt;
+        L.rho = d2{rtt, 0.0};
+        L.restart = 1;
     }
-    st->phase = PH_RESTART;
+    L.phase = PH_RESTART;
 }
+
+// The scalar step of the method that finishes the pending reduction with
+// totals t0, t1.  Runs in thread 0 of every block of the consuming kernel on
+// identical inputs, so every block takes the same decision; only block 0
+// writes the per-iteration record (hist non-null there).
+__device__ void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
+{
+    const int k = L.pending;
+    L.pending = PK_NONE;
+    L.pending_blocks = 0;
+    switch (k) {
+    case PK_NORMY: {
+        const double ny2 = t0.x;
+        L.ny2 = ny2;
+        if (!__builtin_isfinite(ny2)) finish(L, 4);
+        else if (ny2 == 0.0) L.phase = PH_ZERO;
+        else L.thr2 = L.tol2 * ny2;
+        break;
+    }
+    case PK_ZERO:
+        L.relres_rec = L.relres_true = 0.0;
+        finish(L, 0);
+        break;
+    case PK_SETUP_B1:
+        L.matvecs++;
+        setup_step(L, t0.x, true);
+        break;
+    case PK_SETUP_B0:
+        setup_step(L, t0.x, true);
+        break;
+    case PK_SETUP_C1:
+        L.matvecs++;
+        setup_step(L, t0.x, false);
+        break;
+    case PK_SETUP_C0:
+        setup_step(L, t0.x, false);
+        break;
+    case PK_CONFIRM_B:
+        confirm_step(L, t0.x, true);
+        break;
+    case PK_CONFIRM_C:
+        confirm_step(L, t0.x, false);
+        break;
+    case PK_V: {  // alpha = rho / sigma
+        const d2 sigma = t0;
+        const double vv = t1.x;
+        L.matvecs++;
+        L.restart = 0;
+        if (!cfinite(sigma) || !__builtin_isfinite(vv)) { finish(L, 4); break; }
+        if (cabs2(sigma) <= 1e-28 * L.rh2 * vv) { finish(L, 2); break; }
+        const d2 al = cdiv(L.rho, sigma);
+        if (!cfinite(al)) { finish(L, 4); break; }
+        L.alpha = al;
+        if (hist) {
+            hist[L.iters].alpha_re = al.x;
+            hist[L.iters].alpha_im = al.y;
+        }
+        L.phase = PH_RUN;
+        break;
+    }
+    case PK_S: {  // half-step stop test on ||s||
+        const double ss = t0.x;
+        if (!__builtin_isfinite(ss)) { finish(L, 4); break; }
+        if (hist) hist[L.iters].res_half = relres(ss, L.ny2);
+        if (ss <= L.thr2) {
+            L.relres_rec = relres(ss, L.ny2);
+            L.phase = PH_HALF;
+        }
+        break;
+    }
+    case PK_T: {  // omega = t^H s / t^H t
+        const d2 ts = t0;
+        const double tt = t1.x;
+        L.matvecs++;
+        if (!__builtin_isfinite(tt) || !cfinite(ts)) { finish(L, 4); break; }
+        if (tt == 0.0) { finish(L, 3); break; }
+        const d2 om = d2{ts.x / tt, ts.y / tt};
+        if (om.x == 0.0 && om.y == 0.0) { finish(L, 3); break; }
+        L.omega = om;
+        if (hist) {
+            hist[L.iters].omega_re = om.x;
+            hist[L.iters].omega_im = om.y;
+        }
+        break;
+    }
+    case PK_XR: {  // stop test on ||r||, then beta for the next direction
+        const double rr = t0.x;
+        const d2 rho_new = t1;
+        L.iters++;
+        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
+        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
+        L.rr = rr;
+        L.relres_rec = relres(rr, L.ny2);
+        if (rr <= L.thr2) { L.phase = PH_CONFIRM; break; }
+        if (L.iters >= L.maxit) { finish(L, 1); break; }
+        if (!cfinite(rho_new)) { finish(L, 4); break; }
+        if (cabs2(rho_new) <= 1e-28 * L.rh2 * rr) { finish(L, 2); break; }
+        const d2 beta = cmul(cdiv(rho_new, L.rho), cdiv(L.alpha, L.omega));
+        if (!cfinite(beta)) { finish(L, 4); break; }
+        L.rho_old = L.rho;
+        L.rho = rho_new;
+        L.beta = beta;
+        if (hist) {
+            hist[L.iters].beta_re = beta.x;
+            hist[L.iters].beta_im = beta.y;
+        }
+        break;
+    }
+    case PK_HALF:
+        L.iters++;
+        L.phase = PH_CONFIRM;
+        break;
+    case PK_W: {  // alpha = gamma / ||w||^2
+        const double ww = t0.x;
+        L.matvecs++;
+        if (!__builtin_isfinite(ww)) { finish(L, 4); break; }
+        if (ww == 0.0) { finish(L, 2); break; }
+        const double al = L.gamma / ww;
+        L.alpha = d2{al, 0.0};
+        if (hist) {
+            hist[L.iters].alpha_re = al;
+            hist[L.iters].alpha_im = 0.0;
+        }
+        break;
+    }
+    case PK_XR2: {
+        const double rr = t0.x;
+        L.iters++;
+        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
+        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
+        L.rr = rr;
+        L.relres_rec = relres(rr, L.ny2);
+        if (rr <= L.thr2) L.phase = PH_CONFIRM;
+        break;
+    }
+    case PK_Z_RESTART:
+    case PK_Z_RUN: {
+        const double g = t0.x;
+        L.matvecs++;
+        if (!__builtin_isfinite(g)) { finish(L, 4); break; }
+        if (g == 0.0) { finish(L, 2); break; }
+        if (k == PK_Z_RESTART) {
+            L.gamma = g;
+            L.restart = 1;
+            L.phase = PH_RUN;
+        } else {
+            const double beta = g / L.gamma;
+            if (hist) {
+                hist[L.iters - 1].beta_re = beta;
+                hist[L.iters - 1].beta_im = 0.0;
+            }
+            L.beta = d2{beta, 0.0};
+            L.gamma = g;
+            L.restart = 0;
+        }
+        if (L.iters >= L.maxit) finish(L, 1);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// Start of every solver kernel: load state copy q into LDS and finish the
+// reduction the previous kernel left (same fixed order in every block).
+__device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d2* lds)
+{
+    if (threadIdx.x == 0) L = *a.st[q];
+    __syncthreads();
+    if (L.pending != PK_NONE) {
+        d2 t0 = d2{0.0, 0.0}, t1 = d2{0.0, 0.0};
+        if (L.pending_blocks > 0) reduce_partials(a.part[q], L.pending_blocks, lds, t0, t1);
+        if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr);
+        __syncthreads();
+    }
+}
+
+// End of every solver kernel: block 0 writes the state for the next kernel,
+// with the reduction this kernel leaves (kind, number of partial pairs).
+__device__ __forceinline__ void publish(const Args& a, int q, const SolverState& L, int kind,
+                                        int nblocks)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        SolverState o = L;
+        o.pending = kind;
+        o.pending_blocks = nblocks;
+        *a.st[q ^ 1] = o;
+    }
+}
+
+#define SOLVER_PROLOGUE()                  \
+    __shared__ SolverState L;              \
+    __shared__ d2 lds[kMaxWaves];          \
+    prologue(a, q, L, lds)
 
 // --------------------------------------------------------- common kernels
 
-__global__ void k_init(SolverState* st, int maxit)
+__global__ void k_init(SolverState* st, int maxit, double tol2)
 {
-    if (threadIdx.x < 16) st->tickets[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
-        st->phase = PH_RUN;
-        st->restart = 1;
-        st->info = -1;
-        st->iters = st->matvecs = st->confirms = 0;
-        st->maxit = maxit;
-        st->ny2 = st->thr2 = st->rh2 = st->rr = st->gamma = 0.0;
-        st->relres_rec = st->relres_true = __builtin_nan("");
-        st->rho = st->rho_old = st->alpha = st->omega = st->beta = d2{0.0, 0.0};
+        SolverState o;
+        o.phase = PH_RUN;
+        o.restart = 1;
+        o.info = -1;
+        o.iters = o.matvecs = o.confirms = 0;
+        o.maxit = maxit;
+        o.pending = PK_NONE;
+        o.pending_blocks = 0;
+        o.pad0 = o.pad1 = o.pad2 = 0;
+        o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
+        o.tol2 = tol2;
+        o.relres_rec = o.relres_true = __builtin_nan("");
+        o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
+        *st = o;
     }
 }
 
-// Copy the phase word to pinned host memory (end-of-slot status).
-__global__ void k_status(const SolverState* st, int* ring_slot)
+// End of a slot: finish what the slot left and copy the phase word to pinned
+// host memory.
+__global__ void k_status(Args a, int q, int* ring_slot)
 {
-    if (threadIdx.x == 0) {
-        int ph = *(volatile const int*)&st->phase;
-        __hip_atomic_store(ring_slot, ph, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    SOLVER_PROLOGUE();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(ring_slot, L.phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    publish(a, q, L, PK_NONE, 0);
 }
 
-// ||y||^2 and the stop threshold.
-__global__ __launch_bounds__(kBlock) void k_norm_y(Args a)
+// ||y||^2 (the stop threshold follows in the next kernel's step).
+__global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q)
 {
-    d2 pv[1] = {d2{0.0, 0.0}};
+    SOLVER_PROLOGUE();
+    d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock)
-        pv[0].x += cabs2(a.y[i]);
-    d2 tot[1];
-    if (reduce_to_last_block<1>(pv, a.partials, &a.st->tickets[T_NORMY], tot) &&
-        threadIdx.x == 0) {
-        SolverState* st = a.st;
-        double ny2 = tot[0].x;
-        st->ny2 = ny2;
-        if (!__builtin_isfinite(ny2)) finish(st, 4);
-        else if (ny2 == 0.0) st->phase = PH_ZERO;
-        else st->thr2 = a.tol2 * ny2;
-    }
+        v0.x += cabs2(a.y[i]);
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_NORMY, gridDim.x);
 }
 
 // Set-up when the caller says x0 = 0: x = 0, r = y (and r^ = y).
 template <bool BICG>
-__global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a)
+__global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
 {
-    const int ph = read_phase(a.st);
-    if (ph != PH_RUN && ph != PH_ZERO) return;
-    d2 pv[1] = {d2{0.0, 0.0}};
+    SOLVER_PROLOGUE();
+    const int ph = L.phase;
+    if (ph != PH_RUN && ph != PH_ZERO) { publish(a, q, L, PK_NONE, 0); return; }
+    d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         a.x[i] = d2{0.0, 0.0};
         if (ph == PH_RUN) {
             const d2 yi = a.y[i];
             a.r[i] = yi;
             if (BICG) a.rh[i] = yi;
-            pv[0].x += cabs2(yi);
+            v0.x += cabs2(yi);
         }
     }
-    d2 tot[1];
-    if (reduce_to_last_block<1>(pv, a.partials, &a.st->tickets[T_SETUP], tot) &&
-        threadIdx.x == 0) {
-        SolverState* st = a.st;
-        if (ph == PH_ZERO) {
-            st->relres_rec = st->relres_true = 0.0;
-            finish(st, 0);
-        } else {
-            setup_scalar(st, tot[0].x, BICG);
-        }
-    }
+    if (ph == PH_ZERO) { publish(a, q, L, PK_ZERO, 0); return; }
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, BICG ? PK_SETUP_B0 : PK_SETUP_C0, gridDim.x);
 }
 
 // ------------------------------------------------- A x kernels with roles
@@ -226,171 +429,110 @@ __device__ __forceinline__ int role_mode(int ph)
 }
 
 template <Role RO>
-__global__ __launch_bounds__(kBlock) void k_gemv_n_role(Args a)
+__global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 {
-    const int mode = role_mode<RO>(read_phase(a.st));
-    if (mode < 0) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int row0 = wave_id * kR;
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
+    const int row0 = blockIdx.x * kR;
     const int n = a.n;
+    const int t = threadIdx.x;
+    const bool setup = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C);
 
+    if (mode == PH_ZERO) {  // y == 0: zero this block's rows of x
+        if (t < kR && row0 + t < n) a.x[row0 + t] = d2{0.0, 0.0};
+        publish(a, q, L, PK_ZERO, 0);
+        return;
+    }
     // residual-type products read x; the others read a Krylov vector
-    const bool resid = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || mode == PH_CONFIRM);
+    const bool resid = setup || mode == PH_CONFIRM;
     const d2* in = resid ? a.x : (RO == ROLE_T ? a.s : a.p);
 
-    d2 pv[2] = {d2{0.0, 0.0}, d2{0.0, 0.0}};
-    if (mode == PH_ZERO) {
-        // y == 0: zero this wavefront's rows of x
-        if (lane < kR && row0 + lane < n) a.x[row0 + lane] = d2{0.0, 0.0};
-    } else if (row0 < n) {
-        d2 acc[kR];
-        gemv_n_wave<kR, kU>(a.A, a.lda, n, in, row0, acc);
-        // lane 0 finishes the wavefront's rows: output and dot-product terms
-        if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                const int i = row0 + r;
-                if (i >= n) break;
-                const d2 val = acc[r];
-                if (resid) {
-                    const d2 ri = a.y[i] - val;
-                    a.r[i] = ri;
-                    if (RO == ROLE_SETUP_B || RO == ROLE_V) a.rh[i] = ri;
-                    pv[0].x += cabs2(ri);
-                } else if (RO == ROLE_V) {
-                    a.v[i] = val;
-                    pv[0] = cfma_conj(a.rh[i], val, pv[0]);
-                    pv[1].x += cabs2(val);
-                } else if (RO == ROLE_T) {
-                    a.t[i] = val;
-                    pv[0] = cfma_conj(val, a.s[i], pv[0]);
-                    pv[1].x += cabs2(val);
-                } else {  // ROLE_W
-                    a.w[i] = val;
-                    pv[0].x += cabs2(val);
-                }
-            }
+    __shared__ d2 red[kWN][kR];
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    gemv_n_block<kR, kU, kWN>(a.A, a.lda, n, in, row0, red);
+    // thread r of the first wavefront finishes row row0 + r: output and its
+    // dot-product terms
+    const int i = row0 + t;
+    if (t < kR && i < n) {
+        const d2 val = gemv_n_row_total<kR, kWN>(red, t);
+        if (resid) {
+            const d2 ri = a.y[i] - val;
+            a.r[i] = ri;
+            if (RO == ROLE_SETUP_B || RO == ROLE_V) a.rh[i] = ri;
+            pv0.x = cabs2(ri);
+        } else if (RO == ROLE_V) {
+            a.v[i] = val;
+            pv0 = cfma_conj(a.rh[i], val, pv0);
+            pv1.x = cabs2(val);
+        } else if (RO == ROLE_T) {
+            a.t[i] = val;
+            pv0 = cfma_conj(val, a.s[i], pv0);
+            pv1.x = cabs2(val);
+        } else {  // ROLE_W
+            a.w[i] = val;
+            pv0.x = cabs2(val);
         }
     }
-
-    unsigned* ticket = &a.st->tickets[RO == ROLE_SETUP_B || RO == ROLE_SETUP_C ? T_SETUP
-                                      : RO == ROLE_V ? T_V : RO == ROLE_T ? T_T : T_W];
-    d2 tot[2];
-    if (!reduce_to_last_block<2>(pv, a.partials, ticket, tot) || threadIdx.x != 0) return;
-
-    SolverState* st = a.st;
-    if (mode == PH_ZERO) {
-        st->relres_rec = st->relres_true = 0.0;
-        finish(st, 0);
-        return;
-    }
-    if (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C) {
-        st->matvecs++;
-        setup_scalar(st, tot[0].x, RO == ROLE_SETUP_B);
-        return;
-    }
-    if (mode == PH_CONFIRM) {
-        confirm_scalar(st, tot[0].x, RO == ROLE_V);
-        return;
-    }
-    st->matvecs++;
-    if (RO == ROLE_V) {  // alpha = rho / sigma
-        const d2 sigma = tot[0];
-        const double vv = tot[1].x;
-        st->restart = 0;
-        if (!cfinite(sigma) || !__builtin_isfinite(vv)) { finish(st, 4); return; }
-        if (cabs2(sigma) <= 1e-28 * st->rh2 * vv) { finish(st, 2); return; }
-        const d2 al = cdiv(st->rho, sigma);
-        if (!cfinite(al)) { finish(st, 4); return; }
-        st->alpha = al;
-        if (a.hist) {
-            a.hist[st->iters].alpha_re = al.x;
-            a.hist[st->iters].alpha_im = al.y;
-        }
-        st->phase = PH_RUN;
-    } else if (RO == ROLE_T) {  // omega = t^H s / t^H t
-        const d2 ts = tot[0];
-        const double tt = tot[1].x;
-        if (!__builtin_isfinite(tt) || !cfinite(ts)) { finish(st, 4); return; }
-        if (tt == 0.0) { finish(st, 3); return; }
-        const d2 om = d2{ts.x / tt, ts.y / tt};
-        if (om.x == 0.0 && om.y == 0.0) { finish(st, 3); return; }
-        st->omega = om;
-        if (a.hist) {
-            a.hist[st->iters].omega_re = om.x;
-            a.hist[st->iters].omega_im = om.y;
-        }
-    } else {  // ROLE_W: alpha = gamma / |w|^2
-        const double ww = tot[0].x;
-        if (!__builtin_isfinite(ww)) { finish(st, 4); return; }
-        if (ww == 0.0) { finish(st, 2); return; }
-        const double al = st->gamma / ww;
-        st->alpha = d2{al, 0.0};
-        if (a.hist) {
-            a.hist[st->iters].alpha_re = al;
-            a.hist[st->iters].alpha_im = 0.0;
-        }
-    }
+    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    int kind;
+    if (RO == ROLE_SETUP_B) kind = PK_SETUP_B1;
+    else if (RO == ROLE_SETUP_C) kind = PK_SETUP_C1;
+    else if (mode == PH_CONFIRM) kind = RO == ROLE_V ? PK_CONFIRM_B : PK_CONFIRM_C;
+    else kind = RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : PK_W;
+    publish(a, q, L, kind, gridDim.x);
 }
 
 // ------------------------------------------------------- BiCGSTAB vectors
 
 // p = r (new direction) or p = r + beta (p - omega v)
-__global__ __launch_bounds__(kBlock) void k_bicg_p(Args a)
+__global__ __launch_bounds__(kBlock) void k_bicg_p(Args a, int q)
 {
-    const int ph = read_phase(a.st);
-    if (ph != PH_RUN && ph != PH_RESTART) return;
-    const bool fresh = __builtin_amdgcn_readfirstlane(*(volatile const int*)&a.st->restart) != 0;
-    const d2 beta = a.st->beta;
-    const d2 omega = a.st->omega;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 ri = a.r[i];
-        if (fresh) {
-            a.p[i] = ri;
-        } else {
-            const d2 q = cfma(d2{-omega.x, -omega.y}, a.v[i], a.p[i]);  // p - omega v
-            a.p[i] = cfma(beta, q, ri);
+    SOLVER_PROLOGUE();
+    if (L.phase == PH_RUN || L.phase == PH_RESTART) {
+        const bool fresh = L.restart != 0;
+        const d2 beta = L.beta;
+        const d2 nom = d2{-L.omega.x, -L.omega.y};
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+            const d2 ri = a.r[i];
+            if (fresh) {
+                a.p[i] = ri;
+            } else {
+                const d2 d = cfma(nom, a.v[i], a.p[i]);  // p - omega v
+                a.p[i] = cfma(beta, d, ri);
+            }
         }
     }
+    publish(a, q, L, PK_NONE, 0);
 }
 
-// s = r - alpha v, |s|^2; half-step stop test
-__global__ __launch_bounds__(kBlock) void k_bicg_s(Args a)
+// s = r - alpha v, ||s||^2
+__global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 {
-    if (read_phase(a.st) != PH_RUN) return;
-    const d2 alpha = a.st->alpha;
-    const d2 nal = d2{-alpha.x, -alpha.y};
-    d2 pv[1] = {d2{0.0, 0.0}};
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    const d2 nal = d2{-L.alpha.x, -L.alpha.y};
+    d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         const d2 si = cfma(nal, a.v[i], a.r[i]);
         a.s[i] = si;
-        pv[0].x += cabs2(si);
+        v0.x += cabs2(si);
     }
-    d2 tot[1];
-    if (!reduce_to_last_block<1>(pv, a.partials, &a.st->tickets[T_S], tot) ||
-        threadIdx.x != 0)
-        return;
-    SolverState* st = a.st;
-    const double ss = tot[0].x;
-    if (!__builtin_isfinite(ss)) { finish(st, 4); return; }
-    if (a.hist) a.hist[st->iters].res_half = relres(ss, st->ny2);
-    if (ss <= st->thr2) {
-        st->relres_rec = relres(ss, st->ny2);
-        st->phase = PH_HALF;
-    }
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_S, gridDim.x);
 }
 
-// x += alpha p + omega s, r = s - omega t, |r|^2, r^H r; or, after a
+// x += alpha p + omega s, r = s - omega t, ||r||^2, r^H r; or, after a
 // half-step exit, x += alpha p.
-__global__ __launch_bounds__(kBlock) void k_bicg_xr(Args a)
+__global__ __launch_bounds__(kBlock) void k_bicg_xr(Args a, int q)
 {
-    const int ph = read_phase(a.st);
-    if (ph != PH_RUN && ph != PH_HALF) return;
-    const d2 alpha = a.st->alpha;
-    const d2 omega = a.st->omega;
+    SOLVER_PROLOGUE();
+    const int ph = L.phase;
+    if (ph != PH_RUN && ph != PH_HALF) { publish(a, q, L, PK_NONE, 0); return; }
+    const d2 alpha = L.alpha;
+    const d2 omega = L.omega;
     const d2 nom = d2{-omega.x, -omega.y};
-    d2 pv[2] = {d2{0.0, 0.0}, d2{0.0, 0.0}};
+    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         d2 xi = cfma(alpha, a.p[i], a.x[i]);
         if (ph == PH_RUN) {
@@ -398,50 +540,25 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xr(Args a)
             xi = cfma(omega, si, xi);
             const d2 ri = cfma(nom, a.t[i], si);
             a.r[i] = ri;
-            pv[0].x += cabs2(ri);
-            pv[1] = cfma_conj(a.rh[i], ri, pv[1]);
+            v0.x += cabs2(ri);
+            v1 = cfma_conj(a.rh[i], ri, v1);
         }
         a.x[i] = xi;
     }
-    d2 tot[2];
-    if (!reduce_to_last_block<2>(pv, a.partials, &a.st->tickets[T_XR], tot) ||
-        threadIdx.x != 0)
-        return;
-    SolverState* st = a.st;
-    st->iters++;
-    if (ph == PH_HALF) {
-        st->phase = PH_CONFIRM;
-        return;
-    }
-    const double rr = tot[0].x;
-    const d2 rho_new = tot[1];
-    if (!__builtin_isfinite(rr)) { finish(st, 4); return; }
-    if (a.hist) a.hist[st->iters - 1].res_full = relres(rr, st->ny2);
-    st->rr = rr;
-    st->relres_rec = relres(rr, st->ny2);
-    if (rr <= st->thr2) { st->phase = PH_CONFIRM; return; }
-    if (st->iters >= st->maxit) { finish(st, 1); return; }
-    if (!cfinite(rho_new)) { finish(st, 4); return; }
-    if (cabs2(rho_new) <= 1e-28 * st->rh2 * rr) { finish(st, 2); return; }
-    const d2 beta = cmul(cdiv(rho_new, st->rho), cdiv(st->alpha, st->omega));
-    if (!cfinite(beta)) { finish(st, 4); return; }
-    st->rho_old = st->rho;
-    st->rho = rho_new;
-    st->beta = beta;
-    if (a.hist) {
-        a.hist[st->iters].beta_re = beta.x;
-        a.hist[st->iters].beta_im = beta.y;
-    }
+    if (ph == PH_HALF) { publish(a, q, L, PK_HALF, 0); return; }
+    write_partials(v0, v1, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_XR, gridDim.x);
 }
 
 // ----------------------------------------------------------- CGNR vectors
 
-// x += alpha p, r -= alpha w, |r|^2; stop test
-__global__ __launch_bounds__(kBlock) void k_cgnr_xr(Args a)
+// x += alpha p, r -= alpha w, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_cgnr_xr(Args a, int q)
 {
-    if (read_phase(a.st) != PH_RUN) return;
-    const double al = a.st->alpha.x;
-    d2 pv[1] = {d2{0.0, 0.0}};
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    const double al = L.alpha.x;
+    d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         const d2 pi = a.p[i];
         const d2 wi = a.w[i];
@@ -453,102 +570,70 @@ __global__ __launch_bounds__(kBlock) void k_cgnr_xr(Args a)
         ri.y = __builtin_fma(-al, wi.y, ri.y);
         a.x[i] = xi;
         a.r[i] = ri;
-        pv[0].x += cabs2(ri);
+        v0.x += cabs2(ri);
     }
-    d2 tot[1];
-    if (!reduce_to_last_block<1>(pv, a.partials, &a.st->tickets[T_XR2], tot) ||
-        threadIdx.x != 0)
-        return;
-    SolverState* st = a.st;
-    st->iters++;
-    const double rr = tot[0].x;
-    if (!__builtin_isfinite(rr)) { finish(st, 4); return; }
-    if (a.hist) a.hist[st->iters - 1].res_full = relres(rr, st->ny2);
-    st->rr = rr;
-    st->relres_rec = relres(rr, st->ny2);
-    if (rr <= st->thr2) st->phase = PH_CONFIRM;
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_XR2, gridDim.x);
 }
 
 // A^H r, band partials
-__global__ __launch_bounds__(kBlock) void k_cgnr_z1(Args a)
+__global__ __launch_bounds__(kBlock) void k_cgnr_z1(Args a, int q)
 {
-    const int ph = read_phase(a.st);
-    if (ph != PH_RUN && ph != PH_RESTART) return;
-    gemv_c_band<kUC>(a.A, a.lda, a.n, a.r, a.zpart, a.csh);
+    SOLVER_PROLOGUE();
+    if (L.phase == PH_RUN || L.phase == PH_RESTART)
+        gemv_c_band<kUC>(a.A, a.lda, a.n, a.r, a.zpart, a.csh);
+    publish(a, q, L, PK_NONE, 0);
 }
 
-// z = sum of band partials, |z|^2; gamma, beta
-__global__ __launch_bounds__(kBlock) void k_cgnr_z2(Args a)
+// z = sum of band partials, ||z||^2
+__global__ __launch_bounds__(kBlock) void k_cgnr_z2(Args a, int q)
 {
-    const int ph = read_phase(a.st);
-    if (ph != PH_RUN && ph != PH_RESTART) return;
-    d2 pv[1] = {d2{0.0, 0.0}};
+    SOLVER_PROLOGUE();
+    const int ph = L.phase;
+    if (ph != PH_RUN && ph != PH_RESTART) { publish(a, q, L, PK_NONE, 0); return; }
+    d2 v0 = d2{0.0, 0.0};
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
         const d2 zj = gemv_c_gather(a.zpart, a.n, a.csh.nbands, j);
         a.z[j] = zj;
-        pv[0].x += cabs2(zj);
+        v0.x += cabs2(zj);
     }
-    d2 tot[1];
-    if (!reduce_to_last_block<1>(pv, a.partials, &a.st->tickets[T_Z2], tot) ||
-        threadIdx.x != 0)
-        return;
-    SolverState* st = a.st;
-    st->matvecs++;
-    const double g = tot[0].x;
-    if (!__builtin_isfinite(g)) { finish(st, 4); return; }
-    if (g == 0.0) { finish(st, 2); return; }
-    if (ph == PH_RESTART) {
-        st->gamma = g;
-        st->restart = 1;
-        st->phase = PH_RUN;
-    } else {
-        const double beta = g / st->gamma;
-        if (a.hist) {
-            a.hist[st->iters - 1].beta_re = beta;
-            a.hist[st->iters - 1].beta_im = 0.0;
-        }
-        st->beta = d2{beta, 0.0};
-        st->gamma = g;
-        st->restart = 0;
-    }
-    if (st->iters >= st->maxit) finish(st, 1);
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, ph == PH_RESTART ? PK_Z_RESTART : PK_Z_RUN, gridDim.x);
 }
 
 // p = z (new direction) or p = z + beta p
-__global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a)
+__global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a, int q)
 {
-    if (read_phase(a.st) != PH_RUN) return;
-    const bool fresh = __builtin_amdgcn_readfirstlane(*(volatile const int*)&a.st->restart) != 0;
-    const double beta = a.st->beta.x;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 zi = a.z[i];
-        if (fresh) {
-            a.p[i] = zi;
-        } else {
-            d2 pi = a.p[i];
-            pi.x = __builtin_fma(beta, pi.x, zi.x);
-            pi.y = __builtin_fma(beta, pi.y, zi.y);
-            a.p[i] = pi;
+    SOLVER_PROLOGUE();
+    if (L.phase == PH_RUN) {
+        const bool fresh = L.restart != 0;
+        const double beta = L.beta.x;
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+            const d2 zi = a.z[i];
+            if (fresh) {
+                a.p[i] = zi;
+            } else {
+                d2 pi = a.p[i];
+                pi.x = __builtin_fma(beta, pi.x, zi.x);
+                pi.y = __builtin_fma(beta, pi.y, zi.y);
+                a.p[i] = pi;
+            }
         }
     }
+    publish(a, q, L, PK_NONE, 0);
 }
 
 // --------------------------------------------------------- plain products
 
-__global__ __launch_bounds__(kBlock) void k_gemv_n_plain(const d2* __restrict__ A, int64_t lda,
-                                                         int n, const d2* __restrict__ x,
-                                                         d2* __restrict__ y)
+__global__ __launch_bounds__(kBlockN) void k_gemv_n_plain(const d2* __restrict__ A, int64_t lda,
+                                                          int n, const d2* __restrict__ x,
+                                                          d2* __restrict__ y)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int row0 = (blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kR;
-    if (row0 >= n) return;
-    d2 acc[kR];
-    gemv_n_wave<kR, kU>(A, lda, n, x, row0, acc);
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < kR; ++r)
-            if (row0 + r < n) y[row0 + r] = acc[r];
-    }
+    __shared__ d2 red[kWN][kR];
+    const int row0 = blockIdx.x * kR;
+    gemv_n_block<kR, kU, kWN>(A, lda, n, x, row0, red);
+    const int t = threadIdx.x;
+    if (t < kR && row0 + t < n) y[row0 + t] = gemv_n_row_total<kR, kWN>(red, t);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gemv_c_band_plain(const d2* __restrict__ A,
@@ -574,8 +659,7 @@ static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static inline int blocks_n(int64_t n)
 {
-    const int64_t rows_per_block = (int64_t)kR * kWavesPerBlock;
-    int64_t b = (n + rows_per_block - 1) / rows_per_block;
+    int64_t b = (n + kR - 1) / kR;
     return (int)(b < 1 ? 1 : b);
 }
 
@@ -589,7 +673,7 @@ static inline int blocks_e(int64_t n)
 static constexpr int64_t kMaxN = (int64_t)1 << 30;
 
 struct Layout {
-    size_t state, partials, vec, zpart, total;
+    size_t state, partials, part_bytes, vec, zpart, total;
     int nvec;
 };
 
@@ -602,10 +686,11 @@ static Layout layout(int method, int64_t n)
     if (csh.blocks() > pb) pb = csh.blocks();
     const size_t vbytes = align256((size_t)(n > 0 ? n : 1) * sizeof(d2));
     size_t off = 0;
-    L.state = off;
+    L.state = off;  // two SolverState copies of 512 bytes
     off += 1024;
-    L.partials = off;
-    off += align256((size_t)pb * 2 * sizeof(d2));
+    L.partials = off;  // two buffers of pb partial pairs
+    L.part_bytes = align256((size_t)pb * 2 * sizeof(d2));
+    off += 2 * L.part_bytes;
     L.nvec = method == CCG_WS_BICGSTAB ? 6 : method == CCG_WS_CGNR ? 4 : 0;
     L.vec = off;
     off += (size_t)L.nvec * vbytes;
@@ -620,7 +705,12 @@ static Layout layout(int method, int64_t n)
 // end of each slot; one set per host thread and device, kept for the life of
 // the process.
 constexpr int kRing = 8;
-constexpr int kLookahead = 2;
+
+// Slots the host keeps queued ahead of the one whose status it reads.  A
+// slot at n >= 4096 lasts well over 100 us, far longer than the host needs
+// to enqueue the next one, so one slot ahead keeps the GPU busy; small
+// systems run slots of a few tens of microseconds and keep two queued.
+static inline int lookahead(int64_t n) { return n >= 4096 ? 1 : 2; }
 
 struct SyncCtx {
     int device = -1;
@@ -667,7 +757,7 @@ static int check_common(int64_t n, const void* A, int64_t lda, const void* y, co
 }
 
 static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
-                      ccg_z* x, void* work, ccg_hist* hist, double tol)
+                      ccg_z* x, void* work, ccg_hist* hist)
 {
     const Layout L = layout(method, n);
     char* base = (char*)work;
@@ -687,10 +777,11 @@ static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const 
         a.r = vec[0]; a.z = vec[1]; a.p = vec[2]; a.w = vec[3];
         a.zpart = (d2*)(base + L.zpart);
     }
-    a.partials = (d2*)(base + L.partials);
-    a.st = (SolverState*)(base + L.state);
+    a.part[0] = (d2*)(base + L.partials);
+    a.part[1] = (d2*)(base + L.partials + L.part_bytes);
+    a.st[0] = (SolverState*)(base + L.state);
+    a.st[1] = (SolverState*)(base + L.state + 512);
     a.hist = hist;
-    a.tol2 = tol * tol;
     return a;
 }
 
@@ -704,10 +795,12 @@ static void read_result(const SolverState& s, ccg_result* res)
     res->relres_true = s.relres_true;
 }
 
-// Enqueue set-up, then slots until the status ring reports PH_DONE.
+// Enqueue set-up, then slots until the status ring reports PH_DONE.  Every
+// solver kernel reads state copy q and writes copy q ^ 1; the host tracks q
+// across the launches it makes.
 template <bool BICG>
-static int run_solver(const Args& a, uint32_t flags, int32_t maxit, ccg_result* res,
-                      hipStream_t s)
+static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
+                      ccg_result* res, hipStream_t s)
 {
     SyncCtx* sc = nullptr;
     hipError_t e = get_sync(&sc);
@@ -715,48 +808,55 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, ccg_result* 
     const int gN = blocks_n(a.n);
     const int gE = blocks_e(a.n);
     const int gC = a.csh.blocks();
+    int q = 0;
 
-    k_init<<<1, 64, 0, s>>>(a.st, maxit);
-    k_norm_y<<<gE, kBlock, 0, s>>>(a);
+    k_init<<<1, 64, 0, s>>>(a.st[0], maxit, tol2);
+    k_norm_y<<<gE, kBlock, 0, s>>>(a, q);
+    q ^= 1;
     if (flags & CCG_X0_ZERO)
-        k_setup_x0zero<BICG><<<gE, kBlock, 0, s>>>(a);
+        k_setup_x0zero<BICG><<<gE, kBlock, 0, s>>>(a, q);
     else if (BICG)
-        k_gemv_n_role<ROLE_SETUP_B><<<gN, kBlock, 0, s>>>(a);
+        k_gemv_n_role<ROLE_SETUP_B><<<gN, kBlockN, 0, s>>>(a, q);
     else
-        k_gemv_n_role<ROLE_SETUP_C><<<gN, kBlock, 0, s>>>(a);
+        k_gemv_n_role<ROLE_SETUP_C><<<gN, kBlockN, 0, s>>>(a, q);
+    q ^= 1;
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
 
     // Each slot advances the method by at most one iteration or one
     // confirmation; a confirmation is always preceded by an iteration or
     // by the set-up, so 2 * maxit + 4 slots always suffice.
     const int64_t max_slots = 2 * (int64_t)maxit + 4;
-    for (int64_t slot = 0; slot < max_slots + kLookahead; ++slot) {
+    const int ahead = lookahead(a.n);
+    for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
             if (BICG) {
-                k_bicg_p<<<gE, kBlock, 0, s>>>(a);
-                k_gemv_n_role<ROLE_V><<<gN, kBlock, 0, s>>>(a);
-                k_bicg_s<<<gE, kBlock, 0, s>>>(a);
-                k_gemv_n_role<ROLE_T><<<gN, kBlock, 0, s>>>(a);
-                k_bicg_xr<<<gE, kBlock, 0, s>>>(a);
+                k_bicg_p<<<gE, kBlock, 0, s>>>(a, q);
+                k_gemv_n_role<ROLE_V><<<gN, kBlockN, 0, s>>>(a, q ^ 1);
+                k_bicg_s<<<gE, kBlock, 0, s>>>(a, q);
+                k_gemv_n_role<ROLE_T><<<gN, kBlockN, 0, s>>>(a, q ^ 1);
+                k_bicg_xr<<<gE, kBlock, 0, s>>>(a, q);
             } else {
-                k_gemv_n_role<ROLE_W><<<gN, kBlock, 0, s>>>(a);
-                k_cgnr_xr<<<gE, kBlock, 0, s>>>(a);
-                k_cgnr_z1<<<gC, kBlock, 0, s>>>(a);
-                k_cgnr_z2<<<gE, kBlock, 0, s>>>(a);
-                k_cgnr_p<<<gE, kBlock, 0, s>>>(a);
+                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, q);
+                k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, q ^ 1);
+                k_cgnr_z1<<<gC, kBlock, 0, s>>>(a, q);
+                k_cgnr_z2<<<gE, kBlock, 0, s>>>(a, q ^ 1);
+                k_cgnr_p<<<gE, kBlock, 0, s>>>(a, q);
             }
-            k_status<<<1, 64, 0, s>>>(a.st, sc->ring_d + slot % kRing);
+            // five launches flipped the copy five times
+            q ^= 1;
+            k_status<<<1, kBlock, 0, s>>>(a, q, sc->ring_d + slot % kRing);
+            q ^= 1;
             if ((e = hipGetLastError()) != hipSuccess) return (int)e;
             if ((e = hipEventRecord(sc->ev[slot % kRing], s)) != hipSuccess) return (int)e;
         }
-        const int64_t seen = slot - kLookahead;
+        const int64_t seen = slot - ahead;
         if (seen >= 0) {
             if ((e = hipEventSynchronize(sc->ev[seen % kRing])) != hipSuccess) return (int)e;
             if (__atomic_load_n(&sc->ring_h[seen % kRing], __ATOMIC_ACQUIRE) == PH_DONE) break;
         }
     }
     SolverState hs;
-    if ((e = hipMemcpyAsync(&hs, a.st, sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(&hs, a.st[q], sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return (int)e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
     read_result(hs, res);
@@ -782,8 +882,8 @@ static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_
         res->relres_rec = res->relres_true = 0.0;
         return 0;
     }
-    const Args a = make_args(method, n, A, lda, y, x, work, hist, tol);
-    return run_solver<BICG>(a, flags, maxit, res, (hipStream_t)stream);
+    const Args a = make_args(method, n, A, lda, y, x, work, hist);
+    return run_solver<BICG>(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
 }
 
 template <bool BICG>
@@ -828,7 +928,7 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (op == CCG_OP_N) {
-        k_gemv_n_plain<<<blocks_n(n), kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x,
+        k_gemv_n_plain<<<blocks_n(n), kBlockN, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x,
                                                      (d2*)y);
         e = hipGetLastError();
         return e == hipSuccess ? 0 : (int)e;
