@@ -31,6 +31,9 @@ if ROOT not in sys.path:
 
 METRIC = "BiCGSTAB solves/s at 1e-10 residual; matvec HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BLOCK_RHS = 64
+BLOCK_SEED = 5
 LATTICE_M = 20
 X_SEED = 1
 TOL = 1e-10
@@ -69,6 +72,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="bound on the oracle's timed sample")
+    p.add_argument("--no-block", action="store_true",
+                   help="skip the 64 right-hand-side block leg")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run a short mix of the kernels for rocprofv3 and exit")
     return p.parse_args()
@@ -136,6 +141,48 @@ def cpu_baseline(A, y, budget_s):
                       "system (n=8000) by the single-threaded C oracle, %.1f s"
                       % (k, el),
             "iters": res.iters, "relres_true": res.relres_true}
+
+
+def block_leg(A, A_h, steps):
+    """The 20^3 lattice with 64 right-hand sides (X_true seed 5): the product
+    A P on FP64 matrix cores timed with HIP events (8 n^2 k flops per launch),
+    and complete block BiCGSTAB solves of all 64 columns."""
+    import torch
+
+    from paper_1208_4869_amd import ccg, inputs
+    n = A.shape[0]
+    k = BLOCK_RHS
+    Xt = inputs.cn01(np.random.default_rng(BLOCK_SEED), (n, k))
+    Y_h = A_h @ Xt
+    Y = torch.from_numpy(Y_h).cuda()
+    P = torch.from_numpy(Xt).cuda()
+    Z = torch.empty_like(P)
+    wmm = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATMAT, n, k), dtype=torch.uint8,
+                      device="cuda")
+    tg = time_kernel(lambda: ccg.ccg_matmat(A, P, Z, work=wmm), 20)
+    flops = 8.0 * n * n * k
+    work = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_BLOCK, n, k),
+                       dtype=torch.uint8, device="cuda")
+    X = torch.empty_like(P)
+    res = ccg.ccg_bicgstab_block_ex(A, Y, X, TOL, MAXIT, flags=1, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = ccg.ccg_bicgstab_block_ex(A, Y, X, TOL, MAXIT, flags=1, work=work)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    Xg = X.cpu().numpy()
+    rel = np.linalg.norm(Y_h - A_h @ Xg, axis=0) / np.linalg.norm(Y_h, axis=0)
+    log("block: A P %.1f us (%.1f TFLOP/s); 64-column solve %.2f ms" % (
+        tg * 1e6, flops / tg / 1e12, tb * 1e3))
+    return {"rhs": k, "solves_per_s": k / tb, "ms_per_block_solve": tb * 1e3,
+            "max_iters": max(r.iters for r in res),
+            "all_converged": all(r.info == 0 for r in res),
+            "max_relres_true": float(rel.max()),
+            "gemm": {"kernel": "k_zgemm (A P, FP64 MFMA)", "launch_us": tg * 1e6,
+                     "flops_per_launch": flops, "achieved": flops / tg / 1e12,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / tg / 1e12 / FP64_PEAK_TFLOPS}}
 
 
 def profile_kernels(A, y):
@@ -258,6 +305,8 @@ def main():
                  "iters": cres.iters, "matvecs": cres.matvecs, "info": cres.info,
                  "relres_true": crel},
     }
+    if not args.no_block:
+        out["block"] = block_leg(A, A_h, max(args.steps // 3, 2))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (bounded sample, ~%.0f s)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(A_h, y_h, args.cpu_seconds)

@@ -81,7 +81,9 @@ enum { CCG_OP_N = 0, CCG_OP_C = 1 };
 enum {
     CCG_WS_MATVEC_C = 1, /* scratch of ccg_matvec_ex with op = CCG_OP_C */
     CCG_WS_BICGSTAB = 2,
-    CCG_WS_CGNR = 3
+    CCG_WS_CGNR = 3,
+    CCG_WS_MATMAT = 4,        /* scratch of ccg_matmat_ex (nrhs = k) */
+    CCG_WS_BICGSTAB_BLOCK = 5 /* ccg_bicgstab_block_ex (nrhs = k <= 64) */
 };
 
 /* Flags of the _ex solvers. */
@@ -148,6 +150,48 @@ int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
                 ccg_z* x, double tol, int32_t maxit, uint32_t flags,
                 void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
                 void* stream);
+
+/*
+ * Z = A B for k right-hand sides at once: B and Z are n x k, row-major
+ * (element (i, c) at B[i*ldb + c], ldb >= k; same for Z).  The user matvec of
+ * the Usage section applied to k vectors; on FP64 matrix cores
+ * (v_mfma_f64_16x16x4f64), FP64 accumulation in a fixed order (reproducible
+ * bit for bit).  Columns are processed 64 at a time.  B and Z must not
+ * overlap.  Asynchronous; ccg_matmat takes a stream-ordered scratch of
+ * ccg_workspace_bytes(CCG_WS_MATMAT, n, k) bytes, ccg_matmat_ex takes it from
+ * the caller (256-byte aligned).
+ * Arguments: 1 n, 2 k >= 0, 3 A, 4 lda, 5 B, 6 ldb, 7 Z, 8 ldz, [9 work,
+ * 10 work_bytes,] stream.
+ */
+int ccg_matmat(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const ccg_z* B,
+               int64_t ldb, ccg_z* Z, int64_t ldz, void* stream);
+int ccg_matmat_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                  const ccg_z* B, int64_t ldb, ccg_z* Z, int64_t ldz, void* work,
+                  size_t work_bytes, void* stream);
+
+/*
+ * Block BiCGSTAB: the k systems A x_c = y_c (columns of Y, X; n x k,
+ * row-major, 1 <= k <= 64) solved together.  Every column has its own rho,
+ * alpha, omega, beta, stop test, confirmation and info, exactly as
+ * ccg_bicgstab would give it; the two products of an iteration are one
+ * matrix-matrix product each for all columns.  A column that has finished is
+ * frozen (its x is not written again).  Y is read; X holds the initial
+ * guesses and receives the solutions.
+ * ccg_bicgstab_block: arguments 1 n, 2 k, 3 A, 4 lda, 5 Y, 6 ldy >= k, 7 X,
+ * 8 ldx >= k, 9 tol, 10 maxit, 11 info (host array of k), 12 stream;
+ * allocates its workspace, waits on stream.
+ * ccg_bicgstab_block_ex: arguments 1-10 as above, 11 flags (CCG_X0_ZERO or 0),
+ * 12 work (device, 256-byte aligned), 13 work_bytes (>= the
+ * ccg_workspace_bytes(CCG_WS_BICGSTAB_BLOCK, n, k) figure), 14 res (host
+ * array of k ccg_result), 15 stream; waits on stream.
+ */
+int ccg_bicgstab_block(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                       const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
+                       double tol, int32_t maxit, int32_t* info, void* stream);
+int ccg_bicgstab_block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                          const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
+                          double tol, int32_t maxit, uint32_t flags, void* work,
+                          size_t work_bytes, ccg_result* res, void* stream);
 
 #ifdef __cplusplus
 }

@@ -156,6 +156,21 @@ class Oracle:
     def cg(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
         return self._solve(self.lib.oracle_cg, A, y, x0, tol, maxit, flags)
 
+    # -- many right-hand sides: the same routines, one column at a time ----
+    def matmat(self, A, B, cols=None):
+        """Z = A B, column by column through matvec (cols: a subset)."""
+        B = np.asarray(B)
+        cols = range(B.shape[1]) if cols is None else cols
+        return np.stack([self.matvec(A, B[:, c]) for c in cols], axis=1)
+
+    def bicgstab_block(self, A, Y, X0=None, tol=1e-10, maxit=1000, cols=None):
+        """Each column of Y solved by its own BiCGSTAB (column-wise scalars
+        and stop test); cols selects a subset.  Returns a list of Results."""
+        Y = np.asarray(Y)
+        cols = range(Y.shape[1]) if cols is None else cols
+        return [self.bicgstab(A, Y[:, c], None if X0 is None else X0[:, c],
+                              tol=tol, maxit=maxit) for c in cols]
+
 
 _default: Oracle | None = None
 

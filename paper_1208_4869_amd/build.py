@@ -10,8 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libccg.so")
-SOURCES = ["ccg_solvers.hip"]
-HEADERS = ["ccg_device.h", "ccg_gemv.h"]
+SOURCES = ["ccg_solvers.hip", "ccg_block.hip"]
+HEADERS = ["ccg_device.h", "ccg_gemv.h", "ccg_krylov.h", "ccg_host.h"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -22,6 +22,8 @@ OP_C = 1
 WS_MATVEC_C = 1
 WS_BICGSTAB = 2
 WS_CGNR = 3
+WS_MATMAT = 4
+WS_BICGSTAB_BLOCK = 5
 X0_ZERO = 1
 
 INFO_TEXT = {0: "converged", 1: "iteration budget spent",
@@ -82,8 +84,16 @@ def load() -> ctypes.CDLL:
     for name in ("ccg_bicgstab_ex", "ccg_cgnr_ex"):
         getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32, U32, P, S,
                                        ctypes.POINTER(_Result), P, P]
+    lib.ccg_matmat.argtypes = [I64, I64, P, I64, P, I64, P, I64, P]
+    lib.ccg_matmat_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, S, P]
+    lib.ccg_bicgstab_block.argtypes = [I64, I64, P, I64, P, I64, P, I64, D, I32,
+                                       ctypes.POINTER(I32), P]
+    lib.ccg_bicgstab_block_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, D,
+                                          I32, U32, P, S, ctypes.POINTER(_Result),
+                                          P]
     for name in ("ccg_matvec", "ccg_matvec_ex", "ccg_bicgstab", "ccg_cgnr",
-                 "ccg_bicgstab_ex", "ccg_cgnr_ex"):
+                 "ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_matmat", "ccg_matmat_ex",
+                 "ccg_bicgstab_block", "ccg_bicgstab_block_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -226,3 +236,72 @@ def ccg_cgnr_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
 
 def hist_numpy(hist) -> np.ndarray:
     return hist.detach().cpu().numpy()
+
+
+def _rect(M, n, what):
+    torch = _torch()
+    if not isinstance(M, torch.Tensor) or M.dtype != torch.complex128 or \
+            not M.is_cuda or M.dim() != 2 or M.shape[0] != n:
+        raise TypeError("%s must be an n x k complex128 CUDA tensor" % what)
+    if M.shape[1] > 0 and M.shape[0] > 0 and M.stride(1) != 1:
+        raise TypeError("%s must be row-major (unit column stride)" % what)
+    return M.shape[1], max(M.stride(0), M.shape[1], 1)
+
+
+def ccg_matmat(A, B, Z=None, work=None, stream=None):
+    """Z = A B for an n x k block B (FP64 matrix cores); returns Z."""
+    n, lda = _mat(A)
+    k, ldb = _rect(B, n, "B")
+    if Z is None:
+        Z = _torch().empty((n, k), dtype=B.dtype, device=B.device)
+    kz, ldz = _rect(Z, n, "Z")
+    if kz != k:
+        raise TypeError("Z must have as many columns as B")
+    if work is None:
+        rc = load().ccg_matmat(n, k, A.data_ptr(), lda, B.data_ptr(), ldb,
+                               Z.data_ptr(), ldz, _stream(stream))
+    else:
+        rc = load().ccg_matmat_ex(n, k, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                  Z.data_ptr(), ldz, work.data_ptr(),
+                                  work.numel() * work.element_size(),
+                                  _stream(stream))
+    _check(rc, "ccg_matmat")
+    return Z
+
+
+def ccg_bicgstab_block(A, Y, X, tol=1e-10, maxit=1000, stream=None):
+    """Block BiCGSTAB on A X = Y (n x k, k <= 64); X in/out; returns the k
+    info codes."""
+    n, lda = _mat(A)
+    k, ldy = _rect(Y, n, "Y")
+    kx, ldx = _rect(X, n, "X")
+    if kx != k:
+        raise TypeError("X must have as many columns as Y")
+    info = (ctypes.c_int32 * max(k, 1))()
+    _check(load().ccg_bicgstab_block(n, k, A.data_ptr(), lda, Y.data_ptr(), ldy,
+                                     X.data_ptr(), ldx, float(tol), int(maxit),
+                                     info, _stream(stream)),
+           "ccg_bicgstab_block")
+    return [int(info[j]) for j in range(k)]
+
+
+def ccg_bicgstab_block_ex(A, Y, X, tol=1e-10, maxit=1000, flags=0, work=None,
+                          stream=None):
+    """Block BiCGSTAB with caller workspace and flags; returns k Results."""
+    n, lda = _mat(A)
+    k, ldy = _rect(Y, n, "Y")
+    kx, ldx = _rect(X, n, "X")
+    if kx != k:
+        raise TypeError("X must have as many columns as Y")
+    if work is None:
+        torch = _torch()
+        nbytes = max(ccg_workspace_bytes(WS_BICGSTAB_BLOCK, n, max(k, 1)), 256)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    res = (_Result * max(k, 1))()
+    _check(load().ccg_bicgstab_block_ex(
+        n, k, A.data_ptr(), lda, Y.data_ptr(), ldy, X.data_ptr(), ldx,
+        float(tol), int(maxit), int(flags), work.data_ptr(),
+        work.numel() * work.element_size(), res, _stream(stream)),
+        "ccg_bicgstab_block_ex")
+    return [Result(r.info, r.iters, r.matvecs, r.confirms, r.relres_rec,
+                   r.relres_true) for r in list(res)[:k]]

@@ -33,55 +33,12 @@
 #include "../../include/ccg.h"
 #include "ccg_device.h"
 #include "ccg_gemv.h"
+#include "ccg_host.h"
+#include "ccg_krylov.h"
 
 namespace ccg {
 
-// ------------------------------------------------------------------ state
-
-enum Phase : int {
-    PH_RUN = 0,      // iterating
-    PH_HALF = 1,     // BiCGSTAB converged at s: finish x, then confirm
-    PH_CONFIRM = 2,  // compute the true residual next
-    PH_RESTART = 3,  // true residual replaced r: start a new direction
-    PH_ZERO = 4,     // y == 0: x = 0 and stop
-    PH_DONE = 5,
-};
-
-// Reduction left for the next kernel to finish, and the scalar step that
-// goes with it.
-enum Pending : int {
-    PK_NONE = 0,
-    PK_NORMY,      // ||y||^2
-    PK_SETUP_B0,   // BiCGSTAB set-up, r = y (x0 = 0): ||r||^2
-    PK_SETUP_B1,   // BiCGSTAB set-up, r = y - A x: ||r||^2
-    PK_SETUP_C0,   // CGNR set-up, r = y
-    PK_SETUP_C1,   // CGNR set-up, r = y - A x
-    PK_ZERO,       // y == 0: x has been zeroed
-    PK_V,          // r^H v, ||v||^2        -> alpha
-    PK_CONFIRM_B,  // ||y - A x||^2 (BiCGSTAB)
-    PK_CONFIRM_C,  // ||y - A x||^2 (CGNR)
-    PK_S,          // ||s||^2               -> half-step test
-    PK_T,          // t^H s, ||t||^2        -> omega
-    PK_XR,         // ||r||^2, r^H r        -> stop test, beta
-    PK_HALF,       // x += alpha p done after a half-step exit
-    PK_W,          // ||w||^2               -> alpha (CGNR)
-    PK_XR2,        // ||r||^2               -> stop test (CGNR)
-    PK_Z_RUN,      // ||z||^2               -> beta (CGNR)
-    PK_Z_RESTART,  // ||z||^2               -> gamma of a new direction (CGNR)
-};
-
-// The solver's scalars in device memory.  Two copies alternate: a launch
-// reads copy q and block 0 writes copy q ^ 1, so no block of a launch ever
-// reads what its own launch writes.
-struct alignas(16) SolverState {
-    int phase, restart, info, iters;
-    int matvecs, confirms, maxit, pending;
-    int pending_blocks, pad0, pad1, pad2;
-    double ny2, thr2, rh2, rr;
-    double relres_rec, relres_true, gamma, tol2;
-    d2 rho, rho_old, alpha, omega, beta;
-};
-static_assert(sizeof(SolverState) <= 512, "state block");
+size_t block_workspace_bytes(int method, int64_t n, int64_t k);  // ccg_block.hip
 
 struct Args {
     const d2* A;
@@ -102,213 +59,6 @@ constexpr int kU = 1;   // 64-element column chunks per wavefront step in A x
 constexpr int kWN = 8;  // wavefronts per block in A x
 constexpr int kBlockN = kWN * kWave;
 constexpr int kUC = 4;  // rows per step in A^H x
-
-__device__ __forceinline__ void finish(SolverState& L, int info)
-{
-    L.info = info;
-    L.phase = PH_DONE;
-}
-
-__device__ __forceinline__ double relres(double sq, double ny2) { return sqrt(sq / ny2); }
-
-// After r = y - A x (or r = y when x0 = 0) at set-up.
-__device__ void setup_step(SolverState& L, double rr, bool bicg)
-{
-    if (!__builtin_isfinite(rr)) { finish(L, 4); return; }
-    L.rr = rr;
-    L.relres_rec = relres(rr, L.ny2);
-    if (rr <= L.thr2) { L.phase = PH_CONFIRM; return; }
-    L.restart = 1;
-    if (bicg) {
-        L.rh2 = rr;
-        L.rho = d2{rr, 0.0};
-        if (L.maxit <= 0) { finish(L, 1); return; }
-        L.phase = PH_RUN;
-    } else {
-        L.phase = PH_RESTART;  // z = A^H r, p = z come next
-    }
-}
-
-// After the true residual rt = y - A x of a confirmation.
-__device__ void confirm_step(SolverState& L, double rtt, bool bicg)
-{
-    L.matvecs++;
-    L.confirms++;
-    L.relres_true = relres(rtt, L.ny2);
-    if (!__builtin_isfinite(rtt)) { finish(L, 4); return; }
-    if (rtt <= L.thr2) { finish(L, 0); return; }
-    L.rr = rtt;
-    L.relres_rec = relres(rtt, L.ny2);
-    if (L.iters >= L.maxit) { finish(L, 1); return; }
-    if (bicg) {
-        L.rh2 = rtt;
-        L.rho = d2{rtt, 0.0};
-        L.restart = 1;
-    }
-    L.phase = PH_RESTART;
-}
-
-// The scalar step of the method that finishes the pending reduction with
-// totals t0, t1.  Runs in thread 0 of every block of the consuming kernel on
-// identical inputs, so every block takes the same decision; only block 0
-// writes the per-iteration record (hist non-null there).
-__device__ void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
-{
-    const int k = L.pending;
-    L.pending = PK_NONE;
-    L.pending_blocks = 0;
-    switch (k) {
-    case PK_NORMY: {
-        const double ny2 = t0.x;
-        L.ny2 = ny2;
-        if (!__builtin_isfinite(ny2)) finish(L, 4);
-        else if (ny2 == 0.0) L.phase = PH_ZERO;
-        else L.thr2 = L.tol2 * ny2;
-        break;
-    }
-    case PK_ZERO:
-        L.relres_rec = L.relres_true = 0.0;
-        finish(L, 0);
-        break;
-    case PK_SETUP_B1:
-        L.matvecs++;
-        setup_step(L, t0.x, true);
-        break;
-    case PK_SETUP_B0:
-        setup_step(L, t0.x, true);
-        break;
-    case PK_SETUP_C1:
-        L.matvecs++;
-        setup_step(L, t0.x, false);
-        break;
-    case PK_SETUP_C0:
-        setup_step(L, t0.x, false);
-        break;
-    case PK_CONFIRM_B:
-        confirm_step(L, t0.x, true);
-        break;
-    case PK_CONFIRM_C:
-        confirm_step(L, t0.x, false);
-        break;
-    case PK_V: {  // alpha = rho / sigma
-        const d2 sigma = t0;
-        const double vv = t1.x;
-        L.matvecs++;
-        L.restart = 0;
-        if (!cfinite(sigma) || !__builtin_isfinite(vv)) { finish(L, 4); break; }
-        if (cabs2(sigma) <= 1e-28 * L.rh2 * vv) { finish(L, 2); break; }
-        const d2 al = cdiv(L.rho, sigma);
-        if (!cfinite(al)) { finish(L, 4); break; }
-        L.alpha = al;
-        if (hist) {
-            hist[L.iters].alpha_re = al.x;
-            hist[L.iters].alpha_im = al.y;
-        }
-        L.phase = PH_RUN;
-        break;
-    }
-    case PK_S: {  // half-step stop test on ||s||
-        const double ss = t0.x;
-        if (!__builtin_isfinite(ss)) { finish(L, 4); break; }
-        if (hist) hist[L.iters].res_half = relres(ss, L.ny2);
-        if (ss <= L.thr2) {
-            L.relres_rec = relres(ss, L.ny2);
-            L.phase = PH_HALF;
-        }
-        break;
-    }
-    case PK_T: {  // omega = t^H s / t^H t
-        const d2 ts = t0;
-        const double tt = t1.x;
-        L.matvecs++;
-        if (!__builtin_isfinite(tt) || !cfinite(ts)) { finish(L, 4); break; }
-        if (tt == 0.0) { finish(L, 3); break; }
-        const d2 om = d2{ts.x / tt, ts.y / tt};
-        if (om.x == 0.0 && om.y == 0.0) { finish(L, 3); break; }
-        L.omega = om;
-        if (hist) {
-            hist[L.iters].omega_re = om.x;
-            hist[L.iters].omega_im = om.y;
-        }
-        break;
-    }
-    case PK_XR: {  // stop test on ||r||, then beta for the next direction
-        const double rr = t0.x;
-        const d2 rho_new = t1;
-        L.iters++;
-        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
-        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
-        L.rr = rr;
-        L.relres_rec = relres(rr, L.ny2);
-        if (rr <= L.thr2) { L.phase = PH_CONFIRM; break; }
-        if (L.iters >= L.maxit) { finish(L, 1); break; }
-        if (!cfinite(rho_new)) { finish(L, 4); break; }
-        if (cabs2(rho_new) <= 1e-28 * L.rh2 * rr) { finish(L, 2); break; }
-        const d2 beta = cmul(cdiv(rho_new, L.rho), cdiv(L.alpha, L.omega));
-        if (!cfinite(beta)) { finish(L, 4); break; }
-        L.rho_old = L.rho;
-        L.rho = rho_new;
-        L.beta = beta;
-        if (hist) {
-            hist[L.iters].beta_re = beta.x;
-            hist[L.iters].beta_im = beta.y;
-        }
-        break;
-    }
-    case PK_HALF:
-        L.iters++;
-        L.phase = PH_CONFIRM;
-        break;
-    case PK_W: {  // alpha = gamma / ||w||^2
-        const double ww = t0.x;
-        L.matvecs++;
-        if (!__builtin_isfinite(ww)) { finish(L, 4); break; }
-        if (ww == 0.0) { finish(L, 2); break; }
-        const double al = L.gamma / ww;
-        L.alpha = d2{al, 0.0};
-        if (hist) {
-            hist[L.iters].alpha_re = al;
-            hist[L.iters].alpha_im = 0.0;
-        }
-        break;
-    }
-    case PK_XR2: {
-        const double rr = t0.x;
-        L.iters++;
-        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
-        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
-        L.rr = rr;
-        L.relres_rec = relres(rr, L.ny2);
-        if (rr <= L.thr2) L.phase = PH_CONFIRM;
-        break;
-    }
-    case PK_Z_RESTART:
-    case PK_Z_RUN: {
-        const double g = t0.x;
-        L.matvecs++;
-        if (!__builtin_isfinite(g)) { finish(L, 4); break; }
-        if (g == 0.0) { finish(L, 2); break; }
-        if (k == PK_Z_RESTART) {
-            L.gamma = g;
-            L.restart = 1;
-            L.phase = PH_RUN;
-        } else {
-            const double beta = g / L.gamma;
-            if (hist) {
-                hist[L.iters - 1].beta_re = beta;
-                hist[L.iters - 1].beta_im = 0.0;
-            }
-            L.beta = d2{beta, 0.0};
-            L.gamma = g;
-            L.restart = 0;
-        }
-        if (L.iters >= L.maxit) finish(L, 1);
-        break;
-    }
-    default:
-        break;
-    }
-}
 
 // Start of every solver kernel: load state copy q into LDS and finish the
 // reduction the previous kernel left (same fixed order in every block).
@@ -655,8 +405,6 @@ __global__ __launch_bounds__(kBlock) void k_gemv_c_gather_plain(const d2* __rest
 
 // ================================================================== host
 
-static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
 static inline int blocks_n(int64_t n)
 {
     int64_t b = (n + kR - 1) / kR;
@@ -701,47 +449,11 @@ static Layout layout(int method, int64_t n)
     return L;
 }
 
-// Pinned, device-mapped ring of status words and the events that mark the
-// end of each slot; one set per host thread and device, kept for the life of
-// the process.
-constexpr int kRing = 8;
-
 // Slots the host keeps queued ahead of the one whose status it reads.  A
 // slot at n >= 4096 lasts well over 100 us, far longer than the host needs
 // to enqueue the next one, so one slot ahead keeps the GPU busy; small
 // systems run slots of a few tens of microseconds and keep two queued.
 static inline int lookahead(int64_t n) { return n >= 4096 ? 1 : 2; }
-
-struct SyncCtx {
-    int device = -1;
-    int* ring_h = nullptr;
-    int* ring_d = nullptr;
-    hipEvent_t ev[kRing];
-};
-
-static hipError_t get_sync(SyncCtx** out)
-{
-    thread_local std::vector<SyncCtx*> ctxs;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    for (SyncCtx* c : ctxs)
-        if (c->device == dev) { *out = c; return hipSuccess; }
-    SyncCtx* c = new SyncCtx;
-    c->device = dev;
-    e = hipHostMalloc((void**)&c->ring_h, kRing * sizeof(int),
-                      hipHostMallocMapped | hipHostMallocCoherent);
-    if (e != hipSuccess) { delete c; return e; }
-    e = hipHostGetDevicePointer((void**)&c->ring_d, c->ring_h, 0);
-    if (e != hipSuccess) return e;
-    for (int k = 0; k < kRing; ++k) {
-        e = hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming);
-        if (e != hipSuccess) return e;
-    }
-    ctxs.push_back(c);
-    *out = c;
-    return hipSuccess;
-}
 
 static int check_common(int64_t n, const void* A, int64_t lda, const void* y, const void* x,
                         double tol, int32_t maxit)
@@ -963,6 +675,8 @@ extern "C" {
 size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
 {
     if (n < 0 || nrhs < 1) return 0;
+    if (method == CCG_WS_MATMAT || method == CCG_WS_BICGSTAB_BLOCK)
+        return ccg::block_workspace_bytes(method, n, nrhs);
     if (method == CCG_WS_MATVEC_C) {
         const ccg::GemvCShape sh = ccg::gemv_c_shape(n > 0 ? n : 1);
         return (size_t)sh.nbands * (size_t)(n > 0 ? n : 1) * sizeof(ccg_z);
