@@ -11,7 +11,8 @@
 // tile step takes four of them (re*re, -im*im into the real part, re*im,
 // im*re into the imaginary part).  A block of 4 wavefronts owns 64 rows; each
 // wavefront keeps 16 rows x 64 columns of Z in registers (4 column tiles x
-// real/imaginary x 4 FP64 per lane).  The K dimension is split into 8 slices,
+// real/imaginary x 4 FP64 per lane), fed from LDS tiles.  The K dimension is
+// split into 8 slices,
 // slice = blockIdx % 8: blocks are dispatched round robin over the 8 XCDs, so
 // every block on an XCD works on the same slice and the XCD's L2 holds that
 // slice of P (1 MB at n = 8000, k = 64) while A streams through once.  A
@@ -42,87 +43,127 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kSlices = 8;         // K split, one slice per XCD
 constexpr int kRowsPerBlock = 64;  // 4 wavefronts x 16 rows
 constexpr int kMaxCols = 64;       // columns per product pass
-constexpr int kColBlocks = 256;    // blocks of the column-wise vector kernels
+constexpr int kColBlocks = 1024;   // blocks of the column-wise vector kernels
+constexpr int kStepThreads = 512;  // threads of the column step: 8 per column
 
 static inline int kslice_of(int64_t n)
 {
     const int64_t per = (n + kSlices - 1) / kSlices;
-    return (int)(((per + 3) / 4) * 4);
+    return (int)(((per + 7) / 8) * 8);  // a multiple of the LDS stage depth
 }
 
 // ------------------------------------------------------------------ GEMM
 
 // Slice s of Z = A B: Zp[s][i][c] = sum over k in slice s of A[i][k] B[k][c],
 // for i < n, c < ncols (ncols <= 16 NT).
+//
+// The block stages tiles of A (64 rows x kKS) and B (kKS x 16 NT) through LDS,
+// double buffered, with coalesced loads (each thread fetches two consecutive
+// elements of an A row; a wavefront covers 16 rows x 128 bytes), one barrier
+// per stage; the global loads of the next stage are in flight while the
+// matrix cores work on the current one.  Wavefront w multiplies rows
+// 16w..16w+15 of the tile by all 16 NT columns.
+constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
+
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int64_t lda, int n,
                                                   const d2* __restrict__ B, int64_t ldb,
                                                   int ncols, d2* __restrict__ Zp, int kslice)
 {
+    constexpr int AP = kKS + 1;                       // padded A-tile row (LDS banks)
+    constexpr int AE = kRowsPerBlock * kKS / kBlock;  // A elements per thread
+    constexpr int BW = 16 * NT;                       // B-tile width
+    constexpr int BN = kKS * BW;                      // B-tile elements
+    constexpr int BPT = (BN + kBlock - 1) / kBlock;   // B elements per thread
+    __shared__ d2 As[2][kRowsPerBlock * AP];
+    __shared__ d2 Bs[2][BN];
     const int s = blockIdx.x % kSlices;
     const int rb = blockIdx.x / kSlices;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    const int li = lane & 15;  // A row / B column within the 16-wide tile
-    const int lk = lane >> 4;  // k within the 4-deep step
-    const int row = rb * kRowsPerBlock + w * 16 + li;
-    const int rowc = row < n ? row : n - 1;
+    const int t = threadIdx.x;
+    const int lane = t & (kWave - 1);
+    const int w = t / kWave;
+    const int li = lane & 15;  // A row / B column within the 16-wide MFMA tile
+    const int lk = lane >> 4;  // k within the 4-deep MFMA step
     const int k0 = s * kslice;
     const int k1 = k0 + kslice < n ? k0 + kslice : n;
     d4 cre[NT], cim[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        cre[t] = d4{0.0, 0.0, 0.0, 0.0};
-        cim[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NT; ++q) {
+        cre[q] = d4{0.0, 0.0, 0.0, 0.0};
+        cim[q] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    if (k0 < k1) {
-        const d2* Ar = A + (int64_t)rowc * lda;
-        d2 a, b[NT];
-        // operands of the 4-deep step at kk for this lane
-        auto load = [&](int kk, d2& av, d2 (&bv)[NT]) {
-            const int kc = kk + lk;
-            const bool kin = kc < k1;
-            const int kcc = kin ? kc : k1 - 1;
-            av = Ar[kcc];
-            if (!kin) av = d2{0.0, 0.0};
-            const d2* Bk = B + (int64_t)kcc * ldb;
+    // this thread's share of the global tiles
+    const int arow = t / (kKS / AE);
+    const int aseg = (t % (kKS / AE)) * AE;
+    const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
+    const d2* Ar = A + (int64_t)grow * lda;
+    d2 ra[AE], rbv[BPT];
+    auto gload = [&](int kk) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int col = 16 * t + li;
-                const bool cin = kin && col < ncols;
-                bv[t] = Bk[cin ? col : 0];
-                if (!cin) bv[t] = d2{0.0, 0.0};
-            }
-        };
-        load(k0, a, b);
-        for (int kk = k0; kk < k1; kk += 4) {
-            d2 an = a, bn[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bn[t] = b[t];
-            if (kk + 4 < k1) load(kk + 4, an, bn);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                cre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[t].x, cre[t], 0, 0, 0);
-                cre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[t].y, cre[t], 0, 0, 0);
-                cim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[t].y, cim[t], 0, 0, 0);
-                cim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[t].x, cim[t], 0, 0, 0);
-            }
-            a = an;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = bn[t];
+        for (int e = 0; e < AE; ++e) {
+            const int kc = kk + aseg + e;
+            ra[e] = Ar[kc < n ? kc : n - 1];
+            if (kc >= k1) ra[e] = d2{0.0, 0.0};
         }
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const int idx = t + m * kBlock;
+            const int kc = kk + idx / BW;
+            const int c = idx % BW;
+            const bool ok = idx < BN && kc < k1 && c < ncols;
+            rbv[m] = B[(int64_t)(ok ? kc : k0) * ldb + (ok ? c : 0)];
+            if (!ok) rbv[m] = d2{0.0, 0.0};
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = ra[e];
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const int idx = t + m * kBlock;
+            if (idx < BN) Bs[buf][idx] = rbv[m];
+        }
+    };
+    const int nst = k1 > k0 ? (k1 - k0 + kKS - 1) / kKS : 0;
+    if (nst > 0) {
+        gload(k0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < nst) gload(k0 + (st + 1) * kKS);
+#pragma unroll
+        for (int ks = 0; ks < kKS; ks += 4) {
+            const d2 a = As[cur][(w * 16 + li) * AP + ks + lk];
+            d2 b[NT];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].x, cre[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].y, cim[q], 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[q].y, cre[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[q].x, cim[q], 0, 0, 0);
+            }
+        }
+        if (st + 1 < nst) lstore(cur ^ 1);
+        __syncthreads();
     }
     // result register v of a lane holds row lk + 4 v of the wavefront's 16-row
     // tile, column li (the v_mfma_f64_16x16x4f64 result layout; the
     // integer-input product tests pin it)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int col = 16 * t + li;
+    for (int q = 0; q < NT; ++q) {
+        const int col = 16 * q + li;
         if (col >= ncols) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb * kRowsPerBlock + w * 16 + lk + 4 * v;
-            if (r < n) Zp[((int64_t)s * n + r) * ncols + col] = d2{cre[t][v], cim[t][v]};
+            if (r < n) Zp[((int64_t)s * n + r) * ncols + col] = d2{cre[q][v], cim[q][v]};
         }
     }
 }
@@ -253,15 +294,33 @@ __global__ void kb_init(BArgs a, int maxit, double tol2)
 // Column step: finish the column reductions of the previous kernel (nparts
 // blocks) and apply the scalar step of `stage` to every column that has one.
 // With ring_slot, also report whether every column has finished.
-__global__ __launch_bounds__(kBlock) void kb_step(BArgs a, int stage, int nparts, int* ring_slot)
+__global__ __launch_bounds__(kStepThreads) void kb_step(BArgs a, int stage, int nparts,
+                                                       int* ring_slot)
 {
-    __shared__ d2 g0[4][kMaxCols], g1[4][kMaxCols];
+    constexpr int G = kStepThreads / kMaxCols;  // threads per column
+    __shared__ d2 g0[G][kMaxCols], g1[G][kMaxCols];
     __shared__ int done[kMaxCols];
     const int j = threadIdx.x & (kMaxCols - 1);
     const int grp = threadIdx.x / kMaxCols;
+    // thread (j, grp) adds blocks grp, grp + G, ... in order, eight loads in
+    // flight; the G group sums are then added in group order
     d2 s0 = d2{0.0, 0.0}, s1 = d2{0.0, 0.0};
     if (j < a.kp) {
-        for (int b = grp; b < nparts; b += 4) {
+        int b = grp;
+        for (; b + 7 * G < nparts; b += 8 * G) {
+            d2 u0[8], u1[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                u0[m] = a.cpart[((size_t)(b + m * G) * a.kp + j) * 2];
+                u1[m] = a.cpart[((size_t)(b + m * G) * a.kp + j) * 2 + 1];
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                s0 += u0[m];
+                s1 += u1[m];
+            }
+        }
+        for (; b < nparts; b += G) {
             s0 += a.cpart[((size_t)b * a.kp + j) * 2];
             s1 += a.cpart[((size_t)b * a.kp + j) * 2 + 1];
         }
@@ -270,8 +329,11 @@ __global__ __launch_bounds__(kBlock) void kb_step(BArgs a, int stage, int nparts
     g1[grp][j] = s1;
     __syncthreads();
     if (threadIdx.x < a.kp) {
-        const d2 t0 = g0[0][j] + g0[1][j] + g0[2][j] + g0[3][j];
-        const d2 t1 = g1[0][j] + g1[1][j] + g1[2][j] + g1[3][j];
+        d2 t0 = g0[0][j], t1 = g1[0][j];
+        for (int g = 1; g < G; ++g) {
+            t0 += g0[g][j];
+            t1 += g1[g][j];
+        }
         SolverState L = col_state(a, j);
         const int ph = L.phase;
         int kind = PK_NONE;
@@ -537,15 +599,15 @@ static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
 
     kb_init<<<1, kMaxCols, 0, s>>>(a, maxit, tol2);
     kb_normy<<<gC, kBlock, 0, s>>>(a);
-    kb_step<<<1, kBlock, 0, s>>>(a, CS_NORMY, gC, nullptr);
+    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
     if (flags & CCG_X0_ZERO) {
         kb_setup0<<<gC, kBlock, 0, s>>>(a);
-        kb_step<<<1, kBlock, 0, s>>>(a, CS_SETUP0, gC, nullptr);
+        kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
     } else {
         kb_setx<<<gC, kBlock, 0, s>>>(a);
         gemm(a.A, a.lda, a.n, a.B, a.kp, a.kp, a.Zp, s);
         kb_red_setup<<<gC, kBlock, 0, s>>>(a);
-        kb_step<<<1, kBlock, 0, s>>>(a, CS_SETUP1, gC, nullptr);
+        kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP1, gC, nullptr);
     }
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
 
@@ -556,14 +618,14 @@ static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
             kb_p<<<gC, kBlock, 0, s>>>(a);
             gemm(a.A, a.lda, a.n, a.B, a.kp, a.kp, a.Zp, s);
             kb_red1<<<gC, kBlock, 0, s>>>(a);
-            kb_step<<<1, kBlock, 0, s>>>(a, CS_P1, gC, nullptr);
+            kb_step<<<1, kStepThreads, 0, s>>>(a, CS_P1, gC, nullptr);
             kb_s<<<gC, kBlock, 0, s>>>(a);
-            kb_step<<<1, kBlock, 0, s>>>(a, CS_S, gC, nullptr);
+            kb_step<<<1, kStepThreads, 0, s>>>(a, CS_S, gC, nullptr);
             gemm(a.A, a.lda, a.n, a.S, a.kp, a.kp, a.Zp, s);
             kb_red2<<<gC, kBlock, 0, s>>>(a);
-            kb_step<<<1, kBlock, 0, s>>>(a, CS_T, gC, nullptr);
+            kb_step<<<1, kStepThreads, 0, s>>>(a, CS_T, gC, nullptr);
             kb_xr<<<gC, kBlock, 0, s>>>(a);
-            kb_step<<<1, kBlock, 0, s>>>(a, CS_XR, gC, sc->ring_d + slot % kRing);
+            kb_step<<<1, kStepThreads, 0, s>>>(a, CS_XR, gC, sc->ring_d + slot % kRing);
             if ((e = hipGetLastError()) != hipSuccess) return (int)e;
             if ((e = hipEventRecord(sc->ev[slot % kRing], s)) != hipSuccess) return (int)e;
         }
