@@ -254,6 +254,21 @@ def main():
     xcg = xc.cpu().numpy()
     crel = float(np.linalg.norm(y_h - A_h @ xcg) / np.linalg.norm(y_h))
 
+    # --- COCG / COCR: the lattice matrix is complex symmetric (section 3.4)
+    cs = {}
+    for name, fn, wsid in (("cocg", ccg.ccg_cocg_ex, ccg.WS_COCG),
+                           ("cocr", ccg.ccg_cocr_ex, ccg.WS_COCR)):
+        wk = ccg.workspace(wsid, n)
+        xs = torch.empty_like(x)
+        log("timing %d %s solves" % (csteps, name.upper()))
+        stot, slat, sres = time_solves(fn, A, y, xs, wk, csteps, 1)
+        xsg = xs.cpu().numpy()
+        cs[name] = {"solves_per_s": csteps / stot,
+                    "p50_ms": float(np.percentile(slat, 50) * 1e3),
+                    "iters": sres.iters, "matvecs": sres.matvecs, "info": sres.info,
+                    "relres_true": float(np.linalg.norm(y_h - A_h @ xsg)
+                                         / np.linalg.norm(y_h))}
+
     # --- dominant kernel: A x (and A^H x), timed with HIP events
     xin = torch.from_numpy(x_true).cuda()
     yout = torch.empty_like(xin)
@@ -304,6 +319,8 @@ def main():
                  "p50_ms": float(np.percentile(clat, 50) * 1e3),
                  "iters": cres.iters, "matvecs": cres.matvecs, "info": cres.info,
                  "relres_true": crel},
+        "cocg": cs["cocg"],
+        "cocr": cs["cocr"],
     }
     if not args.no_block:
         out["block"] = block_leg(A, A_h, max(args.steps // 3, 2))

@@ -29,7 +29,9 @@
  * Solver status (*info, res->info)
  *   0  converged: ||y - A x||_2 <= tol * ||y||_2, checked on the true residual
  *   1  iteration budget maxit spent
- *   2  breakdown: rho or sigma (BiCGSTAB); ||A p|| or ||A^H r|| zero (CGNR)
+ *   2  breakdown: rho or sigma (BiCGSTAB); ||A p|| or ||A^H r|| zero (CGNR);
+ *      a zero bilinear form (r, r), (p, A p), (r, A r) or (A p, A p) (COCG,
+ *      COCR)
  *   3  breakdown: t^H t or omega zero (BiCGSTAB)
  *   4  a non-finite value was met (x is left at the last finite iterate)
  *   n == 0 is a no-op with info 0; y == 0 gives x = 0 with info 0.
@@ -82,8 +84,10 @@ enum {
     CCG_WS_MATVEC_C = 1, /* scratch of ccg_matvec_ex with op = CCG_OP_C */
     CCG_WS_BICGSTAB = 2,
     CCG_WS_CGNR = 3,
-    CCG_WS_MATMAT = 4,        /* scratch of ccg_matmat_ex (nrhs = k) */
-    CCG_WS_BICGSTAB_BLOCK = 5 /* ccg_bicgstab_block_ex (nrhs = k <= 64) */
+    CCG_WS_MATMAT = 4,         /* scratch of ccg_matmat_ex (nrhs = k) */
+    CCG_WS_BICGSTAB_BLOCK = 5, /* ccg_bicgstab_block_ex (nrhs = k <= 64) */
+    CCG_WS_COCG = 6,
+    CCG_WS_COCR = 7
 };
 
 /* Flags of the _ex solvers. */
@@ -147,6 +151,28 @@ int ccg_bicgstab_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
                     ccg_hist* hist, void* stream);
 
 int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
+                ccg_z* x, double tol, int32_t maxit, uint32_t flags,
+                void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                void* stream);
+
+/*
+ * COCG and COCR for complex symmetric A (A^T = A, not checked): the methods
+ * of the "next releases" section 3.4 (COCR of Sogabe and Zhang, compared
+ * there with COCG).  CG and CR with the unconjugated bilinear form
+ * (a, b) = sum a_i b_i; one product with A per iteration.  Same stop rule,
+ * confirmation, restart, arguments, waiting and info codes as
+ * ccg_bicgstab / ccg_bicgstab_ex (workspace ids CCG_WS_COCG, CCG_WS_COCR).
+ * COCG's record holds alpha and beta (complex) and res_full; COCR's the same.
+ */
+int ccg_cocg(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
+             double tol, int32_t maxit, int32_t* info, void* stream);
+int ccg_cocr(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
+             double tol, int32_t maxit, int32_t* info, void* stream);
+int ccg_cocg_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
+                ccg_z* x, double tol, int32_t maxit, uint32_t flags,
+                void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                void* stream);
+int ccg_cocr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
                 ccg_z* x, double tol, int32_t maxit, uint32_t flags,
                 void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
                 void* stream);

@@ -7,8 +7,9 @@ and it never imports the product library.
 It wraps ``ccg_oracle.c`` (plain sequential complex128 C, built with gcc and
 ``-ffp-contract=off``) through ctypes.  The C file documents what each routine
 follows in the paper (Introduction: the problem A x = y; section 2.1: the
-bicgstab and cgnr methods of the PIM90 set; Usage: matvec / cmatvec kept apart
-from the iteration, tolerance epsilon_err and budget maxit).
+bicgstab and cgnr methods of the PIM90 set; section 3.4: COCR and COCG for
+complex symmetric systems; Usage: matvec / cmatvec kept apart from the
+iteration, tolerance epsilon_err and budget maxit).
 
 Parity status: pinned for every routine (see tests/test_oracle_*.py: dense LU,
 closed forms, finite termination, exact integer products, invariants, third
@@ -92,7 +93,8 @@ class Oracle:
             f = getattr(self.lib, name)
             f.argtypes = [I64, P, I64, P, P]
             f.restype = None
-        for name in ("oracle_bicgstab", "oracle_cgnr", "oracle_cg"):
+        for name in ("oracle_bicgstab", "oracle_cgnr", "oracle_cg",
+                     "oracle_cocg", "oracle_cocr"):
             f = getattr(self.lib, name)
             f.argtypes = [I64, P, I64, P, P, ctypes.c_double, ctypes.c_int32,
                           ctypes.c_uint32, ctypes.POINTER(_Stats), P]
@@ -155,6 +157,12 @@ class Oracle:
 
     def cg(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
         return self._solve(self.lib.oracle_cg, A, y, x0, tol, maxit, flags)
+
+    def cocg(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
+        return self._solve(self.lib.oracle_cocg, A, y, x0, tol, maxit, flags)
+
+    def cocr(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
+        return self._solve(self.lib.oracle_cocr, A, y, x0, tol, maxit, flags)
 
     # -- many right-hand sides: the same routines, one column at a time ----
     def matmat(self, A, B, cols=None):

@@ -17,6 +17,11 @@
  *   - CGNR: conjugate gradients applied to the normal equations
  *     A^H A x = A^H y, which minimises ||y - A x||_2 over a growing Krylov
  *     space (PIM90 set, section 2.1; Templates).
+ *   - COCG and COCR for complex symmetric A (A^T = A): the methods of the
+ *     "next releases" section 3.4 (COCR of Sogabe and Zhang, 2007, compared
+ *     there with COCG).  Both are the CG and CR recurrences with the
+ *     unconjugated bilinear form (a, b) = sum a_i b_i in place of the inner
+ *     product; one product with A per iteration.
  *   - CG: Hestenes-Stiefel conjugate gradients for Hermitian positive-definite
  *     A.  Not in the paper's list; kept only as a pinned reference that other
  *     tests compare CGNR and BiCGSTAB against.
@@ -32,7 +37,8 @@
  *     inside the same iteration budget (tolerance epsilon_err and budget maxit
  *     of the cgmodule structure, Usage section).
  *   - info: 0 converged, 1 iteration budget spent, 2 breakdown of rho or sigma
- *     (BiCGSTAB) or of ||w|| or ||A^H r|| (CGNR), 3 breakdown of omega or
+ *     (BiCGSTAB), of ||w|| or ||A^H r|| (CGNR), or of a bilinear form (r, r),
+ *     (p, A p), (r, A r) or (A p, A p) (COCG, COCR), 3 breakdown of omega or
  *     t^H t (BiCGSTAB), 4 non-finite value met.
  *
  * Arithmetic: C11 double complex, one thread, every sum a left-to-right loop.
@@ -82,6 +88,15 @@ static zc dotc(int64_t n, const zc* a, const zc* b)
     zc s = 0.0;
     for (int64_t i = 0; i < n; ++i)
         s += conj(a[i]) * b[i];
+    return s;
+}
+
+/* (a, b) = sum_i a_i * b_i, the bilinear form of COCG / COCR */
+static zc dotu(int64_t n, const zc* a, const zc* b)
+{
+    zc s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += a[i] * b[i];
     return s;
 }
 
@@ -497,6 +512,230 @@ int oracle_cgnr(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
         for (int64_t i = 0; i < n; ++i)
             p[i] = z[i] + beta * p[i];
         gamma = gamma_new;
+    }
+    st->iters = k;
+    free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------- COCG */
+
+/* COCG: CG with the bilinear form, for complex symmetric A.
+ *   p = r, rho = (r, r); per iteration: q = A p, alpha = rho / (p, q),
+ *   x += alpha p, r -= alpha q, stop test, rho' = (r, r), beta = rho'/rho,
+ *   p = r + beta p.  (r, r) = 0 or (p, q) = 0 with r != 0 is a breakdown. */
+int oracle_cocg(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+                double tol, int32_t maxit, uint32_t flags, oracle_stats* st,
+                oracle_hist* hist)
+{
+    stats_init(st);
+    int bad = bad_args(n, lda, tol, maxit);
+    if (bad) return bad;
+    hist_init(hist, maxit);
+
+    zc* work = (zc*)malloc(sizeof(zc) * (size_t)(4 * (n > 0 ? n : 1)));
+    if (!work) return -100;
+    zc *r = work, *p = r + n, *q = p + n, *tmp = q + n;
+
+    double ny2 = 0.0, rr = 0.0;
+    if (setup(n, A, lda, y, x, flags, r, &ny2, &rr, st)) {
+        free(work);
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    int32_t k = 0;
+    int need_confirm = rr <= thr2;
+    int restart = 1;
+    zc rho = 0.0;
+
+    for (;;) {
+        if (need_confirm) {
+            need_confirm = 0;
+            if (confirm(n, A, lda, y, x, r, tmp, ny2, thr2, k, maxit, &rr, st))
+                break;
+            restart = 1;
+        }
+        if (restart) { /* p = r, rho = (r, r) */
+            rho = dotu(n, r, r);
+            if (!zfinite(rho)) {
+                st->info = 4;
+                break;
+            }
+            if (rho == 0.0) {
+                st->info = 2;
+                break;
+            }
+            zcopy(n, r, p);
+            restart = 0;
+        }
+        if (k >= maxit) {
+            st->info = 1;
+            break;
+        }
+        oracle_matvec(n, A, lda, p, q);
+        st->matvecs++;
+        zc pq = dotu(n, p, q);
+        if (!zfinite(pq)) {
+            st->info = 4;
+            break;
+        }
+        if (pq == 0.0) {
+            st->info = 2;
+            break;
+        }
+        zc alpha = zdiv(rho, pq);
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        rr = norm2sq(n, r);
+        k++;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) {
+            hist[k - 1].alpha_re = creal(alpha);
+            hist[k - 1].alpha_im = cimag(alpha);
+            hist[k - 1].res_full = sqrt(rr / ny2);
+        }
+        st->relres_rec = sqrt(rr / ny2);
+        if (rr <= thr2) {
+            need_confirm = 1;
+            continue;
+        }
+        zc rho_new = dotu(n, r, r);
+        if (!zfinite(rho_new)) {
+            st->info = 4;
+            break;
+        }
+        if (rho_new == 0.0) {
+            st->info = 2;
+            break;
+        }
+        zc beta = zdiv(rho_new, rho);
+        if (hist) {
+            hist[k - 1].beta_re = creal(beta);
+            hist[k - 1].beta_im = cimag(beta);
+        }
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = r[i] + beta * p[i];
+        rho = rho_new;
+    }
+    st->iters = k;
+    free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------- COCR */
+
+/* COCR (Sogabe and Zhang): CR with the bilinear form, for complex symmetric
+ * A.  Keeps u = A r and w = A p; one product (u = A r) per iteration.
+ *   u = A r, p = r, w = u, rho = (r, u); per iteration:
+ *   alpha = rho / (w, w), x += alpha p, r -= alpha w, stop test, u = A r,
+ *   rho' = (r, u), beta = rho'/rho, p = r + beta p, w = u + beta w. */
+int oracle_cocr(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
+                double tol, int32_t maxit, uint32_t flags, oracle_stats* st,
+                oracle_hist* hist)
+{
+    stats_init(st);
+    int bad = bad_args(n, lda, tol, maxit);
+    if (bad) return bad;
+    hist_init(hist, maxit);
+
+    zc* work = (zc*)malloc(sizeof(zc) * (size_t)(5 * (n > 0 ? n : 1)));
+    if (!work) return -100;
+    zc *r = work, *u = r + n, *p = u + n, *w = p + n, *tmp = w + n;
+
+    double ny2 = 0.0, rr = 0.0;
+    if (setup(n, A, lda, y, x, flags, r, &ny2, &rr, st)) {
+        free(work);
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    int32_t k = 0;
+    int need_confirm = rr <= thr2;
+    int restart = 1;
+    zc rho = 0.0;
+
+    for (;;) {
+        if (need_confirm) {
+            need_confirm = 0;
+            if (confirm(n, A, lda, y, x, r, tmp, ny2, thr2, k, maxit, &rr, st))
+                break;
+            restart = 1;
+        }
+        if (restart) { /* u = A r, p = r, w = u, rho = (r, u) */
+            oracle_matvec(n, A, lda, r, u);
+            st->matvecs++;
+            rho = dotu(n, r, u);
+            if (!zfinite(rho)) {
+                st->info = 4;
+                break;
+            }
+            if (rho == 0.0) {
+                st->info = 2;
+                break;
+            }
+            zcopy(n, r, p);
+            zcopy(n, u, w);
+            restart = 0;
+        }
+        if (k >= maxit) {
+            st->info = 1;
+            break;
+        }
+        zc ww = dotu(n, w, w);
+        if (!zfinite(ww)) {
+            st->info = 4;
+            break;
+        }
+        if (ww == 0.0) {
+            st->info = 2;
+            break;
+        }
+        zc alpha = zdiv(rho, ww);
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * w[i];
+        }
+        rr = norm2sq(n, r);
+        k++;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (hist) {
+            hist[k - 1].alpha_re = creal(alpha);
+            hist[k - 1].alpha_im = cimag(alpha);
+            hist[k - 1].res_full = sqrt(rr / ny2);
+        }
+        st->relres_rec = sqrt(rr / ny2);
+        if (rr <= thr2) {
+            need_confirm = 1;
+            continue;
+        }
+        oracle_matvec(n, A, lda, r, u);
+        st->matvecs++;
+        zc rho_new = dotu(n, r, u);
+        if (!zfinite(rho_new)) {
+            st->info = 4;
+            break;
+        }
+        if (rho_new == 0.0) {
+            st->info = 2;
+            break;
+        }
+        zc beta = zdiv(rho_new, rho);
+        if (hist) {
+            hist[k - 1].beta_re = creal(beta);
+            hist[k - 1].beta_im = cimag(beta);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            p[i] = r[i] + beta * p[i];
+            w[i] = u[i] + beta * w[i];
+        }
+        rho = rho_new;
     }
     st->iters = k;
     free(work);

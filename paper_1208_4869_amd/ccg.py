@@ -24,6 +24,8 @@ WS_BICGSTAB = 2
 WS_CGNR = 3
 WS_MATMAT = 4
 WS_BICGSTAB_BLOCK = 5
+WS_COCG = 6
+WS_COCR = 7
 X0_ZERO = 1
 
 INFO_TEXT = {0: "converged", 1: "iteration budget spent",
@@ -78,10 +80,10 @@ def load() -> ctypes.CDLL:
     lib.ccg_matvec_ex.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, S, P]
     lib.ccg_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
     lib.ccg_workspace_bytes.restype = S
-    for name in ("ccg_bicgstab", "ccg_cgnr"):
+    for name in ("ccg_bicgstab", "ccg_cgnr", "ccg_cocg", "ccg_cocr"):
         getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32,
                                        ctypes.POINTER(I32), P]
-    for name in ("ccg_bicgstab_ex", "ccg_cgnr_ex"):
+    for name in ("ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_cocg_ex", "ccg_cocr_ex"):
         getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32, U32, P, S,
                                        ctypes.POINTER(_Result), P, P]
     lib.ccg_matmat.argtypes = [I64, I64, P, I64, P, I64, P, I64, P]
@@ -93,7 +95,8 @@ def load() -> ctypes.CDLL:
                                           P]
     for name in ("ccg_matvec", "ccg_matvec_ex", "ccg_bicgstab", "ccg_cgnr",
                  "ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_matmat", "ccg_matmat_ex",
-                 "ccg_bicgstab_block", "ccg_bicgstab_block_ex"):
+                 "ccg_bicgstab_block", "ccg_bicgstab_block_ex", "ccg_cocg",
+                 "ccg_cocr", "ccg_cocg_ex", "ccg_cocr_ex"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -231,6 +234,28 @@ def ccg_bicgstab_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
 def ccg_cgnr_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
                 hist=None, stream=None) -> Result:
     return _ex("ccg_cgnr_ex", WS_CGNR, A, y, x, tol, maxit, flags, work, hist,
+               stream)
+
+
+def ccg_cocg(A, y, x, tol=1e-10, maxit=1000, stream=None) -> int:
+    """COCG on complex symmetric A x = y, x in/out; returns info."""
+    return _short("ccg_cocg", A, y, x, tol, maxit, stream)
+
+
+def ccg_cocr(A, y, x, tol=1e-10, maxit=1000, stream=None) -> int:
+    """COCR on complex symmetric A x = y, x in/out; returns info."""
+    return _short("ccg_cocr", A, y, x, tol, maxit, stream)
+
+
+def ccg_cocg_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
+                hist=None, stream=None) -> Result:
+    return _ex("ccg_cocg_ex", WS_COCG, A, y, x, tol, maxit, flags, work, hist,
+               stream)
+
+
+def ccg_cocr_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
+                hist=None, stream=None) -> Result:
+    return _ex("ccg_cocr_ex", WS_COCR, A, y, x, tol, maxit, flags, work, hist,
                stream)
 
 

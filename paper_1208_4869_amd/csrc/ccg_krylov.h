@@ -42,6 +42,14 @@ enum Pending : int {
     PK_XR2,        // ||r||^2               -> stop test (CGNR)
     PK_Z_RUN,      // ||z||^2               -> beta (CGNR)
     PK_Z_RESTART,  // ||z||^2               -> gamma of a new direction (CGNR)
+    PK_SETUP_G0,   // COCG set-up, r = y: ||r||^2, (r, r)
+    PK_SETUP_G1,   // COCG set-up, r = y - A x: ||r||^2, (r, r)
+    PK_CONFIRM_G,  // ||y - A x||^2, (r, r) of the true residual (COCG)
+    PK_Q,          // (p, A p)              -> alpha (COCG)
+    PK_XR_G,       // ||r||^2, (r, r)       -> stop test, beta (COCG)
+    PK_U,          // (r, A r)              -> beta, budget (COCR)
+    PK_WW,         // (A p, A p)            -> alpha (COCR)
+    PK_XR_R,       // ||r||^2               -> stop test (COCR)
 };
 
 // The solver's scalars in device memory.  Two copies alternate: a launch
@@ -100,6 +108,15 @@ __device__ inline void confirm_step(SolverState& L, double rtt, bool bicg)
         L.restart = 1;
     }
     L.phase = PH_RESTART;
+}
+
+// COCG at a (re)start: rho = (r, r) of the new residual.
+__device__ inline void cocg_rho_step(SolverState& L, d2 rho)
+{
+    if (!cfinite(rho)) { finish(L, 4); return; }
+    if (rho.x == 0.0 && rho.y == 0.0) { finish(L, 2); return; }
+    L.rho = rho;
+    L.restart = 1;
 }
 
 // The scalar step of the method that finishes the pending reduction with
@@ -257,6 +274,100 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
             L.restart = 0;
         }
         if (L.iters >= L.maxit) finish(L, 1);
+        break;
+    }
+    case PK_SETUP_G1:
+    case PK_SETUP_G0:
+        if (k == PK_SETUP_G1) L.matvecs++;
+        if (!__builtin_isfinite(t0.x)) { finish(L, 4); break; }
+        L.rr = t0.x;
+        L.relres_rec = relres(t0.x, L.ny2);
+        if (t0.x <= L.thr2) { L.phase = PH_CONFIRM; break; }
+        cocg_rho_step(L, t1);
+        if (L.phase == PH_DONE) break;
+        if (L.maxit <= 0) { finish(L, 1); break; }
+        L.phase = PH_RESTART;
+        break;
+    case PK_CONFIRM_G:
+        confirm_step(L, t0.x, false);
+        if (L.phase == PH_RESTART) cocg_rho_step(L, t1);
+        break;
+    case PK_Q: {  // alpha = rho / (p, A p)
+        const d2 pq = t0;
+        L.matvecs++;
+        L.restart = 0;
+        if (!cfinite(pq)) { finish(L, 4); break; }
+        if (pq.x == 0.0 && pq.y == 0.0) { finish(L, 2); break; }
+        const d2 al = cdiv(L.rho, pq);
+        L.alpha = al;
+        if (hist) {
+            hist[L.iters].alpha_re = al.x;
+            hist[L.iters].alpha_im = al.y;
+        }
+        L.phase = PH_RUN;
+        break;
+    }
+    case PK_XR_G: {  // stop test, then beta = (r, r)' / (r, r)
+        const double rr = t0.x;
+        const d2 rho_new = t1;
+        L.iters++;
+        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
+        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
+        L.rr = rr;
+        L.relres_rec = relres(rr, L.ny2);
+        if (rr <= L.thr2) { L.phase = PH_CONFIRM; break; }
+        if (!cfinite(rho_new)) { finish(L, 4); break; }
+        if (rho_new.x == 0.0 && rho_new.y == 0.0) { finish(L, 2); break; }
+        const d2 beta = cdiv(rho_new, L.rho);
+        if (hist) {
+            hist[L.iters - 1].beta_re = beta.x;
+            hist[L.iters - 1].beta_im = beta.y;
+        }
+        L.beta = beta;
+        L.rho = rho_new;
+        if (L.iters >= L.maxit) finish(L, 1);
+        break;
+    }
+    case PK_U: {  // rho' = (r, A r); beta = rho'/rho unless a new direction
+        const d2 rho_new = t0;
+        L.matvecs++;
+        if (L.phase == PH_RESTART) L.restart = 1;
+        if (!cfinite(rho_new)) { finish(L, 4); break; }
+        if (rho_new.x == 0.0 && rho_new.y == 0.0) { finish(L, 2); break; }
+        if (!L.restart) {
+            const d2 beta = cdiv(rho_new, L.rho);
+            if (hist) {
+                hist[L.iters - 1].beta_re = beta.x;
+                hist[L.iters - 1].beta_im = beta.y;
+            }
+            L.beta = beta;
+        }
+        L.rho = rho_new;
+        if (L.iters >= L.maxit) { finish(L, 1); break; }
+        L.phase = PH_RUN;
+        break;
+    }
+    case PK_WW: {  // alpha = rho / (A p, A p)
+        const d2 ww = t0;
+        L.restart = 0;
+        if (!cfinite(ww)) { finish(L, 4); break; }
+        if (ww.x == 0.0 && ww.y == 0.0) { finish(L, 2); break; }
+        const d2 al = cdiv(L.rho, ww);
+        L.alpha = al;
+        if (hist) {
+            hist[L.iters].alpha_re = al.x;
+            hist[L.iters].alpha_im = al.y;
+        }
+        break;
+    }
+    case PK_XR_R: {
+        const double rr = t0.x;
+        L.iters++;
+        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
+        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
+        L.rr = rr;
+        L.relres_rec = relres(rr, L.ny2);
+        if (rr <= L.thr2) L.phase = PH_CONFIRM;
         break;
     }
     default:

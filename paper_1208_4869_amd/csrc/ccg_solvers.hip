@@ -135,31 +135,46 @@ __global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q)
     publish(a, q, L, PK_NORMY, gridDim.x);
 }
 
-// Set-up when the caller says x0 = 0: x = 0, r = y (and r^ = y).
-template <bool BICG>
+// Methods sharing the set-up kernels.
+enum Method { M_BICG = 0, M_CGNR = 1, M_COCG = 2, M_COCR = 3 };
+
+// Set-up when the caller says x0 = 0: x = 0, r = y (and r^ = y for BiCGSTAB;
+// COCG also needs the bilinear (r, r)).
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
 {
     SOLVER_PROLOGUE();
     const int ph = L.phase;
     if (ph != PH_RUN && ph != PH_ZERO) { publish(a, q, L, PK_NONE, 0); return; }
-    d2 v0 = d2{0.0, 0.0};
+    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         a.x[i] = d2{0.0, 0.0};
         if (ph == PH_RUN) {
             const d2 yi = a.y[i];
             a.r[i] = yi;
-            if (BICG) a.rh[i] = yi;
+            if (M == M_BICG) a.rh[i] = yi;
             v0.x += cabs2(yi);
+            if (M == M_COCG) v1 = cfma(yi, yi, v1);
         }
     }
     if (ph == PH_ZERO) { publish(a, q, L, PK_ZERO, 0); return; }
-    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
-    publish(a, q, L, BICG ? PK_SETUP_B0 : PK_SETUP_C0, gridDim.x);
+    write_partials(v0, v1, a.part[q ^ 1], lds);
+    publish(a, q, L, M == M_BICG ? PK_SETUP_B0 : M == M_COCG ? PK_SETUP_G0 : PK_SETUP_C0,
+            gridDim.x);
 }
 
 // ------------------------------------------------- A x kernels with roles
 
-enum Role { ROLE_SETUP_B, ROLE_SETUP_C, ROLE_V, ROLE_T, ROLE_W };
+enum Role {
+    ROLE_SETUP_B,  // BiCGSTAB set-up residual (also r^)
+    ROLE_SETUP_C,  // CGNR / COCR set-up residual
+    ROLE_SETUP_G,  // COCG set-up residual (+ (r, r))
+    ROLE_V,        // BiCGSTAB v = A p
+    ROLE_T,        // BiCGSTAB t = A s
+    ROLE_W,        // CGNR w = A p
+    ROLE_Q,        // COCG q = A p
+    ROLE_U         // COCR u = A r
+};
 
 template <Role RO>
 __device__ __forceinline__ int role_mode(int ph)
@@ -167,8 +182,11 @@ __device__ __forceinline__ int role_mode(int ph)
     switch (RO) {
     case ROLE_SETUP_B:
     case ROLE_SETUP_C:
+    case ROLE_SETUP_G:
         return (ph == PH_RUN || ph == PH_ZERO) ? ph : -1;
     case ROLE_V:
+    case ROLE_Q:
+    case ROLE_U:
         return (ph == PH_RUN || ph == PH_RESTART || ph == PH_CONFIRM) ? ph : -1;
     case ROLE_T:
         return ph == PH_RUN ? ph : -1;
@@ -187,7 +205,7 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     const int row0 = blockIdx.x * kR;
     const int n = a.n;
     const int t = threadIdx.x;
-    const bool setup = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C);
+    const bool setup = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || RO == ROLE_SETUP_G);
 
     if (mode == PH_ZERO) {  // y == 0: zero this block's rows of x
         if (t < kR && row0 + t < n) a.x[row0 + t] = d2{0.0, 0.0};
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     }
     // residual-type products read x; the others read a Krylov vector
     const bool resid = setup || mode == PH_CONFIRM;
-    const d2* in = resid ? a.x : (RO == ROLE_T ? a.s : a.p);
+    const d2* in = resid ? a.x : RO == ROLE_T ? a.s : RO == ROLE_U ? a.r : a.p;
 
     __shared__ d2 red[kWN][kR];
     d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
@@ -211,6 +229,13 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
             a.r[i] = ri;
             if (RO == ROLE_SETUP_B || RO == ROLE_V) a.rh[i] = ri;
             pv0.x = cabs2(ri);
+            if (RO == ROLE_SETUP_G || RO == ROLE_Q) pv1 = cfma(ri, ri, pv1);
+        } else if (RO == ROLE_Q) {
+            a.v[i] = val;  // q
+            pv0 = cfma(a.p[i], val, pv0);
+        } else if (RO == ROLE_U) {
+            a.z[i] = val;  // u
+            pv0 = cfma(a.r[i], val, pv0);
         } else if (RO == ROLE_V) {
             a.v[i] = val;
             pv0 = cfma_conj(a.rh[i], val, pv0);
@@ -228,8 +253,12 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     int kind;
     if (RO == ROLE_SETUP_B) kind = PK_SETUP_B1;
     else if (RO == ROLE_SETUP_C) kind = PK_SETUP_C1;
-    else if (mode == PH_CONFIRM) kind = RO == ROLE_V ? PK_CONFIRM_B : PK_CONFIRM_C;
-    else kind = RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : PK_W;
+    else if (RO == ROLE_SETUP_G) kind = PK_SETUP_G1;
+    else if (mode == PH_CONFIRM)
+        kind = RO == ROLE_V ? PK_CONFIRM_B : RO == ROLE_Q ? PK_CONFIRM_G : PK_CONFIRM_C;
+    else
+        kind = RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : RO == ROLE_W ? PK_W
+             : RO == ROLE_Q ? PK_Q : PK_U;
     publish(a, q, L, kind, gridDim.x);
 }
 
@@ -373,6 +402,89 @@ __global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a, int q)
     publish(a, q, L, PK_NONE, 0);
 }
 
+// ------------------------------------------------------ COCG / COCR vectors
+// (section 3.4: complex symmetric A; the bilinear form (a, b) = sum a_i b_i)
+
+// COCG: p = r (new direction) or p = r + beta p
+__global__ __launch_bounds__(kBlock) void k_cocg_p(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    if (L.phase == PH_RUN || L.phase == PH_RESTART) {
+        const bool fresh = L.restart != 0;
+        const d2 beta = L.beta;
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+            const d2 ri = a.r[i];
+            a.p[i] = fresh ? ri : cfma(beta, a.p[i], ri);
+        }
+    }
+    publish(a, q, L, PK_NONE, 0);
+}
+
+// COCG: x += alpha p, r -= alpha q, ||r||^2, (r, r)
+__global__ __launch_bounds__(kBlock) void k_cocg_xr(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    const d2 alpha = L.alpha;
+    const d2 nal = d2{-alpha.x, -alpha.y};
+    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+        a.x[i] = cfma(alpha, a.p[i], a.x[i]);
+        const d2 ri = cfma(nal, a.v[i], a.r[i]);
+        a.r[i] = ri;
+        v0.x += cabs2(ri);
+        v1 = cfma(ri, ri, v1);
+    }
+    write_partials(v0, v1, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_XR_G, gridDim.x);
+}
+
+// COCR: p = r + beta p, w = u + beta w (p = r, w = u for a new direction),
+// (w, w)
+__global__ __launch_bounds__(kBlock) void k_cocr_pw(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    const bool fresh = L.restart != 0;
+    const d2 beta = L.beta;
+    d2 v0 = d2{0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+        const d2 ri = a.r[i];
+        const d2 ui = a.z[i];
+        d2 pi, wi;
+        if (fresh) {
+            pi = ri;
+            wi = ui;
+        } else {
+            pi = cfma(beta, a.p[i], ri);
+            wi = cfma(beta, a.w[i], ui);
+        }
+        a.p[i] = pi;
+        a.w[i] = wi;
+        v0 = cfma(wi, wi, v0);
+    }
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_WW, gridDim.x);
+}
+
+// COCR: x += alpha p, r -= alpha w, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_cocr_xr(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    const d2 alpha = L.alpha;
+    const d2 nal = d2{-alpha.x, -alpha.y};
+    d2 v0 = d2{0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
+        a.x[i] = cfma(alpha, a.p[i], a.x[i]);
+        const d2 ri = cfma(nal, a.w[i], a.r[i]);
+        a.r[i] = ri;
+        v0.x += cabs2(ri);
+    }
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_XR_R, gridDim.x);
+}
+
 // --------------------------------------------------------- plain products
 
 __global__ __launch_bounds__(kBlockN) void k_gemv_n_plain(const d2* __restrict__ A, int64_t lda,
@@ -439,7 +551,8 @@ static Layout layout(int method, int64_t n)
     L.partials = off;  // two buffers of pb partial pairs
     L.part_bytes = align256((size_t)pb * 2 * sizeof(d2));
     off += 2 * L.part_bytes;
-    L.nvec = method == CCG_WS_BICGSTAB ? 6 : method == CCG_WS_CGNR ? 4 : 0;
+    L.nvec = method == CCG_WS_BICGSTAB ? 6 : method == CCG_WS_CGNR ? 4
+           : method == CCG_WS_COCG ? 3 : method == CCG_WS_COCR ? 4 : 0;
     L.vec = off;
     off += (size_t)L.nvec * vbytes;
     L.zpart = off;
@@ -485,9 +598,11 @@ static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const 
     for (int k = 0; k < L.nvec; ++k) vec[k] = (d2*)(base + L.vec + k * vbytes);
     if (method == CCG_WS_BICGSTAB) {
         a.r = vec[0]; a.rh = vec[1]; a.p = vec[2]; a.v = vec[3]; a.s = vec[4]; a.t = vec[5];
-    } else {
+    } else if (method == CCG_WS_COCG) {
+        a.r = vec[0]; a.p = vec[1]; a.v = vec[2];  // v holds q = A p
+    } else {  // CGNR, COCR (z holds u = A r for COCR)
         a.r = vec[0]; a.z = vec[1]; a.p = vec[2]; a.w = vec[3];
-        a.zpart = (d2*)(base + L.zpart);
+        if (method == CCG_WS_CGNR) a.zpart = (d2*)(base + L.zpart);
     }
     a.part[0] = (d2*)(base + L.partials);
     a.part[1] = (d2*)(base + L.partials + L.part_bytes);
@@ -507,10 +622,16 @@ static void read_result(const SolverState& s, ccg_result* res)
     res->relres_true = s.relres_true;
 }
 
+static int ws_of(int M)
+{
+    return M == M_BICG ? CCG_WS_BICGSTAB : M == M_CGNR ? CCG_WS_CGNR
+         : M == M_COCG ? CCG_WS_COCG : CCG_WS_COCR;
+}
+
 // Enqueue set-up, then slots until the status ring reports PH_DONE.  Every
 // solver kernel reads state copy q and writes copy q ^ 1; the host tracks q
 // across the launches it makes.
-template <bool BICG>
+template <int M>
 static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                       ccg_result* res, hipStream_t s)
 {
@@ -521,17 +642,18 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     const int gE = blocks_e(a.n);
     const int gC = a.csh.blocks();
     int q = 0;
+    auto flip = [&q]() { const int cur = q; q ^= 1; return cur; };
 
     k_init<<<1, 64, 0, s>>>(a.st[0], maxit, tol2);
-    k_norm_y<<<gE, kBlock, 0, s>>>(a, q);
-    q ^= 1;
+    k_norm_y<<<gE, kBlock, 0, s>>>(a, flip());
     if (flags & CCG_X0_ZERO)
-        k_setup_x0zero<BICG><<<gE, kBlock, 0, s>>>(a, q);
-    else if (BICG)
-        k_gemv_n_role<ROLE_SETUP_B><<<gN, kBlockN, 0, s>>>(a, q);
+        k_setup_x0zero<M == M_COCR ? M_CGNR : M><<<gE, kBlock, 0, s>>>(a, flip());
+    else if (M == M_BICG)
+        k_gemv_n_role<ROLE_SETUP_B><<<gN, kBlockN, 0, s>>>(a, flip());
+    else if (M == M_COCG)
+        k_gemv_n_role<ROLE_SETUP_G><<<gN, kBlockN, 0, s>>>(a, flip());
     else
-        k_gemv_n_role<ROLE_SETUP_C><<<gN, kBlockN, 0, s>>>(a, q);
-    q ^= 1;
+        k_gemv_n_role<ROLE_SETUP_C><<<gN, kBlockN, 0, s>>>(a, flip());
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
 
     // Each slot advances the method by at most one iteration or one
@@ -541,23 +663,28 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     const int ahead = lookahead(a.n);
     for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
-            if (BICG) {
-                k_bicg_p<<<gE, kBlock, 0, s>>>(a, q);
-                k_gemv_n_role<ROLE_V><<<gN, kBlockN, 0, s>>>(a, q ^ 1);
-                k_bicg_s<<<gE, kBlock, 0, s>>>(a, q);
-                k_gemv_n_role<ROLE_T><<<gN, kBlockN, 0, s>>>(a, q ^ 1);
-                k_bicg_xr<<<gE, kBlock, 0, s>>>(a, q);
+            if (M == M_BICG) {
+                k_bicg_p<<<gE, kBlock, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_V><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_bicg_s<<<gE, kBlock, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_T><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_bicg_xr<<<gE, kBlock, 0, s>>>(a, flip());
+            } else if (M == M_CGNR) {
+                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
+                k_cgnr_z1<<<gC, kBlock, 0, s>>>(a, flip());
+                k_cgnr_z2<<<gE, kBlock, 0, s>>>(a, flip());
+                k_cgnr_p<<<gE, kBlock, 0, s>>>(a, flip());
+            } else if (M == M_COCG) {
+                k_cocg_p<<<gE, kBlock, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_Q><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_cocg_xr<<<gE, kBlock, 0, s>>>(a, flip());
             } else {
-                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, q);
-                k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, q ^ 1);
-                k_cgnr_z1<<<gC, kBlock, 0, s>>>(a, q);
-                k_cgnr_z2<<<gE, kBlock, 0, s>>>(a, q ^ 1);
-                k_cgnr_p<<<gE, kBlock, 0, s>>>(a, q);
+                k_gemv_n_role<ROLE_U><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_cocr_pw<<<gE, kBlock, 0, s>>>(a, flip());
+                k_cocr_xr<<<gE, kBlock, 0, s>>>(a, flip());
             }
-            // five launches flipped the copy five times
-            q ^= 1;
-            k_status<<<1, kBlock, 0, s>>>(a, q, sc->ring_d + slot % kRing);
-            q ^= 1;
+            k_status<<<1, kBlock, 0, s>>>(a, flip(), sc->ring_d + slot % kRing);
             if ((e = hipGetLastError()) != hipSuccess) return (int)e;
             if ((e = hipEventRecord(sc->ev[slot % kRing], s)) != hipSuccess) return (int)e;
         }
@@ -576,7 +703,7 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     return 0;
 }
 
-template <bool BICG>
+template <int M>
 static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
                     double tol, int32_t maxit, uint32_t flags, void* work, size_t work_bytes,
                     ccg_result* res, ccg_hist* hist, void* stream)
@@ -584,7 +711,7 @@ static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_
     int bad = check_common(n, A, lda, y, x, tol, maxit);
     if (bad) return bad;
     if (flags & ~CCG_X0_ZERO) return -8;
-    const int method = BICG ? CCG_WS_BICGSTAB : CCG_WS_CGNR;
+    const int method = ws_of(M);
     if (n > 0 && !work) return -9;
     if (n > 0 && ((uintptr_t)work & 255)) return -9;
     if (n > 0 && work_bytes < layout(method, n).total) return -10;
@@ -595,10 +722,10 @@ static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_
         return 0;
     }
     const Args a = make_args(method, n, A, lda, y, x, work, hist);
-    return run_solver<BICG>(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
+    return run_solver<M>(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
 }
 
-template <bool BICG>
+template <int M>
 static int solve_short(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
                        double tol, int32_t maxit, int32_t* info, void* stream)
 {
@@ -611,11 +738,11 @@ static int solve_short(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, c
         return 0;
     }
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = layout(BICG ? CCG_WS_BICGSTAB : CCG_WS_CGNR, n).total;
+    const size_t bytes = layout(ws_of(M), n).total;
     void* work = nullptr;
     hipError_t e = hipMallocAsync(&work, bytes, s);
     if (e != hipSuccess) return (int)e;
-    int rc = solve_ex<BICG>(n, A, lda, y, x, tol, maxit, 0u, work, bytes, &res, nullptr, stream);
+    int rc = solve_ex<M>(n, A, lda, y, x, tol, maxit, 0u, work, bytes, &res, nullptr, stream);
     e = hipFreeAsync(work, s);
     if (rc == 0 && e == hipSuccess) e = hipStreamSynchronize(s);
     if (rc != 0) return rc;
@@ -681,7 +808,8 @@ size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
         const ccg::GemvCShape sh = ccg::gemv_c_shape(n > 0 ? n : 1);
         return (size_t)sh.nbands * (size_t)(n > 0 ? n : 1) * sizeof(ccg_z);
     }
-    if (method == CCG_WS_BICGSTAB || method == CCG_WS_CGNR)
+    if (method == CCG_WS_BICGSTAB || method == CCG_WS_CGNR || method == CCG_WS_COCG ||
+        method == CCG_WS_COCR)
         return ccg::layout(method, n).total;
     return 0;
 }
@@ -701,20 +829,20 @@ int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x
 int ccg_bicgstab(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
                  int32_t maxit, int32_t* info, void* stream)
 {
-    return ccg::solve_short<true>(n, A, lda, y, x, tol, maxit, info, stream);
+    return ccg::solve_short<ccg::M_BICG>(n, A, lda, y, x, tol, maxit, info, stream);
 }
 
 int ccg_cgnr(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
              int32_t maxit, int32_t* info, void* stream)
 {
-    return ccg::solve_short<false>(n, A, lda, y, x, tol, maxit, info, stream);
+    return ccg::solve_short<ccg::M_CGNR>(n, A, lda, y, x, tol, maxit, info, stream);
 }
 
 int ccg_bicgstab_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
                     double tol, int32_t maxit, uint32_t flags, void* work, size_t work_bytes,
                     ccg_result* res, ccg_hist* hist, void* stream)
 {
-    return ccg::solve_ex<true>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes, res, hist,
+    return ccg::solve_ex<ccg::M_BICG>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes, res, hist,
                                stream);
 }
 
@@ -722,8 +850,36 @@ int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x
                 int32_t maxit, uint32_t flags, void* work, size_t work_bytes, ccg_result* res,
                 ccg_hist* hist, void* stream)
 {
-    return ccg::solve_ex<false>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes, res,
+    return ccg::solve_ex<ccg::M_CGNR>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes, res,
                                 hist, stream);
+}
+
+int ccg_cocg(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
+             int32_t maxit, int32_t* info, void* stream)
+{
+    return ccg::solve_short<ccg::M_COCG>(n, A, lda, y, x, tol, maxit, info, stream);
+}
+
+int ccg_cocr(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
+             int32_t maxit, int32_t* info, void* stream)
+{
+    return ccg::solve_short<ccg::M_COCR>(n, A, lda, y, x, tol, maxit, info, stream);
+}
+
+int ccg_cocg_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
+                int32_t maxit, uint32_t flags, void* work, size_t work_bytes, ccg_result* res,
+                ccg_hist* hist, void* stream)
+{
+    return ccg::solve_ex<ccg::M_COCG>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes,
+                                      res, hist, stream);
+}
+
+int ccg_cocr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,
+                int32_t maxit, uint32_t flags, void* work, size_t work_bytes, ccg_result* res,
+                ccg_hist* hist, void* stream)
+{
+    return ccg::solve_ex<ccg::M_COCR>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes,
+                                      res, hist, stream);
 }
 
 }  // extern "C"

@@ -16,7 +16,12 @@ Sources of truth used here:
     run on A^H A x = A^H y; BiCGSTAB's alpha equals CG's when A is Hermitian
     positive definite and the shadow residual is r0; omega minimises ||s - w t||
     so ||r|| <= ||s||; CGNR's residual norm never grows;
-  * a third-party solver (SciPy's bicgstab).
+  * a third-party solver (SciPy's bicgstab);
+  * for COCG / COCR (complex symmetric A): on real SPD systems the bilinear
+    form is the inner product, so COCG is CG and COCR is CR, whose residual is
+    the minimum over the Krylov space (checked against a brute-force least
+    squares); finite termination on Q D Q^T with Q real orthogonal; exact
+    bilinear-form breakdowns.
 """
 from __future__ import annotations
 
@@ -525,6 +530,185 @@ def pin_restart(orc):
         r = _solve(orc, m, A, y, tol=1e-18, maxit=120)
         assert r.info == 1 and r.confirms >= 2, (m, r.info, r.confirms)
         assert r.relres_true <= 1e-14
+
+
+# ------------------------------------------- complex symmetric: COCG / COCR
+
+CS = ("cocg", "cocr")
+
+
+def real_spd(n, eigs, seed):
+    rng = np.random.default_rng(seed)
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Qm * np.asarray(eigs, dtype=np.float64)) @ Qm.T
+    return np.ascontiguousarray(0.5 * (A + A.T)).astype(np.complex128)
+
+
+def complex_symmetric_with_spectrum(n, eigs, seed):
+    """Q diag(eigs) Q^T with Q real orthogonal: complex symmetric, spectrum
+    eigs (the bilinear form is preserved by Q, so COCG / COCR see a diagonal
+    system)."""
+    rng = np.random.default_rng(seed)
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Qm * np.asarray(eigs)) @ Qm.T
+    return np.ascontiguousarray(0.5 * (A + A.T))
+
+
+def pin_cocg_is_cg_on_real_spd(orc):
+    """Real symmetric positive definite A and real y: the bilinear form is the
+    inner product, so COCG's alpha_k and beta_k are CG's."""
+    A = real_spd(40, np.linspace(1.0, 9.0, 40), 31)
+    y = np.random.default_rng(32).standard_normal(40).astype(np.complex128)
+    r1 = orc.cocg(A, y, tol=1e-12)
+    r2 = orc.cg(A, y, tol=1e-12)
+    k = min(r1.iters, r2.iters, 8)
+    assert k >= 6
+    assert np.allclose(r1.hist[:k, 0], r2.hist[:k, 0], rtol=1e-9, atol=0)
+    assert np.all(np.abs(r1.hist[:k, 1]) <= 1e-12 * np.abs(r1.hist[:k, 0]))
+    assert np.allclose(r1.hist[:k - 1, 4], r2.hist[:k - 1, 4], rtol=1e-8, atol=0)
+
+
+def krylov_min_residual(A, y, k):
+    """min ||y - A x|| over x in K_k(A, y), by least squares on an
+    orthonormal Krylov basis (brute force, for small k)."""
+    n = A.shape[0]
+    K = np.empty((n, k), dtype=np.complex128)
+    v = y / np.linalg.norm(y)
+    for j in range(k):
+        K[:, j] = v
+        v = A @ v
+        v = v / np.linalg.norm(v)
+    Qk, _ = np.linalg.qr(K)
+    AQ = A @ Qk
+    c, *_ = np.linalg.lstsq(AQ, y, rcond=None)
+    return np.linalg.norm(y - AQ @ c)
+
+
+def pin_cocr_is_minimal_residual_on_real_spd(orc):
+    """Real SPD A, real y: COCR is CR, which minimises ||y - A x|| over the
+    Krylov space K_k(A, y) -- the same residual norms as a brute-force least
+    squares over that space."""
+    A = real_spd(30, np.linspace(1.0, 6.0, 30), 41)
+    y = np.random.default_rng(42).standard_normal(30).astype(np.complex128)
+    r = orc.cocr(A, y, tol=1e-13)
+    ny = np.linalg.norm(y)
+    for k in range(1, 6):
+        want = krylov_min_residual(A, y, k) / ny
+        assert abs(r.hist[k - 1, 7] - want) <= 1e-7 * want, (k, r.hist[k - 1, 7], want)
+
+
+def pin_cs_finite_termination(orc):
+    """Complex symmetric A with 5 distinct eigenvalues: both methods reach
+    1e-12 in at most 5 iterations (one of slack)."""
+    eigs = np.repeat([2 + 1j, 3 - 0.5j, 4 + 2j, 6 + 0.2j, 7 - 1j], [10, 10, 10, 10, 8])
+    A = complex_symmetric_with_spectrum(48, eigs, 43)
+    y = inputs.cn01(np.random.default_rng(44), 48)
+    for m in CS:
+        r = getattr(orc, m)(A, y, tol=1e-12)
+        assert r.info == 0 and r.iters <= 6, (m, r.info, r.iters)
+        assert r.relres_true <= 1e-12
+
+
+def pin_cs_lu(orc):
+    """Complex symmetric systems against a dense LU solve: lattice matrices
+    and a random diagonally shifted G + G^T."""
+    rng = np.random.default_rng(45)
+    G = inputs.cn01(rng, (40, 40))
+    S = (G + G.T) / np.sqrt(80) + (5 + 1j) * np.eye(40)
+    for A in (inputs.lattice_matrix(4), inputs.lattice_matrix(5), S):
+        y = inputs.cn01(rng, A.shape[0])
+        x_lu = lu_solve(A, y)
+        kappa = np.linalg.cond(A)
+        for m in CS:
+            r = getattr(orc, m)(np.ascontiguousarray(A), y)
+            assert r.info == 0 and r.relres_true <= 1e-10, m
+            assert relerr(r.x, x_lu) <= 10 * kappa * 1e-10, m
+
+
+def pin_cs_closed_forms(orc):
+    """A = c I: one iteration, x = y / c.  y = (1, i) with A = I: (r, r) = 0
+    and (r, A r) = 0 -- the bilinear form breaks down at once (info 2)."""
+    c = 1.5 + 2.5j
+    A = c * np.eye(9, dtype=np.complex128)
+    y = inputs.cn01(np.random.default_rng(46), 9)
+    for m in CS:
+        r = getattr(orc, m)(A, y)
+        assert r.info == 0 and r.iters == 1
+        assert relerr(r.x, y / c) <= 16 * U
+    I2 = np.eye(2, dtype=np.complex128)
+    y = np.array([1.0, 1.0j])
+    for m in CS:
+        r = getattr(orc, m)(I2, y)
+        assert r.info == 2 and r.iters == 0 and np.all(r.x == 0), m
+
+
+def pin_cs_exact_first_iterations(orc):
+    """First two iterations of both methods in exact Gaussian-rational
+    arithmetic on a 3 x 3 complex symmetric integer system."""
+    Ai = np.array([[6 + 1j, 1 - 2j, 2 + 0j],
+                   [1 - 2j, 5 + 2j, -1 + 1j],
+                   [2 + 0j, -1 + 1j, 7 - 1j]])
+    yi = np.array([2 - 1j, 1 + 3j, -1 + 1j])
+    A = [[Q.of(Ai[i, j]) for j in range(3)] for i in range(3)]
+    y = [Q.of(v) for v in yi]
+
+    def dotu_q(a, b):
+        return sum((u * v for u, v in zip(a, b)), Q(0))
+
+    # COCG
+    r = list(y)
+    p = list(r)
+    rho = dotu_q(r, r)
+    want = []
+    for _ in range(2):
+        q = qmatvec(A, p)
+        alpha = rho / dotu_q(p, q)
+        r = [r[i] - alpha * q[i] for i in range(3)]
+        rho_new = dotu_q(r, r)
+        beta = rho_new / rho
+        p = [r[i] + beta * p[i] for i in range(3)]
+        rho = rho_new
+        want.append((alpha.c(), beta.c()))
+    res = orc.cocg(Ai.astype(np.complex128), yi.astype(np.complex128), tol=1e-14, maxit=2)
+    for k, (a, b) in enumerate(want):
+        assert abs(res.hist[k, 0] + 1j * res.hist[k, 1] - a) <= 1e-13 * abs(a)
+        if k == 0:
+            assert abs(res.hist[k, 4] + 1j * res.hist[k, 5] - b) <= 1e-13 * abs(b)
+    # COCR
+    r = list(y)
+    u = qmatvec(A, r)
+    p, w = list(r), list(u)
+    rho = dotu_q(r, u)
+    want = []
+    for _ in range(2):
+        alpha = rho / dotu_q(w, w)
+        r = [r[i] - alpha * w[i] for i in range(3)]
+        u = qmatvec(A, r)
+        rho_new = dotu_q(r, u)
+        beta = rho_new / rho
+        p = [r[i] + beta * p[i] for i in range(3)]
+        w = [u[i] + beta * w[i] for i in range(3)]
+        rho = rho_new
+        want.append((alpha.c(), beta.c()))
+    res = orc.cocr(Ai.astype(np.complex128), yi.astype(np.complex128), tol=1e-14, maxit=2)
+    for k, (a, b) in enumerate(want):
+        assert abs(res.hist[k, 0] + 1j * res.hist[k, 1] - a) <= 1e-13 * abs(a)
+        if k == 0:
+            assert abs(res.hist[k, 4] + 1j * res.hist[k, 5] - b) <= 1e-13 * abs(b)
+
+
+def pin_cs_failures(orc):
+    """Non-finite input, iteration budget, zero right-hand side."""
+    A = inputs.lattice_matrix(3)
+    y = inputs.cn01(np.random.default_rng(47), 27)
+    for m in CS:
+        ybad = y.copy()
+        ybad[3] = np.inf
+        assert getattr(orc, m)(A, ybad).info == 4
+        r = getattr(orc, m)(A, y, maxit=1)
+        assert r.info == 1 and r.iters == 1
+        r = getattr(orc, m)(A, np.zeros(27, dtype=np.complex128), x0=y)
+        assert r.info == 0 and np.all(r.x == 0) and r.matvecs == 0
 
 
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

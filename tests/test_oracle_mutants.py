@@ -35,7 +35,7 @@ MUTANTS = [
     ("dot_unconjugated",
      "s += conj(a[i]) * b[i];", "s += a[i] * b[i];", 1),
     ("stop_test_not_squared",
-     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 3),
+     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 5),
     ("residual_sign",
      "rt[i] = y[i] - rt[i];", "rt[i] = y[i] + rt[i];", 1),
     ("division_without_conj",
@@ -62,7 +62,25 @@ MUTANTS = [
      "x[i] = x[i] + alpha * p[i];\n            k++;",
      "(void)p;\n            k++;", 1),
     ("cgnr_r_update_sign",
-     "r[i] = r[i] - alpha * w[i];", "r[i] = r[i] + alpha * w[i];", 1),
+     "r[i] = r[i] - alpha * w[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = alpha;",
+     "r[i] = r[i] + alpha * w[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = alpha;",
+     1),
+    ("cocg_pq_conjugated",
+     "zc pq = dotu(n, p, q);", "zc pq = dotc(n, p, q);", 1),
+    ("cocg_alpha_conj",
+     "zc alpha = zdiv(rho, pq);", "zc alpha = zdiv(rho, conj(pq));", 1),
+    ("cocr_ww_conjugated",
+     "zc ww = dotu(n, w, w);", "zc ww = dotc(n, w, w);", 1),
+    ("cocr_w_update_drops_beta",
+     "w[i] = u[i] + beta * w[i];", "w[i] = u[i];", 1),
+    ("cocr_alpha_inverted",
+     "zc alpha = zdiv(rho, ww);", "zc alpha = zdiv(ww, rho);", 1),
+    ("bilinear_form_conjugated",
+     "s += a[i] * b[i];", "s += conj(a[i]) * b[i];", 1),
+    ("cocr_r_update_wrong_vector",
+     "r[i] = r[i] - alpha * w[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
+     "r[i] = r[i] - alpha * u[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
+     1),
 ]
 
 
