@@ -72,6 +72,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="bound on the oracle's timed sample")
+    p.add_argument("--no-mixed", action="store_true",
+                   help="skip the 26^3 mixed-precision leg")
     p.add_argument("--no-block", action="store_true",
                    help="skip the 64 right-hand-side block leg")
     p.add_argument("--profile-kernels", action="store_true",
@@ -141,6 +143,64 @@ def cpu_baseline(A, y, budget_s):
                       "system (n=8000) by the single-threaded C oracle, %.1f s"
                       % (k, el),
             "iters": res.iters, "relres_true": res.relres_true}
+
+
+def mixed_leg(steps):
+    """The 26^3 lattice (n = 17576, 4.94 GB complex128 + 2.47 GB complex64
+    copy): plain FP64 BiCGSTAB against FP64 refinement around complex64
+    BiCGSTAB (inner tolerance 1e-5), both to 1e-10 on the FP64 true residual.
+    The matrix is gathered on the device from the host displacement table
+    (bitwise the host matrix); y = A x_true (x_true seed 2) by ccg_matvec."""
+    import torch
+
+    from paper_1208_4869_amd import ccg, inputs
+    m = 26
+    t0 = time.time()
+    A = inputs.lattice_matrix_torch(m, "cuda")
+    n = A.shape[0]
+    xt = torch.from_numpy(inputs.cn01(np.random.default_rng(2), n)).cuda()
+    y = ccg.ccg_matvec(ccg.OP_N, A, xt)
+    A32 = ccg.ccg_round_c64(A)
+    torch.cuda.synchronize()
+    log("built the 26^3 system on the device in %.1fs" % (time.time() - t0))
+    x64 = torch.empty_like(y)
+    w64 = ccg.workspace(ccg.WS_BICGSTAB, n)
+    t64, lat64, r64 = time_solves(ccg.ccg_bicgstab_ex, A, y, x64, w64, steps, 1)
+    xm = torch.empty_like(y)
+    wm = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_MIXED, n), dtype=torch.uint8,
+                     device="cuda")
+    rm = ccg.ccg_bicgstab_mixed_ex(A, A32, y, xm, TOL, 10, 1e-5, MAXIT, flags=1, work=wm)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(steps):
+        rm = ccg.ccg_bicgstab_mixed_ex(A, A32, y, xm, TOL, 10, 1e-5, MAXIT, flags=1, work=wm)
+    torch.cuda.synchronize()
+    tm = (time.perf_counter() - ts) / steps
+    # complex64 product (the inner kernel) timed with HIP events
+    x32 = xt.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    tc = time_kernel(lambda: ccg.ccg_matvec_c64(A32, x32, y32), 20)
+    tz = time_kernel(lambda: ccg.ccg_matvec(ccg.OP_N, A, xt, y), 20)
+    diff = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
+    fe_m = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
+    fe_64 = float(torch.linalg.norm(x64 - xt) / torch.linalg.norm(xt))
+    log("26^3: FP64 %.2f ms, mixed %.2f ms (%d outer, %d inner its)" % (
+        t64 / steps * 1e3, tm * 1e3, rm.outer, rm.inner_iters))
+    out = {"workload": "dipole-lattice 26^3, n=17576",
+           "fp64": {"solves_per_s": steps / t64, "ms": t64 / steps * 1e3,
+                    "iters": r64.iters, "matvecs": r64.matvecs,
+                    "relres_true": r64.relres_true, "fwd_err": fe_64},
+           "mixed": {"solves_per_s": 1.0 / tm, "ms": tm * 1e3, "outer": rm.outer,
+                     "inner_iters": rm.inner_iters, "matvecs64": rm.matvecs64,
+                     "matvecs32": rm.matvecs32, "relres_true": rm.relres_true,
+                     "fwd_err": fe_m, "rel_diff_vs_fp64_solution": diff,
+                     "tol_inner": 1e-5},
+           "speedup": (t64 / steps) / tm,
+           "matvec_c128_us": tz * 1e6, "matvec_c128_gbs": 16.0 * n * n / tz / 1e9,
+           "matvec_c64_us": tc * 1e6, "matvec_c64_gbs": 8.0 * n * n / tc / 1e9}
+    del A, A32
+    torch.cuda.empty_cache()
+    return out
 
 
 def block_leg(A, A_h, steps):
@@ -322,6 +382,8 @@ def main():
         "cocg": cs["cocg"],
         "cocr": cs["cocr"],
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(max(args.steps // 3, 3))
     if not args.no_block:
         out["block"] = block_leg(A, A_h, max(args.steps // 3, 2))
     if not args.no_cpu_baseline:

@@ -54,6 +54,10 @@ typedef struct {
     double re, im;
 } ccg_z;
 
+typedef struct {
+    float re, im;
+} ccg_c; /* complex64, real part first (8 bytes); torch.complex64 */
+
 /* Outcome of a solve (host struct). */
 typedef struct {
     int32_t info;       /* status, codes above */
@@ -87,8 +91,20 @@ enum {
     CCG_WS_MATMAT = 4,         /* scratch of ccg_matmat_ex (nrhs = k) */
     CCG_WS_BICGSTAB_BLOCK = 5, /* ccg_bicgstab_block_ex (nrhs = k <= 64) */
     CCG_WS_COCG = 6,
-    CCG_WS_COCR = 7
+    CCG_WS_COCR = 7,
+    CCG_WS_BICGSTAB_MIXED = 8
 };
+
+/* Outcome of a mixed-precision solve (host struct). */
+typedef struct {
+    int32_t info;        /* status, codes above (from the FP64 outer loop) */
+    int32_t outer;       /* refinement steps (inner solves) */
+    int32_t inner_iters; /* inner BiCGSTAB iterations, all steps */
+    int32_t matvecs64;   /* complex128 products (outer residuals) */
+    int32_t matvecs32;   /* complex64 products (inner solves) */
+    int32_t pad;
+    double relres_true;  /* last FP64 ||y - A x|| / ||y|| */
+} ccg_mixed_result;
 
 /* Flags of the _ex solvers. */
 #define CCG_X0_ZERO 1u /* x holds no guess: start from x = 0, skip y - A x */
@@ -176,6 +192,44 @@ int ccg_cocr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
                 ccg_z* x, double tol, int32_t maxit, uint32_t flags,
                 void* work, size_t work_bytes, ccg_result* res, ccg_hist* hist,
                 void* stream);
+
+/*
+ * Mixed precision BiCGSTAB (the single/double switch of the ddprecision
+ * module, Usage section, used inside one solve): FP64 iterative refinement
+ * around an inner complex64 BiCGSTAB.  Each outer step takes the residual
+ * r = y - A x with the complex128 A in FP64, solves A32 d = r / ||r|| with
+ * complex64 vectors and products (FP32 accumulation; the dot products and the
+ * alpha / omega / beta / rho scalars stay FP64) to the relative tolerance
+ * tol_inner, stopping on its recursive residual, and applies x += ||r|| d in
+ * FP64.  The outer loop stops when the FP64 true residual meets tol (info 0)
+ * or after maxit steps (info 1); an inner breakdown or budget only ends that
+ * inner solve.  A32 is the complex64 copy of A (ccg_round_c64), lda32 >= n.
+ * Arguments: 1 n, 2 A, 3 lda, 4 A32, 5 lda32, 6 y, 7 x, 8 tol, 9 maxit
+ * (outer steps), 10 tol_inner (0 < tol_inner < 1), 11 maxit_inner >= 1,
+ * 12 flags (CCG_X0_ZERO or 0), 13 work, 14 work_bytes (>=
+ * ccg_workspace_bytes(CCG_WS_BICGSTAB_MIXED, n, 1)), 15 res (host), 16 stream.
+ * Waits on stream.
+ */
+int ccg_bicgstab_mixed_ex(int64_t n, const ccg_z* A, int64_t lda,
+                          const ccg_c* A32, int64_t lda32, const ccg_z* y,
+                          ccg_z* x, double tol, int32_t maxit, double tol_inner,
+                          int32_t maxit_inner, uint32_t flags, void* work,
+                          size_t work_bytes, ccg_mixed_result* res,
+                          void* stream);
+
+/* y = A x in complex64, the inner product of the mixed-precision solver: each
+ * lane accumulates in FP32 with fused multiply-adds, lanes and wavefronts are
+ * added in FP64 and the total rounded to complex64.  Same layout and
+ * asynchrony as ccg_matvec.  Arguments: 1 n, 2 A (complex64), 3 lda, 4 x,
+ * 5 y, 6 stream. */
+int ccg_matvec_c64(int64_t n, const ccg_c* A, int64_t lda, const ccg_c* x,
+                   ccg_c* y, void* stream);
+
+/* dst = complex64(src) for a rows x cols row-major block (round to nearest).
+ * Arguments: 1 rows, 2 cols, 3 src, 4 lds >= cols, 5 dst, 6 ldd >= cols,
+ * 7 stream.  Asynchronous. */
+int ccg_round_c64(int64_t rows, int64_t cols, const ccg_z* src, int64_t lds,
+                  ccg_c* dst, int64_t ldd, void* stream);
 
 /*
  * Z = A B for k right-hand sides at once: B and Z are n x k, row-major

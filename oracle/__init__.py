@@ -51,6 +51,25 @@ class _Stats(ctypes.Structure):
                 ("relres_true", ctypes.c_double)]
 
 
+class _MixedStats(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("matvecs64", ctypes.c_int32),
+                ("matvecs32", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("relres_true", ctypes.c_double)]
+
+
+@dataclass
+class MixedResult:
+    x: np.ndarray
+    info: int
+    outer: int
+    inner_iters: int
+    matvecs64: int
+    matvecs32: int
+    relres_true: float
+    outer_res: np.ndarray  # ||r|| / ||y|| at each outer check
+
+
 HIST_FIELDS = ("alpha_re", "alpha_im", "omega_re", "omega_im", "beta_re",
                "beta_im", "res_half", "res_full")
 
@@ -89,6 +108,13 @@ class Oracle:
         self.lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
+        self.lib.oracle_matvec_c64.argtypes = [I64, P, I64, P, P]
+        self.lib.oracle_matvec_c64.restype = None
+        self.lib.oracle_bicgstab_mixed.argtypes = [
+            I64, P, I64, P, I64, P, P, ctypes.c_double, ctypes.c_int32,
+            ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
+            ctypes.POINTER(_MixedStats), P]
+        self.lib.oracle_bicgstab_mixed.restype = ctypes.c_int
         for name in ("oracle_matvec", "oracle_matvec_h"):
             f = getattr(self.lib, name)
             f.argtypes = [I64, P, I64, P, P]
@@ -163,6 +189,44 @@ class Oracle:
 
     def cocr(self, A, y, x0=None, tol=1e-10, maxit=1000, flags=0):
         return self._solve(self.lib.oracle_cocr, A, y, x0, tol, maxit, flags)
+
+    # -- mixed precision -----------------------------------------------------
+    def matvec_c64(self, A32, x):
+        A32 = np.asarray(A32)
+        if A32.dtype != np.complex64 or A32.strides[1] != 8:
+            raise TypeError("A32 must be a row-major complex64 matrix")
+        x = np.ascontiguousarray(x, dtype=np.complex64)
+        y = np.empty(A32.shape[0], dtype=np.complex64)
+        self.lib.oracle_matvec_c64(A32.shape[0], A32.ctypes.data, A32.strides[0] // 8,
+                                   x.ctypes.data, y.ctypes.data)
+        return y
+
+    def bicgstab_mixed(self, A, y, A32=None, x0=None, tol=1e-10, maxit=10,
+                       tol_inner=1e-5, maxit_inner=1000):
+        """FP64 refinement around an inner complex64 BiCGSTAB.  A32 defaults
+        to A rounded to complex64."""
+        A, lda = self._mat(A)
+        n = A.shape[0]
+        if A32 is None:
+            A32 = A.astype(np.complex64)
+        A32 = np.ascontiguousarray(A32, dtype=np.complex64)
+        y = np.ascontiguousarray(y, dtype=np.complex128)
+        flags = 0
+        if x0 is None:
+            x = np.zeros(n, dtype=np.complex128)
+            flags = X0_ZERO
+        else:
+            x = np.array(x0, dtype=np.complex128, copy=True)
+        outer_res = np.full(max(maxit, 0) + 1, np.nan)
+        st = _MixedStats()
+        rc = self.lib.oracle_bicgstab_mixed(
+            n, A.ctypes.data, lda, A32.ctypes.data, max(n, 1), y.ctypes.data,
+            x.ctypes.data, float(tol), int(maxit), float(tol_inner),
+            int(maxit_inner), flags, ctypes.byref(st), outer_res.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle argument error %d" % rc)
+        return MixedResult(x, st.info, st.outer, st.inner_iters, st.matvecs64,
+                           st.matvecs32, st.relres_true, outer_res)
 
     # -- many right-hand sides: the same routines, one column at a time ----
     def matmat(self, A, B, cols=None):

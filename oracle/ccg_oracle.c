@@ -22,6 +22,11 @@
  *     there with COCG).  Both are the CG and CR recurrences with the
  *     unconjugated bilinear form (a, b) = sum a_i b_i in place of the inner
  *     product; one product with A per iteration.
+ *   - Mixed precision BiCGSTAB: FP64 iterative refinement around an inner
+ *     complex64 BiCGSTAB -- the single/double precision switch of the
+ *     ddprecision module (Abstract; Usage section) used inside one solve.
+ *     The inner products accumulate in FP32; the inner dot products and
+ *     scalars are FP64; the outer residual and update are FP64.
  *   - CG: Hestenes-Stiefel conjugate gradients for Hermitian positive-definite
  *     A.  Not in the paper's list; kept only as a pinned reference that other
  *     tests compare CGNR and BiCGSTAB against.
@@ -739,6 +744,205 @@ int oracle_cocr(int64_t n, const zc* A, int64_t lda, const zc* y, zc* x,
     }
     st->iters = k;
     free(work);
+    return 0;
+}
+
+/* -------------------------------------------------------- mixed precision */
+
+typedef float complex fc;
+
+typedef struct {
+    int32_t info;        /* 0..4 from the outer loop */
+    int32_t outer;       /* refinement steps (inner solves) */
+    int32_t inner_iters; /* inner iterations, all steps */
+    int32_t matvecs64;   /* FP64 residual products */
+    int32_t matvecs32;   /* complex64 products */
+    int32_t pad;
+    double relres_true;  /* last FP64 ||y - A x|| / ||y|| */
+} oracle_mixed_stats;
+
+/* y = A x in complex64, every row summed left to right in FP32 */
+void oracle_matvec_c64(int64_t n, const fc* A, int64_t lda, const fc* x, fc* y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        fc s = 0.0f;
+        for (int64_t j = 0; j < n; ++j)
+            s += A[i * lda + j] * x[j];
+        y[i] = s;
+    }
+}
+
+static double norm2sq_c64(int64_t n, const fc* v)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double re = crealf(v[i]), im = cimagf(v[i]);
+        s += re * re + im * im;
+    }
+    return s;
+}
+
+/* sum conj(a_i) b_i in FP64 over complex64 vectors */
+static zc dotc_c64(int64_t n, const fc* a, const fc* b)
+{
+    zc s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += conj((zc)a[i]) * (zc)b[i];
+    return s;
+}
+
+/* Inner BiCGSTAB on complex64 vectors for A32 x = b from x = 0: the same
+ * steps as oracle_bicgstab, each vector update done in FP64 and rounded to
+ * complex64 on store, dot products and scalars in FP64, stop on the
+ * recursive residual (no confirmation).  Returns info; *iters, *matvecs. */
+static int inner_bicgstab_c64(int64_t n, const fc* A, int64_t lda, const fc* b, fc* x,
+                              double tol, int32_t maxit, int32_t* iters, int32_t* matvecs,
+                              fc* w)
+{
+    fc *r = w, *rh = r + n, *p = rh + n, *v = p + n, *s = v + n, *t = s + n;
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = 0.0f;
+        r[i] = b[i];
+        rh[i] = b[i];
+    }
+    const double nb2 = norm2sq_c64(n, b);
+    const double thr2 = tol * tol * nb2;
+    double rr = nb2, rh2 = nb2;
+    zc rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int first = 1;
+    int32_t k = 0;
+    *iters = 0;
+    if (!isfinite(rr)) return 4;
+    if (rr <= thr2) return 0;
+    while (k < maxit) {
+        zc rho = dotc_c64(n, rh, r);
+        if (!zfinite(rho)) return 4;
+        if (abs2(rho) <= 1e-28 * rh2 * rr) return 2;
+        if (first) {
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i];
+            first = 0;
+        } else {
+            zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);
+            for (int64_t i = 0; i < n; ++i)
+                p[i] = (fc)((zc)r[i] + beta * ((zc)p[i] - omega * (zc)v[i]));
+        }
+        oracle_matvec_c64(n, A, lda, p, v);
+        (*matvecs)++;
+        zc sigma = dotc_c64(n, rh, v);
+        double vv = norm2sq_c64(n, v);
+        if (!zfinite(sigma) || !isfinite(vv)) return 4;
+        if (abs2(sigma) <= 1e-28 * rh2 * vv) return 2;
+        alpha = zdiv(rho, sigma);
+        for (int64_t i = 0; i < n; ++i) s[i] = (fc)((zc)r[i] - alpha * (zc)v[i]);
+        double ss = norm2sq_c64(n, s);
+        if (!isfinite(ss)) return 4;
+        if (ss <= thr2) {
+            for (int64_t i = 0; i < n; ++i) x[i] = (fc)((zc)x[i] + alpha * (zc)p[i]);
+            *iters = k + 1;
+            return 0;
+        }
+        oracle_matvec_c64(n, A, lda, s, t);
+        (*matvecs)++;
+        double tt = norm2sq_c64(n, t);
+        zc ts = dotc_c64(n, t, s);
+        if (!isfinite(tt) || !zfinite(ts)) return 4;
+        if (tt == 0.0) return 3;
+        omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);
+        if (omega == 0.0) return 3;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = (fc)((zc)x[i] + alpha * (zc)p[i] + omega * (zc)s[i]);
+            r[i] = (fc)((zc)s[i] - omega * (zc)t[i]);
+        }
+        rr = norm2sq_c64(n, r);
+        k++;
+        *iters = k;
+        if (!isfinite(rr)) return 4;
+        rho_old = rho;
+        if (rr <= thr2) return 0;
+    }
+    return 1;
+}
+
+/* FP64 iterative refinement: r = y - A x (FP64, complex128 A); stop when
+ * ||r|| <= tol ||y|| (info 0) or after maxit steps (info 1); otherwise solve
+ * A32 d = r / ||r|| with the inner complex64 BiCGSTAB to tol_inner and set
+ * x += ||r|| d in FP64.  outer_res (maxit + 1 entries or NULL) receives
+ * ||r|| / ||y|| at every outer check. */
+int oracle_bicgstab_mixed(int64_t n, const zc* A, int64_t lda, const fc* A32, int64_t lda32,
+                          const zc* y, zc* x, double tol, int32_t maxit, double tol_inner,
+                          int32_t maxit_inner, uint32_t flags, oracle_mixed_stats* st,
+                          double* outer_res)
+{
+    memset(st, 0, sizeof *st);
+    st->relres_true = NAN;
+    if (n < 0) return -1;
+    if (lda < (n > 1 ? n : 1) || lda32 < (n > 1 ? n : 1)) return -3;
+    if (!(tol > 0.0) || !isfinite(tol) || maxit < 0) return -6;
+    if (!(tol_inner > 0.0) || !(tol_inner < 1.0) || maxit_inner < 1) return -10;
+    if (n == 0) {
+        st->relres_true = 0.0;
+        return 0;
+    }
+    double ny2 = norm2sq(n, y);
+    if (!isfinite(ny2)) {
+        st->info = 4;
+        return 0;
+    }
+    if (ny2 == 0.0) {
+        zzero(n, x);
+        st->relres_true = 0.0;
+        return 0;
+    }
+    zc* r = (zc*)malloc(sizeof(zc) * (size_t)n);
+    fc* f = (fc*)malloc(sizeof(fc) * (size_t)(8 * n));
+    if (!r || !f) {
+        free(r);
+        free(f);
+        return -100;
+    }
+    fc *r32 = f, *d32 = f + n, *w = f + 2 * n;
+    const double thr2 = tol * tol * ny2;
+    for (int32_t outer = 0;; ++outer) {
+        if (outer == 0 && (flags & ORACLE_X0_ZERO)) {
+            zzero(n, x);
+            zcopy(n, y, r);
+        } else {
+            residual(n, A, lda, y, x, r);
+            st->matvecs64++;
+        }
+        double rr = norm2sq(n, r);
+        st->relres_true = sqrt(rr / ny2);
+        if (outer_res) outer_res[outer] = st->relres_true;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (rr <= thr2) {
+            st->info = 0;
+            break;
+        }
+        if (outer >= maxit) {
+            st->info = 1;
+            break;
+        }
+        const double nr = sqrt(rr);
+        const double scale = 1.0 / nr;
+        for (int64_t i = 0; i < n; ++i)
+            r32[i] = (fc)CMPLX(creal(r[i]) * scale, cimag(r[i]) * scale);
+        int32_t it = 0;
+        int info_in = inner_bicgstab_c64(n, A32, lda32, r32, d32, tol_inner, maxit_inner, &it,
+                                         &st->matvecs32, w);
+        st->outer++;
+        st->inner_iters += it;
+        if (info_in == 4) {
+            st->info = 4;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = x[i] + nr * (zc)d32[i];
+    }
+    free(r);
+    free(f);
     return 0;
 }
 

@@ -26,6 +26,7 @@ WS_MATMAT = 4
 WS_BICGSTAB_BLOCK = 5
 WS_COCG = 6
 WS_COCR = 7
+WS_BICGSTAB_MIXED = 8
 X0_ZERO = 1
 
 INFO_TEXT = {0: "converged", 1: "iteration budget spent",
@@ -42,6 +43,23 @@ class _Result(ctypes.Structure):
                 ("matvecs", ctypes.c_int32), ("confirms", ctypes.c_int32),
                 ("relres_rec", ctypes.c_double),
                 ("relres_true", ctypes.c_double)]
+
+
+class _MixedResult(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("matvecs64", ctypes.c_int32),
+                ("matvecs32", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("relres_true", ctypes.c_double)]
+
+
+@dataclass
+class MixedResult:
+    info: int
+    outer: int
+    inner_iters: int
+    matvecs64: int
+    matvecs32: int
+    relres_true: float
 
 
 @dataclass
@@ -86,6 +104,10 @@ def load() -> ctypes.CDLL:
     for name in ("ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_cocg_ex", "ccg_cocr_ex"):
         getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32, U32, P, S,
                                        ctypes.POINTER(_Result), P, P]
+    lib.ccg_bicgstab_mixed_ex.argtypes = [I64, P, I64, P, I64, P, P, D, I32, D, I32,
+                                          U32, P, S, ctypes.POINTER(_MixedResult), P]
+    lib.ccg_round_c64.argtypes = [I64, I64, P, I64, P, I64, P]
+    lib.ccg_matvec_c64.argtypes = [I64, P, I64, P, P, P]
     lib.ccg_matmat.argtypes = [I64, I64, P, I64, P, I64, P, I64, P]
     lib.ccg_matmat_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, S, P]
     lib.ccg_bicgstab_block.argtypes = [I64, I64, P, I64, P, I64, P, I64, D, I32,
@@ -96,7 +118,8 @@ def load() -> ctypes.CDLL:
     for name in ("ccg_matvec", "ccg_matvec_ex", "ccg_bicgstab", "ccg_cgnr",
                  "ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_matmat", "ccg_matmat_ex",
                  "ccg_bicgstab_block", "ccg_bicgstab_block_ex", "ccg_cocg",
-                 "ccg_cocr", "ccg_cocg_ex", "ccg_cocr_ex"):
+                 "ccg_cocr", "ccg_cocg_ex", "ccg_cocr_ex", "ccg_bicgstab_mixed_ex",
+                 "ccg_round_c64", "ccg_matvec_c64"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -257,6 +280,70 @@ def ccg_cocr_ex(A, y, x, tol=1e-10, maxit=1000, flags=0, work=None,
                 hist=None, stream=None) -> Result:
     return _ex("ccg_cocr_ex", WS_COCR, A, y, x, tol, maxit, flags, work, hist,
                stream)
+
+
+def ccg_matvec_c64(A32, x, y=None, stream=None):
+    """y = A32 x in complex64 (FP32 accumulation)."""
+    torch = _torch()
+    if not isinstance(A32, torch.Tensor) or A32.dtype != torch.complex64 or \
+            A32.dim() != 2 or A32.shape[0] != A32.shape[1] or not A32.is_cuda:
+        raise TypeError("A32 must be a square complex64 CUDA tensor")
+    n = A32.shape[0]
+    if n > 0 and A32.stride(1) != 1:
+        raise TypeError("A32 must be row-major")
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex64 or \
+            x.numel() != n or not x.is_cuda:
+        raise TypeError("x must be a complex64 CUDA tensor of n elements")
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load().ccg_matvec_c64(n, A32.data_ptr(), max(A32.stride(0), 1) if n else 1,
+                                 x.data_ptr(), y.data_ptr(), _stream(stream)),
+           "ccg_matvec_c64")
+    return y
+
+
+def ccg_round_c64(src, dst=None, stream=None):
+    """dst = complex64(src) for a 2-D row-major complex128 tensor."""
+    torch = _torch()
+    if not isinstance(src, torch.Tensor) or src.dtype != torch.complex128 or \
+            not src.is_cuda or src.dim() != 2:
+        raise TypeError("src must be a 2-D complex128 CUDA tensor")
+    rows, cols = src.shape
+    if dst is None:
+        dst = torch.empty((rows, cols), dtype=torch.complex64, device=src.device)
+    if dst.dtype != torch.complex64 or tuple(dst.shape) != (rows, cols):
+        raise TypeError("dst must be a complex64 tensor of the same shape")
+    lds = max(src.stride(0), cols, 1)
+    ldd = max(dst.stride(0), cols, 1)
+    _check(load().ccg_round_c64(rows, cols, src.data_ptr(), lds, dst.data_ptr(),
+                                ldd, _stream(stream)), "ccg_round_c64")
+    return dst
+
+
+def ccg_bicgstab_mixed_ex(A, A32, y, x, tol=1e-10, maxit=10, tol_inner=1e-5,
+                          maxit_inner=1000, flags=0, work=None,
+                          stream=None) -> MixedResult:
+    """FP64 refinement around an inner complex64 BiCGSTAB; x in/out."""
+    torch = _torch()
+    n, lda = _mat(A)
+    if not isinstance(A32, torch.Tensor) or A32.dtype != torch.complex64 or \
+            tuple(A32.shape) != (n, n) or not A32.is_cuda or \
+            (n > 0 and A32.stride(1) != 1):
+        raise TypeError("A32 must be an n x n row-major complex64 CUDA tensor")
+    lda32 = max(A32.stride(0), 1) if n > 0 else 1
+    _vec(y, n, "y")
+    _vec(x, n, "x")
+    if work is None:
+        nbytes = max(ccg_workspace_bytes(WS_BICGSTAB_MIXED, n), 256)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    res = _MixedResult()
+    _check(load().ccg_bicgstab_mixed_ex(
+        n, A.data_ptr(), lda, A32.data_ptr(), lda32, y.data_ptr(), x.data_ptr(),
+        float(tol), int(maxit), float(tol_inner), int(maxit_inner), int(flags),
+        work.data_ptr(), work.numel() * work.element_size(), ctypes.byref(res),
+        _stream(stream)), "ccg_bicgstab_mixed_ex")
+    return MixedResult(res.info, res.outer, res.inner_iters, res.matvecs64,
+                       res.matvecs32, res.relres_true)
 
 
 def hist_numpy(hist) -> np.ndarray:

@@ -283,7 +283,8 @@ __global__ void kb_init(BArgs a, int maxit, double tol2)
     o.maxit = maxit;
     o.pending = PK_NONE;
     o.pending_blocks = 0;
-    o.pad0 = o.pad1 = o.pad2 = 0;
+    o.no_confirm = 0;
+    o.pad1 = o.pad2 = 0;
     o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
     o.tol2 = tol2;
     o.relres_rec = o.relres_true = __builtin_nan("");

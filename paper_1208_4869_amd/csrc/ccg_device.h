@@ -10,6 +10,8 @@ namespace ccg {
 
 // complex128 as a 16-byte vector: one global_load_dwordx4 per element.
 typedef double d2 __attribute__((ext_vector_type(2)));
+// complex64 as an 8-byte vector (the mixed-precision inner solver).
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
@@ -59,6 +61,18 @@ __device__ __forceinline__ bool cfinite(d2 a)
 }
 
 __device__ __forceinline__ d2 ldnt(const d2* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ f2 ldnt(const f2* p) { return __builtin_nontemporal_load(p); }
+
+// Vector element access in either precision; arithmetic is done in FP64 and
+// a complex64 store rounds to nearest.
+__device__ __forceinline__ d2 ldv(const d2* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ d2 ldv(const f2* p, int64_t i)
+{
+    const f2 v = p[i];
+    return d2{(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void stv(d2* p, int64_t i, d2 v) { p[i] = v; }
+__device__ __forceinline__ void stv(f2* p, int64_t i, d2 v) { p[i] = f2{(float)v.x, (float)v.y}; }
 
 // Sum over the 64 lanes of a wavefront; every lane receives the total.
 __device__ __forceinline__ double wave_sum(double v)

@@ -86,6 +86,80 @@ __device__ __forceinline__ d2 gemv_n_row_total(const d2 (*red)[R], int r)
     return s;
 }
 
+// The same block layout for complex64 A and x (the mixed-precision inner
+// products): each lane accumulates its strided partial sums in FP32 with
+// fused multiply-adds; the cross-lane and cross-wavefront sums are in FP64.
+// With vec16 (A 16-byte aligned, lda even, x 16-byte aligned) a lane loads
+// two adjacent complex64 per 16-byte load and a wavefront chunk is 128
+// columns; otherwise 8-byte loads and 64-column chunks.  Columns past the
+// last full chunk are taken one per lane.
+__device__ __forceinline__ void cfmaf(f2& acc, f2 a, f2 x)
+{
+    acc.x = __builtin_fmaf(a.x, x.x, acc.x);
+    acc.x = __builtin_fmaf(-a.y, x.y, acc.x);
+    acc.y = __builtin_fmaf(a.x, x.y, acc.y);
+    acc.y = __builtin_fmaf(a.y, x.x, acc.y);
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int R, int W>
+__device__ __forceinline__ void gemv_n_block_f(const f2* __restrict__ A, int64_t lda, int n,
+                                               const f2* __restrict__ x, int row0,
+                                               d2 (*red)[R], bool vec16)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const f2* Ar[R];
+    f2 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = row0 + r < n ? row0 + r : n - 1;
+        Ar[r] = A + (int64_t)row * lda;
+        acc[r] = f2{0.0f, 0.0f};
+    }
+    int jt;  // first column of the per-lane tail
+    if (vec16) {
+        const int nfull = n / (2 * kWave);
+        for (int c = wave; c < nfull; c += W) {
+            const int j = c * 2 * kWave + 2 * lane;
+            const f4 xv = *(const f4*)(x + j);
+            f4 a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = __builtin_nontemporal_load((const f4*)(Ar[r] + j));
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cfmaf(acc[r], f2{a[r].x, a[r].y}, f2{xv.x, xv.y});
+                cfmaf(acc[r], f2{a[r].z, a[r].w}, f2{xv.z, xv.w});
+            }
+        }
+        jt = nfull * 2 * kWave;
+    } else {
+        const int nfull = n / kWave;
+        for (int c = wave; c < nfull; c += W) {
+            const int j = c * kWave + lane;
+            const f2 xv = x[j];
+            f2 a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = ldnt(Ar[r] + j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) cfmaf(acc[r], a[r], xv);
+        }
+        jt = nfull * kWave;
+    }
+    for (int j = jt + wave * kWave + lane; j < n; j += W * kWave) {
+        const f2 xv = x[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) cfmaf(acc[r], ldnt(Ar[r] + j), xv);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const d2 s = wave_sum(d2{(double)acc[r].x, (double)acc[r].y});
+        if (lane == 0) red[wave][r] = s;
+    }
+    __syncthreads();
+}
+
 // Launch shape of the A x kernels for a given n.
 struct GemvNShape {
     int rows_per_wave;

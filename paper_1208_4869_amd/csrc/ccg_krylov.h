@@ -58,7 +58,8 @@ enum Pending : int {
 struct alignas(16) SolverState {
     int phase, restart, info, iters;
     int matvecs, confirms, maxit, pending;
-    int pending_blocks, pad0, pad1, pad2;
+    int pending_blocks, no_confirm, pad1, pad2;  // no_confirm: inner solves stop on
+                                                 // the recursive residual
     double ny2, thr2, rh2, rr;
     double relres_rec, relres_true, gamma, tol2;
     d2 rho, rho_old, alpha, omega, beta;
@@ -79,7 +80,11 @@ __device__ inline void setup_step(SolverState& L, double rr, bool bicg)
     if (!__builtin_isfinite(rr)) { finish(L, 4); return; }
     L.rr = rr;
     L.relres_rec = relres(rr, L.ny2);
-    if (rr <= L.thr2) { L.phase = PH_CONFIRM; return; }
+    if (rr <= L.thr2) {
+        if (L.no_confirm) finish(L, 0);
+        else L.phase = PH_CONFIRM;
+        return;
+    }
     L.restart = 1;
     if (bicg) {
         L.rh2 = rr;
@@ -211,7 +216,11 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
         if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
         L.rr = rr;
         L.relres_rec = relres(rr, L.ny2);
-        if (rr <= L.thr2) { L.phase = PH_CONFIRM; break; }
+        if (rr <= L.thr2) {
+            if (L.no_confirm) finish(L, 0);
+            else L.phase = PH_CONFIRM;
+            break;
+        }
         if (L.iters >= L.maxit) { finish(L, 1); break; }
         if (!cfinite(rho_new)) { finish(L, 4); break; }
         if (cabs2(rho_new) <= 1e-28 * L.rh2 * rr) { finish(L, 2); break; }
@@ -228,7 +237,8 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
     }
     case PK_HALF:
         L.iters++;
-        L.phase = PH_CONFIRM;
+        if (L.no_confirm) finish(L, 0);
+        else L.phase = PH_CONFIRM;
         break;
     case PK_W: {  // alpha = gamma / ||w||^2
         const double ww = t0.x;

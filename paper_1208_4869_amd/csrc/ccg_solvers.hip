@@ -52,6 +52,7 @@ struct Args {
     d2* part[2];                 // per-block partial sums, alternating
     SolverState* st[2];          // state copies, alternating
     ccg_hist* hist;
+    bool vec16;                  // complex64 A with 16-byte aligned rows
 };
 
 constexpr int kR = 4;   // rows per block in A x
@@ -94,7 +95,7 @@ __device__ __forceinline__ void publish(const Args& a, int q, const SolverState&
 
 // --------------------------------------------------------- common kernels
 
-__global__ void k_init(SolverState* st, int maxit, double tol2)
+__global__ void k_init(SolverState* st, int maxit, double tol2, int no_confirm)
 {
     if (threadIdx.x == 0) {
         SolverState o;
@@ -105,7 +106,8 @@ __global__ void k_init(SolverState* st, int maxit, double tol2)
         o.maxit = maxit;
         o.pending = PK_NONE;
         o.pending_blocks = 0;
-        o.pad0 = o.pad1 = o.pad2 = 0;
+        o.no_confirm = no_confirm;
+        o.pad1 = o.pad2 = 0;
         o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
         o.tol2 = tol2;
         o.relres_rec = o.relres_true = __builtin_nan("");
@@ -124,13 +126,16 @@ __global__ void k_status(Args a, int q, int* ring_slot)
     publish(a, q, L, PK_NONE, 0);
 }
 
-// ||y||^2 (the stop threshold follows in the next kernel's step).
+// ||y||^2 (the stop threshold follows in the next kernel's step).  T is the
+// vector element type: d2 (complex128) or f2 (complex64, inner solves).
+template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q)
 {
     SOLVER_PROLOGUE();
+    const T* y = (const T*)a.y;
     d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock)
-        v0.x += cabs2(a.y[i]);
+        v0.x += cabs2(ldv(y, i));
     write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
     publish(a, q, L, PK_NORMY, gridDim.x);
 }
@@ -140,19 +145,23 @@ enum Method { M_BICG = 0, M_CGNR = 1, M_COCG = 2, M_COCR = 3 };
 
 // Set-up when the caller says x0 = 0: x = 0, r = y (and r^ = y for BiCGSTAB;
 // COCG also needs the bilinear (r, r)).
-template <int M>
+template <int M, class T = d2>
 __global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
 {
     SOLVER_PROLOGUE();
     const int ph = L.phase;
     if (ph != PH_RUN && ph != PH_ZERO) { publish(a, q, L, PK_NONE, 0); return; }
+    T* x = (T*)a.x;
+    T* r = (T*)a.r;
+    T* rh = (T*)a.rh;
+    const T* y = (const T*)a.y;
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        a.x[i] = d2{0.0, 0.0};
+        stv(x, i, d2{0.0, 0.0});
         if (ph == PH_RUN) {
-            const d2 yi = a.y[i];
-            a.r[i] = yi;
-            if (M == M_BICG) a.rh[i] = yi;
+            const d2 yi = ldv(y, i);
+            stv(r, i, yi);
+            if (M == M_BICG) stv(rh, i, yi);
             v0.x += cabs2(yi);
             if (M == M_COCG) v1 = cfma(yi, yi, v1);
         }
@@ -196,7 +205,7 @@ __device__ __forceinline__ int role_mode(int ph)
     return -1;
 }
 
-template <Role RO>
+template <Role RO, class T = d2>
 __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 {
     SOLVER_PROLOGUE();
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     const bool setup = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || RO == ROLE_SETUP_G);
 
     if (mode == PH_ZERO) {  // y == 0: zero this block's rows of x
-        if (t < kR && row0 + t < n) a.x[row0 + t] = d2{0.0, 0.0};
+        if (t < kR && row0 + t < n) stv((T*)a.x, row0 + t, d2{0.0, 0.0});
         publish(a, q, L, PK_ZERO, 0);
         return;
     }
@@ -218,16 +227,21 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 
     __shared__ d2 red[kWN][kR];
     d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
-    gemv_n_block<kR, kU, kWN>(a.A, a.lda, n, in, row0, red);
+    if constexpr (sizeof(T) == sizeof(f2))
+        gemv_n_block_f<kR, kWN>((const f2*)a.A, a.lda, n, (const f2*)in, row0, red, a.vec16);
+    else
+        gemv_n_block<kR, kU, kWN>(a.A, a.lda, n, in, row0, red);
     // thread r of the first wavefront finishes row row0 + r: output and its
-    // dot-product terms
+    // dot-product terms (in FP64; complex64 vectors are rounded on store and
+    // the terms use the stored values)
     const int i = row0 + t;
     if (t < kR && i < n) {
-        const d2 val = gemv_n_row_total<kR, kWN>(red, t);
+        d2 val = gemv_n_row_total<kR, kWN>(red, t);
         if (resid) {
-            const d2 ri = a.y[i] - val;
-            a.r[i] = ri;
-            if (RO == ROLE_SETUP_B || RO == ROLE_V) a.rh[i] = ri;
+            T* r = (T*)a.r;
+            stv(r, i, ldv((const T*)a.y, i) - val);
+            const d2 ri = ldv(r, i);
+            if (RO == ROLE_SETUP_B || RO == ROLE_V) stv((T*)a.rh, i, ri);
             pv0.x = cabs2(ri);
             if (RO == ROLE_SETUP_G || RO == ROLE_Q) pv1 = cfma(ri, ri, pv1);
         } else if (RO == ROLE_Q) {
@@ -237,12 +251,16 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
             a.z[i] = val;  // u
             pv0 = cfma(a.r[i], val, pv0);
         } else if (RO == ROLE_V) {
-            a.v[i] = val;
-            pv0 = cfma_conj(a.rh[i], val, pv0);
+            T* v = (T*)a.v;
+            stv(v, i, val);
+            val = ldv(v, i);
+            pv0 = cfma_conj(ldv((const T*)a.rh, i), val, pv0);
             pv1.x = cabs2(val);
         } else if (RO == ROLE_T) {
-            a.t[i] = val;
-            pv0 = cfma_conj(val, a.s[i], pv0);
+            T* tv = (T*)a.t;
+            stv(tv, i, val);
+            val = ldv(tv, i);
+            pv0 = cfma_conj(val, ldv((const T*)a.s, i), pv0);
             pv1.x = cabs2(val);
         } else {  // ROLE_W
             a.w[i] = val;
@@ -265,20 +283,24 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 // ------------------------------------------------------- BiCGSTAB vectors
 
 // p = r (new direction) or p = r + beta (p - omega v)
+template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_p(Args a, int q)
 {
     SOLVER_PROLOGUE();
     if (L.phase == PH_RUN || L.phase == PH_RESTART) {
+        T* p = (T*)a.p;
+        const T* r = (const T*)a.r;
+        const T* v = (const T*)a.v;
         const bool fresh = L.restart != 0;
         const d2 beta = L.beta;
         const d2 nom = d2{-L.omega.x, -L.omega.y};
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-            const d2 ri = a.r[i];
+            const d2 ri = ldv(r, i);
             if (fresh) {
-                a.p[i] = ri;
+                stv(p, i, ri);
             } else {
-                const d2 d = cfma(nom, a.v[i], a.p[i]);  // p - omega v
-                a.p[i] = cfma(beta, d, ri);
+                const d2 d = cfma(nom, ldv(v, i), ldv(p, i));  // p - omega v
+                stv(p, i, cfma(beta, d, ri));
             }
         }
     }
@@ -286,16 +308,19 @@ __global__ __launch_bounds__(kBlock) void k_bicg_p(Args a, int q)
 }
 
 // s = r - alpha v, ||s||^2
+template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 {
     SOLVER_PROLOGUE();
     if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
+    T* s = (T*)a.s;
+    const T* r = (const T*)a.r;
+    const T* v = (const T*)a.v;
     const d2 nal = d2{-L.alpha.x, -L.alpha.y};
     d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 si = cfma(nal, a.v[i], a.r[i]);
-        a.s[i] = si;
-        v0.x += cabs2(si);
+        stv(s, i, cfma(nal, ldv(v, i), ldv(r, i)));
+        v0.x += cabs2(ldv(s, i));
     }
     write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
     publish(a, q, L, PK_S, gridDim.x);
@@ -303,26 +328,33 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 
 // x += alpha p + omega s, r = s - omega t, ||r||^2, r^H r; or, after a
 // half-step exit, x += alpha p.
+template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_xr(Args a, int q)
 {
     SOLVER_PROLOGUE();
     const int ph = L.phase;
     if (ph != PH_RUN && ph != PH_HALF) { publish(a, q, L, PK_NONE, 0); return; }
+    T* x = (T*)a.x;
+    T* r = (T*)a.r;
+    const T* p = (const T*)a.p;
+    const T* s = (const T*)a.s;
+    const T* tv = (const T*)a.t;
+    const T* rh = (const T*)a.rh;
     const d2 alpha = L.alpha;
     const d2 omega = L.omega;
     const d2 nom = d2{-omega.x, -omega.y};
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        d2 xi = cfma(alpha, a.p[i], a.x[i]);
+        d2 xi = cfma(alpha, ldv(p, i), ldv(x, i));
         if (ph == PH_RUN) {
-            const d2 si = a.s[i];
+            const d2 si = ldv(s, i);
             xi = cfma(omega, si, xi);
-            const d2 ri = cfma(nom, a.t[i], si);
-            a.r[i] = ri;
+            stv(r, i, cfma(nom, ldv(tv, i), si));
+            const d2 ri = ldv(r, i);
             v0.x += cabs2(ri);
-            v1 = cfma_conj(a.rh[i], ri, v1);
+            v1 = cfma_conj(ldv(rh, i), ri, v1);
         }
-        a.x[i] = xi;
+        stv(x, i, xi);
     }
     if (ph == PH_HALF) { publish(a, q, L, PK_HALF, 0); return; }
     write_partials(v0, v1, a.part[q ^ 1], lds);
@@ -498,6 +530,18 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_plain(const d2* __restrict__
     if (t < kR && row0 + t < n) y[row0 + t] = gemv_n_row_total<kR, kWN>(red, t);
 }
 
+// y = A x in complex64 (the inner product of the mixed-precision solver)
+__global__ __launch_bounds__(kBlockN) void k_gemv_n_plain_f(const f2* __restrict__ A, int64_t lda,
+                                                            int n, const f2* __restrict__ x,
+                                                            f2* __restrict__ y, bool vec16)
+{
+    __shared__ d2 red[kWN][kR];
+    const int row0 = blockIdx.x * kR;
+    gemv_n_block_f<kR, kWN>(A, lda, n, x, row0, red, vec16);
+    const int t = threadIdx.x;
+    if (t < kR && row0 + t < n) stv(y, row0 + t, gemv_n_row_total<kR, kWN>(red, t));
+}
+
 __global__ __launch_bounds__(kBlock) void k_gemv_c_band_plain(const d2* __restrict__ A,
                                                               int64_t lda, int n,
                                                               const d2* __restrict__ x,
@@ -531,6 +575,12 @@ static inline int blocks_e(int64_t n)
 }
 
 static constexpr int64_t kMaxN = (int64_t)1 << 30;
+
+// complex64 rows start on 16-byte boundaries (16-byte loads of two elements)
+static inline bool rows16(const void* A, int64_t lda)
+{
+    return ((uintptr_t)A & 15) == 0 && (lda & 1) == 0;
+}
 
 struct Layout {
     size_t state, partials, part_bytes, vec, zpart, total;
@@ -631,9 +681,9 @@ static int ws_of(int M)
 // Enqueue set-up, then slots until the status ring reports PH_DONE.  Every
 // solver kernel reads state copy q and writes copy q ^ 1; the host tracks q
 // across the launches it makes.
-template <int M>
+template <int M, class T = d2>
 static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
-                      ccg_result* res, hipStream_t s)
+                      ccg_result* res, hipStream_t s, int no_confirm = 0)
 {
     SyncCtx* sc = nullptr;
     hipError_t e = get_sync(&sc);
@@ -644,12 +694,12 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     int q = 0;
     auto flip = [&q]() { const int cur = q; q ^= 1; return cur; };
 
-    k_init<<<1, 64, 0, s>>>(a.st[0], maxit, tol2);
-    k_norm_y<<<gE, kBlock, 0, s>>>(a, flip());
+    k_init<<<1, 64, 0, s>>>(a.st[0], maxit, tol2, no_confirm);
+    k_norm_y<T><<<gE, kBlock, 0, s>>>(a, flip());
     if (flags & CCG_X0_ZERO)
-        k_setup_x0zero<M == M_COCR ? M_CGNR : M><<<gE, kBlock, 0, s>>>(a, flip());
+        k_setup_x0zero<M == M_COCR ? M_CGNR : M, T><<<gE, kBlock, 0, s>>>(a, flip());
     else if (M == M_BICG)
-        k_gemv_n_role<ROLE_SETUP_B><<<gN, kBlockN, 0, s>>>(a, flip());
+        k_gemv_n_role<ROLE_SETUP_B, T><<<gN, kBlockN, 0, s>>>(a, flip());
     else if (M == M_COCG)
         k_gemv_n_role<ROLE_SETUP_G><<<gN, kBlockN, 0, s>>>(a, flip());
     else
@@ -664,11 +714,11 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
             if (M == M_BICG) {
-                k_bicg_p<<<gE, kBlock, 0, s>>>(a, flip());
-                k_gemv_n_role<ROLE_V><<<gN, kBlockN, 0, s>>>(a, flip());
-                k_bicg_s<<<gE, kBlock, 0, s>>>(a, flip());
-                k_gemv_n_role<ROLE_T><<<gN, kBlockN, 0, s>>>(a, flip());
-                k_bicg_xr<<<gE, kBlock, 0, s>>>(a, flip());
+                k_bicg_p<T><<<gE, kBlock, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_V, T><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_bicg_s<T><<<gE, kBlock, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_T, T><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_bicg_xr<T><<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR) {
                 k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, flip());
                 k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
@@ -793,6 +843,245 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
     return e == hipSuccess ? 0 : (int)e;
 }
 
+// ------------------------------------------------------- mixed precision
+//
+// FP64 iterative refinement around an inner complex64 BiCGSTAB (the single /
+// double switch of the ddprecision module, Usage section, used inside one
+// solve): the outer residual r = y - A x comes from the complex128 A in FP64,
+// the correction d solves A32 d = r / ||r|| in complex64 (FP32 product
+// accumulation, FP64 reductions and scalars) to a loose relative tolerance,
+// and x += ||r|| d is applied in FP64.  The outer loop stops on the FP64 true
+// residual, so info 0 means ||y - A x|| <= tol ||y|| exactly as for
+// ccg_bicgstab.
+
+// r = y - A x with FP64 products, block partials of ||r||^2
+__global__ __launch_bounds__(kBlockN) void k_mix_resid(const d2* __restrict__ A, int64_t lda,
+                                                       int n, const d2* __restrict__ x,
+                                                       const d2* __restrict__ y,
+                                                       d2* __restrict__ r, d2* part)
+{
+    __shared__ d2 red[kWN][kR];
+    __shared__ d2 lds[kMaxWaves];
+    const int row0 = blockIdx.x * kR;
+    gemv_n_block<kR, kU, kWN>(A, lda, n, x, row0, red);
+    const int t = threadIdx.x;
+    d2 v0 = d2{0.0, 0.0};
+    if (t < kR && row0 + t < n) {
+        const d2 ri = y[row0 + t] - gemv_n_row_total<kR, kWN>(red, t);
+        r[row0 + t] = ri;
+        v0.x = cabs2(ri);
+    }
+    write_partials(v0, d2{0.0, 0.0}, part, lds);
+}
+
+// r = y (x0 = 0) and x = 0, block partials of ||r||^2
+__global__ __launch_bounds__(kBlock) void k_mix_copy(int n, const d2* __restrict__ y,
+                                                     d2* __restrict__ x, d2* __restrict__ r,
+                                                     d2* part)
+{
+    __shared__ d2 lds[kMaxWaves];
+    d2 v0 = d2{0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const d2 yi = y[i];
+        r[i] = yi;
+        x[i] = d2{0.0, 0.0};
+        v0.x += cabs2(yi);
+    }
+    write_partials(v0, d2{0.0, 0.0}, part, lds);
+}
+
+// block partials of ||y||^2
+__global__ __launch_bounds__(kBlock) void k_mix_norm(int n, const d2* __restrict__ y, d2* part)
+{
+    __shared__ d2 lds[kMaxWaves];
+    d2 v0 = d2{0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        v0.x += cabs2(y[i]);
+    write_partials(v0, d2{0.0, 0.0}, part, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mix_zero(int n, d2* __restrict__ x)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        x[i] = d2{0.0, 0.0};
+}
+
+// total of nblocks partial pairs -> out (one block)
+__global__ __launch_bounds__(kBlock) void k_mix_total(const d2* part, int nblocks, d2* out)
+{
+    __shared__ d2 lds[kMaxWaves];
+    d2 t0, t1;
+    reduce_partials(part, nblocks, lds, t0, t1);
+    if (threadIdx.x == 0) *out = t0;
+}
+
+// r32 = complex64(r * scale)
+__global__ __launch_bounds__(kBlock) void k_mix_round(int n, const d2* __restrict__ r,
+                                                      double scale, f2* __restrict__ r32)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const d2 v = r[i];
+        r32[i] = f2{(float)(v.x * scale), (float)(v.y * scale)};
+    }
+}
+
+// x += scale * d32 in FP64
+__global__ __launch_bounds__(kBlock) void k_mix_update(int n, const f2* __restrict__ d32,
+                                                       double scale, d2* __restrict__ x)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const f2 d = d32[i];
+        d2 xi = x[i];
+        xi.x = __builtin_fma(scale, (double)d.x, xi.x);
+        xi.y = __builtin_fma(scale, (double)d.y, xi.y);
+        x[i] = xi;
+    }
+}
+
+// dst = complex64(src), row by row
+__global__ __launch_bounds__(kBlock) void k_round_c64(int64_t rows, int64_t cols,
+                                                      const d2* __restrict__ src, int64_t lds_,
+                                                      f2* __restrict__ dst, int64_t ldd)
+{
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / cols, j = e - i * cols;
+        const d2 v = src[i * lds_ + j];
+        dst[i * ldd + j] = f2{(float)v.x, (float)v.y};
+    }
+}
+
+struct MixLayout {
+    size_t inner, r64, r32, d32, part, tot, total;
+};
+
+static MixLayout mix_layout(int64_t n)
+{
+    MixLayout L{};
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t off = 0;
+    L.inner = off;
+    off += layout(CCG_WS_BICGSTAB, n).total;  // complex128-sized: room for complex64
+    L.r64 = off;
+    off += align256(nn * sizeof(d2));
+    L.r32 = off;
+    off += align256(nn * sizeof(f2));
+    L.d32 = off;
+    off += align256(nn * sizeof(f2));
+    L.part = off;
+    int64_t pb = blocks_n(n) > blocks_e(n) ? blocks_n(n) : blocks_e(n);
+    off += align256((size_t)pb * 2 * sizeof(d2));
+    L.tot = off;
+    off += 256;
+    L.total = off;
+    return L;
+}
+
+static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, int64_t lda32,
+                      const ccg_z* y, ccg_z* x, double tol, int32_t maxit, double tol_inner,
+                      int32_t maxit_inner, uint32_t flags, void* work, size_t work_bytes,
+                      ccg_mixed_result* res, void* stream)
+{
+    if (n < 0 || n > kMaxN) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && !A32) return -4;
+    if (lda32 < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && !y) return -6;
+    if (n > 0 && !x) return -7;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return -8;
+    if (maxit < 0) return -9;
+    if (!(tol_inner > 0.0) || !(tol_inner < 1.0)) return -10;
+    if (maxit_inner < 1) return -11;
+    if (flags & ~CCG_X0_ZERO) return -12;
+    const MixLayout ML = mix_layout(n);
+    if (n > 0 && (!work || ((uintptr_t)work & 255))) return -13;
+    if (n > 0 && work_bytes < ML.total) return -14;
+    if (!res) return -15;
+    std::memset(res, 0, sizeof *res);
+    res->relres_true = __builtin_nan("");
+    if (n == 0) {
+        res->relres_true = 0.0;
+        return 0;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)work;
+    d2* r64 = (d2*)(base + ML.r64);
+    f2* r32 = (f2*)(base + ML.r32);
+    f2* d32 = (f2*)(base + ML.d32);
+    d2* part = (d2*)(base + ML.part);
+    d2* tot = (d2*)(base + ML.tot);
+    const int gN = blocks_n(n), gE = blocks_e(n);
+    hipError_t e;
+
+    // the inner solver: BiCGSTAB on complex64 vectors, A32 d = r32
+    Args in = make_args(CCG_WS_BICGSTAB, n, nullptr, lda32, nullptr, nullptr, base + ML.inner,
+                        nullptr);
+    in.A = (const d2*)A32;
+    in.y = (const d2*)r32;
+    in.x = (d2*)d32;
+    in.vec16 = rows16(A32, lda32);  // the inner vectors are 256-byte aligned
+
+    auto residual_norm2 = [&](bool x_zero, double* rr) -> int {
+        if (x_zero)
+            k_mix_copy<<<gE, kBlock, 0, s>>>((int)n, (const d2*)y, (d2*)x, r64, part);
+        else
+            k_mix_resid<<<gN, kBlockN, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x,
+                                               (const d2*)y, r64, part);
+        k_mix_total<<<1, kBlock, 0, s>>>(part, x_zero ? gE : gN, tot);
+        d2 h;
+        if ((e = hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return (int)e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
+        *rr = h.x;
+        return 0;
+    };
+
+    // ||y||^2
+    k_mix_norm<<<gE, kBlock, 0, s>>>((int)n, (const d2*)y, part);
+    k_mix_total<<<1, kBlock, 0, s>>>(part, gE, tot);
+    d2 hy;
+    if ((e = hipMemcpyAsync(&hy, tot, sizeof hy, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return (int)e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
+    const double ny2 = hy.x;
+    if (!std::isfinite(ny2)) {  // x is left as it was
+        res->info = 4;
+        return 0;
+    }
+    if (ny2 == 0.0) {  // y = 0: x = 0
+        k_mix_zero<<<gE, kBlock, 0, s>>>((int)n, (d2*)x);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
+        res->relres_true = 0.0;
+        return 0;
+    }
+    const double thr2 = tol * tol * ny2;
+    for (int outer = 0;; ++outer) {
+        double rr = 0.0;
+        int rc = residual_norm2(outer == 0 && (flags & CCG_X0_ZERO), &rr);
+        if (rc) return rc;
+        if (outer > 0 || !(flags & CCG_X0_ZERO)) res->matvecs64++;
+        res->relres_true = std::sqrt(rr / ny2);
+        if (!std::isfinite(rr)) { res->info = 4; break; }
+        if (rr <= thr2) { res->info = 0; break; }
+        if (outer >= maxit) { res->info = 1; break; }
+        const double nr = std::sqrt(rr);
+        k_mix_round<<<gE, kBlock, 0, s>>>((int)n, r64, 1.0 / nr, r32);
+        ccg_result ir{};
+        rc = run_solver<M_BICG, f2>(in, CCG_X0_ZERO, maxit_inner, tol_inner * tol_inner, &ir, s,
+                                    /*no_confirm=*/1);
+        if (rc) return rc;
+        res->outer++;
+        res->inner_iters += ir.iters;
+        res->matvecs32 += ir.matvecs;
+        if (ir.info == 4) { res->info = 4; break; }
+        k_mix_update<<<gE, kBlock, 0, s>>>((int)n, d32, nr, (d2*)x);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    }
+    return 0;
+}
+
 }  // namespace ccg
 
 // ============================================================== C ABI
@@ -811,6 +1100,7 @@ size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
     if (method == CCG_WS_BICGSTAB || method == CCG_WS_CGNR || method == CCG_WS_COCG ||
         method == CCG_WS_COCR)
         return ccg::layout(method, n).total;
+    if (method == CCG_WS_BICGSTAB_MIXED) return ccg::mix_layout(n).total;
     return 0;
 }
 
@@ -852,6 +1142,52 @@ int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x
 {
     return ccg::solve_ex<ccg::M_CGNR>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes, res,
                                 hist, stream);
+}
+
+int ccg_bicgstab_mixed_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32,
+                          int64_t lda32, const ccg_z* y, ccg_z* x, double tol, int32_t maxit,
+                          double tol_inner, int32_t maxit_inner, uint32_t flags, void* work,
+                          size_t work_bytes, ccg_mixed_result* res, void* stream)
+{
+    return ccg::mixed_impl(n, A, lda, A32, lda32, y, x, tol, maxit, tol_inner, maxit_inner,
+                           flags, work, work_bytes, res, stream);
+}
+
+int ccg_matvec_c64(int64_t n, const ccg_c* A, int64_t lda, const ccg_c* x, ccg_c* y,
+                   void* stream)
+{
+    if (n < 0 || n > ccg::kMaxN) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < (n > 1 ? n : 1)) return -3;
+    if (n > 0 && !x) return -4;
+    if (n > 0 && !y) return -5;
+    if (n == 0) return 0;
+    const char *xb = (const char*)x, *yb = (const char*)y;
+    const size_t vb = (size_t)n * sizeof(ccg_c);
+    if (xb < yb + vb && yb < xb + vb) return -5;
+    const bool v16 = ccg::rows16(A, lda) && ((uintptr_t)x & 15) == 0;
+    ccg::k_gemv_n_plain_f<<<ccg::blocks_n(n), ccg::kBlockN, 0, (hipStream_t)stream>>>(
+        (const ccg::f2*)A, lda, (int)n, (const ccg::f2*)x, (ccg::f2*)y, v16);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+int ccg_round_c64(int64_t rows, int64_t cols, const ccg_z* src, int64_t lds, ccg_c* dst,
+                  int64_t ldd, void* stream)
+{
+    if (rows < 0) return -1;
+    if (cols < 0) return -2;
+    if (rows > 0 && cols > 0 && !src) return -3;
+    if (lds < (cols > 1 ? cols : 1)) return -4;
+    if (rows > 0 && cols > 0 && !dst) return -5;
+    if (ldd < (cols > 1 ? cols : 1)) return -6;
+    if (rows == 0 || cols == 0) return 0;
+    int64_t blocks = (rows * cols + ccg::kBlock - 1) / ccg::kBlock;
+    if (blocks > 4096) blocks = 4096;
+    ccg::k_round_c64<<<(int)blocks, ccg::kBlock, 0, (hipStream_t)stream>>>(
+        rows, cols, (const ccg::d2*)src, lds, (ccg::f2*)dst, ldd);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
 }
 
 int ccg_cocg(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,

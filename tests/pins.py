@@ -711,4 +711,71 @@ def pin_cs_failures(orc):
         assert r.info == 0 and np.all(r.x == 0) and r.matvecs == 0
 
 
+# ------------------------------------------------------------ mixed precision
+
+def pin_mixed_matvec_c64_integer_exact(orc):
+    """complex64 product on small Gaussian integers: every partial sum is an
+    integer below 2^24, so the FP32 sums are exact."""
+    for n, seed in ((1, 0), (9, 1), (32, 2)):
+        A = inputs.gaussian_integer_matrix(n, seed, bound=16)
+        x = inputs.gaussian_integer_vector(n, seed + 7, bound=16)
+        want = exact_matvec_int(A, x)
+        got = orc.matvec_c64(A.astype(np.complex64), x.astype(np.complex64))
+        assert np.array_equal(got.astype(np.complex128), want), n
+
+
+def pin_mixed_solution(orc):
+    """FP64 refinement reaches the FP64 tolerance: true residual <= 1e-10 and
+    the LU solution within the conditioning bound."""
+    systems = [inputs.lattice_matrix(5), inputs.lattice_matrix(6),
+               inputs.dense_matrix(64, 12)]
+    rng = np.random.default_rng(48)
+    for A in systems:
+        y = inputs.cn01(rng, A.shape[0])
+        r = orc.bicgstab_mixed(A, y)
+        assert r.info == 0 and r.relres_true <= 1e-10 and r.outer <= 4
+        kappa = np.linalg.cond(A)
+        assert relerr(r.x, lu_solve(A, y)) <= 10 * kappa * 1e-10
+
+
+def pin_mixed_refinement_contracts(orc):
+    """Each refinement step multiplies the FP64 residual by about the inner
+    tolerance (plus kappa times the complex64 rounding of A): at most 1e-4
+    for tol_inner = 1e-5 and 1e-2 for 1e-3 on these well-conditioned
+    systems."""
+    A = inputs.lattice_matrix(6)
+    y = inputs.cn01(np.random.default_rng(49), A.shape[0])
+    for tin, bound in ((1e-5, 1e-4), (1e-3, 1e-2)):
+        r = orc.bicgstab_mixed(A, y, tol=1e-12, tol_inner=tin)
+        res = r.outer_res[:r.outer + 1]
+        assert r.info == 0 and len(res) >= 2
+        assert np.all(res[1:] <= bound * res[:-1]), res
+
+
+def pin_mixed_exact_float_system(orc):
+    """A and y exactly representable in complex64 (small integers): the first
+    step solves the very system A x = y in complex64, so the FP64 residual
+    after it is the inner tolerance up to complex64 rounding."""
+    A = inputs.gaussian_integer_matrix(24, 5, bound=4) + 40 * np.eye(24)
+    y = inputs.gaussian_integer_vector(24, 6, bound=8)
+    assert np.array_equal(A.astype(np.complex64).astype(np.complex128), A)
+    for tin in (1e-3, 1e-5):
+        r = orc.bicgstab_mixed(A, y, tol=1e-12, tol_inner=tin)
+        assert r.outer_res[1] <= 1.5 * tin, (tin, r.outer_res[:3])
+
+
+def pin_mixed_trivial(orc):
+    A = inputs.lattice_matrix(3)
+    y = inputs.cn01(np.random.default_rng(50), 27)
+    x0 = np.full(27, 1.0 + 1.0j)
+    ybad = y.copy()
+    ybad[4] = np.nan
+    r = orc.bicgstab_mixed(A, ybad, x0=x0)
+    assert r.info == 4 and np.array_equal(r.x, x0)
+    r = orc.bicgstab_mixed(A, np.zeros(27, dtype=np.complex128), x0=x0)
+    assert r.info == 0 and np.all(r.x == 0) and r.outer == 0
+    r = orc.bicgstab_mixed(A, y, maxit=0)
+    assert r.info == 1 and r.outer == 0 and r.relres_true == 1.0
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

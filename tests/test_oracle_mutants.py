@@ -13,14 +13,15 @@ import oracle
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (name, text in ccg_oracle.c, replacement, expected number of occurrences)
+# (name, text in ccg_oracle.c, replacement, expected number of occurrences;
+# a count above one plants the same mistake in every copy of the line)
 MUTANTS = [
     ("beta_drops_alpha_over_omega",
      "zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);",
-     "zc beta = zdiv(rho, rho_old);", 1),
+     "zc beta = zdiv(rho, rho_old);", 2),
     ("omega_conjugated",
      "omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);",
-     "omega = CMPLX(creal(ts) / tt, -cimag(ts) / tt);", 1),
+     "omega = CMPLX(creal(ts) / tt, -cimag(ts) / tt);", 2),
     ("p_update_sign",
      "p[i] = r[i] + beta * (p[i] - omega * v[i]);",
      "p[i] = r[i] + beta * (p[i] + omega * v[i]);", 1),
@@ -31,11 +32,12 @@ MUTANTS = [
     ("cgnr_beta_inverted",
      "double beta = gamma_new / gamma;", "double beta = gamma / gamma_new;", 1),
     ("matvec_transposed",
-     "s += A[i * lda + j] * x[j];", "s += A[j * lda + i] * x[j];", 1),
+     "s += A[i * lda + j] * x[j];\n        y[i] = s;\n    }\n}\n\n/* y = A^H x",
+     "s += A[j * lda + i] * x[j];\n        y[i] = s;\n    }\n}\n\n/* y = A^H x", 1),
     ("dot_unconjugated",
      "s += conj(a[i]) * b[i];", "s += a[i] * b[i];", 1),
     ("stop_test_not_squared",
-     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 5),
+     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 6),
     ("residual_sign",
      "rt[i] = y[i] - rt[i];", "rt[i] = y[i] + rt[i];", 1),
     ("division_without_conj",
@@ -77,6 +79,13 @@ MUTANTS = [
      "zc alpha = zdiv(rho, ww);", "zc alpha = zdiv(ww, rho);", 1),
     ("bilinear_form_conjugated",
      "s += a[i] * b[i];", "s += conj(a[i]) * b[i];", 1),
+    ("mixed_update_unscaled",
+     "x[i] = x[i] + nr * (zc)d32[i];", "x[i] = x[i] + (zc)d32[i];", 1),
+    ("mixed_residual_not_normalised",
+     "const double scale = 1.0 / nr;", "const double scale = 1.0;", 1),
+    ("c64_product_transposed",
+     "s += A[i * lda + j] * x[j];\n        y[i] = s;\n    }\n}\n\nstatic double norm2sq_c64",
+     "s += A[j * lda + i] * x[j];\n        y[i] = s;\n    }\n}\n\nstatic double norm2sq_c64", 1),
     ("cocr_r_update_wrong_vector",
      "r[i] = r[i] - alpha * w[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
      "r[i] = r[i] - alpha * u[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
