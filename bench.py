@@ -76,6 +76,11 @@ def parse():
                    help="skip the 26^3 mixed-precision leg")
     p.add_argument("--no-block", action="store_true",
                    help="skip the 64 right-hand-side block leg")
+    p.add_argument("--no-serve", action="store_true",
+                   help="skip the continuous-batching serving leg")
+    p.add_argument("--serve-requests", type=int, default=512)
+    p.add_argument("--serve-rate", type=float, default=None,
+                   help="Poisson arrival rate (requests/s) of the serving leg")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run a short mix of the kernels for rocprofv3 and exit")
     return p.parse_args()
@@ -245,6 +250,140 @@ def block_leg(A, A_h, steps):
                      "frac": flops / tg / 1e12 / FP64_PEAK_TFLOPS}}
 
 
+SERVE_SIZES = (512, 1024, 2048, 4096)
+SERVE_SEED = 2024
+SERVE_POOL_BYTES = 16 << 30
+
+
+def serve_inputs(nreq):
+    """Requests of the dense family (A = 4 I + G / sqrt(n), G iid CN(0,1);
+    X_true iid CN(0,1); Y = A X_true), n uniform over SERVE_SIZES and k
+    uniform over 1..8, drawn from SERVE_SEED; each request's matrices come
+    from its own seed on the device."""
+    import torch
+    rng = np.random.default_rng(SERVE_SEED)
+    ns = rng.choice(SERVE_SIZES, nreq)
+    ks = rng.integers(1, 9, nreq)
+    g = torch.Generator(device="cuda")
+    reqs = []
+    for i in range(nreq):
+        n, k = int(ns[i]), int(ks[i])
+        g.manual_seed(SERVE_SEED * 1000 + i)
+        A = torch.randn((n, n), dtype=torch.complex128, device="cuda", generator=g)
+        A /= float(np.sqrt(n))
+        A.diagonal().add_(4.0)
+        Xt = torch.randn((n, k), dtype=torch.complex128, device="cuda", generator=g)
+        Y = A @ Xt
+        X = torch.empty((n, k), dtype=torch.complex128, device="cuda")
+        reqs.append((A, Y, X))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def run_server(reqs, arrivals):
+    """Feed reqs to a server at the given arrival times (seconds from the
+    start); returns (makespan, latencies, results, stats)."""
+    from paper_1208_4869_amd import ccg
+    N = len(reqs)
+    lat = np.zeros(N)
+    results = [None] * N
+    index = {}
+    done = 0
+    i = 0
+    with ccg.Server(SERVE_POOL_BYTES, max_active=128) as srv:
+        t0 = time.perf_counter()
+        while done < N:
+            now = time.perf_counter() - t0
+            while i < N and arrivals[i] <= now:
+                A, Y, X = reqs[i]
+                index[srv.submit(A, Y, X, TOL, MAXIT)] = i
+                i += 1
+            act, q = srv.step()
+            while True:
+                t = srv.next_done()
+                if not t:
+                    break
+                j = index.pop(t)
+                results[j] = srv.poll(t)[1]
+                lat[j] = time.perf_counter() - t0 - arrivals[j]
+                done += 1
+            if act == 0 and q == 0 and i < N:
+                wait = arrivals[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+        makespan = time.perf_counter() - t0
+        stats = srv.stats()
+    return makespan, lat, results, stats
+
+
+def serve_leg(nreq, rate):
+    """Continuous batching: nreq requests, first all at once (capacity), then
+    with Poisson arrivals at `rate` requests/s (or 70% of the capacity when
+    rate is None); against the same requests solved one at a time with
+    ccg_bicgstab_block_ex."""
+    import torch
+
+    from paper_1208_4869_amd import ccg
+    t = time.time()
+    reqs = serve_inputs(nreq)
+    rhs = sum(Y.shape[1] for _, Y, _ in reqs)
+    log("built %d serving requests (%d right-hand sides, %.1f GB of A) in %.1fs" % (
+        nreq, rhs, sum(A.numel() * 16 for A, _, _ in reqs) / 1e9, time.time() - t))
+    # one at a time (warm the kernels first)
+    ref = []
+    A, Y, X = reqs[0]
+    ccg.ccg_bicgstab_block_ex(A, Y, X, TOL, MAXIT, flags=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A, Y, X in reqs:
+        ref.append(ccg.ccg_bicgstab_block_ex(A, Y, X, TOL, MAXIT, flags=1))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    X_ref = [X.clone() for _, _, X in reqs]
+    # capacity: everything arrives at t = 0
+    run_server(reqs[:8], np.zeros(8))  # warm-up
+    mk_c, lat_c, res_c, st_c = run_server(reqs, np.zeros(nreq))
+    cap = nreq / mk_c
+    if rate is None:
+        rate = 0.7 * cap
+    gaps = np.random.default_rng(SERVE_SEED + 1).exponential(1.0 / rate, nreq)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    mk_p, lat_p, res_p, st_p = run_server(reqs, arrivals)
+    # every request as alone: bitwise equal x and records
+    same = all(torch.equal(X, Xr) for (_, _, X), Xr in zip(reqs, X_ref))
+    same = same and all(
+        [(a.info, a.iters) for a in r] == [(b.info, b.iters) for b in rr]
+        for r, rr in zip(res_p, ref))
+    ok = all(a.info == 0 and a.relres_true <= TOL for r in res_p for a in r)
+    # algorithmic HBM bytes: one pass over A per product the slowest column
+    # of a request needs (the other columns share it)
+    a_bytes = sum(16.0 * A.shape[0] ** 2 * max(c.matvecs for c in r)
+                  for (A, _, _), r in zip(reqs, res_c))
+    log("serving: capacity %.0f req/s, Poisson %.0f req/s: p50 %.2f ms p99 %.2f ms; "
+        "one at a time %.0f req/s" % (cap, rate, np.percentile(lat_p, 50) * 1e3,
+                                      np.percentile(lat_p, 99) * 1e3, nreq / t_seq))
+    return {"workload": "%d requests, dense n in %s (A = 4I + G/sqrt(n)), k in 1..8, "
+                        "tol 1e-10, FP64" % (nreq, list(SERVE_SIZES)),
+            "rhs_total": rhs,
+            "capacity": {"requests_per_s": cap, "rhs_solves_per_s": rhs / mk_c,
+                         "a_bytes": a_bytes, "a_gbs": a_bytes / mk_c / 1e9,
+                         "hbm_frac": a_bytes / mk_c / 1e9 / HBM_PEAK_GBS,
+                         "makespan_s": mk_c, "ticks": st_c["ticks"],
+                         "peak_active": st_c["peak_active"],
+                         "admission_waits": st_c["admission_waits"],
+                         "p50_ms": float(np.percentile(lat_c, 50) * 1e3),
+                         "p99_ms": float(np.percentile(lat_c, 99) * 1e3)},
+            "poisson": {"rate_per_s": rate, "requests_per_s": nreq / mk_p,
+                        "rhs_solves_per_s": rhs / mk_p, "makespan_s": mk_p,
+                        "p50_ms": float(np.percentile(lat_p, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lat_p, 99) * 1e3),
+                        "ticks": st_p["ticks"], "peak_active": st_p["peak_active"]},
+            "one_at_a_time": {"requests_per_s": nreq / t_seq,
+                              "rhs_solves_per_s": rhs / t_seq},
+            "pool_bytes": SERVE_POOL_BYTES,
+            "all_converged": ok, "bitwise_equal_to_alone": bool(same)}
+
+
 def profile_kernels(A, y):
     """A short, fixed mix for rocprofv3: a device copy of known size (the
     reference for scaling the HBM byte counters), A x, A^H x, one BiCGSTAB and
@@ -386,6 +525,8 @@ def main():
         out["mixed"] = mixed_leg(max(args.steps // 3, 3))
     if not args.no_block:
         out["block"] = block_leg(A, A_h, max(args.steps // 3, 2))
+    if not args.no_serve:
+        out["serve"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (bounded sample, ~%.0f s)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(A_h, y_h, args.cpu_seconds)

@@ -273,6 +273,86 @@ int ccg_bicgstab_block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
                           double tol, int32_t maxit, uint32_t flags, void* work,
                           size_t work_bytes, ccg_result* res, void* stream);
 
+/*
+ * Serving: many independent block systems (the ccg_bicgstab_block problem,
+ * x0 = 0) solved by one server with continuous batching.  Each request is
+ * A (n x n), Y and X (n x k, row-major, 1 <= k <= 16), tol and maxit.
+ *
+ * The server owns a device pool (given by the caller, 256-byte aligned).  A
+ * request is admitted, in arrival order, when a slot is free (at most
+ * max_active at once) and its footprint (A, Y, X and the block-solver
+ * workspace, ccg_server_request_bytes) fits in the free pool; admission
+ * copies A and Y into the pool (hipMemcpyDefault: host or device sources)
+ * and runs the solver set-up.  Every ccg_server_step enqueues one iteration
+ * of every admitted request as one batch of kernels (the grid of each kernel
+ * covers all requests; each request keeps its own scalars, stop tests and
+ * reduction order), so a request's result is bit for bit the result of
+ * ccg_bicgstab_block_ex with CCG_X0_ZERO on the same inputs, alone or in any
+ * mix.  When all columns of a request have finished (or 2 maxit + 4
+ * iterations have been enqueued for it), X is copied to the caller's X and
+ * the request's pool memory is released.
+ *
+ * Sources A, Y and destination X must stay valid and unchanged until
+ * ccg_server_poll reports the request done.  A server is used from one host
+ * thread at a time; its work runs on `stream`.
+ */
+typedef struct ccg_server ccg_server;
+
+#define CCG_SERVER_REJECTED (-1000) /* footprint exceeds the whole pool */
+
+enum {
+    CCG_REQ_QUEUED = 0,  /* waiting for a slot or pool space */
+    CCG_REQ_RUNNING = 1, /* admitted; iterating or copying out */
+    CCG_REQ_DONE = 2     /* finished; res filled, ticket released */
+};
+
+typedef struct {
+    int64_t ticks;           /* batched iterations enqueued */
+    int64_t submitted, admitted, completed, rejected;
+    int64_t admission_waits; /* steps in which the queue head did not fit */
+    int32_t active, queued, peak_active, pad;
+    uint64_t pool_used, pool_peak; /* bytes of request footprints */
+} ccg_server_stats;
+
+/* Creates a server on the current device.  Arguments: 1 pool (device,
+ * 256-byte aligned), 2 pool_bytes, 3 max_active (1..128), 4 stream, 5 out.
+ * The pool stays the caller's: it must outlive the server. */
+int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active,
+                      void* stream, ccg_server** out);
+
+/* Waits for the server's stream and releases its host resources. */
+int ccg_server_destroy(ccg_server* srv);
+
+/* Bytes of pool a request of n rows and k right-hand sides occupies. */
+size_t ccg_server_request_bytes(int64_t n, int64_t k);
+
+/* Queues a request.  Arguments: 1 srv, 2 n, 3 k (1..16), 4 A, 5 lda, 6 Y,
+ * 7 ldy >= k, 8 X, 9 ldx >= k, 10 tol, 11 maxit, 12 ticket (out).
+ * Returns CCG_SERVER_REJECTED when the request could never fit the pool.
+ * n = 0 completes at once (info 0). */
+int ccg_server_submit(ccg_server* srv, int64_t n, int64_t k, const ccg_z* A,
+                      int64_t lda, const ccg_z* Y, int64_t ldy, ccg_z* X,
+                      int64_t ldx, double tol, int32_t maxit, int64_t* ticket);
+
+/* One scheduling step: completes finished copy-outs, admits from the queue,
+ * enqueues one batched iteration and reads the stop flags of the previous
+ * one.  Blocks at most for one iteration.  Arguments: 1 srv, 2 active and
+ * 3 queued (out, may be NULL). */
+int ccg_server_step(ccg_server* srv, int32_t* active, int32_t* queued);
+
+/* State of a request (CCG_REQ_*).  On CCG_REQ_DONE, res (host array of k)
+ * receives the per-column results and the ticket is released; polling it
+ * again returns -2.  Does not block. */
+int ccg_server_poll(ccg_server* srv, int64_t ticket, int32_t* state,
+                    ccg_result* res);
+
+/* Hands out the tickets of finished requests in the order they finished
+ * (ticket 0: none left); each is then read with ccg_server_poll.  Tickets
+ * already released by ccg_server_poll are skipped.  Does not block. */
+int ccg_server_next_done(ccg_server* srv, int64_t* ticket);
+
+int ccg_server_get_stats(const ccg_server* srv, ccg_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,8 @@ WS_COCG = 6
 WS_COCR = 7
 WS_BICGSTAB_MIXED = 8
 X0_ZERO = 1
+SERVER_REJECTED = -1000
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 INFO_TEXT = {0: "converged", 1: "iteration budget spent",
              2: "breakdown (rho/sigma or |Ap|/|A^H r| zero)",
@@ -50,6 +52,15 @@ class _MixedResult(ctypes.Structure):
                 ("inner_iters", ctypes.c_int32), ("matvecs64", ctypes.c_int32),
                 ("matvecs32", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("relres_true", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("submitted", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
+                ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("peak_active", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("pool_used", ctypes.c_uint64), ("pool_peak", ctypes.c_uint64)]
 
 
 @dataclass
@@ -115,6 +126,21 @@ def load() -> ctypes.CDLL:
     lib.ccg_bicgstab_block_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, D,
                                           I32, U32, P, S, ctypes.POINTER(_Result),
                                           P]
+    lib.ccg_server_create.argtypes = [P, S, I32, P, ctypes.POINTER(P)]
+    lib.ccg_server_destroy.argtypes = [P]
+    lib.ccg_server_request_bytes.argtypes = [I64, I64]
+    lib.ccg_server_request_bytes.restype = S
+    lib.ccg_server_submit.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, D, I32,
+                                      ctypes.POINTER(I64)]
+    lib.ccg_server_step.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.ccg_server_poll.argtypes = [P, I64, ctypes.POINTER(I32),
+                                    ctypes.POINTER(_Result)]
+    lib.ccg_server_get_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.ccg_server_next_done.argtypes = [P, ctypes.POINTER(I64)]
+    for name in ("ccg_server_create", "ccg_server_destroy", "ccg_server_submit",
+                 "ccg_server_step", "ccg_server_poll", "ccg_server_get_stats",
+                 "ccg_server_next_done"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("ccg_matvec", "ccg_matvec_ex", "ccg_bicgstab", "ccg_cgnr",
                  "ccg_bicgstab_ex", "ccg_cgnr_ex", "ccg_matmat", "ccg_matmat_ex",
                  "ccg_bicgstab_block", "ccg_bicgstab_block_ex", "ccg_cocg",
@@ -417,3 +443,120 @@ def ccg_bicgstab_block_ex(A, Y, X, tol=1e-10, maxit=1000, flags=0, work=None,
         "ccg_bicgstab_block_ex")
     return [Result(r.info, r.iters, r.matvecs, r.confirms, r.relres_rec,
                    r.relres_true) for r in list(res)[:k]]
+
+
+class Rejected(CcgError):
+    """The request's footprint exceeds the server's whole pool."""
+
+
+def ccg_server_request_bytes(n: int, k: int) -> int:
+    return int(load().ccg_server_request_bytes(n, k))
+
+
+def _serve_mat(M, rows, what, square=False):
+    torch = _torch()
+    if not isinstance(M, torch.Tensor) or M.dtype != torch.complex128 or \
+            M.dim() != 2 or M.shape[0] != rows or (square and M.shape[1] != rows):
+        raise TypeError("%s must be a complex128 tensor with %d rows" % (what, rows))
+    if M.numel() > 0 and M.stride(1) != 1:
+        raise TypeError("%s must be row-major (unit column stride)" % what)
+    return max(M.stride(0), M.shape[1], 1)
+
+
+class Server:
+    """Continuous-batching server of block BiCGSTAB requests (the
+    ccg_server_* entry points).  ``pool`` is a device uint8 tensor or a byte
+    count (then allocated here).  Tensors of a request may live on the device
+    or in host memory; the server keeps references to them until the request
+    is reported done."""
+
+    def __init__(self, pool, max_active=64, stream=None):
+        torch = _torch()
+        if isinstance(pool, int):
+            pool = torch.empty(pool, dtype=torch.uint8, device="cuda")
+        self.pool = pool
+        self._stream = _stream(stream)
+        h = ctypes.c_void_p()
+        _check(load().ccg_server_create(pool.data_ptr(), pool.numel(),
+                                        int(max_active), self._stream,
+                                        ctypes.byref(h)), "ccg_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, A, Y, X, tol=1e-10, maxit=1000) -> int:
+        n = A.shape[0] if hasattr(A, "shape") else 0
+        lda = _serve_mat(A, n, "A", square=True)
+        ldy = _serve_mat(Y, n, "Y")
+        ldx = _serve_mat(X, n, "X")
+        k = Y.shape[1]
+        if X.shape[1] != k:
+            raise TypeError("X must have as many columns as Y")
+        t = ctypes.c_int64(0)
+        rc = load().ccg_server_submit(self._h, n, k, A.data_ptr(), lda,
+                                      Y.data_ptr(), ldy, X.data_ptr(), ldx,
+                                      float(tol), int(maxit), ctypes.byref(t))
+        if rc == SERVER_REJECTED:
+            raise Rejected("request of n=%d, k=%d does not fit the pool" % (n, k))
+        _check(rc, "ccg_server_submit")
+        self._keep[t.value] = (A, Y, X, k)
+        return int(t.value)
+
+    def step(self):
+        a = ctypes.c_int32(0)
+        q = ctypes.c_int32(0)
+        _check(load().ccg_server_step(self._h, ctypes.byref(a), ctypes.byref(q)),
+               "ccg_server_step")
+        return int(a.value), int(q.value)
+
+    def poll(self, ticket):
+        """(state, results): results is the list of k Results once done."""
+        k = self._keep[ticket][3]
+        st = ctypes.c_int32(-1)
+        res = (_Result * k)()
+        _check(load().ccg_server_poll(self._h, ticket, ctypes.byref(st), res),
+               "ccg_server_poll")
+        if st.value != REQ_DONE:
+            return int(st.value), None
+        del self._keep[ticket]
+        return REQ_DONE, [Result(r.info, r.iters, r.matvecs, r.confirms,
+                                 r.relres_rec, r.relres_true) for r in res]
+
+    def next_done(self) -> int:
+        """Ticket of a finished request not handed out before, or 0."""
+        t = ctypes.c_int64(0)
+        _check(load().ccg_server_next_done(self._h, ctypes.byref(t)),
+               "ccg_server_next_done")
+        return int(t.value)
+
+    def stats(self) -> dict:
+        o = _ServerStats()
+        _check(load().ccg_server_get_stats(self._h, ctypes.byref(o)),
+               "ccg_server_get_stats")
+        return {f: int(getattr(o, f)) for f, _ in o._fields_ if f != "pad"}
+
+    def run_all(self, tickets):
+        """Step until every ticket is done; returns {ticket: results}.
+        Finished tickets outside ``tickets`` are handed out and dropped."""
+        out = {}
+        left = set(tickets)
+        while left:
+            self.step()
+            while True:
+                t = self.next_done()
+                if not t:
+                    break
+                if t in left:
+                    out[t] = self.poll(t)[1]
+                    left.discard(t)
+        return out
+
+    def close(self):
+        if self._h:
+            _check(load().ccg_server_destroy(self._h), "ccg_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -30,6 +30,11 @@
 
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <unordered_map>
+#include <utility>
+#include <vector>
 
 #include "../../include/ccg.h"
 #include "ccg_device.h"
@@ -66,9 +71,9 @@ static inline int kslice_of(int64_t n)
 constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
 
 template <int NT>
-__global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int64_t lda, int n,
-                                                  const d2* __restrict__ B, int64_t ldb,
-                                                  int ncols, d2* __restrict__ Zp, int kslice)
+__device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda, int n,
+                                           const d2* __restrict__ B, int64_t ldb, int ncols,
+                                           d2* __restrict__ Zp, int kslice, int bid)
 {
     constexpr int AP = kKS + 1;                       // padded A-tile row (LDS banks)
     constexpr int AE = kRowsPerBlock * kKS / kBlock;  // A elements per thread
@@ -77,8 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int6
     constexpr int BPT = (BN + kBlock - 1) / kBlock;   // B elements per thread
     __shared__ d2 As[2][kRowsPerBlock * AP];
     __shared__ d2 Bs[2][BN];
-    const int s = blockIdx.x % kSlices;
-    const int rb = blockIdx.x / kSlices;
+    const int s = bid % kSlices;
+    const int rb = bid / kSlices;
     const int t = threadIdx.x;
     const int lane = t & (kWave - 1);
     const int w = t / kWave;
@@ -168,6 +173,14 @@ __global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int6
     }
 }
 
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int64_t lda, int n,
+                                                  const d2* __restrict__ B, int64_t ldb,
+                                                  int ncols, d2* __restrict__ Zp, int kslice)
+{
+    zgemm_body<NT>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+}
+
 // Z[i][c] = sum over slices s (in order) of Zp[s][i][c]
 __device__ __forceinline__ d2 slice_sum(const d2* __restrict__ Zp, int64_t n, int ncols,
                                         int64_t i, int c)
@@ -244,15 +257,17 @@ __device__ __forceinline__ SolverState& col_state(const BArgs& a, int j)
 }
 
 // Element loop of the column-wise kernels: every thread keeps one column
-// (kp divides the block size), rows advance by gridDim.x * kBlock / kp.
+// (kp divides the block size), rows advance by nblk * kBlock / kp.  bid and
+// nblk are the block's index and the block count of the system it works on
+// (the grid itself, or the system's share of a batched grid).
 #define COL_LOOP(a)                                                              \
     const int j = threadIdx.x & ((a).kp - 1);                                    \
     const int64_t total = (int64_t)(a).n * (a).kp;                               \
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;      \
-         e += (int64_t)gridDim.x * kBlock)
+    for (int64_t e = (int64_t)bid * kBlock + threadIdx.x; e < total;             \
+         e += (int64_t)nblk * kBlock)
 
 // Per-block column partials: threads of the same column add in thread order.
-__device__ __forceinline__ void col_partials(const BArgs& a, d2 v0, d2 v1)
+__device__ __forceinline__ void col_partials(const BArgs& a, int bid, d2 v0, d2 v1)
 {
     __shared__ d2 l0[kBlock], l1[kBlock];
     l0[threadIdx.x] = v0;
@@ -265,8 +280,8 @@ __device__ __forceinline__ void col_partials(const BArgs& a, d2 v0, d2 v1)
             s0 += l0[m];
             s1 += l1[m];
         }
-        a.cpart[((size_t)blockIdx.x * a.kp + t) * 2] = s0;
-        a.cpart[((size_t)blockIdx.x * a.kp + t) * 2 + 1] = s1;
+        a.cpart[((size_t)bid * a.kp + t) * 2] = s0;
+        a.cpart[((size_t)bid * a.kp + t) * 2 + 1] = s1;
     }
 }
 
@@ -294,9 +309,10 @@ __global__ void kb_init(BArgs a, int maxit, double tol2)
 
 // Column step: finish the column reductions of the previous kernel (nparts
 // blocks) and apply the scalar step of `stage` to every column that has one.
-// With ring_slot, also report whether every column has finished.
-__global__ __launch_bounds__(kStepThreads) void kb_step(BArgs a, int stage, int nparts,
-                                                       int* ring_slot)
+// With ring_slot (pinned host word) and/or dev_flag (device word), also
+// report whether every column has finished.
+__device__ __forceinline__ void kb_step_body(const BArgs& a, int stage, int nparts,
+                                             int* ring_slot, int* dev_flag = nullptr)
 {
     constexpr int G = kStepThreads / kMaxCols;  // threads per column
     __shared__ d2 g0[G][kMaxCols], g1[G][kMaxCols];
@@ -357,18 +373,20 @@ __global__ __launch_bounds__(kStepThreads) void kb_step(BArgs a, int stage, int 
         }
         done[j] = L.phase == PH_DONE;
     }
-    if (ring_slot) {
+    if (ring_slot || dev_flag) {
         __syncthreads();
         if (threadIdx.x == 0) {
             int all = 1;
             for (int c = 0; c < a.kp; ++c) all &= done[c];
-            __hip_atomic_store(ring_slot, all ? (int)PH_DONE : (int)PH_RUN, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ring_slot)
+                __hip_atomic_store(ring_slot, all ? (int)PH_DONE : (int)PH_RUN, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            if (dev_flag) *dev_flag = all;
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_normy(BArgs a)
+__device__ __forceinline__ void kb_normy_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -378,11 +396,11 @@ __global__ __launch_bounds__(kBlock) void kb_normy(BArgs a)
             v0.x += cabs2(a.Y[i * a.ldy + j]);
         }
     }
-    col_partials(a, v0, d2{0.0, 0.0});
+    col_partials(a, bid, v0, d2{0.0, 0.0});
 }
 
 // x0 = 0: x = 0, r = r^ = y
-__global__ __launch_bounds__(kBlock) void kb_setup0(BArgs a)
+__device__ __forceinline__ void kb_setup0_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -399,11 +417,11 @@ __global__ __launch_bounds__(kBlock) void kb_setup0(BArgs a)
             }
         }
     }
-    col_partials(a, v0, d2{0.0, 0.0});
+    col_partials(a, bid, v0, d2{0.0, 0.0});
 }
 
 // general x0: B = x (x = 0 for y = 0 columns)
-__global__ __launch_bounds__(kBlock) void kb_setx(BArgs a)
+__device__ __forceinline__ void kb_setx_body(const BArgs& a, int bid, int nblk)
 {
     COL_LOOP(a)
     {
@@ -417,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void kb_setx(BArgs a)
 }
 
 // r = r^ = y - (A x), ||r||^2
-__global__ __launch_bounds__(kBlock) void kb_red_setup(BArgs a)
+__device__ __forceinline__ void kb_red_setup_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -430,12 +448,12 @@ __global__ __launch_bounds__(kBlock) void kb_red_setup(BArgs a)
             v0.x += cabs2(ri);
         }
     }
-    col_partials(a, v0, d2{0.0, 0.0});
+    col_partials(a, bid, v0, d2{0.0, 0.0});
 }
 
 // p = r or r + beta (p - omega v); the product input B is p, or x for a
 // column that confirms, or 0.
-__global__ __launch_bounds__(kBlock) void kb_p(BArgs a)
+__device__ __forceinline__ void kb_p_body(const BArgs& a, int bid, int nblk)
 {
     COL_LOOP(a)
     {
@@ -464,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void kb_p(BArgs a)
 
 // after the first product: v = A p (+ r^H v, ||v||^2), or the confirming
 // residual r = r^ = y - A x (+ ||r||^2)
-__global__ __launch_bounds__(kBlock) void kb_red1(BArgs a)
+__device__ __forceinline__ void kb_red1_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -485,11 +503,11 @@ __global__ __launch_bounds__(kBlock) void kb_red1(BArgs a)
             }
         }
     }
-    col_partials(a, v0, v1);
+    col_partials(a, bid, v0, v1);
 }
 
 // s = r - alpha v, ||s||^2
-__global__ __launch_bounds__(kBlock) void kb_s(BArgs a)
+__device__ __forceinline__ void kb_s_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -503,11 +521,11 @@ __global__ __launch_bounds__(kBlock) void kb_s(BArgs a)
         }
         a.S[e] = si;
     }
-    col_partials(a, v0, d2{0.0, 0.0});
+    col_partials(a, bid, v0, d2{0.0, 0.0});
 }
 
 // after the second product: t = A s (+ t^H s, ||t||^2)
-__global__ __launch_bounds__(kBlock) void kb_red2(BArgs a)
+__device__ __forceinline__ void kb_red2_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -520,12 +538,12 @@ __global__ __launch_bounds__(kBlock) void kb_red2(BArgs a)
             v1.x += cabs2(z);
         }
     }
-    col_partials(a, v0, v1);
+    col_partials(a, bid, v0, v1);
 }
 
 // x += alpha p + omega s, r = s - omega t (+ ||r||^2, r^H r); after a
 // half-step exit x += alpha p.  Finished columns are not touched.
-__global__ __launch_bounds__(kBlock) void kb_xr(BArgs a)
+__device__ __forceinline__ void kb_xr_body(const BArgs& a, int bid, int nblk)
 {
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     COL_LOOP(a)
@@ -548,8 +566,24 @@ __global__ __launch_bounds__(kBlock) void kb_xr(BArgs a)
             *xp = xi;
         }
     }
-    col_partials(a, v0, v1);
+    col_partials(a, bid, v0, v1);
 }
+
+// One system per grid.
+__global__ __launch_bounds__(kStepThreads) void kb_step(BArgs a, int stage, int nparts,
+                                                       int* ring_slot)
+{
+    kb_step_body(a, stage, nparts, ring_slot);
+}
+__global__ __launch_bounds__(kBlock) void kb_normy(BArgs a) { kb_normy_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_setup0(BArgs a) { kb_setup0_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_setx(BArgs a) { kb_setx_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_red_setup(BArgs a) { kb_red_setup_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_p(BArgs a) { kb_p_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_red1(BArgs a) { kb_red1_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_s(BArgs a) { kb_s_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_red2(BArgs a) { kb_red2_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void kb_xr(BArgs a) { kb_xr_body(a, blockIdx.x, gridDim.x); }
 
 // ----------------------------------------------------------------- host
 
@@ -703,6 +737,454 @@ static int block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const ccg
 
 }  // namespace ccg
 
+
+namespace ccg {
+
+// --------------------------------------------------------------- serving
+//
+// Continuous batching of independent block systems.  Every admitted request
+// has a record in a device table; each kernel of a batched iteration runs one
+// grid over all records: block b finds its record by a binary search over the
+// records' first block indices and runs the block solver's body with its
+// index within the record's share.  The block partition, reduction order and
+// product slices of a request are those of the same request solved alone,
+// whatever else is in the batch.  Product shares start at multiples of 8, so
+// the slice of a product block is still the XCD it runs on.
+
+constexpr int kServeCols = 16;  // one 16-wide product tile per request
+constexpr int kMaxActive = 128;
+
+struct SlotRec {
+    BArgs a;
+    int c0, gC;  // column-kernel blocks [c0, c0 + gC) of the batched grid
+    int g0, gG;  // product blocks [g0, g0 + gG)
+    int kslice;
+    int slot;    // index of the request's done word
+};
+
+__device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, int b, bool prod)
+{
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int start = prod ? tab[mid].g0 : tab[mid].c0;
+        if (start <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// A request whose columns have all finished (done word set by the last
+// column step) is skipped by every later batched kernel.
+#define SERVE_COL_KERNEL(name)                                                        \
+    __global__ __launch_bounds__(kBlock) void kv_##name(                              \
+        const SlotRec* __restrict__ tab, int m, const int* __restrict__ sdone)        \
+    {                                                                                 \
+        const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, false)];                  \
+        if (sdone[r.slot]) return;                                                    \
+        const BArgs a = r.a;                                                          \
+        kb_##name##_body(a, blockIdx.x - r.c0, r.gC);                                 \
+    }
+SERVE_COL_KERNEL(p)
+SERVE_COL_KERNEL(red1)
+SERVE_COL_KERNEL(s)
+SERVE_COL_KERNEL(red2)
+SERVE_COL_KERNEL(xr)
+#undef SERVE_COL_KERNEL
+
+__global__ __launch_bounds__(kBlock) void kv_gemm(const SlotRec* __restrict__ tab, int m,
+                                                  const int* __restrict__ sdone, int use_s)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
+    if (sdone[r.slot]) return;
+    const BArgs a = r.a;
+    zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
+                  blockIdx.x - r.g0);
+}
+
+// One block per record.  With ring (pinned, one word per slot), the step also
+// reports the request's all-done state to the host and to the done word.
+__global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restrict__ tab,
+                                                        int* sdone, int stage, int* ring)
+{
+    const SlotRec& r = tab[blockIdx.x];
+    if (sdone[r.slot]) return;
+    const BArgs a = r.a;
+    kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
+}
+
+__global__ void kv_clear(int* sdone, int slot)
+{
+    if (threadIdx.x == 0) sdone[slot] = 0;
+}
+
+// First-fit allocator over the pool (offsets and sizes are multiples of 256).
+class PoolAlloc {
+    std::map<size_t, size_t> free_;  // offset -> bytes
+public:
+    void init(size_t off, size_t bytes)
+    {
+        free_.clear();
+        if (bytes) free_[off] = bytes;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t o = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[o + bytes] = rest;
+            *off = o;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && off + bytes == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct ServeReq {
+    int64_t ticket = 0;
+    int64_t n = 0;
+    int k = 0;
+    const d2* A = nullptr;
+    int64_t lda = 0;
+    const d2* Y = nullptr;
+    int64_t ldy = 0;
+    d2* X = nullptr;
+    int64_t ldx = 0;
+    double tol = 0.0;
+    int32_t maxit = 0;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    int state = CCG_REQ_QUEUED;
+    bool retiring = false;      // copy-out enqueued
+    int64_t ticks = 0, max_ticks = 0, last_tick = -1;
+    SlotRec rec{};
+    std::vector<ccg_result> res;
+};
+
+// Pool bytes of one request: A, Y, X and the block-solver workspace.
+static size_t serve_bytes(int64_t n, int k)
+{
+    return align256((size_t)n * n * sizeof(d2)) + 2 * align256((size_t)n * k * sizeof(d2)) +
+           block_layout(n, k).total;
+}
+
+}  // namespace ccg
+
+struct ccg_server {
+    int device = 0;
+    hipStream_t s = nullptr;
+    char* pool = nullptr;
+    size_t pool_bytes = 0, head = 0;
+    int max_active = 0;
+    int* sdone_d = nullptr;
+    ccg::SlotRec* tab_d = nullptr;
+    ccg::PoolAlloc alloc;
+    std::deque<ccg::ServeReq*> queue;
+    std::deque<int64_t> finished;  // done tickets not yet handed out by next_done
+    std::unordered_map<int64_t, ccg::ServeReq*> reqs;
+    ccg::ServeReq* slots[ccg::kMaxActive] = {};
+    int64_t next_ticket = 1;
+    // batched iterations: pinned done words [kRing][kMaxActive], one event each
+    int* ring_h = nullptr;
+    int* ring_d = nullptr;
+    hipEvent_t tick_ev[ccg::kRing] = {};
+    std::vector<std::pair<int, int64_t>> members[ccg::kRing];  // (slot, ticket)
+    int64_t tick = 0, seen = 0;
+    // table uploads: pinned staging [kRing][kMaxActive]
+    ccg::SlotRec* stage_h = nullptr;
+    hipEvent_t stage_ev[ccg::kRing] = {};
+    bool stage_pending[ccg::kRing] = {};
+    int stage_next = 0;
+    std::vector<std::pair<int, int64_t>> table;  // (slot, ticket) of the device table
+    int tot_c = 0, tot_g = 0;
+    // copy-out: pinned column records [kMaxActive][kServeCols]
+    char* res_h = nullptr;
+    hipEvent_t slot_ev[ccg::kMaxActive] = {};
+    ccg_server_stats st{};
+};
+
+namespace ccg {
+
+static int serve_admit(ccg_server* S, ServeReq* r, int slot)
+{
+    const int64_t n = r->n;
+    const int k = r->k;
+    hipStream_t s = S->s;
+    char* base = S->pool + r->off;
+    size_t o = 0;
+    d2* A = (d2*)(base + o);
+    o += align256((size_t)n * n * sizeof(d2));
+    d2* Y = (d2*)(base + o);
+    o += align256((size_t)n * k * sizeof(d2));
+    d2* X = (d2*)(base + o);
+    o += align256((size_t)n * k * sizeof(d2));
+    char* w = base + o;
+    const BLayout L = block_layout(n, k);
+    BArgs a{};
+    a.A = A;
+    a.lda = n;
+    a.n = (int)n;
+    a.k = k;
+    a.kp = pow2_at_least(k);
+    a.Y = Y;
+    a.ldy = k;
+    a.X = X;
+    a.ldx = k;
+    d2* m[7];
+    for (int q = 0; q < 7; ++q) m[q] = (d2*)(w + L.mats + q * L.mat_bytes);
+    a.R = m[0]; a.RH = m[1]; a.P = m[2]; a.V = m[3]; a.S = m[4]; a.T = m[5]; a.B = m[6];
+    a.Zp = (d2*)(w + L.zp);
+    a.cpart = (d2*)(w + L.cpart);
+    a.cst = (SolverState*)(w + L.cst);
+    const size_t row = (size_t)k * sizeof(d2);
+    hipError_t e;
+    if ((e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
+                              hipMemcpyDefault, s)) != hipSuccess)
+        return (int)e;
+    if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
+        hipSuccess)
+        return (int)e;
+    // x keeps the caller's values in columns the solver never writes
+    if ((e = hipMemcpy2DAsync(X, row, r->X, r->ldx * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
+        hipSuccess)
+        return (int)e;
+    const int gC = col_blocks(n, a.kp);
+    kv_clear<<<1, kWave, 0, s>>>(S->sdone_d, slot);
+    kb_init<<<1, kMaxCols, 0, s>>>(a, r->maxit, r->tol * r->tol);
+    kb_normy<<<gC, kBlock, 0, s>>>(a);
+    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
+    kb_setup0<<<gC, kBlock, 0, s>>>(a);
+    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    r->rec.a = a;
+    r->rec.gC = gC;
+    r->rec.gG = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
+    r->rec.kslice = kslice_of(n);
+    r->rec.slot = slot;
+    r->slot = slot;
+    r->state = CCG_REQ_RUNNING;
+    r->ticks = 0;
+    r->max_ticks = 2 * (int64_t)r->maxit + 4;
+    S->slots[slot] = r;
+    S->st.admitted++;
+    S->st.pool_used += r->bytes;
+    if (S->st.pool_used > S->st.pool_peak) S->st.pool_peak = S->st.pool_used;
+    return 0;
+}
+
+// Enqueue the copy-out of a request whose columns have finished.
+static int serve_retire(ccg_server* S, ServeReq* r)
+{
+    hipStream_t s = S->s;
+    const size_t row = (size_t)r->k * sizeof(d2);
+    hipError_t e;
+    if ((e = hipMemcpy2DAsync(r->X, r->ldx * sizeof(d2), r->rec.a.X, row, row, r->n,
+                              hipMemcpyDefault, s)) != hipSuccess)
+        return (int)e;
+    char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
+    if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return (int)e;
+    if ((e = hipEventRecord(S->slot_ev[r->slot], s)) != hipSuccess) return (int)e;
+    r->retiring = true;
+    return 0;
+}
+
+// Finish the requests whose copy-out has completed (wait: block on them).
+static int serve_collect(ccg_server* S, bool wait)
+{
+    for (int q = 0; q < S->max_active; ++q) {
+        ServeReq* r = S->slots[q];
+        if (!r || !r->retiring) continue;
+        hipError_t e = wait ? hipEventSynchronize(S->slot_ev[q]) : hipEventQuery(S->slot_ev[q]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return (int)e;
+        const char* src = S->res_h + (size_t)q * kServeCols * kStateStride;
+        r->res.resize(r->k);
+        for (int j = 0; j < r->k; ++j) {
+            const SolverState& c = *(const SolverState*)(src + (size_t)j * kStateStride);
+            ccg_result& o = r->res[j];
+            o.info = c.phase == PH_DONE ? c.info : 1;
+            o.iters = c.iters;
+            o.matvecs = c.matvecs;
+            o.confirms = c.confirms;
+            o.relres_rec = c.relres_rec;
+            o.relres_true = c.relres_true;
+        }
+        r->state = CCG_REQ_DONE;
+        r->retiring = false;
+        S->finished.push_back(r->ticket);
+        S->alloc.release(r->off, r->bytes);
+        S->st.pool_used -= r->bytes;
+        S->st.completed++;
+        S->slots[q] = nullptr;
+    }
+    return 0;
+}
+
+// Read the done words of tick `seen` (waiting for it) and retire what ended.
+static int serve_read_tick(ccg_server* S)
+{
+    const int u = (int)(S->seen % kRing);
+    hipError_t e = hipEventSynchronize(S->tick_ev[u]);
+    if (e != hipSuccess) return (int)e;
+    for (const auto& mt : S->members[u]) {
+        ServeReq* r = S->slots[mt.first];
+        if (!r || r->ticket != mt.second || r->retiring || r->state != CCG_REQ_RUNNING) continue;
+        const int w = __atomic_load_n(&S->ring_h[u * kMaxActive + mt.first], __ATOMIC_ACQUIRE);
+        const bool out_of_budget = r->ticks >= r->max_ticks && r->last_tick == S->seen;
+        if (w == PH_DONE || out_of_budget) {
+            int rc = serve_retire(S, r);
+            if (rc) return rc;
+        }
+    }
+    S->members[u].clear();
+    S->seen++;
+    return 0;
+}
+
+static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, int64_t>>& want)
+{
+    const int u = S->stage_next;
+    S->stage_next = (S->stage_next + 1) % kRing;
+    if (S->stage_pending[u]) {
+        hipError_t e = hipEventSynchronize(S->stage_ev[u]);
+        if (e != hipSuccess) return (int)e;
+        S->stage_pending[u] = false;
+    }
+    SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
+    int c = 0, g = 0;
+    for (size_t i = 0; i < want.size(); ++i) {
+        SlotRec rec = S->slots[want[i].first]->rec;
+        rec.c0 = c;
+        rec.g0 = g;
+        c += rec.gC;
+        g += rec.gG;
+        h[i] = rec;
+    }
+    S->tot_c = c;
+    S->tot_g = g;
+    S->table = want;
+    if (want.empty()) return 0;
+    hipError_t e = hipMemcpyAsync(S->tab_d, h, want.size() * sizeof(SlotRec),
+                                  hipMemcpyHostToDevice, S->s);
+    if (e != hipSuccess) return (int)e;
+    if ((e = hipEventRecord(S->stage_ev[u], S->s)) != hipSuccess) return (int)e;
+    S->stage_pending[u] = true;
+    return 0;
+}
+
+static bool serve_iterating(const ServeReq* r)
+{
+    return r && r->state == CCG_REQ_RUNNING && !r->retiring && r->ticks < r->max_ticks;
+}
+
+// Admission in arrival order while a slot is free and the head fits the pool.
+static int serve_admit_queue(ccg_server* S)
+{
+    while (!S->queue.empty()) {
+        int slot = -1;
+        for (int q = 0; q < S->max_active && slot < 0; ++q)
+            if (!S->slots[q]) slot = q;
+        if (slot < 0) break;
+        ServeReq* r = S->queue.front();
+        size_t off = 0;
+        if (!S->alloc.alloc(r->bytes, &off)) {
+            // the head waits until retirements free enough of the pool
+            S->st.admission_waits++;
+            break;
+        }
+        r->off = off;
+        S->queue.pop_front();
+        int rc = serve_admit(S, r, slot);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+static int serve_step(ccg_server* S)
+{
+    int rc;
+    hipError_t e;
+    // 1. finished copy-outs free their slots and pool blocks; admit
+    if ((rc = serve_collect(S, false))) return rc;
+    if ((rc = serve_admit_queue(S))) return rc;
+    // 2. the table of this iteration: admitted requests still iterating (a
+    //    slot may hold another request than in the last table: compare tickets)
+    std::vector<std::pair<int, int64_t>> want;
+    for (int q = 0; q < S->max_active; ++q)
+        if (serve_iterating(S->slots[q])) want.emplace_back(q, S->slots[q]->ticket);
+    if (want != S->table && (rc = serve_upload_table(S, want))) return rc;
+    // 3. one batched iteration
+    if (!want.empty()) {
+        while (S->seen + kRing <= S->tick)
+            if ((rc = serve_read_tick(S))) return rc;
+        const int u = (int)(S->tick % kRing);
+        const int m = (int)want.size();
+        hipStream_t s = S->s;
+        const SlotRec* tab = S->tab_d;
+        kv_p<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
+        kv_red1<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_P1, nullptr);
+        kv_s<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_S, nullptr);
+        kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
+        kv_red2<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_T, nullptr);
+        kv_xr<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_XR,
+                                           S->ring_d + (size_t)u * kMaxActive);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if ((e = hipEventRecord(S->tick_ev[u], s)) != hipSuccess) return (int)e;
+        S->members[u] = want;
+        for (const auto& w : want) {
+            ServeReq* r = S->slots[w.first];
+            r->ticks++;
+            r->last_tick = S->tick;
+        }
+        S->tick++;
+        S->st.ticks++;
+    }
+    // 4. read the stop flags one iteration behind (all of them when idle) and
+    //    enqueue the copy-out of what has finished
+    const int64_t behind = want.empty() ? 0 : 1;
+    while (S->seen + behind < S->tick)
+        if ((rc = serve_read_tick(S))) return rc;
+    // 5. with nothing left iterating, wait for the copy-outs
+    bool iterating = false;
+    for (int q = 0; q < S->max_active; ++q) iterating = iterating || serve_iterating(S->slots[q]);
+    if (!iterating && (rc = serve_collect(S, true))) return rc;
+    int act = 0;
+    for (int q = 0; q < S->max_active; ++q)
+        if (S->slots[q]) act++;
+    S->st.active = act;
+    S->st.queued = (int32_t)S->queue.size();
+    if (act > S->st.peak_active) S->st.peak_active = act;
+    return 0;
+}
+
+}  // namespace ccg
+
 // ============================================================== C ABI
 
 namespace ccg {
@@ -809,6 +1291,185 @@ int ccg_bicgstab_block(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const 
     if (rc != 0) return rc;
     if (e != hipSuccess) return (int)e;
     for (int64_t j = 0; j < k; ++j) info[j] = res[(size_t)j].info;
+    return 0;
+}
+
+
+// ------------------------------------------------------------- serving ABI
+
+size_t ccg_server_request_bytes(int64_t n, int64_t k)
+{
+    if (n < 0 || n > ccg::kMaxNB || k < 1 || k > ccg::kServeCols) return 0;
+    return n == 0 ? 0 : ccg::serve_bytes(n, (int)k);
+}
+
+int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* stream,
+                      ccg_server** out)
+{
+    using namespace ccg;
+    if (!pool || ((uintptr_t)pool & 255)) return -1;
+    const size_t head = align256(kMaxActive * sizeof(int)) + align256(kMaxActive * sizeof(SlotRec));
+    if (pool_bytes < head) return -2;
+    if (max_active < 1 || max_active > kMaxActive) return -3;
+    if (!out) return -5;
+    *out = nullptr;
+    ccg_server* S = new ccg_server;
+    hipError_t e = hipGetDevice(&S->device);
+    S->s = (hipStream_t)stream;
+    S->pool = (char*)pool;
+    S->pool_bytes = pool_bytes;
+    S->head = head;
+    S->max_active = max_active;
+    S->sdone_d = (int*)pool;
+    S->tab_d = (SlotRec*)((char*)pool + align256(kMaxActive * sizeof(int)));
+    S->alloc.init(head, (pool_bytes - head) & ~(size_t)255);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&S->ring_h, (size_t)kRing * kMaxActive * sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&S->ring_d, S->ring_h, 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&S->stage_h, (size_t)kRing * kMaxActive * sizeof(SlotRec),
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&S->res_h, (size_t)kMaxActive * kServeCols * kStateStride,
+                          hipHostMallocDefault);
+    for (int q = 0; q < kRing && e == hipSuccess; ++q) {
+        e = hipEventCreateWithFlags(&S->tick_ev[q], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S->stage_ev[q], hipEventDisableTiming);
+    }
+    for (int q = 0; q < kMaxActive && e == hipSuccess; ++q)
+        e = hipEventCreateWithFlags(&S->slot_ev[q], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        ccg_server_destroy(S);
+        return (int)e;
+    }
+    *out = S;
+    return 0;
+}
+
+int ccg_server_destroy(ccg_server* S)
+{
+    if (!S) return -1;
+    hipError_t e = hipStreamSynchronize(S->s);
+    for (auto& kv : S->reqs) delete kv.second;
+    auto keep = [&e](hipError_t e2) {
+        if (e == hipSuccess) e = e2;
+    };
+    for (int q = 0; q < ccg::kRing; ++q) {
+        if (S->tick_ev[q]) keep(hipEventDestroy(S->tick_ev[q]));
+        if (S->stage_ev[q]) keep(hipEventDestroy(S->stage_ev[q]));
+    }
+    for (int q = 0; q < ccg::kMaxActive; ++q)
+        if (S->slot_ev[q]) keep(hipEventDestroy(S->slot_ev[q]));
+    if (S->ring_h) keep(hipHostFree(S->ring_h));
+    if (S->stage_h) keep(hipHostFree(S->stage_h));
+    if (S->res_h) keep(hipHostFree(S->res_h));
+    delete S;
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                      const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx, double tol,
+                      int32_t maxit, int64_t* ticket)
+{
+    using namespace ccg;
+    if (!S) return -1;
+    if (n < 0 || n > kMaxNB) return -2;
+    if (k < 1 || k > kServeCols) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && !Y) return -6;
+    if (ldy < k) return -7;
+    if (n > 0 && !X) return -8;
+    if (ldx < k) return -9;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return -10;
+    if (maxit < 0) return -11;
+    if (!ticket) return -12;
+    const size_t bytes = n > 0 ? serve_bytes(n, (int)k) : 0;
+    if (bytes > S->pool_bytes - S->head) {
+        S->st.rejected++;
+        return CCG_SERVER_REJECTED;
+    }
+    ServeReq* r = new ServeReq;
+    r->ticket = S->next_ticket++;
+    r->n = n;
+    r->k = (int)k;
+    r->A = (const d2*)A;
+    r->lda = lda;
+    r->Y = (const d2*)Y;
+    r->ldy = ldy;
+    r->X = (d2*)X;
+    r->ldx = ldx;
+    r->tol = tol;
+    r->maxit = maxit;
+    r->bytes = bytes;
+    S->reqs[r->ticket] = r;
+    S->st.submitted++;
+    if (n == 0) {
+        r->state = CCG_REQ_DONE;
+        r->res.assign((size_t)k, ccg_result{});
+        for (auto& o : r->res) o.relres_rec = o.relres_true = 0.0;
+        S->finished.push_back(r->ticket);
+        S->st.completed++;
+    } else {
+        S->queue.push_back(r);
+        S->st.queued = (int32_t)S->queue.size();
+    }
+    *ticket = r->ticket;
+    return 0;
+}
+
+int ccg_server_step(ccg_server* S, int32_t* active, int32_t* queued)
+{
+    if (!S) return -1;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev != S->device) return -1;
+    int rc = ccg::serve_step(S);
+    if (active) *active = S->st.active;
+    if (queued) *queued = S->st.queued;
+    return rc;
+}
+
+int ccg_server_poll(ccg_server* S, int64_t ticket, int32_t* state, ccg_result* res)
+{
+    if (!S) return -1;
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return -2;
+    if (!state) return -3;
+    ccg::ServeReq* r = it->second;
+    if (r->state == CCG_REQ_DONE && !res) return -4;
+    *state = r->state;
+    if (r->state == CCG_REQ_DONE) {
+        for (int j = 0; j < r->k; ++j) res[j] = r->res[(size_t)j];
+        S->reqs.erase(it);
+        delete r;
+    }
+    return 0;
+}
+
+int ccg_server_next_done(ccg_server* S, int64_t* ticket)
+{
+    if (!S) return -1;
+    if (!ticket) return -2;
+    *ticket = 0;
+    while (!S->finished.empty()) {
+        const int64_t t = S->finished.front();
+        S->finished.pop_front();
+        if (S->reqs.count(t)) {  // not released by an earlier poll
+            *ticket = t;
+            break;
+        }
+    }
+    return 0;
+}
+
+int ccg_server_get_stats(const ccg_server* S, ccg_server_stats* out)
+{
+    if (!S) return -1;
+    if (!out) return -2;
+    *out = S->st;
     return 0;
 }
 

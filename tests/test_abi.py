@@ -93,3 +93,33 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ccg, "lib_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(ccg.CcgError):
         ccg.load()
+
+
+def test_server_argument_errors_are_rejected_on_the_host(lib):
+    from paper_1208_4869_amd import ccg
+    P = ctypes.c_void_p
+    out = P()
+    big = 1 << 30
+    assert lib.ccg_server_create(None, big, 4, None, ctypes.byref(out)) == -1
+    assert lib.ccg_server_create(P(256 + 8), big, 4, None, ctypes.byref(out)) == -1
+    assert lib.ccg_server_create(P(256), 100, 4, None, ctypes.byref(out)) == -2
+    assert lib.ccg_server_create(P(256), big, 0, None, ctypes.byref(out)) == -3
+    assert lib.ccg_server_create(P(256), big, 129, None, ctypes.byref(out)) == -3
+    assert lib.ccg_server_create(P(256), big, 4, None, None) == -5
+    t = ctypes.c_int64()
+    assert lib.ccg_server_submit(None, 4, 1, P(256), 4, P(256), 1, P(256), 1,
+                                 1e-10, 10, ctypes.byref(t)) == -1
+    assert lib.ccg_server_step(None, None, None) == -1
+    st = ctypes.c_int32()
+    assert lib.ccg_server_poll(None, 1, ctypes.byref(st), None) == -1
+    assert lib.ccg_server_destroy(None) == -1
+    assert lib.ccg_server_get_stats(None, None) == -1
+    # footprints: A, Y, X and the block workspace; k limited to 16
+    assert ccg.ccg_server_request_bytes(0, 1) == 0
+    assert ccg.ccg_server_request_bytes(-1, 1) == 0
+    assert ccg.ccg_server_request_bytes(10, 0) == 0
+    assert ccg.ccg_server_request_bytes(10, 17) == 0
+    for n, k in ((512, 1), (4096, 8), (1000, 16)):
+        b = ccg.ccg_server_request_bytes(n, k)
+        assert b >= 16 * n * n + 2 * 16 * n * k + 15 * 16 * n * k
+        assert b % 256 == 0
