@@ -386,8 +386,9 @@ def serve_leg(nreq, rate):
 
 def profile_kernels(A, y):
     """A short, fixed mix for rocprofv3: a device copy of known size (the
-    reference for scaling the HBM byte counters), A x, A^H x, one BiCGSTAB and
-    one CGNR solve."""
+    reference for scaling the HBM byte counters), A x, A^H x, the complex64
+    product on complex64(A), the 64-column product A P, one BiCGSTAB and one
+    CGNR solve."""
     import torch
 
     from paper_1208_4869_amd import ccg
@@ -396,15 +397,23 @@ def profile_kernels(A, y):
     src.fill_(1.0)
     dst = torch.empty_like(src)
     x = torch.ones(n, dtype=torch.complex128, device="cuda")
+    A32 = ccg.ccg_round_c64(A)
+    x32 = x.to(torch.complex64)
+    P = torch.ones((n, BLOCK_RHS), dtype=torch.complex128, device="cuda")
+    Z = torch.empty_like(P)
+    wmm = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATMAT, n, BLOCK_RHS),
+                      dtype=torch.uint8, device="cuda")
     for _ in range(5):
         dst.copy_(src)
         ccg.ccg_matvec(ccg.OP_N, A, x)
         ccg.ccg_matvec(ccg.OP_C, A, x)
+        ccg.ccg_matvec_c64(A32, x32)
+        ccg.ccg_matmat(A, P, Z, work=wmm)
     ccg.ccg_bicgstab_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
     ccg.ccg_cgnr_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
     torch.cuda.synchronize()
-    log("profile mix done: copy %d bytes x5, matvec N/C x5, 1 BiCGSTAB, 1 CGNR"
-        % (src.numel() * 8))
+    log("profile mix done: copy %d bytes x5, matvec N/C/c64 x5, A P (k=%d) x5, "
+        "1 BiCGSTAB, 1 CGNR" % (src.numel() * 8, BLOCK_RHS))
 
 
 def main():
