@@ -92,7 +92,8 @@ enum {
     CCG_WS_BICGSTAB_BLOCK = 5, /* ccg_bicgstab_block_ex (nrhs = k <= 64) */
     CCG_WS_COCG = 6,
     CCG_WS_COCR = 7,
-    CCG_WS_BICGSTAB_MIXED = 8
+    CCG_WS_BICGSTAB_MIXED = 8,
+    CCG_WS_T3_MATVEC = 9 /* scratch of ccg_t3_matvec (ccg_t3_workspace_bytes) */
 };
 
 /* Outcome of a mixed-precision solve (host struct). */
@@ -272,6 +273,50 @@ int ccg_bicgstab_block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
                           const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
                           double tol, int32_t maxit, uint32_t flags, void* work,
                           size_t work_bytes, ccg_result* res, void* stream);
+
+/*
+ * Structured product: A is a three-level Toeplitz matrix on an m x m x m
+ * lattice (n = m^3, point index ix + m iy + m^2 iz), A_ij = T(p_i - p_j) for
+ * a kernel T on the displacement box [-(m-1), m-1]^3 -- the shape of the
+ * discrete-dipole systems of the Introduction, used through the user's own
+ * matrix scheme that the Usage section leaves to the caller's matvec.  The
+ * product is a zero-padded 3-D FFT convolution on an M^3 grid (M the
+ * smallest power of two >= 2m - 1; 1 <= m <= 128): O(n log n) work and O(n)
+ * memory instead of the dense 16 n^2 bytes.
+ *
+ * ccg_t3_setup: 1 m, 2 table (device, (2m-1)^3 complex128; displacement
+ * (dx, dy, dz) at ((dz+m-1)(2m-1) + (dy+m-1))(2m-1) + (dx+m-1); the zero
+ * displacement is the diagonal), 3 op (device, 256-byte aligned, receives the
+ * transformed kernel; op_bytes >= ccg_t3_op_bytes(m)), 4 op_bytes, 5 stream.
+ * Asynchronous; the table may be freed once the stream has passed the call.
+ * ccg_t3_matvec: y = A x; 1 m, 2 op, 3 x, 4 y (may equal x), 5 work (device,
+ * 256-byte aligned, >= ccg_t3_workspace_bytes(CCG_WS_T3_MATVEC, m)),
+ * 6 work_bytes, 7 stream.  Asynchronous.
+ * ccg_t3_bicgstab_ex / ccg_t3_cocg_ex / ccg_t3_cocr_ex: the solvers of
+ * ccg_bicgstab_ex / ccg_cocg_ex / ccg_cocr_ex with the structured product;
+ * 1 m, 2 op, 3 y, 4 x, 5 tol, 6 maxit, 7 flags, 8 work (>=
+ * ccg_t3_workspace_bytes(CCG_WS_BICGSTAB / _COCG / _COCR, m)), 9 work_bytes,
+ * 10 res, 11 hist, 12 stream.  COCG and COCR need T(d) = T(-d) (A complex
+ * symmetric), which the lattice kernel has.  Wait on stream.
+ */
+size_t ccg_t3_op_bytes(int64_t m);
+size_t ccg_t3_workspace_bytes(int method, int64_t m);
+int ccg_t3_setup(int64_t m, const ccg_z* table, void* op, size_t op_bytes,
+                 void* stream);
+int ccg_t3_matvec(int64_t m, const void* op, const ccg_z* x, ccg_z* y,
+                  void* work, size_t work_bytes, void* stream);
+int ccg_t3_bicgstab_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x,
+                       double tol, int32_t maxit, uint32_t flags, void* work,
+                       size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                       void* stream);
+int ccg_t3_cocg_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x,
+                   double tol, int32_t maxit, uint32_t flags, void* work,
+                   size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                   void* stream);
+int ccg_t3_cocr_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x,
+                   double tol, int32_t maxit, uint32_t flags, void* work,
+                   size_t work_bytes, ccg_result* res, ccg_hist* hist,
+                   void* stream);
 
 /*
  * Serving: many independent block systems (the ccg_bicgstab_block problem,

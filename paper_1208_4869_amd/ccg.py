@@ -27,6 +27,7 @@ WS_BICGSTAB_BLOCK = 5
 WS_COCG = 6
 WS_COCR = 7
 WS_BICGSTAB_MIXED = 8
+WS_T3_MATVEC = 9
 X0_ZERO = 1
 SERVER_REJECTED = -1000
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
@@ -126,6 +127,18 @@ def load() -> ctypes.CDLL:
     lib.ccg_bicgstab_block_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, D,
                                           I32, U32, P, S, ctypes.POINTER(_Result),
                                           P]
+    lib.ccg_t3_op_bytes.argtypes = [I64]
+    lib.ccg_t3_op_bytes.restype = S
+    lib.ccg_t3_workspace_bytes.argtypes = [ctypes.c_int, I64]
+    lib.ccg_t3_workspace_bytes.restype = S
+    lib.ccg_t3_setup.argtypes = [I64, P, P, S, P]
+    lib.ccg_t3_matvec.argtypes = [I64, P, P, P, P, S, P]
+    for name in ("ccg_t3_bicgstab_ex", "ccg_t3_cocg_ex", "ccg_t3_cocr_ex"):
+        getattr(lib, name).argtypes = [I64, P, P, P, D, I32, U32, P, S,
+                                       ctypes.POINTER(_Result), P, P]
+    for name in ("ccg_t3_setup", "ccg_t3_matvec", "ccg_t3_bicgstab_ex",
+                 "ccg_t3_cocg_ex", "ccg_t3_cocr_ex"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.ccg_server_create.argtypes = [P, S, I32, P, ctypes.POINTER(P)]
     lib.ccg_server_destroy.argtypes = [P]
     lib.ccg_server_request_bytes.argtypes = [I64, I64]
@@ -560,3 +573,89 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------ structured lattice operator
+
+def ccg_t3_op_bytes(m: int) -> int:
+    return int(load().ccg_t3_op_bytes(m))
+
+
+def ccg_t3_workspace_bytes(method: int, m: int) -> int:
+    return int(load().ccg_t3_workspace_bytes(method, m))
+
+
+class T3Operator:
+    """Three-level Toeplitz operator of an m^3 lattice (ccg_t3_setup): holds
+    the transformed kernel on the device.  ``table`` is the (2m-1)^3 kernel
+    (complex128, host array or device tensor) in the layout of
+    ``inputs.lattice_table``."""
+
+    def __init__(self, m: int, table, stream=None):
+        torch = _torch()
+        self.m = int(m)
+        self.n = self.m ** 3
+        w = 2 * self.m - 1
+        if not isinstance(table, torch.Tensor):
+            table = torch.from_numpy(np.ascontiguousarray(table))
+        table = table.to("cuda").contiguous()
+        if table.dtype != torch.complex128 or table.numel() != w ** 3:
+            raise TypeError("table must hold (2m-1)^3 complex128 values")
+        nb = ccg_t3_op_bytes(self.m)
+        if nb == 0:
+            raise ValueError("lattice edge m=%d out of range (1..128)" % self.m)
+        self.op = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        _check(load().ccg_t3_setup(self.m, table.data_ptr(), self.op.data_ptr(), nb,
+                                   _stream(stream)), "ccg_t3_setup")
+        self._table = table  # kept until the set-up has run
+        self._work = None
+
+    def workspace(self, method: int):
+        torch = _torch()
+        return torch.empty(max(ccg_t3_workspace_bytes(method, self.m), 256),
+                           dtype=torch.uint8, device="cuda")
+
+    def matvec(self, x, y=None, work=None, stream=None):
+        """y = A x (x, y complex128 device vectors of m^3 elements)."""
+        _vec(x, self.n, "x")
+        if y is None:
+            y = _torch().empty_like(x)
+        _vec(y, self.n, "y")
+        if work is None:
+            if self._work is None:
+                self._work = self.workspace(WS_T3_MATVEC)
+            work = self._work
+        _check(load().ccg_t3_matvec(self.m, self.op.data_ptr(), x.data_ptr(),
+                                    y.data_ptr(), work.data_ptr(),
+                                    work.numel() * work.element_size(),
+                                    _stream(stream)), "ccg_t3_matvec")
+        return y
+
+    def _solve(self, name, method, y, x, tol, maxit, flags, work, hist, stream):
+        _vec(y, self.n, "y")
+        _vec(x, self.n, "x")
+        if work is None:
+            work = self.workspace(method)
+        res = _Result()
+        _check(getattr(load(), name)(
+            self.m, self.op.data_ptr(), y.data_ptr(), x.data_ptr(), float(tol),
+            int(maxit), int(flags), work.data_ptr(),
+            work.numel() * work.element_size(), ctypes.byref(res),
+            hist.data_ptr() if hist is not None else None, _stream(stream)), name)
+        return Result(res.info, res.iters, res.matvecs, res.confirms,
+                      res.relres_rec, res.relres_true)
+
+    def bicgstab(self, y, x, tol=1e-10, maxit=1000, flags=0, work=None, hist=None,
+                 stream=None) -> Result:
+        return self._solve("ccg_t3_bicgstab_ex", WS_BICGSTAB, y, x, tol, maxit, flags,
+                           work, hist, stream)
+
+    def cocg(self, y, x, tol=1e-10, maxit=1000, flags=0, work=None, hist=None,
+             stream=None) -> Result:
+        return self._solve("ccg_t3_cocg_ex", WS_COCG, y, x, tol, maxit, flags, work,
+                           hist, stream)
+
+    def cocr(self, y, x, tol=1e-10, maxit=1000, flags=0, work=None, hist=None,
+             stream=None) -> Result:
+        return self._solve("ccg_t3_cocr_ex", WS_COCR, y, x, tol, maxit, flags, work,
+                           hist, stream)

@@ -35,6 +35,7 @@
 #include "ccg_gemv.h"
 #include "ccg_host.h"
 #include "ccg_krylov.h"
+#include "ccg_t3.h"
 
 namespace ccg {
 
@@ -53,6 +54,7 @@ struct Args {
     SolverState* st[2];          // state copies, alternating
     ccg_hist* hist;
     bool vec16;                  // complex64 A with 16-byte aligned rows
+    T3Geom t3;                   // structured product (A unused)
 };
 
 constexpr int kR = 4;   // rows per block in A x
@@ -205,6 +207,73 @@ __device__ __forceinline__ int role_mode(int ph)
     return -1;
 }
 
+template <Role RO>
+__device__ __forceinline__ constexpr bool role_setup()
+{
+    return RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || RO == ROLE_SETUP_G;
+}
+
+// The vector a product of role RO multiplies in mode `mode`: x for the
+// residual-type products (set-up, confirmation), else the role's Krylov vector.
+template <Role RO>
+__device__ __forceinline__ const d2* role_input(const Args& a, int mode)
+{
+    const bool resid = role_setup<RO>() || mode == PH_CONFIRM;
+    return resid ? a.x : RO == ROLE_T ? a.s : RO == ROLE_U ? a.r : a.p;
+}
+
+// Element i of a product of role RO is val: store what the role stores and
+// add its dot-product terms to pv0, pv1 (in FP64; complex64 vectors are
+// rounded on store and the terms use the stored values).
+template <Role RO, class T>
+__device__ __forceinline__ void role_finish(const Args& a, int mode, int i, d2 val, d2& pv0,
+                                            d2& pv1)
+{
+    const bool resid = role_setup<RO>() || mode == PH_CONFIRM;
+    if (resid) {
+        T* r = (T*)a.r;
+        stv(r, i, ldv((const T*)a.y, i) - val);
+        const d2 ri = ldv(r, i);
+        if (RO == ROLE_SETUP_B || RO == ROLE_V) stv((T*)a.rh, i, ri);
+        pv0.x += cabs2(ri);
+        if (RO == ROLE_SETUP_G || RO == ROLE_Q) pv1 = cfma(ri, ri, pv1);
+    } else if (RO == ROLE_Q) {
+        a.v[i] = val;  // q
+        pv0 = cfma(a.p[i], val, pv0);
+    } else if (RO == ROLE_U) {
+        a.z[i] = val;  // u
+        pv0 = cfma(a.r[i], val, pv0);
+    } else if (RO == ROLE_V) {
+        T* v = (T*)a.v;
+        stv(v, i, val);
+        val = ldv(v, i);
+        pv0 = cfma_conj(ldv((const T*)a.rh, i), val, pv0);
+        pv1.x += cabs2(val);
+    } else if (RO == ROLE_T) {
+        T* tv = (T*)a.t;
+        stv(tv, i, val);
+        val = ldv(tv, i);
+        pv0 = cfma_conj(val, ldv((const T*)a.s, i), pv0);
+        pv1.x += cabs2(val);
+    } else {  // ROLE_W
+        a.w[i] = val;
+        pv0.x += cabs2(val);
+    }
+}
+
+// The reduction a product of role RO leaves for the next kernel.
+template <Role RO>
+__device__ __forceinline__ int role_kind(int mode)
+{
+    if (RO == ROLE_SETUP_B) return PK_SETUP_B1;
+    if (RO == ROLE_SETUP_C) return PK_SETUP_C1;
+    if (RO == ROLE_SETUP_G) return PK_SETUP_G1;
+    if (mode == PH_CONFIRM)
+        return RO == ROLE_V ? PK_CONFIRM_B : RO == ROLE_Q ? PK_CONFIRM_G : PK_CONFIRM_C;
+    return RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : RO == ROLE_W ? PK_W
+         : RO == ROLE_Q ? PK_Q : PK_U;
+}
+
 template <Role RO, class T = d2>
 __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 {
@@ -214,16 +283,13 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     const int row0 = blockIdx.x * kR;
     const int n = a.n;
     const int t = threadIdx.x;
-    const bool setup = (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || RO == ROLE_SETUP_G);
 
     if (mode == PH_ZERO) {  // y == 0: zero this block's rows of x
         if (t < kR && row0 + t < n) stv((T*)a.x, row0 + t, d2{0.0, 0.0});
         publish(a, q, L, PK_ZERO, 0);
         return;
     }
-    // residual-type products read x; the others read a Krylov vector
-    const bool resid = setup || mode == PH_CONFIRM;
-    const d2* in = resid ? a.x : RO == ROLE_T ? a.s : RO == ROLE_U ? a.r : a.p;
+    const d2* in = role_input<RO>(a, mode);
 
     __shared__ d2 red[kWN][kR];
     d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
@@ -231,53 +297,81 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
         gemv_n_block_f<kR, kWN>((const f2*)a.A, a.lda, n, (const f2*)in, row0, red, a.vec16);
     else
         gemv_n_block<kR, kU, kWN>(a.A, a.lda, n, in, row0, red);
-    // thread r of the first wavefront finishes row row0 + r: output and its
-    // dot-product terms (in FP64; complex64 vectors are rounded on store and
-    // the terms use the stored values)
+    // thread r of the first wavefront finishes row row0 + r
     const int i = row0 + t;
-    if (t < kR && i < n) {
-        d2 val = gemv_n_row_total<kR, kWN>(red, t);
-        if (resid) {
-            T* r = (T*)a.r;
-            stv(r, i, ldv((const T*)a.y, i) - val);
-            const d2 ri = ldv(r, i);
-            if (RO == ROLE_SETUP_B || RO == ROLE_V) stv((T*)a.rh, i, ri);
-            pv0.x = cabs2(ri);
-            if (RO == ROLE_SETUP_G || RO == ROLE_Q) pv1 = cfma(ri, ri, pv1);
-        } else if (RO == ROLE_Q) {
-            a.v[i] = val;  // q
-            pv0 = cfma(a.p[i], val, pv0);
-        } else if (RO == ROLE_U) {
-            a.z[i] = val;  // u
-            pv0 = cfma(a.r[i], val, pv0);
-        } else if (RO == ROLE_V) {
-            T* v = (T*)a.v;
-            stv(v, i, val);
-            val = ldv(v, i);
-            pv0 = cfma_conj(ldv((const T*)a.rh, i), val, pv0);
-            pv1.x = cabs2(val);
-        } else if (RO == ROLE_T) {
-            T* tv = (T*)a.t;
-            stv(tv, i, val);
-            val = ldv(tv, i);
-            pv0 = cfma_conj(val, ldv((const T*)a.s, i), pv0);
-            pv1.x = cabs2(val);
-        } else {  // ROLE_W
-            a.w[i] = val;
-            pv0.x = cabs2(val);
+    if (t < kR && i < n) role_finish<RO, T>(a, mode, i, gemv_n_row_total<kR, kWN>(red, t), pv0, pv1);
+    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    publish(a, q, L, role_kind<RO>(mode), gridDim.x);
+}
+
+// ------------------------------------- structured (three-level Toeplitz) products
+//
+// The same roles with the product computed by the five FFT passes of
+// ccg_t3.h.  The first pass applies the pending scalar step (and so learns
+// the phase and the input vector); the passes in between only carry the
+// state; the last pass finishes the product and does what k_gemv_n_role does
+// with each element.
+
+template <Role RO, int R>
+__global__ __launch_bounds__(kBlock) void k_t3_x(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO) t3_pass_x<R>(a.t3, role_input<RO>(a, mode));
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO, int R>
+__global__ __launch_bounds__(kBlock) void k_t3_y(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO) t3_pass_y<R>(a.t3);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO, int R>
+__global__ __launch_bounds__(kBlock) void k_t3_z(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO) t3_pass_z<R>(a.t3);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO, int R>
+__global__ __launch_bounds__(kBlock) void k_t3_yi(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO) t3_pass_yi<R>(a.t3);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO, int R>
+__global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
+    if (mode == PH_ZERO) {  // y == 0: x = 0
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock)
+            a.x[i] = d2{0.0, 0.0};
+        publish(a, q, L, PK_ZERO, 0);
+        return;
+    }
+    d2 v[R];
+    const int line = t3_pass_xi<R>(a.t3, v);
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    if (line >= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int ix = t3_point(r);
+            if (ix < a.t3.m) role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[r], pv0, pv1);
         }
     }
     write_partials(pv0, pv1, a.part[q ^ 1], lds);
-    int kind;
-    if (RO == ROLE_SETUP_B) kind = PK_SETUP_B1;
-    else if (RO == ROLE_SETUP_C) kind = PK_SETUP_C1;
-    else if (RO == ROLE_SETUP_G) kind = PK_SETUP_G1;
-    else if (mode == PH_CONFIRM)
-        kind = RO == ROLE_V ? PK_CONFIRM_B : RO == ROLE_Q ? PK_CONFIRM_G : PK_CONFIRM_C;
-    else
-        kind = RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : RO == ROLE_W ? PK_W
-             : RO == ROLE_Q ? PK_Q : PK_U;
-    publish(a, q, L, kind, gridDim.x);
+    publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
 // ------------------------------------------------------- BiCGSTAB vectors
@@ -559,6 +653,128 @@ __global__ __launch_bounds__(kBlock) void k_gemv_c_gather_plain(const d2* __rest
         y[j] = gemv_c_gather(part, n, nbands, j);
 }
 
+
+// ------------------------------------------ structured product, plain and set-up
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3p_x(T3Geom g, const d2* __restrict__ x)
+{
+    t3_pass_x<R>(g, x);
+}
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3p_y(T3Geom g) { t3_pass_y<R>(g); }
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3p_z(T3Geom g) { t3_pass_z<R>(g); }
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3p_yi(T3Geom g) { t3_pass_yi<R>(g); }
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3p_xi(T3Geom g, d2* __restrict__ y)
+{
+    d2 v[R];
+    const int line = t3_pass_xi<R>(g, v);
+    if (line < 0) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int ix = t3_point(r);
+        if (ix < g.m) y[ix + (int64_t)g.m * line] = v[r];
+    }
+}
+
+// tw[t] = e^{-2 pi i t / M}
+__global__ void k_t3_twiddle(d2* tw, int M)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < M / 2) {
+        double sn, cs;
+        sincospi(2.0 * t / M, &sn, &cs);
+        tw[t] = d2{cs, -sn};
+    }
+}
+
+// Kernel value at padded grid coordinate c (the displacement c, or c - M for
+// the wrapped negative displacements); outside the displacement box: none.
+__device__ __forceinline__ bool t3_disp(int c, int m, int M, int& d)
+{
+    if (c <= m - 1) { d = c; return true; }
+    if (c >= M - (m - 1)) { d = c - M; return true; }
+    return false;
+}
+
+// Set-up pass 1: lines (y, z) of the wrapped kernel, forward along x ->
+// S[(z M + kx) M + y].  table: (2m-1)^3 values, displacement (dx, dy, dz) at
+// ((dz + m-1)(2m-1) + (dy + m-1))(2m-1) + (dx + m-1).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3_s1(const d2* __restrict__ table, T3Geom g,
+                                                  d2* __restrict__ S)
+{
+    const int m = g.m, M = g.M, w = 2 * m - 1;
+    const int line = t3_line();
+    if (line >= M * M) return;
+    const int y = line % M, z = line / M;
+    int dy = 0, dz = 0;
+    const bool yz = t3_disp(y, m, M, dy) && t3_disp(z, m, M, dz);
+    d2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int x = t3_point(r);
+        int dx = 0;
+        const bool ok = yz && x < M && t3_disp(x, m, M, dx);
+        v[r] = ok ? table[((int64_t)(dz + m - 1) * w + (dy + m - 1)) * w + (dx + m - 1)]
+                  : d2{0.0, 0.0};
+    }
+    t3_fwd<R>(v, M, g.tw);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int kx = t3_point(r);
+        if (kx < M) S[((int64_t)z * M + kx) * M + y] = v[r];
+    }
+}
+
+// Set-up pass 2: lines (kx, z), forward along y -> K[(kx M + ky) M + z]
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3_s2(T3Geom g, const d2* __restrict__ S,
+                                                  d2* __restrict__ K)
+{
+    const int M = g.M;
+    const int line = t3_line();
+    if (line >= M * M) return;
+    const int kx = line % M, z = line / M;
+    d2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = t3_point(r);
+        v[r] = y < M ? S[((int64_t)z * M + kx) * M + y] : d2{0.0, 0.0};
+    }
+    t3_fwd<R>(v, M, g.tw);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int ky = t3_point(r);
+        if (ky < M) K[((int64_t)kx * M + ky) * M + z] = v[r];
+    }
+}
+
+// Set-up pass 3: lines (kx, ky), forward along z, times M^-3 (exact), in place
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_t3_s3(T3Geom g, d2* __restrict__ K, double scale)
+{
+    const int M = g.M;
+    const int line = t3_line();
+    if (line >= M * M) return;
+    d2* row = K + (int64_t)line * M;
+    d2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int z = t3_point(r);
+        v[r] = z < M ? row[z] : d2{0.0, 0.0};
+    }
+    t3_fwd<R>(v, M, g.tw);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int kz = t3_point(r);
+        if (kz < M) row[kz] = d2{v[r].x * scale, v[r].y * scale};
+    }
+}
+
 // ================================================================== host
 
 static inline int blocks_n(int64_t n)
@@ -587,12 +803,13 @@ struct Layout {
     int nvec;
 };
 
-static Layout layout(int method, int64_t n)
+static Layout layout(int method, int64_t n, int64_t min_partials = 0)
 {
     Layout L{};
     const GemvCShape csh = gemv_c_shape(n > 0 ? n : 1);
     int64_t pb = blocks_n(n);
     if (pb < 512) pb = 512;
+    if (pb < min_partials) pb = min_partials;
     if (csh.blocks() > pb) pb = csh.blocks();
     const size_t vbytes = align256((size_t)(n > 0 ? n : 1) * sizeof(d2));
     size_t off = 0;
@@ -678,13 +895,54 @@ static int ws_of(int M)
          : M == M_COCG ? CCG_WS_COCG : CCG_WS_COCR;
 }
 
+static inline int t3_blocks(int64_t lines)
+{
+    return (int)((lines + kT3LinesPerBlock - 1) / kT3LinesPerBlock);
+}
+
+// The five passes of a structured product of role RO (state copy q in, q
+// advanced past them).
+template <Role RO, int R>
+static void launch_t3_role(const Args& a, int& q, hipStream_t s)
+{
+    const int64_t m = a.t3.m, M = a.t3.M;
+    k_t3_x<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
+    q ^= 1;
+    k_t3_y<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(a, q);
+    q ^= 1;
+    k_t3_z<RO, R><<<t3_blocks(M * M), kBlock, 0, s>>>(a, q);
+    q ^= 1;
+    k_t3_yi<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(a, q);
+    q ^= 1;
+    k_t3_role<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
+    q ^= 1;
+}
+
+// A product of role RO: dense (one k_gemv_n_role launch) or structured.
+template <Role RO, class T, bool S3>
+static void launch_product(const Args& a, int& q, hipStream_t s)
+{
+    if constexpr (S3) {
+        if (a.t3.M <= kWave)
+            launch_t3_role<RO, 1>(a, q, s);
+        else if (a.t3.M == 2 * kWave)
+            launch_t3_role<RO, 2>(a, q, s);
+        else
+            launch_t3_role<RO, 4>(a, q, s);
+    } else {
+        k_gemv_n_role<RO, T><<<blocks_n(a.n), kBlockN, 0, s>>>(a, q);
+        q ^= 1;
+    }
+}
+
 // Enqueue set-up, then slots until the status ring reports PH_DONE.  Every
 // solver kernel reads state copy q and writes copy q ^ 1; the host tracks q
-// across the launches it makes.
-template <int M, class T = d2>
+// across the launches it makes.  S3: products by the structured operator.
+template <int M, class T = d2, bool S3 = false>
 static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                       ccg_result* res, hipStream_t s, int no_confirm = 0)
 {
+    static_assert(!(S3 && M == M_CGNR), "CGNR needs A^H: dense only");
     SyncCtx* sc = nullptr;
     hipError_t e = get_sync(&sc);
     if (e != hipSuccess) return (int)e;
@@ -699,25 +957,25 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     if (flags & CCG_X0_ZERO)
         k_setup_x0zero<M == M_COCR ? M_CGNR : M, T><<<gE, kBlock, 0, s>>>(a, flip());
     else if (M == M_BICG)
-        k_gemv_n_role<ROLE_SETUP_B, T><<<gN, kBlockN, 0, s>>>(a, flip());
+        launch_product<ROLE_SETUP_B, T, S3>(a, q, s);
     else if (M == M_COCG)
-        k_gemv_n_role<ROLE_SETUP_G><<<gN, kBlockN, 0, s>>>(a, flip());
+        launch_product<ROLE_SETUP_G, T, S3>(a, q, s);
     else
-        k_gemv_n_role<ROLE_SETUP_C><<<gN, kBlockN, 0, s>>>(a, flip());
+        launch_product<ROLE_SETUP_C, T, S3>(a, q, s);
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
 
     // Each slot advances the method by at most one iteration or one
     // confirmation; a confirmation is always preceded by an iteration or
     // by the set-up, so 2 * maxit + 4 slots always suffice.
     const int64_t max_slots = 2 * (int64_t)maxit + 4;
-    const int ahead = lookahead(a.n);
+    const int ahead = S3 ? 2 : lookahead(a.n);  // structured slots are short
     for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
             if (M == M_BICG) {
                 k_bicg_p<T><<<gE, kBlock, 0, s>>>(a, flip());
-                k_gemv_n_role<ROLE_V, T><<<gN, kBlockN, 0, s>>>(a, flip());
+                launch_product<ROLE_V, T, S3>(a, q, s);
                 k_bicg_s<T><<<gE, kBlock, 0, s>>>(a, flip());
-                k_gemv_n_role<ROLE_T, T><<<gN, kBlockN, 0, s>>>(a, flip());
+                launch_product<ROLE_T, T, S3>(a, q, s);
                 k_bicg_xr<T><<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR) {
                 k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, flip());
@@ -727,10 +985,10 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                 k_cgnr_p<<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_COCG) {
                 k_cocg_p<<<gE, kBlock, 0, s>>>(a, flip());
-                k_gemv_n_role<ROLE_Q><<<gN, kBlockN, 0, s>>>(a, flip());
+                launch_product<ROLE_Q, T, S3>(a, q, s);
                 k_cocg_xr<<<gE, kBlock, 0, s>>>(a, flip());
             } else {
-                k_gemv_n_role<ROLE_U><<<gN, kBlockN, 0, s>>>(a, flip());
+                launch_product<ROLE_U, T, S3>(a, q, s);
                 k_cocr_pw<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cocr_xr<<<gE, kBlock, 0, s>>>(a, flip());
             }
@@ -1082,6 +1340,164 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
     return 0;
 }
 
+
+// ------------------------------------------------------ structured operator
+
+static constexpr int64_t kT3MaxEdge = kT3MaxM / 2;  // lattice edge m <= 128
+
+struct T3OpLayout {
+    int M;
+    size_t tw, K, S, total;
+};
+
+static T3OpLayout t3_op_layout(int64_t m)
+{
+    T3OpLayout L{};
+    L.M = t3_padded((int)m);
+    const size_t M3 = (size_t)L.M * L.M * L.M;
+    L.tw = 0;
+    L.K = align256((size_t)(L.M / 2 > 0 ? L.M / 2 : 1) * sizeof(d2));
+    L.S = L.K + align256(M3 * sizeof(d2));
+    L.total = L.S + align256(M3 * sizeof(d2));  // S: set-up scratch
+    return L;
+}
+
+// Scratch of one product: G1 (M m^2) and G2 (M^2 m).
+static size_t t3_grid_bytes(int64_t m)
+{
+    const size_t M = (size_t)t3_padded((int)m);
+    return align256(M * m * m * sizeof(d2)) + align256(M * M * m * sizeof(d2));
+}
+
+static T3Geom t3_geom(int64_t m, const void* op, void* grids)
+{
+    const T3OpLayout L = t3_op_layout(m);
+    T3Geom g{};
+    g.m = (int)m;
+    g.M = L.M;
+    g.tw = (const d2*)((const char*)op + L.tw);
+    g.K = (const d2*)((const char*)op + L.K);
+    g.g1 = (d2*)grids;
+    g.g2 = (d2*)((char*)grids + align256((size_t)L.M * m * m * sizeof(d2)));
+    return g;
+}
+
+static size_t t3_workspace(int method, int64_t m)
+{
+    if (method == CCG_WS_T3_MATVEC) return t3_grid_bytes(m);
+    const int64_t n = m * m * m;
+    return layout(method, n, t3_blocks(m * m)).total + t3_grid_bytes(m);
+}
+
+template <int R>
+static void t3_matvec_launch(const T3Geom& g, const d2* x, d2* y, hipStream_t s)
+{
+    const int64_t m = g.m, M = g.M;
+    k_t3p_x<R><<<t3_blocks(m * m), kBlock, 0, s>>>(g, x);
+    k_t3p_y<R><<<t3_blocks(M * m), kBlock, 0, s>>>(g);
+    k_t3p_z<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g);
+    k_t3p_yi<R><<<t3_blocks(M * m), kBlock, 0, s>>>(g);
+    k_t3p_xi<R><<<t3_blocks(m * m), kBlock, 0, s>>>(g, y);
+}
+
+template <int R>
+static void t3_setup_launch(const T3Geom& g, const d2* table, d2* K, d2* S, hipStream_t s)
+{
+    const int64_t M = g.M;
+    k_t3_twiddle<<<(int)((M / 2 + kBlock - 1) / kBlock > 0 ? (M / 2 + kBlock - 1) / kBlock : 1),
+                   kBlock, 0, s>>>((d2*)g.tw, (int)M);
+    k_t3_s1<R><<<t3_blocks(M * M), kBlock, 0, s>>>(table, g, S);
+    k_t3_s2<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g, S, K);
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    k_t3_s3<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g, K, std::ldexp(1.0, -3 * lg));
+}
+
+static int t3_setup_impl(int64_t m, const ccg_z* table, void* op, size_t op_bytes, void* stream)
+{
+    if (m < 1 || m > kT3MaxEdge) return -1;
+    if (!table) return -2;
+    if (!op || ((uintptr_t)op & 255)) return -3;
+    const T3OpLayout L = t3_op_layout(m);
+    if (op_bytes < L.total) return -4;
+    hipStream_t s = (hipStream_t)stream;
+    T3Geom g = t3_geom(m, op, nullptr);
+    d2* K = (d2*)((char*)op + L.K);
+    d2* S = (d2*)((char*)op + L.S);
+    if (L.M <= kWave)
+        t3_setup_launch<1>(g, (const d2*)table, K, S, s);
+    else if (L.M == 2 * kWave)
+        t3_setup_launch<2>(g, (const d2*)table, K, S, s);
+    else
+        t3_setup_launch<4>(g, (const d2*)table, K, S, s);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+static int t3_matvec_impl(int64_t m, const void* op, const ccg_z* x, ccg_z* y, void* work,
+                          size_t work_bytes, void* stream)
+{
+    if (m < 0 || m > kT3MaxEdge) return -1;
+    if (m == 0) return 0;
+    if (!op || ((uintptr_t)op & 255)) return -2;
+    if (!x) return -3;
+    if (!y) return -4;
+    if (!work || ((uintptr_t)work & 255)) return -5;
+    if (work_bytes < t3_grid_bytes(m)) return -6;
+    const T3Geom g = t3_geom(m, op, work);
+    hipStream_t s = (hipStream_t)stream;
+    if (g.M <= kWave)
+        t3_matvec_launch<1>(g, (const d2*)x, (d2*)y, s);
+    else if (g.M == 2 * kWave)
+        t3_matvec_launch<2>(g, (const d2*)x, (d2*)y, s);
+    else
+        t3_matvec_launch<4>(g, (const d2*)x, (d2*)y, s);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+template <int M>
+static int t3_solve(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double tol,
+                    int32_t maxit, uint32_t flags, void* work, size_t work_bytes,
+                    ccg_result* res, ccg_hist* hist, void* stream)
+{
+    if (m < 0 || m > kT3MaxEdge) return -1;
+    if (m > 0 && (!op || ((uintptr_t)op & 255))) return -2;
+    if (m > 0 && !y) return -3;
+    if (m > 0 && !x) return -4;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return -5;
+    if (maxit < 0) return -6;
+    if (flags & ~CCG_X0_ZERO) return -7;
+    const int method = ws_of(M);
+    if (m > 0 && (!work || ((uintptr_t)work & 255))) return -8;
+    if (m > 0 && work_bytes < t3_workspace(method, m)) return -9;
+    if (!res) return -10;
+    if (m == 0) {
+        std::memset(res, 0, sizeof *res);
+        res->relres_rec = res->relres_true = 0.0;
+        return 0;
+    }
+    const int64_t n = m * m * m;
+    const Layout L = layout(method, n, t3_blocks(m * m));
+    // make_args carves the vectors and partial buffers with the default
+    // partial count; rebuild them here with the structured one
+    Args a = make_args(method, n, nullptr, 1, y, x, work, hist);
+    char* base = (char*)work;
+    a.part[0] = (d2*)(base + L.partials);
+    a.part[1] = (d2*)(base + L.partials + L.part_bytes);
+    const size_t vbytes = align256((size_t)n * sizeof(d2));
+    d2* vec[6] = {};
+    for (int k = 0; k < L.nvec; ++k) vec[k] = (d2*)(base + L.vec + k * vbytes);
+    if (method == CCG_WS_BICGSTAB) {
+        a.r = vec[0]; a.rh = vec[1]; a.p = vec[2]; a.v = vec[3]; a.s = vec[4]; a.t = vec[5];
+    } else if (method == CCG_WS_COCG) {
+        a.r = vec[0]; a.p = vec[1]; a.v = vec[2];
+    } else {
+        a.r = vec[0]; a.z = vec[1]; a.p = vec[2]; a.w = vec[3];
+    }
+    a.t3 = t3_geom(m, op, base + L.total);
+    return run_solver<M, d2, true>(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
+}
 }  // namespace ccg
 
 // ============================================================== C ABI
@@ -1216,6 +1632,56 @@ int ccg_cocr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x
 {
     return ccg::solve_ex<ccg::M_COCR>(n, A, lda, y, x, tol, maxit, flags, work, work_bytes,
                                       res, hist, stream);
+}
+
+size_t ccg_t3_op_bytes(int64_t m)
+{
+    if (m < 1 || m > ccg::kT3MaxEdge) return 0;
+    return ccg::t3_op_layout(m).total;
+}
+
+size_t ccg_t3_workspace_bytes(int method, int64_t m)
+{
+    if (m < 1 || m > ccg::kT3MaxEdge) return 0;
+    if (method != CCG_WS_T3_MATVEC && method != CCG_WS_BICGSTAB && method != CCG_WS_COCG &&
+        method != CCG_WS_COCR)
+        return 0;
+    return ccg::t3_workspace(method, m);
+}
+
+int ccg_t3_setup(int64_t m, const ccg_z* table, void* op, size_t op_bytes, void* stream)
+{
+    return ccg::t3_setup_impl(m, table, op, op_bytes, stream);
+}
+
+int ccg_t3_matvec(int64_t m, const void* op, const ccg_z* x, ccg_z* y, void* work,
+                  size_t work_bytes, void* stream)
+{
+    return ccg::t3_matvec_impl(m, op, x, y, work, work_bytes, stream);
+}
+
+int ccg_t3_bicgstab_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double tol,
+                       int32_t maxit, uint32_t flags, void* work, size_t work_bytes,
+                       ccg_result* res, ccg_hist* hist, void* stream)
+{
+    return ccg::t3_solve<ccg::M_BICG>(m, op, y, x, tol, maxit, flags, work, work_bytes, res,
+                                      hist, stream);
+}
+
+int ccg_t3_cocg_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double tol,
+                   int32_t maxit, uint32_t flags, void* work, size_t work_bytes, ccg_result* res,
+                   ccg_hist* hist, void* stream)
+{
+    return ccg::t3_solve<ccg::M_COCG>(m, op, y, x, tol, maxit, flags, work, work_bytes, res,
+                                      hist, stream);
+}
+
+int ccg_t3_cocr_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double tol,
+                   int32_t maxit, uint32_t flags, void* work, size_t work_bytes, ccg_result* res,
+                   ccg_hist* hist, void* stream)
+{
+    return ccg::t3_solve<ccg::M_COCR>(m, op, y, x, tol, maxit, flags, work, work_bytes, res,
+                                      hist, stream);
 }
 
 }  // extern "C"

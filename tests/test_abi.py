@@ -123,3 +123,38 @@ def test_server_argument_errors_are_rejected_on_the_host(lib):
         b = ccg.ccg_server_request_bytes(n, k)
         assert b >= 16 * n * n + 2 * 16 * n * k + 15 * 16 * n * k
         assert b % 256 == 0
+
+
+def test_structured_argument_errors_are_rejected_on_the_host(lib):
+    from paper_1208_4869_amd import ccg
+    from paper_1208_4869_amd.ccg import _Result
+    P = ctypes.c_void_p
+    d = P(256)
+    assert ccg.ccg_t3_op_bytes(0) == 0 and ccg.ccg_t3_op_bytes(129) == 0
+    M = 64  # padded edge at m = 20
+    assert ccg.ccg_t3_op_bytes(20) >= 2 * 16 * M ** 3
+    assert ccg.ccg_t3_workspace_bytes(ccg.WS_T3_MATVEC, 20) >= 16 * (M * 400 + M * M * 20)
+    assert ccg.ccg_t3_workspace_bytes(ccg.WS_CGNR, 20) == 0  # no structured CGNR
+    big = 1 << 30
+    assert lib.ccg_t3_setup(0, d, d, big, None) == -1
+    assert lib.ccg_t3_setup(129, d, d, big, None) == -1
+    assert lib.ccg_t3_setup(4, None, d, big, None) == -2
+    assert lib.ccg_t3_setup(4, d, P(264), big, None) == -3
+    assert lib.ccg_t3_setup(4, d, d, 64, None) == -4
+    assert lib.ccg_t3_matvec(0, None, None, None, None, 0, None) == 0
+    assert lib.ccg_t3_matvec(4, None, d, d, d, big, None) == -2
+    assert lib.ccg_t3_matvec(4, d, None, d, d, big, None) == -3
+    assert lib.ccg_t3_matvec(4, d, d, None, d, big, None) == -4
+    assert lib.ccg_t3_matvec(4, d, d, d, P(300), big, None) == -5
+    assert lib.ccg_t3_matvec(4, d, d, d, d, 16, None) == -6
+    res = _Result()
+    for fn in (lib.ccg_t3_bicgstab_ex, lib.ccg_t3_cocg_ex, lib.ccg_t3_cocr_ex):
+        ok = [4, d, d, d, 1e-10, 10, 0, d, big, ctypes.byref(res), None, None]
+        for pos, bad in ((0, -1), (0, 129), (1, None), (2, None), (3, None), (4, 0.0),
+                         (5, -1), (6, 2), (7, None), (8, 16), (9, None)):
+            args = list(ok)
+            args[pos] = bad
+            assert fn(*args) == -(pos + 1), (fn, pos)
+        args = list(ok)
+        args[0] = 0
+        assert fn(*args) == 0 and res.info == 0

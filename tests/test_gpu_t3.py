@@ -1,0 +1,162 @@
+"""GPU tests of the structured (three-level Toeplitz) product and the solvers
+that use it, against the oracle's dense product and solvers on the same
+matrix.
+
+The oracle defines the product as the dense A x with A_ij = T(p_i - p_j); the
+FFT convolution reaches it up to rounding.  The bound used: a radix-2 FFT of
+length M has a normwise relative error of at most about log2(M) * 5u per
+transform; a product does a forward and an inverse transform along 3 axes
+and one pointwise product, and the circulant's norm is at most sum |T|, so
+||y_fft - A x|| <= 30 log2(M) u (sum |T|) ||x|| (a factor of 2 to spare)."""
+import numpy as np
+import pytest
+
+from gpu_util import U, dev, host_relres
+from paper_1208_4869_amd import ccg, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dense_from_table(table, m):
+    off = inputs.lattice_offsets(m)
+    c = inputs.lattice_center(m)
+    return table[c + off[:, None] - off[None, :]]
+
+
+def fft_bound(table, m, x):
+    M = 1
+    while M < 2 * m - 1:
+        M *= 2
+    lg = max(np.log2(M), 1.0)
+    return 30 * lg * U * np.abs(table).sum() * np.linalg.norm(x)
+
+
+def random_table(m, seed):
+    rng = np.random.default_rng(seed)
+    return inputs.cn01(rng, (2 * m - 1) ** 3)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8, 13, 20])
+def test_product_random_table(orc, m):
+    """A kernel with no symmetry (T(d) != T(-d)): the dense product of the
+    oracle on the matrix built from the table, within the FFT bound."""
+    table = random_table(m, 100 + m)
+    A = dense_from_table(table, m)
+    x = inputs.cn01(np.random.default_rng(m), m ** 3)
+    op = ccg.T3Operator(m, table)
+    y = op.matvec(dev(x)).cpu().numpy()
+    ref = orc.matvec(A, x)
+    err = np.linalg.norm(y - ref)
+    assert err <= fft_bound(table, m, x), (m, err, fft_bound(table, m, x))
+    # in place and repeatable bit for bit
+    xd = dev(x)
+    y2 = op.matvec(xd, xd).cpu().numpy()
+    assert np.array_equal(y2, y)
+
+
+@pytest.mark.parametrize("m", [6, 20])
+def test_product_lattice_matches_dense_gpu(orc, m):
+    """The lattice kernel: the structured product, the oracle's dense product
+    and the dense GPU product agree within the bound."""
+    table = inputs.lattice_table(m)
+    A = inputs.lattice_matrix(m)
+    x = inputs.cn01(np.random.default_rng(7), m ** 3)
+    y = ccg.T3Operator(m, table).matvec(dev(x)).cpu().numpy()
+    ref = orc.matvec(A, x)
+    yd = ccg.ccg_matvec(ccg.OP_N, dev(A), dev(x)).cpu().numpy()
+    bound = fft_bound(table, m, x)
+    assert np.linalg.norm(y - ref) <= bound
+    assert np.linalg.norm(y - yd) <= 2 * bound
+
+
+def sampled_rows(table, m, x, rows):
+    """(A x)_i for sampled rows i, from the definition A_ij = T(p_i - p_j)."""
+    off = inputs.lattice_offsets(m)
+    c = inputs.lattice_center(m)
+    return np.array([np.dot(table[c + off[i] - off], x) for i in rows])
+
+
+@pytest.mark.parametrize("m,seed", [(33, 1), (64, 2), (100, 3)])
+def test_product_large_sampled(m, seed):
+    """Padded grids of 128 and 256 points per edge (two and four points per
+    lane): sampled rows of the product against their direct sums."""
+    table = random_table(m, seed)
+    rng = np.random.default_rng(seed + 50)
+    x = inputs.cn01(rng, m ** 3)
+    y = ccg.T3Operator(m, table).matvec(dev(x)).cpu().numpy()
+    rows = np.concatenate([[0, m ** 3 - 1, m - 1, m * m - 1],
+                           rng.integers(0, m ** 3, 40)])
+    want = sampled_rows(table, m, x, rows)
+    # per-row share of the normwise bound: every row is at most the norm
+    assert np.max(np.abs(y[rows] - want)) <= fft_bound(table, m, x)
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "cocg", "cocr"])
+@pytest.mark.parametrize("m", [6, 12, 20])
+def test_solvers_lattice(orc, method, m):
+    """Structured solves of the lattice system against the oracle on the
+    dense matrix: true residual (host, dense A) <= tol, forward error within
+    100x the oracle's, iterations within 1."""
+    import torch
+    A, xt, y = inputs.lattice_system(m, 2)
+    op = ccg.T3Operator(m, inputs.lattice_table(m))
+    x = torch.full((m ** 3,), float("nan"), dtype=torch.complex128, device="cuda")
+    res = getattr(op, method)(dev(y), x, 1e-10, 1000, flags=ccg.X0_ZERO)
+    xg = x.cpu().numpy()
+    ref = getattr(orc, method)(A, y, tol=1e-10, maxit=1000)
+    rel, slack = host_relres(A, xg, y)
+    assert res.info == 0 and ref.info == 0, (res, ref.info)
+    assert rel <= 1e-10 + slack, rel
+    assert abs(res.iters - ref.iters) <= 1, (res.iters, ref.iters)
+    fe = np.linalg.norm(xg - xt) / np.linalg.norm(xt)
+    fe_ref = np.linalg.norm(ref.x - xt) / np.linalg.norm(xt)
+    assert fe <= 100 * max(fe_ref, 1e-13), (fe, fe_ref)
+
+
+def test_solver_warm_start_zero_rhs_nonfinite_budget(orc):
+    import torch
+    m = 5
+    A, xt, y = inputs.lattice_system(m, 3)
+    op = ccg.T3Operator(m, inputs.lattice_table(m))
+    n = m ** 3
+    # general x0 (set-up product y - A x0)
+    x0 = inputs.cn01(np.random.default_rng(9), n)
+    x = dev(x0)
+    res = op.bicgstab(dev(y), x)
+    rel, slack = host_relres(A, x.cpu().numpy(), y)
+    ref = orc.bicgstab(A, y, x0=x0)
+    assert res.info == 0 and rel <= 1e-10 + slack
+    assert abs(res.iters - ref.iters) <= 1
+    # y = 0 with a guess: x = 0, info 0
+    x = dev(x0)
+    res = op.cocr(dev(np.zeros(n, np.complex128)), x)
+    assert res.info == 0 and np.all(x.cpu().numpy() == 0)
+    # NaN in y: info 4, x untouched
+    ybad = y.copy()
+    ybad[3] = np.nan
+    x = dev(x0)
+    res = op.cocg(dev(ybad), x)
+    assert res.info == 4 and np.array_equal(x.cpu().numpy(), x0)
+    # budget
+    x = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    res = op.bicgstab(dev(y), x, maxit=1, flags=ccg.X0_ZERO)
+    ref = orc.bicgstab(A, y, maxit=1)
+    assert res.info == 1 and ref.info == 1 and res.matvecs == ref.matvecs
+
+
+def test_solver_large_lattice_sampled():
+    """A 40^3 lattice (n = 64000, dense A would take 65 GB): BiCGSTAB with the
+    structured product; sampled rows of the true residual from the table."""
+    import torch
+    m = 40
+    table = inputs.lattice_table(m)
+    rng = np.random.default_rng(11)
+    y = inputs.cn01(rng, m ** 3)
+    op = ccg.T3Operator(m, table)
+    x = torch.zeros(m ** 3, dtype=torch.complex128, device="cuda")
+    res = op.bicgstab(dev(y), x, 1e-10, 1000, flags=ccg.X0_ZERO)
+    assert res.info == 0 and res.relres_true <= 1e-10
+    xg = x.cpu().numpy()
+    rows = rng.integers(0, m ** 3, 40)
+    r = y[rows] - sampled_rows(table, m, xg, rows)
+    assert np.max(np.abs(r)) <= 1e-10 * np.linalg.norm(y) + fft_bound(table, m, xg)
