@@ -76,6 +76,8 @@ def parse():
                    help="skip the 26^3 mixed-precision leg")
     p.add_argument("--no-block", action="store_true",
                    help="skip the 64 right-hand-side block leg")
+    p.add_argument("--no-structured", action="store_true",
+                   help="skip the structured (FFT) lattice product leg")
     p.add_argument("--no-serve", action="store_true",
                    help="skip the continuous-batching serving leg")
     p.add_argument("--serve-requests", type=int, default=512)
@@ -384,6 +386,69 @@ def serve_leg(nreq, rate):
             "all_converged": ok, "bitwise_equal_to_alone": bool(same)}
 
 
+def t3_bytes(m):
+    """Algorithmic HBM bytes of one structured product: x and y, the kernel
+    transform (M^3), and the two intermediate grids, each written once and
+    read once per direction (G1: M m^2, G2: M^2 m)."""
+    M = 1
+    while M < 2 * m - 1:
+        M *= 2
+    return 16.0 * (2 * m ** 3 + M ** 3 + 4 * M * m * m + 4 * M * M * m), M
+
+
+def structured_leg(steps):
+    """The lattice systems with the structured product (zero-padded 3-D FFT
+    convolution, ccg_t3_*): product time per lattice edge, and BiCGSTAB /
+    COCG / COCR solves of the 20^3, 26^3 and 64^3 lattices (x_true seeds 1,
+    2, 3 as in the dense legs; y = A x_true by the structured product)."""
+    import torch
+
+    from paper_1208_4869_amd import ccg, inputs
+    out = {"products": [], "solves": []}
+    for m in (20, 26, 64, 100):
+        op = ccg.T3Operator(m, inputs.lattice_table(m))
+        x = torch.from_numpy(inputs.cn01(np.random.default_rng(m), m ** 3)).cuda()
+        y = torch.empty_like(x)
+        work = op.workspace(ccg.WS_T3_MATVEC)
+        t = time_kernel(lambda: op.matvec(x, y, work), 20)
+        b, M = t3_bytes(m)
+        out["products"].append({"m": m, "n": m ** 3, "M": M, "us": t * 1e6,
+                                "bytes": b, "gbs": b / t / 1e9,
+                                "dense_bytes": 16.0 * m ** 6})
+        log("structured product m=%d (n=%d, M=%d): %.1f us, %.0f GB/s of %.3g bytes"
+            % (m, m ** 3, M, t * 1e6, b / t / 1e9, b))
+        del op, work
+    for m, seed in ((LATTICE_M, X_SEED), (26, 2), (64, 3)):
+        op = ccg.T3Operator(m, inputs.lattice_table(m))
+        n = m ** 3
+        xt = torch.from_numpy(inputs.cn01(np.random.default_rng(seed), n)).cuda()
+        yv = op.matvec(xt)
+        for name in ("bicgstab", "cocg", "cocr"):
+            meth = {"bicgstab": ccg.WS_BICGSTAB, "cocg": ccg.WS_COCG,
+                    "cocr": ccg.WS_COCR}[name]
+            work = op.workspace(meth)
+            xs = torch.empty_like(xt)
+            fn = getattr(op, name)
+            fn(yv, xs, TOL, MAXIT, flags=1, work=work)
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                r = fn(yv, xs, TOL, MAXIT, flags=1, work=work)
+                lat.append(time.perf_counter() - t0)
+            fe = float(torch.linalg.norm(xs - xt) / torch.linalg.norm(xt))
+            out["solves"].append({"m": m, "n": n, "method": name,
+                                  "solves_per_s": 1.0 / np.mean(lat),
+                                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                  "iters": r.iters, "matvecs": r.matvecs, "info": r.info,
+                                  "relres_true_device": r.relres_true, "fwd_err": fe})
+            log("structured %s m=%d: %.0f solves/s (%d its)" % (name, m, 1.0 / np.mean(lat),
+                                                               r.iters))
+        del op
+    torch.cuda.empty_cache()
+    return out
+
+
 def profile_kernels(A, y):
     """A short, fixed mix for rocprofv3: a device copy of known size (the
     reference for scaling the HBM byte counters), A x, A^H x, the complex64
@@ -534,6 +599,8 @@ def main():
         out["mixed"] = mixed_leg(max(args.steps // 3, 3))
     if not args.no_block:
         out["block"] = block_leg(A, A_h, max(args.steps // 3, 2))
+    if not args.no_structured:
+        out["structured"] = structured_leg(max(args.steps // 3, 3))
     if not args.no_serve:
         out["serve"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
