@@ -1,5 +1,7 @@
-// ccg_solvers.hip -- BiCGSTAB and CGNR for dense complex128 A x = y on
-// gfx950, and the matrix-vector entry points of the C ABI (include/ccg.h).
+// ccg_solvers.hip -- BiCGSTAB, CGNR, COCG and COCR for complex128 A x = y on
+// gfx950 (dense A, or the structured lattice operator of ccg_t3.h), the
+// mixed-precision BiCGSTAB, and the matrix-vector entry points of the C ABI
+// (include/ccg.h).
 //
 // Methods: the bicgstab and cgnr codes of the PIM90 set (Codes, section 2.1),
 // with the matrix-vector product apart from the iteration (Abstract; Usage:
@@ -14,15 +16,17 @@
 //   CGNR slot:     w = A p (+ |w|^2) | x, r update (+ |r|^2) | A^H r band
 //                  partials | z = band sum (+ |z|^2) | p-update
 //
-// Every reduction is fused into the kernel that produces its operand; the
-// block partials go to the last block of the grid (atomic ticket), which adds
-// them in a fixed order and runs the method's scalar step (alpha, omega,
-// beta, rho, stop and breakdown tests) in device memory.  No scalar crosses to
-// the host during a solve.  A device phase word drives the control flow:
-// every kernel reads it on entry and does its part only in the phases where it
-// has one, so the host enqueues the same slot over and over and learns that
-// the solve is over from a one-word status copied to pinned host memory at
-// the end of each slot, a few slots behind the device.
+// Every reduction is fused into the kernel that produces its operand, which
+// writes one partial sum per block with plain stores; the next kernel on the
+// stream starts by adding those partials in a fixed order (every block does
+// it and gets the same bits) and runs the method's scalar step (alpha, omega,
+// beta, rho, stop and breakdown tests) in device memory; block 0 publishes the
+// new state to the other of two state copies.  No atomic read-modify-write;
+// no scalar crosses to the host during a solve.  A device phase word drives
+// the control flow: every kernel reads it on entry and does its part only in
+// the phases where it has one, so the host enqueues the same slot over and
+// over and learns that the solve is over from a one-word status copied to
+// pinned host memory at the end of each slot, a slot or two behind the device.
 #include <hip/hip_runtime.h>
 
 #include <climits>
