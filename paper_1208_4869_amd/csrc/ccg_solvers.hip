@@ -59,6 +59,7 @@ struct Args {
     ccg_hist* hist;
     bool vec16;                  // complex64 A with 16-byte aligned rows
     T3Geom t3;                   // structured product (A unused)
+    int* status;                 // pinned word: the phase after the prologue, or null
 };
 
 constexpr int kR = 4;   // rows per block in A x
@@ -79,6 +80,10 @@ __device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d
         if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr);
         __syncthreads();
     }
+    // the first kernel of a slot reports where the previous slot left the
+    // method (a plain store to pinned host memory, system scope)
+    if (a.status && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(a.status, L.phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // End of every solver kernel: block 0 writes the state for the next kernel,
@@ -101,23 +106,29 @@ __device__ __forceinline__ void publish(const Args& a, int q, const SolverState&
 
 // --------------------------------------------------------- common kernels
 
+__device__ __forceinline__ void init_state(SolverState& o, int maxit, double tol2,
+                                           int no_confirm)
+{
+    o.phase = PH_RUN;
+    o.restart = 1;
+    o.info = -1;
+    o.iters = o.matvecs = o.confirms = 0;
+    o.maxit = maxit;
+    o.pending = PK_NONE;
+    o.pending_blocks = 0;
+    o.no_confirm = no_confirm;
+    o.pad1 = o.pad2 = 0;
+    o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
+    o.tol2 = tol2;
+    o.relres_rec = o.relres_true = __builtin_nan("");
+    o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
+}
+
 __global__ void k_init(SolverState* st, int maxit, double tol2, int no_confirm)
 {
     if (threadIdx.x == 0) {
         SolverState o;
-        o.phase = PH_RUN;
-        o.restart = 1;
-        o.info = -1;
-        o.iters = o.matvecs = o.confirms = 0;
-        o.maxit = maxit;
-        o.pending = PK_NONE;
-        o.pending_blocks = 0;
-        o.no_confirm = no_confirm;
-        o.pad1 = o.pad2 = 0;
-        o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
-        o.tol2 = tol2;
-        o.relres_rec = o.relres_true = __builtin_nan("");
-        o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
+        init_state(o, maxit, tol2, no_confirm);
         *st = o;
     }
 }
@@ -132,12 +143,18 @@ __global__ void k_status(Args a, int q, int* ring_slot)
     publish(a, q, L, PK_NONE, 0);
 }
 
-// ||y||^2 (the stop threshold follows in the next kernel's step).  T is the
-// vector element type: d2 (complex128) or f2 (complex64, inner solves).
+// First kernel of a solve: the initial state (every block builds the same
+// record; block 0 publishes it) and ||y||^2 (the stop threshold follows in
+// the next kernel's step).  T is the vector element type: d2 (complex128) or
+// f2 (complex64, inner solves).
 template <class T = d2>
-__global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q)
+__global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q, int maxit, double tol2,
+                                                   int no_confirm)
 {
-    SOLVER_PROLOGUE();
+    __shared__ SolverState L;
+    __shared__ d2 lds[kMaxWaves];
+    if (threadIdx.x == 0) init_state(L, maxit, tol2, no_confirm);
+    __syncthreads();
     const T* y = (const T*)a.y;
     d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock)
@@ -227,42 +244,47 @@ __device__ __forceinline__ const d2* role_input(const Args& a, int mode)
 }
 
 // Element i of a product of role RO is val: store what the role stores and
-// add its dot-product terms to pv0, pv1 (in FP64; complex64 vectors are
-// rounded on store and the terms use the stored values).
+// return its dot-product terms (in FP64; complex64 vectors are rounded on
+// store and the terms use the stored values).
+struct Terms {
+    d2 t0, t1;
+};
+
 template <Role RO, class T>
-__device__ __forceinline__ void role_finish(const Args& a, int mode, int i, d2 val, d2& pv0,
-                                            d2& pv1)
+__device__ __forceinline__ Terms role_finish(const Args& a, int mode, int i, const d2 val)
 {
+    const d2 z = d2{0.0, 0.0};
     const bool resid = role_setup<RO>() || mode == PH_CONFIRM;
     if (resid) {
         T* r = (T*)a.r;
         stv(r, i, ldv((const T*)a.y, i) - val);
         const d2 ri = ldv(r, i);
         if (RO == ROLE_SETUP_B || RO == ROLE_V) stv((T*)a.rh, i, ri);
-        pv0.x += cabs2(ri);
-        if (RO == ROLE_SETUP_G || RO == ROLE_Q) pv1 = cfma(ri, ri, pv1);
-    } else if (RO == ROLE_Q) {
+        const d2 b = (RO == ROLE_SETUP_G || RO == ROLE_Q) ? cfma(ri, ri, z) : z;
+        return Terms{d2{cabs2(ri), 0.0}, b};
+    }
+    if (RO == ROLE_Q) {
         a.v[i] = val;  // q
-        pv0 = cfma(a.p[i], val, pv0);
-    } else if (RO == ROLE_U) {
+        return Terms{cfma(a.p[i], val, z), z};
+    }
+    if (RO == ROLE_U) {
         a.z[i] = val;  // u
-        pv0 = cfma(a.r[i], val, pv0);
-    } else if (RO == ROLE_V) {
+        return Terms{cfma(a.r[i], val, z), z};
+    }
+    if (RO == ROLE_V) {
         T* v = (T*)a.v;
         stv(v, i, val);
-        val = ldv(v, i);
-        pv0 = cfma_conj(ldv((const T*)a.rh, i), val, pv0);
-        pv1.x += cabs2(val);
-    } else if (RO == ROLE_T) {
+        const d2 vs = ldv(v, i);
+        return Terms{cfma_conj(ldv((const T*)a.rh, i), vs, z), d2{cabs2(vs), 0.0}};
+    }
+    if (RO == ROLE_T) {
         T* tv = (T*)a.t;
         stv(tv, i, val);
-        val = ldv(tv, i);
-        pv0 = cfma_conj(val, ldv((const T*)a.s, i), pv0);
-        pv1.x += cabs2(val);
-    } else {  // ROLE_W
-        a.w[i] = val;
-        pv0.x += cabs2(val);
+        const d2 ts = ldv(tv, i);
+        return Terms{cfma_conj(ts, ldv((const T*)a.s, i), z), d2{cabs2(ts), 0.0}};
     }
+    a.w[i] = val;  // ROLE_W
+    return Terms{d2{cabs2(val), 0.0}, z};
 }
 
 // The reduction a product of role RO leaves for the next kernel.
@@ -303,7 +325,11 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
         gemv_n_block<kR, kU, kWN>(a.A, a.lda, n, in, row0, red);
     // thread r of the first wavefront finishes row row0 + r
     const int i = row0 + t;
-    if (t < kR && i < n) role_finish<RO, T>(a, mode, i, gemv_n_row_total<kR, kWN>(red, t), pv0, pv1);
+    if (t < kR && i < n) {
+        const Terms tm = role_finish<RO, T>(a, mode, i, gemv_n_row_total<kR, kWN>(red, t));
+        pv0 = tm.t0;
+        pv1 = tm.t1;
+    }
     write_partials(pv0, pv1, a.part[q ^ 1], lds);
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
@@ -371,7 +397,11 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int ix = t3_point(r);
-            if (ix < a.t3.m) role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[r], pv0, pv1);
+            if (ix < a.t3.m) {
+                const Terms tm = role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[r]);
+                pv0 += tm.t0;
+                pv1 += tm.t1;
+            }
         }
     }
     write_partials(pv0, pv1, a.part[q ^ 1], lds);
@@ -910,15 +940,17 @@ template <Role RO, int R>
 static void launch_t3_role(const Args& a, int& q, hipStream_t s)
 {
     const int64_t m = a.t3.m, M = a.t3.M;
+    Args b = a;  // only the first pass reports a status word
+    b.status = nullptr;
     k_t3_x<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
     q ^= 1;
-    k_t3_y<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(a, q);
+    k_t3_y<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(b, q);
     q ^= 1;
-    k_t3_z<RO, R><<<t3_blocks(M * M), kBlock, 0, s>>>(a, q);
+    k_t3_z<RO, R><<<t3_blocks(M * M), kBlock, 0, s>>>(b, q);
     q ^= 1;
-    k_t3_yi<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(a, q);
+    k_t3_yi<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(b, q);
     q ^= 1;
-    k_t3_role<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
+    k_t3_role<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(b, q);
     q ^= 1;
 }
 
@@ -939,9 +971,40 @@ static void launch_product(const Args& a, int& q, hipStream_t s)
     }
 }
 
-// Enqueue set-up, then slots until the status ring reports PH_DONE.  Every
-// solver kernel reads state copy q and writes copy q ^ 1; the host tracks q
-// across the launches it makes.  S3: products by the structured operator.
+// Wait until the pinned status word idx has been written (it holds
+// kStatusEmpty until then) and return it.  While waiting, the stream is
+// polled now and then so that a failed launch ends the wait with its error.
+constexpr int kStatusEmpty = -1;
+
+static int wait_status(SyncCtx* sc, int idx, hipStream_t s, int* phase)
+{
+    for (uint64_t spin = 1;; ++spin) {
+        const int v = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
+        if (v != kStatusEmpty) {
+            *phase = v;
+            return 0;
+        }
+        if ((spin & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {  // drained: the word must be there now
+                const int w = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
+                if (w == kStatusEmpty) return (int)hipErrorUnknown;
+                *phase = w;
+                return 0;
+            }
+            if (e != hipErrorNotReady) return (int)e;
+        }
+        __builtin_ia32_pause();
+    }
+}
+
+// Enqueue set-up, then slots until the status word of a slot reads PH_DONE.
+// Every solver kernel reads state copy q and writes copy q ^ 1; the host
+// tracks q across the launches it makes.  The status of slot j is written by
+// the first kernel of slot j + 1 after its prologue (the last slot the host
+// may enqueue is followed by a status kernel), into pinned word j mod kRing,
+// which the host clears before it enqueues the writer.  S3: products by the
+// structured operator.
 template <int M, class T = d2, bool S3 = false>
 static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                       ccg_result* res, hipStream_t s, int no_confirm = 0)
@@ -956,8 +1019,7 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     int q = 0;
     auto flip = [&q]() { const int cur = q; q ^= 1; return cur; };
 
-    k_init<<<1, 64, 0, s>>>(a.st[0], maxit, tol2, no_confirm);
-    k_norm_y<T><<<gE, kBlock, 0, s>>>(a, flip());
+    k_norm_y<T><<<gE, kBlock, 0, s>>>(a, flip(), maxit, tol2, no_confirm);
     if (flags & CCG_X0_ZERO)
         k_setup_x0zero<M == M_COCR ? M_CGNR : M, T><<<gE, kBlock, 0, s>>>(a, flip());
     else if (M == M_BICG)
@@ -975,35 +1037,47 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     const int ahead = S3 ? 2 : lookahead(a.n);  // structured slots are short
     for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
+            Args f = a;  // the slot's first kernel reports slot - 1
+            f.status = nullptr;
+            if (slot > 0) {
+                const int w = (int)((slot - 1) % kRing);
+                __atomic_store_n(&sc->ring_h[w], kStatusEmpty, __ATOMIC_RELEASE);
+                f.status = sc->ring_d + w;
+            }
             if (M == M_BICG) {
-                k_bicg_p<T><<<gE, kBlock, 0, s>>>(a, flip());
+                k_bicg_p<T><<<gE, kBlock, 0, s>>>(f, flip());
                 launch_product<ROLE_V, T, S3>(a, q, s);
                 k_bicg_s<T><<<gE, kBlock, 0, s>>>(a, flip());
                 launch_product<ROLE_T, T, S3>(a, q, s);
                 k_bicg_xr<T><<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR) {
-                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(a, flip());
+                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(f, flip());
                 k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cgnr_z1<<<gC, kBlock, 0, s>>>(a, flip());
                 k_cgnr_z2<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cgnr_p<<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_COCG) {
-                k_cocg_p<<<gE, kBlock, 0, s>>>(a, flip());
+                k_cocg_p<<<gE, kBlock, 0, s>>>(f, flip());
                 launch_product<ROLE_Q, T, S3>(a, q, s);
                 k_cocg_xr<<<gE, kBlock, 0, s>>>(a, flip());
             } else {
-                launch_product<ROLE_U, T, S3>(a, q, s);
+                launch_product<ROLE_U, T, S3>(f, q, s);
                 k_cocr_pw<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cocr_xr<<<gE, kBlock, 0, s>>>(a, flip());
             }
-            k_status<<<1, kBlock, 0, s>>>(a, flip(), sc->ring_d + slot % kRing);
+            if (slot == max_slots - 1) {
+                const int w = (int)(slot % kRing);
+                __atomic_store_n(&sc->ring_h[w], kStatusEmpty, __ATOMIC_RELEASE);
+                k_status<<<1, kBlock, 0, s>>>(a, flip(), sc->ring_d + w);
+            }
             if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-            if ((e = hipEventRecord(sc->ev[slot % kRing], s)) != hipSuccess) return (int)e;
         }
         const int64_t seen = slot - ahead;
         if (seen >= 0) {
-            if ((e = hipEventSynchronize(sc->ev[seen % kRing])) != hipSuccess) return (int)e;
-            if (__atomic_load_n(&sc->ring_h[seen % kRing], __ATOMIC_ACQUIRE) == PH_DONE) break;
+            int phase = 0;
+            int rc = wait_status(sc, (int)(seen % kRing), s, &phase);
+            if (rc) return rc;
+            if (phase == PH_DONE) break;
         }
     }
     SolverState hs;

@@ -158,3 +158,14 @@ def test_structured_argument_errors_are_rejected_on_the_host(lib):
         args = list(ok)
         args[0] = 0
         assert fn(*args) == 0 and res.info == 0
+
+
+def test_build_flags_kernels_with_scratch():
+    from paper_1208_4869_amd import build
+    remarks = "\n".join([
+        "a.hip:1:1: remark: Function Name: _Z3fooPi [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark: Function Name: _Z3barPi [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 48 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert build.scratch_kernels(remarks) == [("_Z3barPi", 48)]
