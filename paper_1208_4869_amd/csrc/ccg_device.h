@@ -118,14 +118,31 @@ __device__ __forceinline__ void write_partials(d2 v0, d2 v1, d2* part, d2* lds)
 
 // Totals of the nblocks partial pairs written by the previous kernel.  Every
 // thread of the block takes part in the loads; the totals are valid in
-// thread 0.  Thread t adds blocks t, t + blockDim.x, ... in increasing order.
+// thread 0.  Thread t adds blocks t, t + blockDim.x, ... in increasing order,
+// with the loads of eight of them in flight at a time.
 __device__ __forceinline__ void reduce_partials(const d2* part, int nblocks, d2* lds,
                                                 d2& t0, d2& t1)
 {
+    constexpr int kInFlight = 8;
+    const int step = blockDim.x;
     d2 a0 = d2{0.0, 0.0}, a1 = d2{0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        a0 += part[2 * b];
-        a1 += part[2 * b + 1];
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kInFlight * step) {
+        d2 u0[kInFlight], u1[kInFlight];
+#pragma unroll
+        for (int m = 0; m < kInFlight; ++m) {
+            const int b = b0 + m * step;
+            if (b < nblocks) {
+                u0[m] = part[2 * b];
+                u1[m] = part[2 * b + 1];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kInFlight; ++m) {
+            if (b0 + m * step < nblocks) {
+                a0 += u0[m];
+                a1 += u1[m];
+            }
+        }
     }
     t0 = block_sum(a0, lds);
     t1 = block_sum(a1, lds);

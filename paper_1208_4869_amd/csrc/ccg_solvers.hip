@@ -972,8 +972,11 @@ static void launch_product(const Args& a, int& q, hipStream_t s)
 }
 
 // Wait until the pinned status word idx has been written (it holds
-// kStatusEmpty until then) and return it.  While waiting, the stream is
-// polled now and then so that a failed launch ends the wait with its error.
+// kStatusEmpty until then) and return it.  The wait only reads host memory;
+// after about a millisecond without the word it also polls the stream, so
+// that a failed launch ends the wait with its error.  (Any stream query or
+// event wait makes the runtime open the next dispatch with a cache
+// invalidation, a few microseconds per slot, so the fast path makes none.)
 constexpr int kStatusEmpty = -1;
 
 static int wait_status(SyncCtx* sc, int idx, hipStream_t s, int* phase)
@@ -984,7 +987,7 @@ static int wait_status(SyncCtx* sc, int idx, hipStream_t s, int* phase)
             *phase = v;
             return 0;
         }
-        if ((spin & 255) == 0) {
+        if (spin >= (1u << 14) && (spin & 1023) == 0) {
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {  // drained: the word must be there now
                 const int w = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
