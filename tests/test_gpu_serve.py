@@ -204,3 +204,35 @@ def test_serve_server_reuse_many_rounds():
     check_equal(got, [alone(A, Y) for A, Y, _ in reqs])
     assert stats["admitted"] == len(reqs)
     assert stats["peak_active"] <= 2
+
+
+def test_serve_full_size_mix(orc):
+    """The benchmark's request distribution (n in {512, 1024, 2048, 4096},
+    k in 1..8, dense family; 24 requests from one seed), arriving while
+    others iterate under a pool that cannot hold them all: every request
+    equals the block solver alone bit for bit, every column meets the
+    tolerance on the host, and sampled columns match the oracle."""
+    import torch
+    rng = np.random.default_rng(2024)
+    ns = rng.choice([512, 1024, 2048, 4096], 24)
+    ks = rng.integers(1, 9, 24)
+    reqs = [make_request(int(n), int(k), 500 + i) for i, (n, k) in enumerate(zip(ns, ks))]
+    pool = 3 * ccg.ccg_server_request_bytes(4096, 8)
+    got, stats = serve([(A, Y) for A, Y, _ in reqs], pool_bytes=pool, steps_between=1)
+    assert stats["completed"] == len(reqs) and stats["admission_waits"] > 0
+    for i, ((A, Y, Xt), (X, res)) in enumerate(zip(reqs, got)):
+        Xr, resr = alone(A, Y)
+        assert np.array_equal(X, Xr), i
+        for c in range(Y.shape[1]):
+            assert res[c].info == 0 and same_result(res[c], resr[c])
+            rel, slack = host_relres(A, X[:, c], Y[:, c])
+            assert rel <= 1e-10 + slack, (i, c, rel)
+        torch.cuda.empty_cache()
+    for i in (int(np.argmax(ns)), int(np.argmin(ns))):
+        A, Y, Xt = reqs[i]
+        ref = orc.bicgstab(A, Y[:, 0], tol=1e-10, maxit=1000)
+        X, res = got[i]
+        assert ref.info == 0 and abs(res[0].iters - ref.iters) <= 1
+        fe = np.linalg.norm(X[:, 0] - Xt[:, 0]) / np.linalg.norm(Xt[:, 0])
+        fe_ref = np.linalg.norm(ref.x - Xt[:, 0]) / np.linalg.norm(Xt[:, 0])
+        assert fe <= 100 * max(fe_ref, 1e-13)
