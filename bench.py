@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 METRIC = "BiCGSTAB solves/s at 1e-10 residual; matvec HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 BLOCK_RHS = 64
 BLOCK_SEED = 5
 LATTICE_M = 20
@@ -242,7 +243,42 @@ def block_leg(A, A_h, steps):
     rel = np.linalg.norm(Y_h - A_h @ Xg, axis=0) / np.linalg.norm(Y_h, axis=0)
     log("block: A P %.1f us (%.1f TFLOP/s); 64-column solve %.2f ms" % (
         tg * 1e6, flops / tg / 1e12, tb * 1e3))
+    # mixed precision: complex64 product on FP32 matrix cores + FP64 refinement
+    A32 = ccg.ccg_round_c64(A)
+    w32 = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATMAT_C64, n, k), dtype=torch.uint8,
+                      device="cuda")
+    t32 = time_kernel(lambda: ccg.ccg_matmat_c64(A32, P, Z, work=w32), 20)
+    wm = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_BLOCK_MIXED, n, k),
+                     dtype=torch.uint8, device="cuda")
+    Xm = torch.empty_like(P)
+    rm = ccg.ccg_bicgstab_block_mixed_ex(A, A32, Y, Xm, TOL, 10, 1e-5, MAXIT, flags=1, work=wm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rm = ccg.ccg_bicgstab_block_mixed_ex(A, A32, Y, Xm, TOL, 10, 1e-5, MAXIT, flags=1,
+                                             work=wm)
+    torch.cuda.synchronize()
+    tmix = (time.perf_counter() - t0) / steps
+    Xmg = Xm.cpu().numpy()
+    relm = np.linalg.norm(Y_h - A_h @ Xmg, axis=0) / np.linalg.norm(Y_h, axis=0)
+    fem = np.linalg.norm(Xmg - Xt, axis=0) / np.linalg.norm(Xt, axis=0)
+    fe64 = np.linalg.norm(Xg - Xt, axis=0) / np.linalg.norm(Xt, axis=0)
+    log("block mixed: complex64 A P %.1f us (%.1f TFLOP/s); 64-column solve %.2f ms" % (
+        t32 * 1e6, flops / t32 / 1e12, tmix * 1e3))
+    del A32
     return {"rhs": k, "solves_per_s": k / tb, "ms_per_block_solve": tb * 1e3,
+            "mixed": {"solves_per_s": k / tmix, "ms_per_block_solve": tmix * 1e3,
+                      "speedup_vs_fp64_block": tb / tmix,
+                      "max_outer": max(r.outer for r in rm),
+                      "max_inner_iters": max(r.inner_iters for r in rm),
+                      "all_converged": all(r.info == 0 for r in rm),
+                      "max_relres_true": float(relm.max()),
+                      "max_fwd_err": float(fem.max()),
+                      "max_fwd_err_fp64_block": float(fe64.max()),
+                      "gemm_c64": {"kernel": "k_cgemm (A32 P, FP32 MFMA)",
+                                   "launch_us": t32 * 1e6, "achieved": flops / t32 / 1e12,
+                                   "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": flops / t32 / 1e12 / FP32_PEAK_TFLOPS}},
             "max_iters": max(r.iters for r in res),
             "all_converged": all(r.info == 0 for r in res),
             "max_relres_true": float(rel.max()),

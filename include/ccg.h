@@ -93,7 +93,9 @@ enum {
     CCG_WS_COCG = 6,
     CCG_WS_COCR = 7,
     CCG_WS_BICGSTAB_MIXED = 8,
-    CCG_WS_T3_MATVEC = 9 /* scratch of ccg_t3_matvec (ccg_t3_workspace_bytes) */
+    CCG_WS_T3_MATVEC = 9, /* scratch of ccg_t3_matvec (ccg_t3_workspace_bytes) */
+    CCG_WS_MATMAT_C64 = 10,           /* scratch of ccg_matmat_c64 (nrhs = k) */
+    CCG_WS_BICGSTAB_BLOCK_MIXED = 11  /* ccg_bicgstab_block_mixed_ex (k <= 64) */
 };
 
 /* Outcome of a mixed-precision solve (host struct). */
@@ -273,6 +275,44 @@ int ccg_bicgstab_block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
                           const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
                           double tol, int32_t maxit, uint32_t flags, void* work,
                           size_t work_bytes, ccg_result* res, void* stream);
+
+/*
+ * Z = A32 B with A32 complex64 (the copy made by ccg_round_c64), B and Z
+ * complex128 n x k row-major: B is rounded to complex64 as it is read, the
+ * products accumulate in FP32 on the FP32 matrix cores
+ * (v_mfma_f32_16x16x4f32), each of the 8 K-slices is widened to FP64 and the
+ * slices are added in FP64 in a fixed order.  The product of the mixed block
+ * solver below.  Arguments: 1 n, 2 k, 3 A32, 4 lda32, 5 B, 6 ldb, 7 Z, 8 ldz,
+ * 9 work (256-byte aligned, >= ccg_workspace_bytes(CCG_WS_MATMAT_C64, n, k)),
+ * 10 work_bytes, 11 stream.  Asynchronous.
+ */
+int ccg_matmat_c64(int64_t n, int64_t k, const ccg_c* A32, int64_t lda32,
+                   const ccg_z* B, int64_t ldb, ccg_z* Z, int64_t ldz,
+                   void* work, size_t work_bytes, void* stream);
+
+/*
+ * Mixed-precision block BiCGSTAB: ccg_bicgstab_mixed_ex for k right-hand
+ * sides at once (1 <= k <= 64).  Per outer step the FP64 residual
+ * R = Y - A X (FP64 matrix cores); every column not yet within tol solves
+ * A32 D = R / ||R|| with the block solver on the complex64 product
+ * (ccg_matmat_c64) to tol_inner (recursive residual) and takes
+ * X += ||R|| D in FP64.  The inner Krylov vectors stay complex128 (O(n k)
+ * bytes; the complex64 copy halves the O(n^2) bytes of A).  Per column: info
+ * 0 within tol, 1 after maxit outer steps, 4 non-finite (x left as given);
+ * y = 0 gives x = 0.  Arguments: 1 n, 2 k, 3 A, 4 lda, 5 A32, 6 lda32, 7 Y,
+ * 8 ldy >= k, 9 X, 10 ldx >= k, 11 tol, 12 maxit (outer), 13 tol_inner
+ * (0 < tol_inner < 1), 14 maxit_inner >= 1, 15 flags (CCG_X0_ZERO or 0),
+ * 16 work (>= ccg_workspace_bytes(CCG_WS_BICGSTAB_BLOCK_MIXED, n, k)),
+ * 17 work_bytes, 18 res (host array of k ccg_mixed_result), 19 stream.
+ * Waits on stream.
+ */
+int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A,
+                                int64_t lda, const ccg_c* A32, int64_t lda32,
+                                const ccg_z* Y, int64_t ldy, ccg_z* X,
+                                int64_t ldx, double tol, int32_t maxit,
+                                double tol_inner, int32_t maxit_inner,
+                                uint32_t flags, void* work, size_t work_bytes,
+                                ccg_mixed_result* res, void* stream);
 
 /*
  * Structured product: A is a three-level Toeplitz matrix on an m x m x m

@@ -28,6 +28,8 @@ WS_COCG = 6
 WS_COCR = 7
 WS_BICGSTAB_MIXED = 8
 WS_T3_MATVEC = 9
+WS_MATMAT_C64 = 10
+WS_BICGSTAB_BLOCK_MIXED = 11
 X0_ZERO = 1
 SERVER_REJECTED = -1000
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
@@ -127,6 +129,12 @@ def load() -> ctypes.CDLL:
     lib.ccg_bicgstab_block_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, D,
                                           I32, U32, P, S, ctypes.POINTER(_Result),
                                           P]
+    lib.ccg_matmat_c64.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, S, P]
+    lib.ccg_matmat_c64.restype = ctypes.c_int
+    lib.ccg_bicgstab_block_mixed_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, I64,
+                                                D, I32, D, I32, U32, P, S,
+                                                ctypes.POINTER(_MixedResult), P]
+    lib.ccg_bicgstab_block_mixed_ex.restype = ctypes.c_int
     lib.ccg_t3_op_bytes.argtypes = [I64]
     lib.ccg_t3_op_bytes.restype = S
     lib.ccg_t3_workspace_bytes.argtypes = [ctypes.c_int, I64]
@@ -573,6 +581,62 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _rect64(M, n, what):
+    torch = _torch()
+    if not isinstance(M, torch.Tensor) or M.dtype != torch.complex64 or \
+            not M.is_cuda or M.dim() != 2 or M.shape[0] != n:
+        raise TypeError("%s must be an n x n complex64 CUDA tensor" % what)
+    if M.numel() > 0 and M.stride(1) != 1:
+        raise TypeError("%s must be row-major" % what)
+    return max(M.stride(0), M.shape[1], 1)
+
+
+def ccg_matmat_c64(A32, B, Z=None, work=None, stream=None):
+    """Z = A32 B (A32 complex64, B rounded to complex64, FP32 accumulation on
+    the matrix cores, FP64 slice sums); B and Z complex128."""
+    torch = _torch()
+    n = A32.shape[0]
+    lda32 = _rect64(A32, n, "A32")
+    k, ldb = _rect(B, n, "B")
+    if Z is None:
+        Z = torch.empty((n, k), dtype=torch.complex128, device=B.device)
+    kz, ldz = _rect(Z, n, "Z")
+    if kz != k:
+        raise TypeError("Z must have as many columns as B")
+    if work is None:
+        work = torch.empty(max(ccg_workspace_bytes(WS_MATMAT_C64, n, max(k, 1)), 256),
+                           dtype=torch.uint8, device=B.device)
+    _check(load().ccg_matmat_c64(n, k, A32.data_ptr(), lda32, B.data_ptr(), ldb,
+                                 Z.data_ptr(), ldz, work.data_ptr(),
+                                 work.numel() * work.element_size(), _stream(stream)),
+           "ccg_matmat_c64")
+    return Z
+
+
+def ccg_bicgstab_block_mixed_ex(A, A32, Y, X, tol=1e-10, maxit=10, tol_inner=1e-5,
+                                maxit_inner=1000, flags=0, work=None, stream=None):
+    """Mixed-precision block BiCGSTAB (k <= 64 columns); X in/out; returns k
+    MixedResults."""
+    torch = _torch()
+    n, lda = _mat(A)
+    lda32 = _rect64(A32, n, "A32")
+    k, ldy = _rect(Y, n, "Y")
+    kx, ldx = _rect(X, n, "X")
+    if kx != k:
+        raise TypeError("X must have as many columns as Y")
+    if work is None:
+        work = torch.empty(max(ccg_workspace_bytes(WS_BICGSTAB_BLOCK_MIXED, n, max(k, 1)), 256),
+                           dtype=torch.uint8, device=A.device)
+    res = (_MixedResult * max(k, 1))()
+    _check(load().ccg_bicgstab_block_mixed_ex(
+        n, k, A.data_ptr(), lda, A32.data_ptr(), lda32, Y.data_ptr(), ldy, X.data_ptr(), ldx,
+        float(tol), int(maxit), float(tol_inner), int(maxit_inner), int(flags),
+        work.data_ptr(), work.numel() * work.element_size(), res, _stream(stream)),
+        "ccg_bicgstab_block_mixed_ex")
+    return [MixedResult(r.info, r.outer, r.inner_iters, r.matvecs64, r.matvecs32,
+                        r.relres_true) for r in list(res)[:k]]
 
 
 # ------------------------------------------------ structured lattice operator

@@ -222,6 +222,154 @@ static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int 
     }
 }
 
+// ----------------------------------------------------- complex64 product
+
+// Slice s of Z = A32 B for the mixed-precision block solver: A32 complex64,
+// B complex128 rounded to complex64 as it is staged, products accumulated in
+// FP32 on the matrix cores (v_mfma_f32_16x16x4f32, four real products per
+// complex step as in zgemm_body), each slice result widened to FP64 on store
+// into the same slice buffer, so the FP64 slice sum and column kernels are
+// shared.  Tiles: 64 rows x 16 k per LDS stage (8 KB of A, as the FP64
+// kernel's 64 x 8).  Result register v of a lane holds row 4 lk + v, column
+// li (the v_mfma_f32_16x16x4f32 layout, unlike the FP64 instruction's
+// lk + 4 v; the integer-input product tests pin it).
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kKS32 = 16;
+
+static inline int kslice32_of(int64_t n)
+{
+    const int64_t per = (n + kSlices - 1) / kSlices;
+    return (int)(((per + kKS32 - 1) / kKS32) * kKS32);
+}
+
+template <int NT>
+__device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda, int n,
+                                           const d2* __restrict__ B, int64_t ldb, int ncols,
+                                           d2* __restrict__ Zp, int kslice, int bid)
+{
+    constexpr int AP = kKS32 + 1;
+    constexpr int AE = kRowsPerBlock * kKS32 / kBlock;  // 4
+    constexpr int BW = 16 * NT;
+    constexpr int BN = kKS32 * BW;
+    constexpr int BPT = (BN + kBlock - 1) / kBlock;
+    __shared__ f2 As[2][kRowsPerBlock * AP];
+    __shared__ f2 Bs[2][BN];
+    const int s = bid % kSlices;
+    const int rb = bid / kSlices;
+    const int t = threadIdx.x;
+    const int lane = t & (kWave - 1);
+    const int w = t / kWave;
+    const int li = lane & 15;
+    const int lk = lane >> 4;
+    const int k0 = s * kslice;
+    const int k1 = k0 + kslice < n ? k0 + kslice : n;
+    f4v cre[NT], cim[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        cre[q] = f4v{0.f, 0.f, 0.f, 0.f};
+        cim[q] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    const int arow = t / (kKS32 / AE);
+    const int aseg = (t % (kKS32 / AE)) * AE;
+    const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
+    const f2* Ar = A + (int64_t)grow * lda;
+    f2 ra[AE], rbv[BPT];
+    auto gload = [&](int kk) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int kc = kk + aseg + e;
+            ra[e] = Ar[kc < n ? kc : n - 1];
+            if (kc >= k1) ra[e] = f2{0.f, 0.f};
+        }
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const int idx = t + m * kBlock;
+            const int kc = kk + idx / BW;
+            const int c = idx % BW;
+            const bool ok = idx < BN && kc < k1 && c < ncols;
+            const d2 bv = B[(int64_t)(ok ? kc : k0) * ldb + (ok ? c : 0)];
+            rbv[m] = ok ? f2{(float)bv.x, (float)bv.y} : f2{0.f, 0.f};
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = ra[e];
+#pragma unroll
+        for (int m = 0; m < BPT; ++m) {
+            const int idx = t + m * kBlock;
+            if (idx < BN) Bs[buf][idx] = rbv[m];
+        }
+    };
+    const int nst = k1 > k0 ? (k1 - k0 + kKS32 - 1) / kKS32 : 0;
+    if (nst > 0) {
+        gload(k0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < nst) gload(k0 + (st + 1) * kKS32);
+#pragma unroll
+        for (int ks = 0; ks < kKS32; ks += 4) {
+            const f2 a = As[cur][(w * 16 + li) * AP + ks + lk];
+            f2 b[NT];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, cre[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].y, cim[q], 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b[q].y, cre[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].x, cim[q], 0, 0, 0);
+            }
+        }
+        if (st + 1 < nst) lstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int col = 16 * q + li;
+        if (col >= ncols) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = rb * kRowsPerBlock + w * 16 + 4 * lk + v;
+            if (r < n)
+                Zp[((int64_t)s * n + r) * ncols + col] = d2{(double)cre[q][v], (double)cim[q][v]};
+        }
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_cgemm(const f2* __restrict__ A, int64_t lda, int n,
+                                                  const d2* __restrict__ B, int64_t ldb,
+                                                  int ncols, d2* __restrict__ Zp, int kslice)
+{
+    cgemm_body<NT>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+}
+
+template <int NT>
+static void launch_cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
+                         d2* Zp, hipStream_t s)
+{
+    const int rblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    k_cgemm<NT><<<rblocks * kSlices, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
+                                                      kslice32_of(n));
+}
+
+static void cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,
+                  hipStream_t s)
+{
+    switch ((ncols + 15) / 16) {
+    case 1: launch_cgemm<1>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    case 2: launch_cgemm<2>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    case 3: launch_cgemm<3>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    default: launch_cgemm<4>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    }
+}
+
 static size_t zpart_bytes(int64_t n, int ncols)
 {
     return align256((size_t)kSlices * (size_t)n * (size_t)ncols * sizeof(d2));
@@ -246,6 +394,8 @@ struct BArgs {
     d2* Zp;                          // slice results
     d2* cpart;                       // [blocks][kp][2] column partials
     SolverState* cst;                // kp records
+    const f2* A32;                   // complex64 A: products on FP32 matrix cores
+    int64_t lda32;
 };
 
 constexpr size_t kStateStride = 256;
@@ -285,7 +435,7 @@ __device__ __forceinline__ void col_partials(const BArgs& a, int bid, d2 v0, d2 
     }
 }
 
-__global__ void kb_init(BArgs a, int maxit, double tol2)
+__global__ void kb_init(BArgs a, int maxit, double tol2, int no_confirm)
 {
     const int j = threadIdx.x;
     if (j >= a.kp) return;
@@ -298,7 +448,7 @@ __global__ void kb_init(BArgs a, int maxit, double tol2)
     o.maxit = maxit;
     o.pending = PK_NONE;
     o.pending_blocks = 0;
-    o.no_confirm = 0;
+    o.no_confirm = no_confirm;
     o.pad1 = o.pad2 = 0;
     o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
     o.tol2 = tol2;
@@ -624,15 +774,25 @@ static BLayout block_layout(int64_t n, int k)
     return L;
 }
 
+// Z slices = A B for the block solver: FP64 matrix cores, or the complex64
+// copy of A on FP32 matrix cores when the arguments carry one.
+static void block_product(const BArgs& a, const d2* B, hipStream_t s)
+{
+    if (a.A32)
+        cgemm(a.A32, a.lda32, a.n, B, a.kp, a.kp, a.Zp, s);
+    else
+        gemm(a.A, a.lda, a.n, B, a.kp, a.kp, a.Zp, s);
+}
+
 static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
-                     ccg_result* res, hipStream_t s)
+                     ccg_result* res, hipStream_t s, int no_confirm = 0)
 {
     SyncCtx* sc = nullptr;
     hipError_t e = get_sync(&sc);
     if (e != hipSuccess) return (int)e;
     const int gC = col_blocks(a.n, a.kp);
 
-    kb_init<<<1, kMaxCols, 0, s>>>(a, maxit, tol2);
+    kb_init<<<1, kMaxCols, 0, s>>>(a, maxit, tol2, no_confirm);
     kb_normy<<<gC, kBlock, 0, s>>>(a);
     kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
     if (flags & CCG_X0_ZERO) {
@@ -640,7 +800,7 @@ static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
         kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
     } else {
         kb_setx<<<gC, kBlock, 0, s>>>(a);
-        gemm(a.A, a.lda, a.n, a.B, a.kp, a.kp, a.Zp, s);
+        block_product(a, a.B, s);
         kb_red_setup<<<gC, kBlock, 0, s>>>(a);
         kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP1, gC, nullptr);
     }
@@ -651,12 +811,12 @@ static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
     for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
         if (slot < max_slots) {
             kb_p<<<gC, kBlock, 0, s>>>(a);
-            gemm(a.A, a.lda, a.n, a.B, a.kp, a.kp, a.Zp, s);
+            block_product(a, a.B, s);
             kb_red1<<<gC, kBlock, 0, s>>>(a);
             kb_step<<<1, kStepThreads, 0, s>>>(a, CS_P1, gC, nullptr);
             kb_s<<<gC, kBlock, 0, s>>>(a);
             kb_step<<<1, kStepThreads, 0, s>>>(a, CS_S, gC, nullptr);
-            gemm(a.A, a.lda, a.n, a.S, a.kp, a.kp, a.Zp, s);
+            block_product(a, a.S, s);
             kb_red2<<<gC, kBlock, 0, s>>>(a);
             kb_step<<<1, kStepThreads, 0, s>>>(a, CS_T, gC, nullptr);
             kb_xr<<<gC, kBlock, 0, s>>>(a);
@@ -969,7 +1129,7 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
         return (int)e;
     const int gC = col_blocks(n, a.kp);
     kv_clear<<<1, kWave, 0, s>>>(S->sdone_d, slot);
-    kb_init<<<1, kMaxCols, 0, s>>>(a, r->maxit, r->tol * r->tol);
+    kb_init<<<1, kMaxCols, 0, s>>>(a, r->maxit, r->tol * r->tol, 0);
     kb_normy<<<gC, kBlock, 0, s>>>(a);
     kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
     kb_setup0<<<gC, kBlock, 0, s>>>(a);
@@ -1183,6 +1343,260 @@ static int serve_step(ccg_server* S)
     return 0;
 }
 
+
+// --------------------------------------------------- mixed block solver
+//
+// FP64 iterative refinement around the block solver run on the complex64
+// copy of A (products on FP32 matrix cores, see cgemm_body): per outer step
+// R = Y - A X in FP64 (FP64 matrix cores), every column not yet converged
+// solves A32 D = R / ||R|| to tol_inner (recursive residual, no
+// confirmation) and takes X += ||R|| D in FP64.  The inner Krylov vectors
+// stay FP64: they are O(n k) bytes against the O(n^2) of A, whose bytes the
+// complex64 copy halves.
+
+struct ColScale {
+    double v[kMaxCols];
+};
+
+// out[c] = sum over i (in order of blocks of threads) of |M[i][c]|^2
+__global__ __launch_bounds__(kBlock) void km_colnorm(const d2* __restrict__ M, int64_t ld,
+                                                     int n, double* __restrict__ out)
+{
+    __shared__ d2 lds[kMaxWaves];
+    const int c = blockIdx.x;
+    d2 acc = d2{0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) acc.x += cabs2(M[(int64_t)i * ld + c]);
+    const d2 tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[c] = tot.x;
+}
+
+// R = Y - (sum of the slices of Zp) in columns c < k (Zp null: R = Y); the
+// padding columns of R are zero.  R is n x kp, Zp n x k per slice.
+__global__ __launch_bounds__(kBlock) void km_resid(const d2* __restrict__ Y, int64_t ldy,
+                                                   const d2* __restrict__ Zp, int n, int k,
+                                                   int kp, d2* __restrict__ R)
+{
+    const int64_t total = (int64_t)n * kp;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / kp;
+        const int c = (int)(e - i * kp);
+        d2 r = d2{0.0, 0.0};
+        if (c < k) {
+            r = Y[i * ldy + c];
+            if (Zp) r = r - slice_sum(Zp, n, k, i, c);
+        }
+        R[e] = r;
+    }
+}
+
+// Ys = R scaled by column (scale 0 for the columns that sit out)
+__global__ __launch_bounds__(kBlock) void km_scale(const d2* __restrict__ R, int n, int kp,
+                                                   ColScale sc, d2* __restrict__ Ys)
+{
+    const int64_t total = (int64_t)n * kp;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double f = sc.v[e % kp];
+        const d2 r = R[e];
+        Ys[e] = d2{r.x * f, r.y * f};
+    }
+}
+
+// X[:, c] += nr[c] D[:, c] for the columns with nr[c] != 0; zero: X[:, c] = 0
+// first where zero.v[c] != 0
+__global__ __launch_bounds__(kBlock) void km_update(d2* __restrict__ X, int64_t ldx, int n, int k,
+                                                    int kp, const d2* __restrict__ D, ColScale nr,
+                                                    ColScale zero)
+{
+    const int64_t total = (int64_t)n * k;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / k;
+        const int c = (int)(e - i * k);
+        d2* xp = X + i * ldx + c;
+        if (zero.v[c] != 0.0) *xp = d2{0.0, 0.0};
+        const double f = nr.v[c];
+        if (f != 0.0) {
+            const d2 d = D[i * kp + c];
+            *xp = *xp + d2{d.x * f, d.y * f};
+        }
+    }
+}
+
+struct BMixLayout {
+    BLayout inner;
+    size_t R, Ys, D, norms, total;
+};
+
+static BMixLayout bmix_layout(int64_t n, int k)
+{
+    BMixLayout L{};
+    L.inner = block_layout(n, k);
+    const int kp = pow2_at_least(k);
+    const size_t mb = align256((size_t)(n > 0 ? n : 1) * kp * sizeof(d2));
+    size_t off = L.inner.total;
+    L.R = off;
+    off += mb;
+    L.Ys = off;
+    off += mb;
+    L.D = off;
+    off += mb;
+    L.norms = off;
+    off += align256(kMaxCols * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+static int elem_blocks(int64_t total)
+{
+    int64_t b = (total + kBlock - 1) / kBlock;
+    if (b > 2048) b = 2048;
+    return (int)(b < 1 ? 1 : b);
+}
+
+static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const ccg_c* A32,
+                            int64_t lda32, const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
+                            double tol, int32_t maxit, double tol_inner, int32_t maxit_inner,
+                            uint32_t flags, void* work, size_t work_bytes, ccg_mixed_result* res,
+                            void* stream)
+{
+    if (n < 0 || n > kMaxNB) return -1;
+    if (k < 1 || k > kMaxCols) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < (n > 1 ? n : 1)) return -4;
+    if (n > 0 && !A32) return -5;
+    if (lda32 < (n > 1 ? n : 1)) return -6;
+    if (n > 0 && !Y) return -7;
+    if (ldy < k) return -8;
+    if (n > 0 && !X) return -9;
+    if (ldx < k) return -10;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return -11;
+    if (maxit < 0) return -12;
+    if (!(tol_inner > 0.0) || !(tol_inner < 1.0)) return -13;
+    if (maxit_inner < 1) return -14;
+    if (flags & ~CCG_X0_ZERO) return -15;
+    if (n > 0 && (!work || ((uintptr_t)work & 255))) return -16;
+    const BMixLayout L = bmix_layout(n, (int)k);
+    if (n > 0 && work_bytes < L.total) return -17;
+    if (!res) return -18;
+    for (int64_t j = 0; j < k; ++j) {
+        std::memset(&res[j], 0, sizeof res[j]);
+        res[j].relres_true = 0.0;
+    }
+    if (n == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    const int kk = (int)k;
+    const int kp = pow2_at_least(kk);
+    char* base = (char*)work;
+    d2* R = (d2*)(base + L.R);
+    d2* Ys = (d2*)(base + L.Ys);
+    d2* D = (d2*)(base + L.D);
+    double* nrm_d = (double*)(base + L.norms);
+    // inner solver: A32 D = Ys
+    BArgs ai{};
+    ai.A = nullptr;
+    ai.lda = lda;
+    ai.A32 = (const f2*)A32;
+    ai.lda32 = lda32;
+    ai.n = (int)n;
+    ai.k = kk;
+    ai.kp = kp;
+    ai.Y = Ys;
+    ai.ldy = kp;
+    ai.X = D;
+    ai.ldx = kp;
+    d2* m[7];
+    for (int q = 0; q < 7; ++q) m[q] = (d2*)(base + L.inner.mats + q * L.inner.mat_bytes);
+    ai.R = m[0]; ai.RH = m[1]; ai.P = m[2]; ai.V = m[3]; ai.S = m[4]; ai.T = m[5]; ai.B = m[6];
+    ai.Zp = (d2*)(base + L.inner.zp);
+    ai.cpart = (d2*)(base + L.inner.cpart);
+    ai.cst = (SolverState*)(base + L.inner.cst);
+
+    hipError_t e;
+    std::vector<double> nrm(kk), ny2(kk);
+    auto colnorms = [&](const d2* M, int64_t ld, double* host) -> int {
+        km_colnorm<<<kk, kBlock, 0, s>>>(M, ld, (int)n, nrm_d);
+        hipError_t e2 = hipGetLastError();
+        if (e2 == hipSuccess)
+            e2 = hipMemcpyAsync(host, nrm_d, kk * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        return (int)e2;
+    };
+    int rc = colnorms((const d2*)Y, ldy, ny2.data());
+    if (rc) return rc;
+    // columns still iterating
+    std::vector<char> live(kk, 1);
+    ColScale zero{}, none{};
+    for (int c = 0; c < kk; ++c) {
+        if (!std::isfinite(ny2[c])) {  // x left as given
+            res[c].info = 4;
+            live[c] = 0;
+        } else if (ny2[c] == 0.0) {  // x = 0
+            zero.v[c] = 1.0;
+            live[c] = 0;
+        }
+    }
+    const bool x0zero = (flags & CCG_X0_ZERO) != 0;
+    if (x0zero)
+        for (int c = 0; c < kk; ++c)
+            if (live[c]) zero.v[c] = 1.0;
+    // apply the zeroing now so that the residual below sees it
+    km_update<<<elem_blocks(n * k), kBlock, 0, s>>>((d2*)X, ldx, (int)n, kk, kp, D, none, zero);
+    std::vector<ccg_result> inner(kk);
+    for (int outer = 0;; ++outer) {
+        if (outer == 0 && x0zero) {
+            km_resid<<<elem_blocks(n * kp), kBlock, 0, s>>>((const d2*)Y, ldy, nullptr, (int)n,
+                                                            kk, kp, R);
+        } else {
+            gemm((const d2*)A, lda, (int)n, (const d2*)X, ldx, kk, ai.Zp, s);
+            km_resid<<<elem_blocks(n * kp), kBlock, 0, s>>>((const d2*)Y, ldy, ai.Zp, (int)n, kk,
+                                                            kp, R);
+            for (int c = 0; c < kk; ++c)
+                if (live[c]) res[c].matvecs64++;
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if ((rc = colnorms(R, kp, nrm.data()))) return rc;
+        ColScale sc{}, nr{};
+        int active = 0;
+        for (int c = 0; c < kk; ++c) {
+            if (!live[c]) continue;
+            const double rel = std::sqrt(nrm[c] / ny2[c]);
+            res[c].relres_true = rel;
+            if (!std::isfinite(nrm[c])) {
+                res[c].info = 4;
+                live[c] = 0;
+            } else if (rel <= tol) {
+                res[c].info = 0;
+                live[c] = 0;
+            } else if (outer >= maxit) {
+                res[c].info = 1;
+                live[c] = 0;
+            } else {
+                const double r = std::sqrt(nrm[c]);
+                sc.v[c] = 1.0 / r;
+                nr.v[c] = r;
+                ++active;
+            }
+        }
+        if (!active) break;
+        km_scale<<<elem_blocks(n * kp), kBlock, 0, s>>>(R, (int)n, kp, sc, Ys);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        rc = run_block(ai, CCG_X0_ZERO, maxit_inner, tol_inner * tol_inner, inner.data(), s, 1);
+        if (rc) return rc;
+        km_update<<<elem_blocks(n * k), kBlock, 0, s>>>((d2*)X, ldx, (int)n, kk, kp, D, nr,
+                                                          none);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        for (int c = 0; c < kk; ++c) {
+            if (nr.v[c] == 0.0) continue;
+            res[c].outer++;
+            res[c].inner_iters += inner[c].iters;
+            res[c].matvecs32 += inner[c].matvecs;
+        }
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
+    return 0;
+}
 }  // namespace ccg
 
 // ============================================================== C ABI
@@ -1198,6 +1612,12 @@ size_t block_workspace_bytes(int method, int64_t n, int64_t k)
         return zpart_bytes(n > 0 ? n : 1, kc);
     }
     if (method == CCG_WS_BICGSTAB_BLOCK && k <= kMaxCols) return block_layout(n, (int)k).total;
+    if (method == CCG_WS_MATMAT_C64) {
+        const int kc = (int)(k < kMaxCols ? k : kMaxCols);
+        return zpart_bytes(n > 0 ? n : 1, kc);
+    }
+    if (method == CCG_WS_BICGSTAB_BLOCK_MIXED && k <= kMaxCols)
+        return bmix_layout(n, (int)k).total;
     return 0;
 }
 
@@ -1294,6 +1714,46 @@ int ccg_bicgstab_block(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const 
     return 0;
 }
 
+
+
+int ccg_matmat_c64(int64_t n, int64_t k, const ccg_c* A32, int64_t lda32, const ccg_z* B,
+                   int64_t ldb, ccg_z* Z, int64_t ldz, void* work, size_t work_bytes,
+                   void* stream)
+{
+    using namespace ccg;
+    if (n < 0 || n > kMaxNB) return -1;
+    if (k < 0) return -2;
+    if (n > 0 && k > 0 && !A32) return -3;
+    if (lda32 < (n > 1 ? n : 1)) return -4;
+    if (n > 0 && k > 0 && !B) return -5;
+    if (ldb < (k > 1 ? k : 1)) return -6;
+    if (n > 0 && k > 0 && !Z) return -7;
+    if (ldz < (k > 1 ? k : 1)) return -8;
+    if (n == 0 || k == 0) return 0;
+    const int kc = (int)(k < kMaxCols ? k : kMaxCols);
+    if (!work || ((uintptr_t)work & 255)) return -9;
+    if (work_bytes < zpart_bytes(n, kc)) return -10;
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t c0 = 0; c0 < k; c0 += kMaxCols) {
+        const int nc = (int)(k - c0 < kMaxCols ? k - c0 : kMaxCols);
+        cgemm((const f2*)A32, lda32, (int)n, (const d2*)B + c0, ldb, nc, (d2*)work, s);
+        int64_t blocks = ((int64_t)n * nc + kBlock - 1) / kBlock;
+        if (blocks > 2048) blocks = 2048;
+        k_zgemm_sum<<<(int)blocks, kBlock, 0, s>>>((const d2*)work, (int)n, nc, (d2*)Z + c0, ldz);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                                const ccg_c* A32, int64_t lda32, const ccg_z* Y, int64_t ldy,
+                                ccg_z* X, int64_t ldx, double tol, int32_t maxit,
+                                double tol_inner, int32_t maxit_inner, uint32_t flags, void* work,
+                                size_t work_bytes, ccg_mixed_result* res, void* stream)
+{
+    return ccg::block_mixed_impl(n, k, A, lda, A32, lda32, Y, ldy, X, ldx, tol, maxit, tol_inner,
+                                 maxit_inner, flags, work, work_bytes, res, stream);
+}
 
 // ------------------------------------------------------------- serving ABI
 

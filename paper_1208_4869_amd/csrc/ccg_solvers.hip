@@ -1588,7 +1588,8 @@ extern "C" {
 size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
 {
     if (n < 0 || nrhs < 1) return 0;
-    if (method == CCG_WS_MATMAT || method == CCG_WS_BICGSTAB_BLOCK)
+    if (method == CCG_WS_MATMAT || method == CCG_WS_BICGSTAB_BLOCK ||
+        method == CCG_WS_MATMAT_C64 || method == CCG_WS_BICGSTAB_BLOCK_MIXED)
         return ccg::block_workspace_bytes(method, n, nrhs);
     if (method == CCG_WS_MATVEC_C) {
         const ccg::GemvCShape sh = ccg::gemv_c_shape(n > 0 ? n : 1);

@@ -169,3 +169,29 @@ def test_build_flags_kernels_with_scratch():
         "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 48 [-Rpass-analysis=kernel-resource-usage]",
     ])
     assert build.scratch_kernels(remarks) == [("_Z3barPi", 48)]
+
+
+def test_block_mixed_argument_errors_are_rejected_on_the_host(lib):
+    from paper_1208_4869_amd import ccg
+    from paper_1208_4869_amd.ccg import _MixedResult
+    P = ctypes.c_void_p
+    d = P(256)
+    big = 1 << 30
+    assert ccg.ccg_workspace_bytes(ccg.WS_MATMAT_C64, 100, 8) >= 8 * 100 * 8 * 16
+    assert ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_BLOCK_MIXED, 100, 8) > \
+        ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_BLOCK, 100, 8)
+    assert ccg.ccg_workspace_bytes(ccg.WS_BICGSTAB_BLOCK_MIXED, 100, 65) == 0
+    assert lib.ccg_matmat_c64(4, 2, None, 4, d, 2, d, 2, d, big, None) == -3
+    assert lib.ccg_matmat_c64(4, 2, d, 3, d, 2, d, 2, d, big, None) == -4
+    assert lib.ccg_matmat_c64(4, 2, d, 4, d, 2, d, 2, P(300), big, None) == -9
+    assert lib.ccg_matmat_c64(4, 2, d, 4, d, 2, d, 2, d, 8, None) == -10
+    assert lib.ccg_matmat_c64(0, 2, None, 1, None, 2, None, 2, None, 0, None) == 0
+    res = (_MixedResult * 2)()
+    ok = [4, 2, d, 4, d, 4, d, 2, d, 2, 1e-10, 10, 1e-5, 100, 0, d, big, res, None]
+    for pos, bad in ((0, -1), (1, 0), (1, 65), (2, None), (3, 3), (4, None), (5, 3),
+                     (6, None), (7, 1), (8, None), (9, 1), (10, 0.0), (11, -1),
+                     (12, 1.0), (13, 0), (14, 2), (15, None), (16, 8), (17, None)):
+        args = list(ok)
+        args[pos] = bad
+        want = -(pos + 1) if pos != 1 else -2
+        assert lib.ccg_bicgstab_block_mixed_ex(*args) == want, (pos, bad)
