@@ -291,6 +291,7 @@ def block_leg(A, A_h, steps):
 SERVE_SIZES = (512, 1024, 2048, 4096)
 SERVE_SEED = 2024
 SERVE_POOL_BYTES = 16 << 30
+SERVE_TOL_INNER = 1e-5
 
 
 def serve_inputs(nreq):
@@ -318,9 +319,10 @@ def serve_inputs(nreq):
     return reqs
 
 
-def run_server(reqs, arrivals):
+def run_server(reqs, arrivals, mixed=False, tol_inner=SERVE_TOL_INNER):
     """Feed reqs to a server at the given arrival times (seconds from the
-    start); returns (makespan, latencies, results, stats)."""
+    start); mixed: FP64 refinement around complex64 inner solves.  Returns
+    (makespan, latencies, results, stats)."""
     from paper_1208_4869_amd import ccg
     N = len(reqs)
     lat = np.zeros(N)
@@ -334,7 +336,10 @@ def run_server(reqs, arrivals):
             now = time.perf_counter() - t0
             while i < N and arrivals[i] <= now:
                 A, Y, X = reqs[i]
-                index[srv.submit(A, Y, X, TOL, MAXIT)] = i
+                if mixed:
+                    index[srv.submit(A, Y, X, TOL, 10, mixed=True, tol_inner=tol_inner)] = i
+                else:
+                    index[srv.submit(A, Y, X, TOL, MAXIT)] = i
                 i += 1
             act, q = srv.step()
             while True:
@@ -400,6 +405,16 @@ def serve_leg(nreq, rate):
     log("serving: capacity %.0f req/s, Poisson %.0f req/s: p50 %.2f ms p99 %.2f ms; "
         "one at a time %.0f req/s" % (cap, rate, np.percentile(lat_p, 50) * 1e3,
                                       np.percentile(lat_p, 99) * 1e3, nreq / t_seq))
+    # the mixed-precision variant on the same requests and arrivals
+    X64 = [X.clone() for _, _, X in reqs]
+    run_server(reqs[:8], np.zeros(8), mixed=True)  # warm-up
+    mk_mc, lat_mc, res_mc, st_mc = run_server(reqs, np.zeros(nreq), mixed=True)
+    mk_mp, lat_mp, res_mp, st_mp = run_server(reqs, arrivals, mixed=True)
+    ok_m = all(a.info == 0 and a.relres_true <= TOL for r in res_mp for a in r)
+    dmax = max(float(torch.linalg.norm(X - Xr) / torch.linalg.norm(Xr))
+               for (_, _, X), Xr in zip(reqs, X64))
+    log("serving, mixed: capacity %.0f req/s; Poisson p50 %.2f ms p99 %.2f ms" % (
+        nreq / mk_mc, np.percentile(lat_mp, 50) * 1e3, np.percentile(lat_mp, 99) * 1e3))
     return {"workload": "%d requests, dense n in %s (A = 4I + G/sqrt(n)), k in 1..8, "
                         "tol 1e-10, FP64" % (nreq, list(SERVE_SIZES)),
             "rhs_total": rhs,
@@ -418,6 +433,15 @@ def serve_leg(nreq, rate):
                         "ticks": st_p["ticks"], "peak_active": st_p["peak_active"]},
             "one_at_a_time": {"requests_per_s": nreq / t_seq,
                               "rhs_solves_per_s": rhs / t_seq},
+            "mixed": {"capacity_requests_per_s": nreq / mk_mc,
+                      "capacity_rhs_solves_per_s": rhs / mk_mc,
+                      "capacity_speedup_vs_fp64": mk_c / mk_mc,
+                      "poisson_p50_ms": float(np.percentile(lat_mp, 50) * 1e3),
+                      "poisson_p99_ms": float(np.percentile(lat_mp, 99) * 1e3),
+                      "poisson_requests_per_s": nreq / mk_mp,
+                      "all_converged": ok_m,
+                      "max_rel_diff_vs_fp64_solution": dmax,
+                      "ticks_capacity": st_mc["ticks"]},
             "pool_bytes": SERVE_POOL_BYTES,
             "all_converged": ok, "bitwise_equal_to_alone": bool(same)}
 

@@ -419,6 +419,26 @@ int ccg_server_submit(ccg_server* srv, int64_t n, int64_t k, const ccg_z* A,
                       int64_t lda, const ccg_z* Y, int64_t ldy, ccg_z* X,
                       int64_t ldx, double tol, int32_t maxit, int64_t* ticket);
 
+/* A mixed-precision request (the ccg_bicgstab_block_mixed_ex problem, x0 =
+ * 0): the server keeps A and a complex64 copy it rounds itself; per outer
+ * step the FP64 residual and its column norms are formed for this request
+ * alone, and the inner block solve (complex64 products on FP32 matrix cores)
+ * joins the batched iterations with the other requests.  maxit counts outer
+ * steps; tol_inner (0 < tol_inner < 1) and maxit_inner bound each inner
+ * solve.  Its ccg_result per column: info as in ccg_bicgstab_block_mixed_ex,
+ * iters = inner iterations, matvecs = complex64 products, confirms = FP64
+ * residual products after the first, relres_rec = relres_true = the FP64
+ * true relative residual.  Arguments 1-11 as ccg_server_submit, 12 tol_inner,
+ * 13 maxit_inner, 14 ticket (out). */
+int ccg_server_submit_mixed(ccg_server* srv, int64_t n, int64_t k,
+                            const ccg_z* A, int64_t lda, const ccg_z* Y,
+                            int64_t ldy, ccg_z* X, int64_t ldx, double tol,
+                            int32_t maxit, double tol_inner,
+                            int32_t maxit_inner, int64_t* ticket);
+
+/* Bytes of pool a mixed-precision request occupies. */
+size_t ccg_server_request_bytes_mixed(int64_t n, int64_t k);
+
 /* One scheduling step: completes finished copy-outs, admits from the queue,
  * enqueues one batched iteration and reads the stop flags of the previous
  * one.  Blocks at most for one iteration.  Arguments: 1 srv, 2 active and

@@ -153,12 +153,17 @@ def load() -> ctypes.CDLL:
     lib.ccg_server_request_bytes.restype = S
     lib.ccg_server_submit.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, D, I32,
                                       ctypes.POINTER(I64)]
+    lib.ccg_server_submit_mixed.argtypes = [P, I64, I64, P, I64, P, I64, P, I64, D, I32,
+                                            D, I32, ctypes.POINTER(I64)]
+    lib.ccg_server_request_bytes_mixed.argtypes = [I64, I64]
+    lib.ccg_server_request_bytes_mixed.restype = S
     lib.ccg_server_step.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.ccg_server_poll.argtypes = [P, I64, ctypes.POINTER(I32),
                                     ctypes.POINTER(_Result)]
     lib.ccg_server_get_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
     lib.ccg_server_next_done.argtypes = [P, ctypes.POINTER(I64)]
     for name in ("ccg_server_create", "ccg_server_destroy", "ccg_server_submit",
+                 "ccg_server_submit_mixed",
                  "ccg_server_step", "ccg_server_poll", "ccg_server_get_stats",
                  "ccg_server_next_done"):
         getattr(lib, name).restype = ctypes.c_int
@@ -470,7 +475,9 @@ class Rejected(CcgError):
     """The request's footprint exceeds the server's whole pool."""
 
 
-def ccg_server_request_bytes(n: int, k: int) -> int:
+def ccg_server_request_bytes(n: int, k: int, mixed: bool = False) -> int:
+    if mixed:
+        return int(load().ccg_server_request_bytes_mixed(n, k))
     return int(load().ccg_server_request_bytes(n, k))
 
 
@@ -504,7 +511,10 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, A, Y, X, tol=1e-10, maxit=1000) -> int:
+    def submit(self, A, Y, X, tol=1e-10, maxit=1000, mixed=False, tol_inner=1e-5,
+               maxit_inner=1000) -> int:
+        """Queue a request; mixed: FP64 refinement around inner solves on the
+        server's complex64 copy of A (maxit then counts outer steps)."""
         n = A.shape[0] if hasattr(A, "shape") else 0
         lda = _serve_mat(A, n, "A", square=True)
         ldy = _serve_mat(Y, n, "Y")
@@ -513,9 +523,15 @@ class Server:
         if X.shape[1] != k:
             raise TypeError("X must have as many columns as Y")
         t = ctypes.c_int64(0)
-        rc = load().ccg_server_submit(self._h, n, k, A.data_ptr(), lda,
-                                      Y.data_ptr(), ldy, X.data_ptr(), ldx,
-                                      float(tol), int(maxit), ctypes.byref(t))
+        if mixed:
+            rc = load().ccg_server_submit_mixed(self._h, n, k, A.data_ptr(), lda,
+                                                Y.data_ptr(), ldy, X.data_ptr(), ldx,
+                                                float(tol), int(maxit), float(tol_inner),
+                                                int(maxit_inner), ctypes.byref(t))
+        else:
+            rc = load().ccg_server_submit(self._h, n, k, A.data_ptr(), lda,
+                                          Y.data_ptr(), ldy, X.data_ptr(), ldx,
+                                          float(tol), int(maxit), ctypes.byref(t))
         if rc == SERVER_REJECTED:
             raise Rejected("request of n=%d, k=%d does not fit the pool" % (n, k))
         _check(rc, "ccg_server_submit")

@@ -900,450 +900,6 @@ static int block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const ccg
 
 namespace ccg {
 
-// --------------------------------------------------------------- serving
-//
-// Continuous batching of independent block systems.  Every admitted request
-// has a record in a device table; each kernel of a batched iteration runs one
-// grid over all records: block b finds its record by a binary search over the
-// records' first block indices and runs the block solver's body with its
-// index within the record's share.  The block partition, reduction order and
-// product slices of a request are those of the same request solved alone,
-// whatever else is in the batch.  Product shares start at multiples of 8, so
-// the slice of a product block is still the XCD it runs on.
-
-constexpr int kServeCols = 16;  // one 16-wide product tile per request
-constexpr int kMaxActive = 128;
-
-struct SlotRec {
-    BArgs a;
-    int c0, gC;  // column-kernel blocks [c0, c0 + gC) of the batched grid
-    int g0, gG;  // product blocks [g0, g0 + gG)
-    int kslice;
-    int slot;    // index of the request's done word
-};
-
-__device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, int b, bool prod)
-{
-    int lo = 0, hi = m - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int start = prod ? tab[mid].g0 : tab[mid].c0;
-        if (start <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-// A request whose columns have all finished (done word set by the last
-// column step) is skipped by every later batched kernel.
-#define SERVE_COL_KERNEL(name)                                                        \
-    __global__ __launch_bounds__(kBlock) void kv_##name(                              \
-        const SlotRec* __restrict__ tab, int m, const int* __restrict__ sdone)        \
-    {                                                                                 \
-        const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, false)];                  \
-        if (sdone[r.slot]) return;                                                    \
-        const BArgs a = r.a;                                                          \
-        kb_##name##_body(a, blockIdx.x - r.c0, r.gC);                                 \
-    }
-SERVE_COL_KERNEL(p)
-SERVE_COL_KERNEL(red1)
-SERVE_COL_KERNEL(s)
-SERVE_COL_KERNEL(red2)
-SERVE_COL_KERNEL(xr)
-#undef SERVE_COL_KERNEL
-
-__global__ __launch_bounds__(kBlock) void kv_gemm(const SlotRec* __restrict__ tab, int m,
-                                                  const int* __restrict__ sdone, int use_s)
-{
-    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
-    if (sdone[r.slot]) return;
-    const BArgs a = r.a;
-    zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
-                  blockIdx.x - r.g0);
-}
-
-// One block per record.  With ring (pinned, one word per slot), the step also
-// reports the request's all-done state to the host and to the done word.
-__global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restrict__ tab,
-                                                        int* sdone, int stage, int* ring)
-{
-    const SlotRec& r = tab[blockIdx.x];
-    if (sdone[r.slot]) return;
-    const BArgs a = r.a;
-    kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
-}
-
-__global__ void kv_clear(int* sdone, int slot)
-{
-    if (threadIdx.x == 0) sdone[slot] = 0;
-}
-
-// First-fit allocator over the pool (offsets and sizes are multiples of 256).
-class PoolAlloc {
-    std::map<size_t, size_t> free_;  // offset -> bytes
-public:
-    void init(size_t off, size_t bytes)
-    {
-        free_.clear();
-        if (bytes) free_[off] = bytes;
-    }
-    bool alloc(size_t bytes, size_t* off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            const size_t o = it->first, rest = it->second - bytes;
-            free_.erase(it);
-            if (rest) free_[o + bytes] = rest;
-            *off = o;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && off + bytes == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
-
-struct ServeReq {
-    int64_t ticket = 0;
-    int64_t n = 0;
-    int k = 0;
-    const d2* A = nullptr;
-    int64_t lda = 0;
-    const d2* Y = nullptr;
-    int64_t ldy = 0;
-    d2* X = nullptr;
-    int64_t ldx = 0;
-    double tol = 0.0;
-    int32_t maxit = 0;
-    size_t bytes = 0, off = 0;
-    int slot = -1;
-    int state = CCG_REQ_QUEUED;
-    bool retiring = false;      // copy-out enqueued
-    int64_t ticks = 0, max_ticks = 0, last_tick = -1;
-    SlotRec rec{};
-    std::vector<ccg_result> res;
-};
-
-// Pool bytes of one request: A, Y, X and the block-solver workspace.
-static size_t serve_bytes(int64_t n, int k)
-{
-    return align256((size_t)n * n * sizeof(d2)) + 2 * align256((size_t)n * k * sizeof(d2)) +
-           block_layout(n, k).total;
-}
-
-}  // namespace ccg
-
-struct ccg_server {
-    int device = 0;
-    hipStream_t s = nullptr;
-    char* pool = nullptr;
-    size_t pool_bytes = 0, head = 0;
-    int max_active = 0;
-    int* sdone_d = nullptr;
-    ccg::SlotRec* tab_d = nullptr;
-    ccg::PoolAlloc alloc;
-    std::deque<ccg::ServeReq*> queue;
-    std::deque<int64_t> finished;  // done tickets not yet handed out by next_done
-    std::unordered_map<int64_t, ccg::ServeReq*> reqs;
-    ccg::ServeReq* slots[ccg::kMaxActive] = {};
-    int64_t next_ticket = 1;
-    // batched iterations: pinned done words [kRing][kMaxActive], one event each
-    int* ring_h = nullptr;
-    int* ring_d = nullptr;
-    hipEvent_t tick_ev[ccg::kRing] = {};
-    std::vector<std::pair<int, int64_t>> members[ccg::kRing];  // (slot, ticket)
-    int64_t tick = 0, seen = 0;
-    // table uploads: pinned staging [kRing][kMaxActive]
-    ccg::SlotRec* stage_h = nullptr;
-    hipEvent_t stage_ev[ccg::kRing] = {};
-    bool stage_pending[ccg::kRing] = {};
-    int stage_next = 0;
-    std::vector<std::pair<int, int64_t>> table;  // (slot, ticket) of the device table
-    int tot_c = 0, tot_g = 0;
-    // copy-out: pinned column records [kMaxActive][kServeCols]
-    char* res_h = nullptr;
-    hipEvent_t slot_ev[ccg::kMaxActive] = {};
-    ccg_server_stats st{};
-};
-
-namespace ccg {
-
-static int serve_admit(ccg_server* S, ServeReq* r, int slot)
-{
-    const int64_t n = r->n;
-    const int k = r->k;
-    hipStream_t s = S->s;
-    char* base = S->pool + r->off;
-    size_t o = 0;
-    d2* A = (d2*)(base + o);
-    o += align256((size_t)n * n * sizeof(d2));
-    d2* Y = (d2*)(base + o);
-    o += align256((size_t)n * k * sizeof(d2));
-    d2* X = (d2*)(base + o);
-    o += align256((size_t)n * k * sizeof(d2));
-    char* w = base + o;
-    const BLayout L = block_layout(n, k);
-    BArgs a{};
-    a.A = A;
-    a.lda = n;
-    a.n = (int)n;
-    a.k = k;
-    a.kp = pow2_at_least(k);
-    a.Y = Y;
-    a.ldy = k;
-    a.X = X;
-    a.ldx = k;
-    d2* m[7];
-    for (int q = 0; q < 7; ++q) m[q] = (d2*)(w + L.mats + q * L.mat_bytes);
-    a.R = m[0]; a.RH = m[1]; a.P = m[2]; a.V = m[3]; a.S = m[4]; a.T = m[5]; a.B = m[6];
-    a.Zp = (d2*)(w + L.zp);
-    a.cpart = (d2*)(w + L.cpart);
-    a.cst = (SolverState*)(w + L.cst);
-    const size_t row = (size_t)k * sizeof(d2);
-    hipError_t e;
-    if ((e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
-                              hipMemcpyDefault, s)) != hipSuccess)
-        return (int)e;
-    if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
-        hipSuccess)
-        return (int)e;
-    // x keeps the caller's values in columns the solver never writes
-    if ((e = hipMemcpy2DAsync(X, row, r->X, r->ldx * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
-        hipSuccess)
-        return (int)e;
-    const int gC = col_blocks(n, a.kp);
-    kv_clear<<<1, kWave, 0, s>>>(S->sdone_d, slot);
-    kb_init<<<1, kMaxCols, 0, s>>>(a, r->maxit, r->tol * r->tol, 0);
-    kb_normy<<<gC, kBlock, 0, s>>>(a);
-    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
-    kb_setup0<<<gC, kBlock, 0, s>>>(a);
-    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
-    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-    r->rec.a = a;
-    r->rec.gC = gC;
-    r->rec.gG = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
-    r->rec.kslice = kslice_of(n);
-    r->rec.slot = slot;
-    r->slot = slot;
-    r->state = CCG_REQ_RUNNING;
-    r->ticks = 0;
-    r->max_ticks = 2 * (int64_t)r->maxit + 4;
-    S->slots[slot] = r;
-    S->st.admitted++;
-    S->st.pool_used += r->bytes;
-    if (S->st.pool_used > S->st.pool_peak) S->st.pool_peak = S->st.pool_used;
-    return 0;
-}
-
-// Enqueue the copy-out of a request whose columns have finished.
-static int serve_retire(ccg_server* S, ServeReq* r)
-{
-    hipStream_t s = S->s;
-    const size_t row = (size_t)r->k * sizeof(d2);
-    hipError_t e;
-    if ((e = hipMemcpy2DAsync(r->X, r->ldx * sizeof(d2), r->rec.a.X, row, row, r->n,
-                              hipMemcpyDefault, s)) != hipSuccess)
-        return (int)e;
-    char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
-    if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
-                            hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return (int)e;
-    if ((e = hipEventRecord(S->slot_ev[r->slot], s)) != hipSuccess) return (int)e;
-    r->retiring = true;
-    return 0;
-}
-
-// Finish the requests whose copy-out has completed (wait: block on them).
-static int serve_collect(ccg_server* S, bool wait)
-{
-    for (int q = 0; q < S->max_active; ++q) {
-        ServeReq* r = S->slots[q];
-        if (!r || !r->retiring) continue;
-        hipError_t e = wait ? hipEventSynchronize(S->slot_ev[q]) : hipEventQuery(S->slot_ev[q]);
-        if (e == hipErrorNotReady) continue;
-        if (e != hipSuccess) return (int)e;
-        const char* src = S->res_h + (size_t)q * kServeCols * kStateStride;
-        r->res.resize(r->k);
-        for (int j = 0; j < r->k; ++j) {
-            const SolverState& c = *(const SolverState*)(src + (size_t)j * kStateStride);
-            ccg_result& o = r->res[j];
-            o.info = c.phase == PH_DONE ? c.info : 1;
-            o.iters = c.iters;
-            o.matvecs = c.matvecs;
-            o.confirms = c.confirms;
-            o.relres_rec = c.relres_rec;
-            o.relres_true = c.relres_true;
-        }
-        r->state = CCG_REQ_DONE;
-        r->retiring = false;
-        S->finished.push_back(r->ticket);
-        S->alloc.release(r->off, r->bytes);
-        S->st.pool_used -= r->bytes;
-        S->st.completed++;
-        S->slots[q] = nullptr;
-    }
-    return 0;
-}
-
-// Read the done words of tick `seen` (waiting for it) and retire what ended.
-static int serve_read_tick(ccg_server* S)
-{
-    const int u = (int)(S->seen % kRing);
-    hipError_t e = hipEventSynchronize(S->tick_ev[u]);
-    if (e != hipSuccess) return (int)e;
-    for (const auto& mt : S->members[u]) {
-        ServeReq* r = S->slots[mt.first];
-        if (!r || r->ticket != mt.second || r->retiring || r->state != CCG_REQ_RUNNING) continue;
-        const int w = __atomic_load_n(&S->ring_h[u * kMaxActive + mt.first], __ATOMIC_ACQUIRE);
-        const bool out_of_budget = r->ticks >= r->max_ticks && r->last_tick == S->seen;
-        if (w == PH_DONE || out_of_budget) {
-            int rc = serve_retire(S, r);
-            if (rc) return rc;
-        }
-    }
-    S->members[u].clear();
-    S->seen++;
-    return 0;
-}
-
-static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, int64_t>>& want)
-{
-    const int u = S->stage_next;
-    S->stage_next = (S->stage_next + 1) % kRing;
-    if (S->stage_pending[u]) {
-        hipError_t e = hipEventSynchronize(S->stage_ev[u]);
-        if (e != hipSuccess) return (int)e;
-        S->stage_pending[u] = false;
-    }
-    SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
-    int c = 0, g = 0;
-    for (size_t i = 0; i < want.size(); ++i) {
-        SlotRec rec = S->slots[want[i].first]->rec;
-        rec.c0 = c;
-        rec.g0 = g;
-        c += rec.gC;
-        g += rec.gG;
-        h[i] = rec;
-    }
-    S->tot_c = c;
-    S->tot_g = g;
-    S->table = want;
-    if (want.empty()) return 0;
-    hipError_t e = hipMemcpyAsync(S->tab_d, h, want.size() * sizeof(SlotRec),
-                                  hipMemcpyHostToDevice, S->s);
-    if (e != hipSuccess) return (int)e;
-    if ((e = hipEventRecord(S->stage_ev[u], S->s)) != hipSuccess) return (int)e;
-    S->stage_pending[u] = true;
-    return 0;
-}
-
-static bool serve_iterating(const ServeReq* r)
-{
-    return r && r->state == CCG_REQ_RUNNING && !r->retiring && r->ticks < r->max_ticks;
-}
-
-// Admission in arrival order while a slot is free and the head fits the pool.
-static int serve_admit_queue(ccg_server* S)
-{
-    while (!S->queue.empty()) {
-        int slot = -1;
-        for (int q = 0; q < S->max_active && slot < 0; ++q)
-            if (!S->slots[q]) slot = q;
-        if (slot < 0) break;
-        ServeReq* r = S->queue.front();
-        size_t off = 0;
-        if (!S->alloc.alloc(r->bytes, &off)) {
-            // the head waits until retirements free enough of the pool
-            S->st.admission_waits++;
-            break;
-        }
-        r->off = off;
-        S->queue.pop_front();
-        int rc = serve_admit(S, r, slot);
-        if (rc) return rc;
-    }
-    return 0;
-}
-
-static int serve_step(ccg_server* S)
-{
-    int rc;
-    hipError_t e;
-    // 1. finished copy-outs free their slots and pool blocks; admit
-    if ((rc = serve_collect(S, false))) return rc;
-    if ((rc = serve_admit_queue(S))) return rc;
-    // 2. the table of this iteration: admitted requests still iterating (a
-    //    slot may hold another request than in the last table: compare tickets)
-    std::vector<std::pair<int, int64_t>> want;
-    for (int q = 0; q < S->max_active; ++q)
-        if (serve_iterating(S->slots[q])) want.emplace_back(q, S->slots[q]->ticket);
-    if (want != S->table && (rc = serve_upload_table(S, want))) return rc;
-    // 3. one batched iteration
-    if (!want.empty()) {
-        while (S->seen + kRing <= S->tick)
-            if ((rc = serve_read_tick(S))) return rc;
-        const int u = (int)(S->tick % kRing);
-        const int m = (int)want.size();
-        hipStream_t s = S->s;
-        const SlotRec* tab = S->tab_d;
-        kv_p<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
-        kv_red1<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_P1, nullptr);
-        kv_s<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_S, nullptr);
-        kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
-        kv_red2<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_T, nullptr);
-        kv_xr<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_XR,
-                                           S->ring_d + (size_t)u * kMaxActive);
-        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-        if ((e = hipEventRecord(S->tick_ev[u], s)) != hipSuccess) return (int)e;
-        S->members[u] = want;
-        for (const auto& w : want) {
-            ServeReq* r = S->slots[w.first];
-            r->ticks++;
-            r->last_tick = S->tick;
-        }
-        S->tick++;
-        S->st.ticks++;
-    }
-    // 4. read the stop flags one iteration behind (all of them when idle) and
-    //    enqueue the copy-out of what has finished
-    const int64_t behind = want.empty() ? 0 : 1;
-    while (S->seen + behind < S->tick)
-        if ((rc = serve_read_tick(S))) return rc;
-    // 5. with nothing left iterating, wait for the copy-outs
-    bool iterating = false;
-    for (int q = 0; q < S->max_active; ++q) iterating = iterating || serve_iterating(S->slots[q]);
-    if (!iterating && (rc = serve_collect(S, true))) return rc;
-    int act = 0;
-    for (int q = 0; q < S->max_active; ++q)
-        if (S->slots[q]) act++;
-    S->st.active = act;
-    S->st.queued = (int32_t)S->queue.size();
-    if (act > S->st.peak_active) S->st.peak_active = act;
-    return 0;
-}
-
-
 // --------------------------------------------------- mixed block solver
 //
 // FP64 iterative refinement around the block solver run on the complex64
@@ -1597,6 +1153,709 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
     return 0;
 }
+
+// --------------------------------------------------------------- serving
+//
+// Continuous batching of independent block systems.  Every admitted request
+// has a record in a device table; each kernel of a batched iteration runs one
+// grid over all records: block b finds its record by a binary search over the
+// records' first block indices and runs the block solver's body with its
+// index within the record's share.  The block partition, reduction order and
+// product slices of a request are those of the same request solved alone,
+// whatever else is in the batch.  Product shares start at multiples of 8, so
+// the slice of a product block is still the XCD it runs on.
+
+constexpr int kServeCols = 16;  // one 16-wide product tile per request
+constexpr int kMaxActive = 128;
+
+struct SlotRec {
+    BArgs a;
+    int c0, gC;  // column-kernel blocks [c0, c0 + gC) of the batched grid
+    int g0, gG;  // product blocks [g0, g0 + gG)
+    int kslice;
+    int slot;    // index of the request's done word
+};
+
+__device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, int b, bool prod)
+{
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int start = prod ? tab[mid].g0 : tab[mid].c0;
+        if (start <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// A request whose columns have all finished (done word set by the last
+// column step) is skipped by every later batched kernel.
+#define SERVE_COL_KERNEL(name)                                                        \
+    __global__ __launch_bounds__(kBlock) void kv_##name(                              \
+        const SlotRec* __restrict__ tab, int m, const int* __restrict__ sdone)        \
+    {                                                                                 \
+        const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, false)];                  \
+        if (sdone[r.slot]) return;                                                    \
+        const BArgs a = r.a;                                                          \
+        kb_##name##_body(a, blockIdx.x - r.c0, r.gC);                                 \
+    }
+SERVE_COL_KERNEL(p)
+SERVE_COL_KERNEL(red1)
+SERVE_COL_KERNEL(s)
+SERVE_COL_KERNEL(red2)
+SERVE_COL_KERNEL(xr)
+#undef SERVE_COL_KERNEL
+
+// The product of every record: FP64 records here, the inner solves of mixed
+// requests (records with a complex64 A) in kv_cgemm; each kernel's grid
+// covers all records and skips the other kind.
+__global__ __launch_bounds__(kBlock) void kv_gemm(const SlotRec* __restrict__ tab, int m,
+                                                  const int* __restrict__ sdone, int use_s)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
+    if (sdone[r.slot] || r.a.A32) return;
+    const BArgs a = r.a;
+    zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
+                  blockIdx.x - r.g0);
+}
+
+__global__ __launch_bounds__(kBlock) void kv_cgemm(const SlotRec* __restrict__ tab, int m,
+                                                   const int* __restrict__ sdone, int use_s)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
+    if (sdone[r.slot] || !r.a.A32) return;
+    const BArgs a = r.a;
+    cgemm_body<1>(a.A32, a.lda32, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
+                  blockIdx.x - r.g0);
+}
+
+// A32 = complex64(A), n x n, A32 dense (lda32 = n); round to nearest
+__global__ __launch_bounds__(kBlock) void km_round(const d2* __restrict__ A, int64_t lda, int n,
+                                                   f2* __restrict__ A32)
+{
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / n;
+        const d2 v = A[i * lda + (e - i * n)];
+        A32[e] = f2{(float)v.x, (float)v.y};
+    }
+}
+
+// One block per record.  With ring (pinned, one word per slot), the step also
+// reports the request's all-done state to the host and to the done word.
+__global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restrict__ tab,
+                                                        int* sdone, int stage, int* ring)
+{
+    const SlotRec& r = tab[blockIdx.x];
+    if (sdone[r.slot]) return;
+    const BArgs a = r.a;
+    kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
+}
+
+__global__ void kv_clear(int* sdone, int slot)
+{
+    if (threadIdx.x == 0) sdone[slot] = 0;
+}
+
+// First-fit allocator over the pool (offsets and sizes are multiples of 256).
+class PoolAlloc {
+    std::map<size_t, size_t> free_;  // offset -> bytes
+public:
+    void init(size_t off, size_t bytes)
+    {
+        free_.clear();
+        if (bytes) free_[off] = bytes;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t o = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[o + bytes] = rest;
+            *off = o;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && off + bytes == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct ServeReq {
+    int64_t ticket = 0;
+    int64_t n = 0;
+    int k = 0;
+    const d2* A = nullptr;
+    int64_t lda = 0;
+    const d2* Y = nullptr;
+    int64_t ldy = 0;
+    d2* X = nullptr;
+    int64_t ldx = 0;
+    double tol = 0.0;
+    int32_t maxit = 0;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    int state = CCG_REQ_QUEUED;
+    bool retiring = false;      // copy-out enqueued
+    int64_t ticks = 0, max_ticks = 0, last_tick = -1;
+    SlotRec rec{};
+    std::vector<ccg_result> res;
+    // mixed precision (FP64 refinement around inner solves on complex64 A)
+    bool mixed = false;
+    double tol_inner = 0.0;
+    int32_t maxit_inner = 0;
+    int phase = 0;              // MP_* below; FP64 requests stay in MP_INNER
+    int64_t solve_id = 0;       // id of the block solve now iterating
+    bool waiting = false;       // an event of this phase is outstanding
+    int outer = 0;              // FP64 residuals evaluated after the first
+    d2 *Ad = nullptr, *Yd = nullptr, *Xd = nullptr;  // pool copies
+    d2 *R = nullptr, *Ys = nullptr, *D = nullptr;
+    double* norms_d = nullptr;
+    std::vector<double> ny2, relres;
+    std::vector<int> info, outers, inner_iters, mv32, mv64;
+    std::vector<char> live;
+    ColScale nr{};
+};
+
+enum MixPhase { MP_INNER = 0, MP_NORMY, MP_RESID };
+
+// Pool bytes of one request: A, Y, X and the block-solver workspace; a mixed
+// request also holds complex64 A and the refinement vectors.
+static size_t serve_bytes(int64_t n, int k)
+{
+    return align256((size_t)n * n * sizeof(d2)) + 2 * align256((size_t)n * k * sizeof(d2)) +
+           block_layout(n, k).total;
+}
+
+static size_t serve_bytes_mixed(int64_t n, int k)
+{
+    return align256((size_t)n * n * sizeof(d2)) + align256((size_t)n * n * sizeof(f2)) +
+           2 * align256((size_t)n * k * sizeof(d2)) + bmix_layout(n, k).total;
+}
+
+}  // namespace ccg
+
+struct ccg_server {
+    int device = 0;
+    hipStream_t s = nullptr;
+    char* pool = nullptr;
+    size_t pool_bytes = 0, head = 0;
+    int max_active = 0;
+    int* sdone_d = nullptr;
+    ccg::SlotRec* tab_d = nullptr;
+    ccg::PoolAlloc alloc;
+    std::deque<ccg::ServeReq*> queue;
+    std::deque<int64_t> finished;  // done tickets not yet handed out by next_done
+    std::unordered_map<int64_t, ccg::ServeReq*> reqs;
+    ccg::ServeReq* slots[ccg::kMaxActive] = {};
+    int64_t next_ticket = 1;
+    int64_t next_solve = 1;
+    // batched iterations: pinned done words [kRing][kMaxActive], one event each
+    int* ring_h = nullptr;
+    int* ring_d = nullptr;
+    hipEvent_t tick_ev[ccg::kRing] = {};
+    std::vector<std::pair<int, int64_t>> members[ccg::kRing];  // (slot, solve id)
+    int64_t tick = 0, seen = 0;
+    // table uploads: pinned staging [kRing][kMaxActive]
+    ccg::SlotRec* stage_h = nullptr;
+    hipEvent_t stage_ev[ccg::kRing] = {};
+    bool stage_pending[ccg::kRing] = {};
+    int stage_next = 0;
+    std::vector<std::pair<int, int64_t>> table;  // (slot, solve id) of the device table
+    int tot_c = 0, tot_g = 0;
+    // copy-out: pinned column records [kMaxActive][kServeCols]
+    char* res_h = nullptr;
+    double* norms_h = nullptr;  // pinned column norms of mixed requests
+    hipEvent_t slot_ev[ccg::kMaxActive] = {};
+    ccg_server_stats st{};
+};
+
+namespace ccg {
+
+// Enqueue the set-up of a block solve of request r (inner solve of a mixed
+// request, or the whole solve of an FP64 one) and make it iterate.
+static int serve_start_solve(ccg_server* S, ServeReq* r, int32_t maxit, double tol2,
+                             int no_confirm)
+{
+    hipStream_t s = S->s;
+    const BArgs& a = r->rec.a;
+    const int gC = r->rec.gC;
+    kv_clear<<<1, kWave, 0, s>>>(S->sdone_d, r->slot);
+    kb_init<<<1, kMaxCols, 0, s>>>(a, maxit, tol2, no_confirm);
+    kb_normy<<<gC, kBlock, 0, s>>>(a);
+    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
+    kb_setup0<<<gC, kBlock, 0, s>>>(a);
+    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    r->phase = MP_INNER;
+    r->solve_id = S->next_solve++;
+    r->ticks = 0;
+    r->max_ticks = 2 * (int64_t)maxit + 4;
+    return 0;
+}
+
+// Enqueue the column norms of M (n x k, ld) into the request's pinned row and
+// record its event.
+static int serve_norms(ccg_server* S, ServeReq* r, const d2* M, int64_t ld)
+{
+    hipStream_t s = S->s;
+    km_colnorm<<<r->k, kBlock, 0, s>>>(M, ld, (int)r->n, r->norms_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    double* dst = S->norms_h + (size_t)r->slot * kServeCols;
+    if ((e = hipMemcpyAsync(dst, r->norms_d, r->k * sizeof(double), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+        return (int)e;
+    if ((e = hipEventRecord(S->slot_ev[r->slot], s)) != hipSuccess) return (int)e;
+    r->waiting = true;
+    return 0;
+}
+
+static int serve_admit(ccg_server* S, ServeReq* r, int slot)
+{
+    const int64_t n = r->n;
+    const int k = r->k;
+    hipStream_t s = S->s;
+    char* base = S->pool + r->off;
+    size_t o = 0;
+    d2* A = (d2*)(base + o);
+    o += align256((size_t)n * n * sizeof(d2));
+    f2* A32 = nullptr;
+    if (r->mixed) {
+        A32 = (f2*)(base + o);
+        o += align256((size_t)n * n * sizeof(f2));
+    }
+    d2* Y = (d2*)(base + o);
+    o += align256((size_t)n * k * sizeof(d2));
+    d2* X = (d2*)(base + o);
+    o += align256((size_t)n * k * sizeof(d2));
+    char* w = base + o;
+    const BLayout L = block_layout(n, k);
+    const int kp = pow2_at_least(k);
+    BArgs a{};
+    a.A = A;
+    a.lda = n;
+    a.n = (int)n;
+    a.k = k;
+    a.kp = kp;
+    a.Y = Y;
+    a.ldy = k;
+    a.X = X;
+    a.ldx = k;
+    d2* m[7];
+    for (int q = 0; q < 7; ++q) m[q] = (d2*)(w + L.mats + q * L.mat_bytes);
+    a.R = m[0]; a.RH = m[1]; a.P = m[2]; a.V = m[3]; a.S = m[4]; a.T = m[5]; a.B = m[6];
+    a.Zp = (d2*)(w + L.zp);
+    a.cpart = (d2*)(w + L.cpart);
+    a.cst = (SolverState*)(w + L.cst);
+    r->Ad = A;
+    r->Yd = Y;
+    r->Xd = X;
+    if (r->mixed) {
+        // the block solver runs the inner solves A32 D = Ys
+        const BMixLayout M = bmix_layout(n, k);
+        r->R = (d2*)(w + M.R);
+        r->Ys = (d2*)(w + M.Ys);
+        r->D = (d2*)(w + M.D);
+        r->norms_d = (double*)(w + M.norms);
+        a.A32 = A32;
+        a.lda32 = n;
+        a.Y = r->Ys;
+        a.ldy = kp;
+        a.X = r->D;
+        a.ldx = kp;
+    }
+    const size_t row = (size_t)k * sizeof(d2);
+    hipError_t e;
+    if ((e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
+                              hipMemcpyDefault, s)) != hipSuccess)
+        return (int)e;
+    if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
+        hipSuccess)
+        return (int)e;
+    // x keeps the caller's values in columns the solver never writes
+    if ((e = hipMemcpy2DAsync(X, row, r->X, r->ldx * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
+        hipSuccess)
+        return (int)e;
+    r->rec.a = a;
+    r->rec.gC = col_blocks(n, kp);
+    r->rec.gG = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
+    r->rec.kslice = r->mixed ? kslice32_of(n) : kslice_of(n);
+    r->rec.slot = slot;
+    r->slot = slot;
+    r->state = CCG_REQ_RUNNING;
+    S->slots[slot] = r;
+    S->st.admitted++;
+    S->st.pool_used += r->bytes;
+    if (S->st.pool_used > S->st.pool_peak) S->st.pool_peak = S->st.pool_used;
+    int rc;
+    if (r->mixed) {
+        km_round<<<elem_blocks(n * n), kBlock, 0, s>>>(A, n, (int)n, A32);
+        r->ny2.assign(k, 0.0);
+        r->relres.assign(k, 0.0);
+        r->info.assign(k, 0);
+        r->outers.assign(k, 0);
+        r->inner_iters.assign(k, 0);
+        r->mv32.assign(k, 0);
+        r->mv64.assign(k, 0);
+        r->live.assign(k, 1);
+        r->outer = 0;
+        r->phase = MP_NORMY;
+        r->ticks = r->max_ticks = 0;
+        if ((rc = serve_norms(S, r, Y, k))) return rc;
+    } else if ((rc = serve_start_solve(S, r, r->maxit, r->tol * r->tol, 0))) {
+        return rc;
+    }
+    return 0;
+}
+
+// Enqueue the copy-out of a request whose columns have finished.
+static int serve_retire(ccg_server* S, ServeReq* r)
+{
+    hipStream_t s = S->s;
+    const size_t row = (size_t)r->k * sizeof(d2);
+    hipError_t e;
+    if ((e = hipMemcpy2DAsync(r->X, r->ldx * sizeof(d2), r->Xd, row, row, r->n,
+                              hipMemcpyDefault, s)) != hipSuccess)
+        return (int)e;
+    if (!r->mixed) {
+        char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
+        if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
+                                hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return (int)e;
+    }
+    if ((e = hipEventRecord(S->slot_ev[r->slot], s)) != hipSuccess) return (int)e;
+    r->retiring = true;
+    return 0;
+}
+
+// A mixed request whose FP64 residual norms are on the host: decide every
+// column (within tol, outer budget spent, non-finite) and start the inner
+// solve of the others, or retire the request.
+static int serve_mixed_decide(ccg_server* S, ServeReq* r, const double* nrm)
+{
+    hipStream_t s = S->s;
+    ColScale sc{};
+    r->nr = ColScale{};
+    int active = 0;
+    for (int c = 0; c < r->k; ++c) {
+        if (!r->live[c]) continue;
+        const double rel = std::sqrt(nrm[c] / r->ny2[c]);
+        r->relres[c] = rel;
+        if (!std::isfinite(nrm[c])) {
+            r->info[c] = 4;
+            r->live[c] = 0;
+        } else if (rel <= r->tol) {
+            r->info[c] = 0;
+            r->live[c] = 0;
+        } else if (r->outer >= r->maxit) {
+            r->info[c] = 1;
+            r->live[c] = 0;
+        } else {
+            const double v = std::sqrt(nrm[c]);
+            sc.v[c] = 1.0 / v;
+            r->nr.v[c] = v;
+            ++active;
+        }
+    }
+    if (!active) return serve_retire(S, r);
+    const int kp = r->rec.a.kp;
+    km_scale<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->R, (int)r->n, kp, sc, r->Ys);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    return serve_start_solve(S, r, r->maxit_inner, r->tol_inner * r->tol_inner, 1);
+}
+
+// A mixed request whose event has completed: the norms of y (first event) or
+// of the FP64 residual after an inner solve.
+static int serve_mixed_event(ccg_server* S, ServeReq* r)
+{
+    hipStream_t s = S->s;
+    const double* nrm = S->norms_h + (size_t)r->slot * kServeCols;
+    const int kp = r->rec.a.kp;
+    if (r->phase == MP_NORMY) {
+        ColScale zero{}, none{};
+        for (int c = 0; c < r->k; ++c) {
+            r->ny2[c] = nrm[c];
+            if (!std::isfinite(nrm[c])) {  // x left as given
+                r->info[c] = 4;
+                r->live[c] = 0;
+            } else {  // x0 = 0 (y = 0: x = 0, info 0, done)
+                zero.v[c] = 1.0;
+                if (nrm[c] == 0.0) r->live[c] = 0;
+            }
+        }
+        km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp,
+                                                               r->D, none, zero);
+        km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, nullptr, (int)r->n, r->k,
+                                                           kp, r->R);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        r->phase = MP_RESID;
+        return serve_mixed_decide(S, r, nrm);  // with x0 = 0 the residual is y
+    }
+    // MP_RESID after an inner solve: count it, then decide
+    const char* src = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
+    for (int c = 0; c < r->k; ++c) {
+        if (r->nr.v[c] == 0.0) continue;
+        const SolverState& st = *(const SolverState*)(src + (size_t)c * kStateStride);
+        r->outers[c]++;
+        r->inner_iters[c] += st.iters;
+        r->mv32[c] += st.matvecs;
+        r->mv64[c]++;
+    }
+    r->outer++;
+    return serve_mixed_decide(S, r, nrm);
+}
+
+// An inner solve of mixed request r has ended: x += ||r|| d, then the FP64
+// residual and its column norms (and the inner records, for the counts).
+static int serve_mixed_outer(ccg_server* S, ServeReq* r)
+{
+    hipStream_t s = S->s;
+    const int kp = r->rec.a.kp;
+    char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return (int)e;
+    km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp, r->D,
+                                                           r->nr, ColScale{});
+    gemm(r->Ad, r->n, (int)r->n, r->Xd, r->k, r->k, r->rec.a.Zp, s);
+    km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, r->rec.a.Zp, (int)r->n, r->k,
+                                                       kp, r->R);
+    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    r->phase = MP_RESID;
+    return serve_norms(S, r, r->R, kp);
+}
+
+// Requests with an outstanding event: finished copy-outs free their slots and
+// pool blocks; mixed requests whose norms have arrived move on.  wait: block
+// on them.
+static int serve_collect(ccg_server* S, bool wait)
+{
+    for (int q = 0; q < S->max_active; ++q) {
+        ServeReq* r = S->slots[q];
+        if (!r || !(r->retiring || r->waiting)) continue;
+        hipError_t e = wait ? hipEventSynchronize(S->slot_ev[q]) : hipEventQuery(S->slot_ev[q]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return (int)e;
+        if (r->waiting && !r->retiring) {
+            r->waiting = false;
+            int rc = serve_mixed_event(S, r);
+            if (rc) return rc;
+            continue;
+        }
+        r->res.resize(r->k);
+        if (r->mixed) {
+            for (int j = 0; j < r->k; ++j) {
+                ccg_result& o = r->res[j];
+                o.info = r->info[j];
+                o.iters = r->inner_iters[j];
+                o.matvecs = r->mv32[j];
+                o.confirms = r->mv64[j];
+                o.relres_rec = r->relres[j];
+                o.relres_true = r->relres[j];
+            }
+        } else {
+            const char* src = S->res_h + (size_t)q * kServeCols * kStateStride;
+            for (int j = 0; j < r->k; ++j) {
+                const SolverState& c = *(const SolverState*)(src + (size_t)j * kStateStride);
+                ccg_result& o = r->res[j];
+                o.info = c.phase == PH_DONE ? c.info : 1;
+                o.iters = c.iters;
+                o.matvecs = c.matvecs;
+                o.confirms = c.confirms;
+                o.relres_rec = c.relres_rec;
+                o.relres_true = c.relres_true;
+            }
+        }
+        r->state = CCG_REQ_DONE;
+        r->retiring = false;
+        r->waiting = false;
+        S->finished.push_back(r->ticket);
+        S->alloc.release(r->off, r->bytes);
+        S->st.pool_used -= r->bytes;
+        S->st.completed++;
+        S->slots[q] = nullptr;
+    }
+    return 0;
+}
+
+// Read the done words of tick `seen` (waiting for it): FP64 requests that
+// ended retire, mixed requests whose inner solve ended take an outer step.
+static int serve_read_tick(ccg_server* S)
+{
+    const int u = (int)(S->seen % kRing);
+    hipError_t e = hipEventSynchronize(S->tick_ev[u]);
+    if (e != hipSuccess) return (int)e;
+    for (const auto& mt : S->members[u]) {
+        ServeReq* r = S->slots[mt.first];
+        // the entry must belong to the request's current solve (a mixed
+        // request starts a new inner solve, with a new id, per outer step)
+        if (!r || r->solve_id != mt.second || r->retiring || r->state != CCG_REQ_RUNNING ||
+            r->phase != MP_INNER)
+            continue;
+        const int w = __atomic_load_n(&S->ring_h[u * kMaxActive + mt.first], __ATOMIC_ACQUIRE);
+        const bool out_of_budget = r->ticks >= r->max_ticks && r->last_tick == S->seen;
+        if (w == PH_DONE || out_of_budget) {
+            int rc = r->mixed ? serve_mixed_outer(S, r) : serve_retire(S, r);
+            if (rc) return rc;
+        }
+    }
+    S->members[u].clear();
+    S->seen++;
+    return 0;
+}
+
+static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, int64_t>>& want)
+{
+    const int u = S->stage_next;
+    S->stage_next = (S->stage_next + 1) % kRing;
+    if (S->stage_pending[u]) {
+        hipError_t e = hipEventSynchronize(S->stage_ev[u]);
+        if (e != hipSuccess) return (int)e;
+        S->stage_pending[u] = false;
+    }
+    SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
+    int c = 0, g = 0;
+    for (size_t i = 0; i < want.size(); ++i) {
+        SlotRec rec = S->slots[want[i].first]->rec;
+        rec.c0 = c;
+        rec.g0 = g;
+        c += rec.gC;
+        g += rec.gG;
+        h[i] = rec;
+    }
+    S->tot_c = c;
+    S->tot_g = g;
+    S->table = want;
+    if (want.empty()) return 0;
+    hipError_t e = hipMemcpyAsync(S->tab_d, h, want.size() * sizeof(SlotRec),
+                                  hipMemcpyHostToDevice, S->s);
+    if (e != hipSuccess) return (int)e;
+    if ((e = hipEventRecord(S->stage_ev[u], S->s)) != hipSuccess) return (int)e;
+    S->stage_pending[u] = true;
+    return 0;
+}
+
+static bool serve_iterating(const ServeReq* r)
+{
+    return r && r->state == CCG_REQ_RUNNING && !r->retiring && r->phase == MP_INNER &&
+           r->ticks < r->max_ticks;
+}
+
+// Admission in arrival order while a slot is free and the head fits the pool.
+static int serve_admit_queue(ccg_server* S)
+{
+    while (!S->queue.empty()) {
+        int slot = -1;
+        for (int q = 0; q < S->max_active && slot < 0; ++q)
+            if (!S->slots[q]) slot = q;
+        if (slot < 0) break;
+        ServeReq* r = S->queue.front();
+        size_t off = 0;
+        if (!S->alloc.alloc(r->bytes, &off)) {
+            // the head waits until retirements free enough of the pool
+            S->st.admission_waits++;
+            break;
+        }
+        r->off = off;
+        S->queue.pop_front();
+        int rc = serve_admit(S, r, slot);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+static int serve_step(ccg_server* S)
+{
+    int rc;
+    hipError_t e;
+    // 1. finished copy-outs free their slots and pool blocks; admit
+    if ((rc = serve_collect(S, false))) return rc;
+    if ((rc = serve_admit_queue(S))) return rc;
+    // 2. the table of this iteration: admitted requests still iterating (a
+    //    slot may hold another request than in the last table: compare tickets)
+    std::vector<std::pair<int, int64_t>> want;
+    bool any64 = false, any32 = false;
+    for (int q = 0; q < S->max_active; ++q)
+        if (serve_iterating(S->slots[q])) {
+            want.emplace_back(q, S->slots[q]->solve_id);
+            (S->slots[q]->mixed ? any32 : any64) = true;
+        }
+    if (want != S->table && (rc = serve_upload_table(S, want))) return rc;
+    // 3. one batched iteration
+    if (!want.empty()) {
+        while (S->seen + kRing <= S->tick)
+            if ((rc = serve_read_tick(S))) return rc;
+        const int u = (int)(S->tick % kRing);
+        const int m = (int)want.size();
+        hipStream_t s = S->s;
+        const SlotRec* tab = S->tab_d;
+        kv_p<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        if (any64) kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
+        if (any32) kv_cgemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
+        kv_red1<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_P1, nullptr);
+        kv_s<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_S, nullptr);
+        if (any64) kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
+        if (any32) kv_cgemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
+        kv_red2<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_T, nullptr);
+        kv_xr<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_XR,
+                                           S->ring_d + (size_t)u * kMaxActive);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if ((e = hipEventRecord(S->tick_ev[u], s)) != hipSuccess) return (int)e;
+        S->members[u] = want;
+        for (const auto& w : want) {
+            ServeReq* r = S->slots[w.first];
+            r->ticks++;
+            r->last_tick = S->tick;
+        }
+        S->tick++;
+        S->st.ticks++;
+    }
+    // 4. read the stop flags one iteration behind (all of them when idle) and
+    //    enqueue the copy-out of what has finished
+    const int64_t behind = want.empty() ? 0 : 1;
+    while (S->seen + behind < S->tick)
+        if ((rc = serve_read_tick(S))) return rc;
+    // 5. with nothing left iterating, wait for the copy-outs
+    bool iterating = false;
+    for (int q = 0; q < S->max_active; ++q) iterating = iterating || serve_iterating(S->slots[q]);
+    if (!iterating && (rc = serve_collect(S, true))) return rc;
+    int act = 0;
+    for (int q = 0; q < S->max_active; ++q)
+        if (S->slots[q]) act++;
+    S->st.active = act;
+    S->st.queued = (int32_t)S->queue.size();
+    if (act > S->st.peak_active) S->st.peak_active = act;
+    return 0;
+}
+
+
 }  // namespace ccg
 
 // ============================================================== C ABI
@@ -1763,6 +2022,12 @@ size_t ccg_server_request_bytes(int64_t n, int64_t k)
     return n == 0 ? 0 : ccg::serve_bytes(n, (int)k);
 }
 
+size_t ccg_server_request_bytes_mixed(int64_t n, int64_t k)
+{
+    if (n < 0 || n > ccg::kMaxNB || k < 1 || k > ccg::kServeCols) return 0;
+    return n == 0 ? 0 : ccg::serve_bytes_mixed(n, (int)k);
+}
+
 int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* stream,
                       ccg_server** out)
 {
@@ -1792,6 +2057,9 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&S->res_h, (size_t)kMaxActive * kServeCols * kStateStride,
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&S->norms_h, (size_t)kMaxActive * kServeCols * sizeof(double),
                           hipHostMallocDefault);
     for (int q = 0; q < kRing && e == hipSuccess; ++q) {
         e = hipEventCreateWithFlags(&S->tick_ev[q], hipEventDisableTiming);
@@ -1824,13 +2092,15 @@ int ccg_server_destroy(ccg_server* S)
     if (S->ring_h) keep(hipHostFree(S->ring_h));
     if (S->stage_h) keep(hipHostFree(S->stage_h));
     if (S->res_h) keep(hipHostFree(S->res_h));
+    if (S->norms_h) keep(hipHostFree(S->norms_h));
     delete S;
     return e == hipSuccess ? 0 : (int)e;
 }
 
-int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64_t lda,
-                      const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx, double tol,
-                      int32_t maxit, int64_t* ticket)
+static int server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                         const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx, double tol,
+                         int32_t maxit, bool mixed, double tol_inner, int32_t maxit_inner,
+                         int64_t* ticket)
 {
     using namespace ccg;
     if (!S) return -1;
@@ -1844,8 +2114,14 @@ int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64
     if (ldx < k) return -9;
     if (!(tol > 0.0) || !std::isfinite(tol)) return -10;
     if (maxit < 0) return -11;
-    if (!ticket) return -12;
-    const size_t bytes = n > 0 ? serve_bytes(n, (int)k) : 0;
+    if (mixed) {
+        if (!(tol_inner > 0.0) || !(tol_inner < 1.0)) return -12;
+        if (maxit_inner < 1) return -13;
+        if (!ticket) return -14;
+    } else if (!ticket) {
+        return -12;
+    }
+    const size_t bytes = n == 0 ? 0 : mixed ? serve_bytes_mixed(n, (int)k) : serve_bytes(n, (int)k);
     if (bytes > S->pool_bytes - S->head) {
         S->st.rejected++;
         return CCG_SERVER_REJECTED;
@@ -1862,6 +2138,9 @@ int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64
     r->ldx = ldx;
     r->tol = tol;
     r->maxit = maxit;
+    r->mixed = mixed;
+    r->tol_inner = tol_inner;
+    r->maxit_inner = maxit_inner;
     r->bytes = bytes;
     S->reqs[r->ticket] = r;
     S->st.submitted++;
@@ -1877,6 +2156,22 @@ int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64
     }
     *ticket = r->ticket;
     return 0;
+}
+
+int ccg_server_submit(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                      const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx, double tol,
+                      int32_t maxit, int64_t* ticket)
+{
+    return server_submit(S, n, k, A, lda, Y, ldy, X, ldx, tol, maxit, false, 0.0, 0, ticket);
+}
+
+int ccg_server_submit_mixed(ccg_server* S, int64_t n, int64_t k, const ccg_z* A, int64_t lda,
+                            const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx, double tol,
+                            int32_t maxit, double tol_inner, int32_t maxit_inner,
+                            int64_t* ticket)
+{
+    return server_submit(S, n, k, A, lda, Y, ldy, X, ldx, tol, maxit, true, tol_inner,
+                         maxit_inner, ticket);
 }
 
 int ccg_server_step(ccg_server* S, int32_t* active, int32_t* queued)

@@ -195,3 +195,16 @@ def test_block_mixed_argument_errors_are_rejected_on_the_host(lib):
         args[pos] = bad
         want = -(pos + 1) if pos != 1 else -2
         assert lib.ccg_bicgstab_block_mixed_ex(*args) == want, (pos, bad)
+
+
+def test_server_mixed_argument_errors_are_rejected_on_the_host(lib):
+    from paper_1208_4869_amd import ccg
+    P = ctypes.c_void_p
+    t = ctypes.c_int64()
+    assert lib.ccg_server_submit_mixed(None, 4, 1, P(256), 4, P(256), 1, P(256), 1, 1e-10, 10,
+                                       1e-5, 100, ctypes.byref(t)) == -1
+    for n, k in ((512, 1), (4096, 8)):
+        b = ccg.ccg_server_request_bytes(n, k)
+        bm = ccg.ccg_server_request_bytes(n, k, mixed=True)
+        assert bm >= b + 8 * n * n  # the complex64 copy of A on top
+    assert ccg.ccg_server_request_bytes(10, 17, mixed=True) == 0

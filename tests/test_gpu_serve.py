@@ -236,3 +236,79 @@ def test_serve_full_size_mix(orc):
         fe = np.linalg.norm(X[:, 0] - Xt[:, 0]) / np.linalg.norm(Xt[:, 0])
         fe_ref = np.linalg.norm(ref.x - Xt[:, 0]) / np.linalg.norm(Xt[:, 0])
         assert fe <= 100 * max(fe_ref, 1e-13)
+
+
+def alone_mixed(A, Y, maxit=10, tol_inner=1e-5):
+    import torch
+    n, k = Y.shape
+    Ad = dev(A)
+    X = torch.full((n, k), float("nan"), dtype=torch.complex128, device="cuda")
+    res = ccg.ccg_bicgstab_block_mixed_ex(Ad, ccg.ccg_round_c64(Ad), dev(Y), X, 1e-10, maxit,
+                                          tol_inner, 1000, flags=ccg.X0_ZERO)
+    return X.cpu().numpy(), res
+
+
+def test_serve_mixed_and_fp64_in_one_mix():
+    """Mixed-precision requests (FP64 refinement, inner solves on complex64
+    products) and FP64 requests share the batched iterations: each mixed
+    request equals ccg_bicgstab_block_mixed_ex alone bit for bit, each FP64
+    request the block solver alone; a small pool forces waits."""
+    import torch
+    specs = [(300, 3, True), (64, 1, False), (513, 8, True), (1024, 2, False),
+             (200, 16, True), (100, 5, False), (1024, 4, True), (7, 2, True)]
+    reqs = [make_request(n, k, 700 + i) for i, (n, k, _) in enumerate(specs)]
+    need = max(ccg.ccg_server_request_bytes(A.shape[0], Y.shape[1], mixed=mx)
+               for (A, Y, _), (_, _, mx) in zip(reqs, specs))
+    out, held = {}, []
+    with ccg.Server(2 * need, max_active=4) as srv:
+        tickets = []
+        for (A, Y, _), (_, _, mx) in zip(reqs, specs):
+            n, k = Y.shape
+            X = torch.full((n, k), float("nan"), dtype=torch.complex128, device="cuda")
+            tickets.append(srv.submit(dev(A), dev(Y), X, 1e-10, 10 if mx else 1000,
+                                      mixed=mx))
+            held.append(X)
+            srv.step()
+        res = srv.run_all(tickets)
+        stats = srv.stats()
+    assert stats["completed"] == len(reqs) and stats["admission_waits"] > 0
+    for i, ((A, Y, Xt), (n, k, mx)) in enumerate(zip(reqs, specs)):
+        X = held[i].cpu().numpy()
+        got = res[tickets[i]]
+        if mx:
+            Xr, rr = alone_mixed(A, Y)
+            assert np.array_equal(X, Xr), i
+            for a, b in zip(got, rr):
+                assert (a.info, a.iters, a.matvecs, a.confirms) == \
+                    (b.info, b.inner_iters, b.matvecs32, b.matvecs64), (i, a, b)
+                assert a.relres_true == b.relres_true
+        else:
+            Xr, rr = alone(A, Y)
+            assert np.array_equal(X, Xr), i
+            for a, b in zip(got, rr):
+                assert same_result(a, b)
+        for c in range(k):
+            rel, slack = host_relres(A, X[:, c], Y[:, c])
+            assert got[c].info == 0 and rel <= 1e-10 + slack, (i, c, rel)
+
+
+def test_serve_mixed_special_columns():
+    """A mixed request with a zero and a non-finite column, and outer budget 0."""
+    import torch
+    A, Y, _ = make_request(150, 3, 77)
+    Y = Y.copy()
+    Y[:, 1] = 0
+    Y[5, 2] = np.nan
+    X0 = np.full((150, 3), 1.5 - 2j)
+    with ccg.Server(4 * ccg.ccg_server_request_bytes(150, 3, mixed=True)) as srv:
+        X = dev(X0)
+        t = srv.submit(dev(A), dev(Y), X, 1e-10, 10, mixed=True)
+        X2 = dev(X0)
+        t2 = srv.submit(dev(A), dev(Y), X2, 1e-10, 0, mixed=True)
+        res = srv.run_all([t, t2])
+    Xg = X.cpu().numpy()
+    assert [r.info for r in res[t]] == [0, 0, 4]
+    assert np.all(Xg[:, 1] == 0) and np.array_equal(Xg[:, 2], X0[:, 2])
+    rel, slack = host_relres(A, Xg[:, 0], Y[:, 0])
+    assert rel <= 1e-10 + slack
+    assert res[t2][0].info == 1 and np.all(X2.cpu().numpy()[:, 0] == 0)
