@@ -58,13 +58,29 @@ __device__ __forceinline__ d2 shfl_xor_d2(d2 v, int mask)
     return d2{__shfl_xor(v.x, mask, kWave), __shfl_xor(v.y, mask, kWave)};
 }
 
+// Lane stages of a transform: spans h = top, top/2, ..., 1 with top =
+// min(M/2, 32): at most six.  Their twiddles are loaded for all stages before
+// the first butterfly (fixed-length loops, unrolled, guarded by h >= 1), so
+// the loads are in flight together instead of one per stage.
+constexpr int kLaneStages = 6;
+
+__device__ __forceinline__ int t3_top(int M) { return M < kWave ? M / 2 : kWave / 2; }
+
 // Forward transform of one line held as R registers per lane (R = M / 64 for
 // M >= 64, else 1 with lanes >= M idle).  tw[t] = e^{-2 pi i t / M}, t < M/2.
 template <int R>
 __device__ __forceinline__ void t3_fwd(d2 (&v)[R], int M, const d2* __restrict__ tw)
 {
     const int l = threadIdx.x & (kWave - 1);
+    const int top = t3_top(M);
+    d2 w[kLaneStages];
+#pragma unroll
+    for (int i = 0; i < kLaneStages; ++i) {
+        const int h = top >> i;
+        w[i] = h >= 1 ? tw[(l & (h - 1)) * (M / (2 * h))] : d2{1.0, 0.0};
+    }
     // spans held in registers (h >= 64)
+#pragma unroll
     for (int hr = R / 2; hr >= 1; hr >>= 1) {
         const int h = hr * kWave;
         const int step = M / (2 * h);
@@ -78,14 +94,15 @@ __device__ __forceinline__ void t3_fwd(d2 (&v)[R], int M, const d2* __restrict__
         }
     }
     // spans across lanes
-    const int top = M < kWave ? M / 2 : kWave / 2;
-    for (int h = top; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int i = 0; i < kLaneStages; ++i) {
+        const int h = top >> i;
+        if (h < 1) break;
         const bool bottom = (l & h) != 0;
-        const d2 w = tw[(l & (h - 1)) * (M / (2 * h))];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const d2 pv = shfl_xor_d2(v[r], h);
-            v[r] = bottom ? cmul(pv - v[r], w) : v[r] + pv;
+            v[r] = bottom ? cmul(pv - v[r], w[i]) : v[r] + pv;
         }
     }
 }
@@ -95,17 +112,27 @@ template <int R>
 __device__ __forceinline__ void t3_inv(d2 (&v)[R], int M, const d2* __restrict__ tw)
 {
     const int l = threadIdx.x & (kWave - 1);
-    const int top = M < kWave ? M / 2 : kWave / 2;
-    for (int h = 1; h <= top; h <<= 1) {
+    const int top = t3_top(M);
+    const int nls = top >= 1 ? 32 - __builtin_clz(top) : 0;  // lane stages
+    d2 w[kLaneStages];
+#pragma unroll
+    for (int i = 0; i < kLaneStages; ++i) {
+        const int h = 1 << i;
+        w[i] = i < nls ? tw[(l & (h - 1)) * (M / (2 * h))] : d2{1.0, 0.0};
+    }
+#pragma unroll
+    for (int i = 0; i < kLaneStages; ++i) {
+        if (i >= nls) break;
+        const int h = 1 << i;
         const bool bottom = (l & h) != 0;
-        const d2 w = tw[(l & (h - 1)) * (M / (2 * h))];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const d2 u = bottom ? cmul_conj(v[r], w) : v[r];
+            const d2 u = bottom ? cmul_conj(v[r], w[i]) : v[r];
             const d2 pu = shfl_xor_d2(u, h);
             v[r] = bottom ? pu - u : u + pu;
         }
     }
+#pragma unroll
     for (int hr = 1; hr <= R / 2; hr <<= 1) {
         const int h = hr * kWave;
         const int step = M / (2 * h);
