@@ -115,7 +115,7 @@ class Oracle:
             ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
             ctypes.POINTER(_MixedStats), P]
         self.lib.oracle_bicgstab_mixed.restype = ctypes.c_int
-        for name in ("oracle_matvec", "oracle_matvec_h"):
+        for name in ("oracle_matvec", "oracle_matvec_h", "oracle_matvec_sym_upper"):
             f = getattr(self.lib, name)
             f.argtypes = [I64, P, I64, P, P]
             f.restype = None
@@ -144,6 +144,15 @@ class Oracle:
         y = np.empty(A.shape[0], dtype=np.complex128)
         self.lib.oracle_matvec(A.shape[0], A.ctypes.data, lda, x.ctypes.data,
                                y.ctypes.data)
+        return y
+
+    def matvec_sym_upper(self, A, x):
+        """A x for complex symmetric A read from its upper triangle only."""
+        A, lda = self._mat(A)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.empty(A.shape[0], dtype=np.complex128)
+        self.lib.oracle_matvec_sym_upper(A.shape[0], A.ctypes.data, lda,
+                                         x.ctypes.data, y.ctypes.data)
         return y
 
     def matvec_h(self, A, x):

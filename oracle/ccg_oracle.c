@@ -156,6 +156,24 @@ void oracle_matvec_h(int64_t n, const zc* A, int64_t lda, const zc* x, zc* y)
     }
 }
 
+/* y = A x for a complex symmetric A (A^T = A, the matrices of COCG and COCR,
+ * section 3.4) of which only the upper triangle is stored:
+ *   y_i = sum_{j < i} A_ji x_j + sum_{j >= i} A_ij x_j,
+ * summed over j in increasing order.  Elements below the diagonal are never
+ * read.  On a matrix that is symmetric in full this is oracle_matvec's sum
+ * term for term, in the same order. */
+void oracle_matvec_sym_upper(int64_t n, const zc* A, int64_t lda, const zc* x, zc* y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        zc s = 0.0;
+        for (int64_t j = 0; j < i; ++j)
+            s += A[j * lda + i] * x[j];
+        for (int64_t j = i; j < n; ++j)
+            s += A[i * lda + j] * x[j];
+        y[i] = s;
+    }
+}
+
 /* rt = y - A x */
 static void residual(int64_t n, const zc* A, int64_t lda, const zc* y,
                      const zc* x, zc* rt)

@@ -221,6 +221,35 @@ def pin_lattice_adjoint_symmetry(orc):
     assert np.array_equal(orc.matvec_h(A, x), np.conj(orc.matvec(A, np.conj(x))))
 
 
+def pin_sym_upper_integer_exact(orc):
+    """The upper-triangle product of a complex symmetric matrix: on Gaussian
+    integers it equals, exactly, the product with the symmetric matrix whose
+    upper triangle is the stored one, and NaN stored below the diagonal never
+    reaches the result (so the lower triangle is not read)."""
+    for n, seed in ((1, 20), (2, 21), (7, 22), (33, 23)):
+        A = inputs.gaussian_integer_matrix(n, seed, bound=512)
+        S = np.triu(A) + np.triu(A, 1).T
+        x = inputs.gaussian_integer_vector(n, seed + 100, bound=512)
+        want = exact_matvec_int(S, x)
+        stored = A.copy()
+        stored[np.tril_indices(n, -1)] = complex(np.nan, np.nan)
+        assert np.array_equal(orc.matvec_sym_upper(stored, x), want), n
+
+
+def pin_sym_upper_is_full_product_on_symmetric(orc):
+    """On a matrix symmetric in full, the upper-triangle product makes the
+    same sums in the same order as the dense product: equal bit for bit."""
+    n = 41
+    rng = np.random.default_rng(24)
+    B = inputs.cn01(rng, (n, n))
+    A = B + B.T
+    x = inputs.cn01(rng, n)
+    assert np.array_equal(orc.matvec_sym_upper(A, x), orc.matvec(A, x))
+    L = inputs.lattice_matrix(3)
+    xl = inputs.cn01(rng, L.shape[0])
+    assert np.array_equal(orc.matvec_sym_upper(L, xl), orc.matvec(L, xl))
+
+
 # ------------------------------------------------------------- solver pins
 
 def pin_lu_dense(orc, sizes=(1, 2, 3, 4, 8, 16, 32, 64)):

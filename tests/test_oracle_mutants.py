@@ -90,6 +90,11 @@ MUTANTS = [
      "r[i] = r[i] - alpha * w[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
      "r[i] = r[i] - alpha * u[i];\n        }\n        rr = norm2sq(n, r);\n        k++;\n        if (!isfinite(rr)) {\n            st->info = 4;\n            break;\n        }\n        if (hist) {\n            hist[k - 1].alpha_re = creal(alpha);",
      1),
+    ("sym_lower_read_from_row",
+     "s += A[j * lda + i] * x[j];", "s += A[i * lda + j] * x[j];", 1),
+    ("sym_diagonal_dropped",
+     "for (int64_t j = i; j < n; ++j)\n            s += A[i * lda + j] * x[j];",
+     "for (int64_t j = i + 1; j < n; ++j)\n            s += A[i * lda + j] * x[j];", 1),
 ]
 
 
