@@ -84,6 +84,8 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=512)
     p.add_argument("--serve-rate", type=float, default=None,
                    help="Poisson arrival rate (requests/s) of the serving leg")
+    p.add_argument("--no-sym", action="store_true",
+                   help="skip the upper-triangle (complex symmetric) leg")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run a short mix of the kernels for rocprofv3 and exit")
     return p.parse_args()
@@ -101,17 +103,19 @@ def make_inputs():
     return A, x_true, y
 
 
-def time_solves(fn, A, y, x, work, steps, warmup, hist=None):
+def time_solves(fn, A, y, x, work, steps, warmup, hist=None, flags=1):
+    """Solves from x0 = 0 (flag 1) plus `flags`; host clock per solve."""
     import torch
     res = None
+    flags |= 1
     for _ in range(warmup):
-        res = fn(A, y, x, TOL, MAXIT, flags=1, work=work, hist=hist)
+        res = fn(A, y, x, TOL, MAXIT, flags=flags, work=work, hist=hist)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        res = fn(A, y, x, TOL, MAXIT, flags=1, work=work, hist=hist)
+        res = fn(A, y, x, TOL, MAXIT, flags=flags, work=work, hist=hist)
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
@@ -509,6 +513,46 @@ def structured_leg(steps):
     return out
 
 
+def sym_leg(A, A_h, y, y_h, steps):
+    """The lattice matrix is complex symmetric: the upper-triangle product
+    (CCG_OP_S, half the bytes of A x) timed with HIP events, and BiCGSTAB,
+    COCG and COCR run with it (flag A_SYM_UPPER) on the same system."""
+    import torch
+
+    from paper_1208_4869_amd import ccg
+    n = A.shape[0]
+    xin = torch.from_numpy(inputs_cn01(n)).cuda()
+    yout = torch.empty_like(xin)
+    ws = ccg.workspace(ccg.WS_MATVEC_S, n)
+    ts = time_kernel(lambda: ccg.ccg_matvec_ex(ccg.OP_S, A, xin, yout, ws), 50)
+    tri = 16.0 * n * (n + 1) / 2 + 32.0 * n
+    log("upper-triangle product: %.1f us (%.0f GB/s of triangle bytes)"
+        % (ts * 1e6, tri / ts / 1e9))
+    out = {"product": {"kernel": "k_symv (tiles) + gather", "launch_us": ts * 1e6,
+                       "bytes_per_launch": tri, "achieved_gbs": tri / ts / 1e9,
+                       "frac": tri / ts / 1e9 / HBM_PEAK_GBS,
+                       "partials_bytes": float(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_S, n))}}
+    for name, fn, wsid in (("bicgstab", ccg.ccg_bicgstab_ex, ccg.WS_BICGSTAB),
+                           ("cocg", ccg.ccg_cocg_ex, ccg.WS_COCG),
+                           ("cocr", ccg.ccg_cocr_ex, ccg.WS_COCR)):
+        wk = ccg.workspace(wsid | ccg.WS_SYM, n)
+        xs = torch.empty(n, dtype=torch.complex128, device="cuda")
+        log("timing %d %s solves with the upper-triangle product" % (steps, name.upper()))
+        stot, slat, sres = time_solves(fn, A, y, xs, wk, steps, 1, flags=ccg.A_SYM_UPPER)
+        xsg = xs.cpu().numpy()
+        out[name] = {"solves_per_s": steps / stot,
+                     "p50_ms": float(np.percentile(slat, 50) * 1e3),
+                     "iters": sres.iters, "matvecs": sres.matvecs, "info": sres.info,
+                     "relres_true": float(np.linalg.norm(y_h - A_h @ xsg)
+                                          / np.linalg.norm(y_h))}
+    return out
+
+
+def inputs_cn01(n):
+    from paper_1208_4869_amd import inputs
+    return inputs.cn01(np.random.default_rng(X_SEED + 1), n)
+
+
 def profile_kernels(A, y):
     """A short, fixed mix for rocprofv3: a device copy of known size (the
     reference for scaling the HBM byte counters), A x, A^H x, the complex64
@@ -532,12 +576,13 @@ def profile_kernels(A, y):
         dst.copy_(src)
         ccg.ccg_matvec(ccg.OP_N, A, x)
         ccg.ccg_matvec(ccg.OP_C, A, x)
+        ccg.ccg_matvec(ccg.OP_S, A, x)
         ccg.ccg_matvec_c64(A32, x32)
         ccg.ccg_matmat(A, P, Z, work=wmm)
     ccg.ccg_bicgstab_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
     ccg.ccg_cgnr_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
     torch.cuda.synchronize()
-    log("profile mix done: copy %d bytes x5, matvec N/C/c64 x5, A P (k=%d) x5, "
+    log("profile mix done: copy %d bytes x5, matvec N/C/S/c64 x5, A P (k=%d) x5, "
         "1 BiCGSTAB, 1 CGNR" % (src.numel() * 8, BLOCK_RHS))
 
 
@@ -655,6 +700,8 @@ def main():
         "cocg": cs["cocg"],
         "cocr": cs["cocr"],
     }
+    if not args.no_sym:
+        out["symmetric"] = sym_leg(A, A_h, y, y_h, csteps)
     if not args.no_mixed:
         out["mixed"] = mixed_leg(max(args.steps // 3, 3))
     if not args.no_block:

@@ -81,7 +81,7 @@ typedef struct {
     double res_half, res_full;
 } ccg_hist;
 
-enum { CCG_OP_N = 0, CCG_OP_C = 1 };
+enum { CCG_OP_N = 0, CCG_OP_C = 1, CCG_OP_S = 2 };
 
 /* Method ids for ccg_workspace_bytes. */
 enum {
@@ -95,8 +95,14 @@ enum {
     CCG_WS_BICGSTAB_MIXED = 8,
     CCG_WS_T3_MATVEC = 9, /* scratch of ccg_t3_matvec (ccg_t3_workspace_bytes) */
     CCG_WS_MATMAT_C64 = 10,           /* scratch of ccg_matmat_c64 (nrhs = k) */
-    CCG_WS_BICGSTAB_BLOCK_MIXED = 11  /* ccg_bicgstab_block_mixed_ex (k <= 64) */
+    CCG_WS_BICGSTAB_BLOCK_MIXED = 11, /* ccg_bicgstab_block_mixed_ex (k <= 64) */
+    CCG_WS_MATVEC_S = 12              /* scratch of ccg_matvec_ex, op = CCG_OP_S */
 };
+
+/* Added to CCG_WS_BICGSTAB, CCG_WS_COCG or CCG_WS_COCR: the workspace of that
+ * solver run with the flag CCG_A_SYM_UPPER (room for the tile partials of
+ * the upper-triangle product, about n * ceil(n / 128) * 16 bytes more). */
+#define CCG_WS_SYM 0x100
 
 /* Outcome of a mixed-precision solve (host struct). */
 typedef struct {
@@ -111,22 +117,32 @@ typedef struct {
 
 /* Flags of the _ex solvers. */
 #define CCG_X0_ZERO 1u /* x holds no guess: start from x = 0, skip y - A x */
+/* A is complex symmetric (A^T = A, not checked; the matrices of COCG and
+ * COCR, section 3.4): every product reads only the upper triangle (elements
+ * (i, j) with j >= i), half the bytes of a dense product; what lies below the
+ * diagonal is never read and may hold anything.  For ccg_bicgstab_ex,
+ * ccg_cocg_ex and ccg_cocr_ex (ccg_cgnr_ex rejects it as argument 8); the
+ * workspace is ccg_workspace_bytes(method | CCG_WS_SYM, n, 1). */
+#define CCG_A_SYM_UPPER 2u
 
 /*
- * y = op(A) x, op(A) = A (op = CCG_OP_N) or A^H (op = CCG_OP_C).
- * The user matvec / cmatvec of the Usage section; cmatvec is read as the
- * conjugate transpose, which CGNR needs.  Sums are in FP64 with a fixed order
- * (results are bitwise reproducible from run to run).  x and y must not
- * overlap.  Enqueued on stream, no wait.  CCG_OP_C takes a stream-ordered
- * scratch of ccg_workspace_bytes(CCG_WS_MATVEC_C, n, 1) bytes from the HIP
- * stream-ordered allocator; ccg_matvec_ex takes it from the caller instead.
+ * y = op(A) x, op(A) = A (op = CCG_OP_N) or A^H (op = CCG_OP_C), or y = A x
+ * for a complex symmetric A read from its upper triangle (op = CCG_OP_S:
+ * y_i = sum_{j<i} A_ji x_j + sum_{j>=i} A_ij x_j; below the diagonal nothing
+ * is read).  The user matvec / cmatvec of the Usage section; cmatvec is read
+ * as the conjugate transpose, which CGNR needs.  Sums are in FP64 with a
+ * fixed order (results are bitwise reproducible from run to run).  x and y
+ * must not overlap.  Enqueued on stream, no wait.  CCG_OP_C and CCG_OP_S
+ * take a stream-ordered scratch of ccg_workspace_bytes(CCG_WS_MATVEC_C or
+ * CCG_WS_MATVEC_S, n, 1) bytes from the HIP stream-ordered allocator;
+ * ccg_matvec_ex takes it from the caller instead.
  * Arguments: 1 op, 2 n >= 0, 3 A, 4 lda >= max(1,n), 5 x, 6 y, 7 stream.
  */
 int ccg_matvec(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
                ccg_z* y, void* stream);
 
-/* As ccg_matvec, with caller scratch (8: work, 9: work_bytes; unused for
- * CCG_OP_N, may be NULL/0 there). Argument 10 is the stream. */
+/* As ccg_matvec, with caller scratch (7: work, 8: work_bytes; unused for
+ * CCG_OP_N, may be NULL/0 there). Argument 9 is the stream. */
 int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda,
                   const ccg_z* x, ccg_z* y, void* work, size_t work_bytes,
                   void* stream);
@@ -159,10 +175,11 @@ int ccg_cgnr(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x,
 
 /*
  * Extended forms: caller workspace, flags, outcome and per-iteration record.
- * Arguments: 1 n, 2 A, 3 lda, 4 y, 5 x, 6 tol, 7 maxit, 8 flags (CCG_X0_ZERO
- * or 0), 9 work (device, 256-byte aligned), 10 work_bytes (>= the
- * ccg_workspace_bytes figure), 11 res (host, not NULL), 12 hist (device array
- * of maxit ccg_hist, or NULL), 13 stream.  Wait on stream before returning.
+ * Arguments: 1 n, 2 A, 3 lda, 4 y, 5 x, 6 tol, 7 maxit, 8 flags (CCG_X0_ZERO,
+ * CCG_A_SYM_UPPER, or 0), 9 work (device, 256-byte aligned), 10 work_bytes
+ * (>= the ccg_workspace_bytes figure), 11 res (host, not NULL), 12 hist
+ * (device array of maxit ccg_hist, or NULL), 13 stream.  Wait on stream
+ * before returning.
  */
 int ccg_bicgstab_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
                     ccg_z* x, double tol, int32_t maxit, uint32_t flags,

@@ -19,6 +19,7 @@ from . import build as _build
 
 OP_N = 0
 OP_C = 1
+OP_S = 2  # complex symmetric A read from its upper triangle
 WS_MATVEC_C = 1
 WS_BICGSTAB = 2
 WS_CGNR = 3
@@ -30,7 +31,10 @@ WS_BICGSTAB_MIXED = 8
 WS_T3_MATVEC = 9
 WS_MATMAT_C64 = 10
 WS_BICGSTAB_BLOCK_MIXED = 11
+WS_MATVEC_S = 12
+WS_SYM = 0x100  # added to WS_BICGSTAB / WS_COCG / WS_COCR with A_SYM_UPPER
 X0_ZERO = 1
+A_SYM_UPPER = 2  # solver flag: products read only the upper triangle of A
 SERVER_REJECTED = -1000
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
@@ -224,7 +228,8 @@ def ccg_workspace_bytes(method: int, n: int, nrhs: int = 1) -> int:
 
 
 def ccg_matvec(op: int, A, x, y=None, stream=None):
-    """y = A x (op = OP_N) or A^H x (op = OP_C); returns y."""
+    """y = A x (op = OP_N), A^H x (op = OP_C), or A x from the upper triangle
+    of a complex symmetric A (op = OP_S); returns y."""
     n, lda = _mat(A)
     _vec(x, n, "x")
     if y is None:
@@ -289,7 +294,8 @@ def _ex(name, method, A, y, x, tol, maxit, flags, work, hist, stream):
     _vec(y, n, "y")
     _vec(x, n, "x")
     if work is None:
-        work = workspace(method, n, A.device)
+        work = workspace(method | (WS_SYM if flags & A_SYM_UPPER else 0), n,
+                         A.device)
     res = _Result()
     _check(getattr(load(), name)(
         n, A.data_ptr(), lda, y.data_ptr(), x.data_ptr(), float(tol),

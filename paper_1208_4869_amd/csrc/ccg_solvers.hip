@@ -39,6 +39,7 @@
 #include "ccg_gemv.h"
 #include "ccg_host.h"
 #include "ccg_krylov.h"
+#include "ccg_symv.h"
 #include "ccg_t3.h"
 
 namespace ccg {
@@ -59,6 +60,7 @@ struct Args {
     ccg_hist* hist;
     bool vec16;                  // complex64 A with 16-byte aligned rows
     T3Geom t3;                   // structured product (A unused)
+    SymGeom sym;                 // upper-triangle product (sym.T > 0), else dense
     int* status;                 // pinned word: the phase after the prologue, or null
 };
 
@@ -408,6 +410,48 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
+// ------------------------------ upper-triangle products of complex symmetric A
+//
+// The same roles with the product read from the upper triangle (ccg_symv.h):
+// the tile pass applies the pending scalar step and writes the partials; the
+// gather pass sums them and does what k_gemv_n_role does with each element.
+
+template <Role RO, int CW>
+__global__ __launch_bounds__(kBlock) void k_sym_tile(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    __shared__ SymTileLds<CW> tl;
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO)
+        symv_block<CW>(a.A, a.lda, a.n, role_input<RO>(a, mode), a.sym, blockIdx.x, tl);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO>
+__global__ __launch_bounds__(kBlock) void k_sym_role(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int mode = role_mode<RO>(L.phase);
+    if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
+    const int e = blockIdx.x * kWave + (int)(threadIdx.x & (kWave - 1));
+    const bool wave0 = threadIdx.x < kWave;
+    if (mode == PH_ZERO) {  // y == 0: x = 0
+        if (wave0 && e < a.n) a.x[e] = d2{0.0, 0.0};
+        publish(a, q, L, PK_ZERO, 0);
+        return;
+    }
+    __shared__ d2 red[kSymWaves][kWave];
+    const d2 val = symv_gather(a.sym.part, a.n, a.sym.T, e, red);
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    if (wave0 && e < a.n) {
+        const Terms tm = role_finish<RO, d2>(a, mode, e, val);
+        pv0 = tm.t0;
+        pv1 = tm.t1;
+    }
+    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    publish(a, q, L, role_kind<RO>(mode), gridDim.x);
+}
+
 // ------------------------------------------------------- BiCGSTAB vectors
 
 // p = r (new direction) or p = r + beta (p - omega v)
@@ -687,6 +731,24 @@ __global__ __launch_bounds__(kBlock) void k_gemv_c_gather_plain(const d2* __rest
         y[j] = gemv_c_gather(part, n, nbands, j);
 }
 
+template <int CW>
+__global__ __launch_bounds__(kBlock) void k_symv_plain(const d2* __restrict__ A, int64_t lda,
+                                                       int n, const d2* __restrict__ x,
+                                                       SymGeom g)
+{
+    __shared__ SymTileLds<CW> tl;
+    symv_block<CW>(A, lda, n, x, g, blockIdx.x, tl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_symv_gather_plain(SymGeom g, int n,
+                                                              d2* __restrict__ y)
+{
+    __shared__ d2 red[kSymWaves][kWave];
+    const int e = blockIdx.x * kWave + (int)(threadIdx.x & (kWave - 1));
+    const d2 val = symv_gather(g.part, n, g.T, e, red);
+    if (threadIdx.x < kWave && e < n) y[e] = val;
+}
+
 
 // ------------------------------------------ structured product, plain and set-up
 
@@ -833,11 +895,29 @@ static inline bool rows16(const void* A, int64_t lda)
 }
 
 struct Layout {
-    size_t state, partials, part_bytes, vec, zpart, total;
+    size_t state, partials, part_bytes, vec, zpart, spart, total;
     int nvec;
 };
 
-static Layout layout(int method, int64_t n, int64_t min_partials = 0)
+// Tile geometry of the upper-triangle product of an n x n matrix.
+static SymGeom sym_geom(int64_t n, void* part)
+{
+    SymGeom g;
+    g.S = sym_edge(n);
+    g.T = (int)sym_ntiles(n, g.S);
+    g.part = (d2*)part;
+    return g;
+}
+
+static size_t sym_part_bytes(int64_t n)
+{
+    const SymGeom g = sym_geom(n > 0 ? n : 1, nullptr);
+    return align256((size_t)g.T * (size_t)(n > 0 ? n : 1) * sizeof(d2));
+}
+
+// sym: the products read the upper triangle of a complex symmetric A (room
+// for their tile partials).
+static Layout layout(int method, int64_t n, int64_t min_partials = 0, bool sym = false)
 {
     Layout L{};
     const GemvCShape csh = gemv_c_shape(n > 0 ? n : 1);
@@ -859,6 +939,8 @@ static Layout layout(int method, int64_t n, int64_t min_partials = 0)
     L.zpart = off;
     if (method == CCG_WS_CGNR || method == CCG_WS_MATVEC_C)
         off += align256((size_t)csh.nbands * (size_t)(n > 0 ? n : 1) * sizeof(d2));
+    L.spart = off;
+    if (sym) off += sym_part_bytes(n);
     L.total = off;
     return L;
 }
@@ -883,9 +965,9 @@ static int check_common(int64_t n, const void* A, int64_t lda, const void* y, co
 }
 
 static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
-                      ccg_z* x, void* work, ccg_hist* hist)
+                      ccg_z* x, void* work, ccg_hist* hist, bool sym = false)
 {
-    const Layout L = layout(method, n);
+    const Layout L = layout(method, n, 0, sym);
     char* base = (char*)work;
     const size_t vbytes = align256((size_t)n * sizeof(d2));
     Args a{};
@@ -910,6 +992,7 @@ static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const 
     a.st[0] = (SolverState*)(base + L.state);
     a.st[1] = (SolverState*)(base + L.state + 512);
     a.hist = hist;
+    a.sym = sym ? sym_geom(n, base + L.spart) : SymGeom{0, 0, nullptr};
     return a;
 }
 
@@ -954,7 +1037,24 @@ static void launch_t3_role(const Args& a, int& q, hipStream_t s)
     q ^= 1;
 }
 
-// A product of role RO: dense (one k_gemv_n_role launch) or structured.
+// The two passes of an upper-triangle product of role RO.
+template <Role RO>
+static void launch_sym_role(const Args& a, int& q, hipStream_t s)
+{
+    Args b = a;  // only the first pass reports a status word
+    b.status = nullptr;
+    const int64_t nb = sym_nblocks(a.sym.T);
+    if (a.sym.S == 2 * kWave)
+        k_sym_tile<RO, 2><<<(unsigned)nb, kBlock, 0, s>>>(a, q);
+    else
+        k_sym_tile<RO, 1><<<(unsigned)nb, kBlock, 0, s>>>(a, q);
+    q ^= 1;
+    k_sym_role<RO><<<(unsigned)((a.n + kWave - 1) / kWave), kBlock, 0, s>>>(b, q);
+    q ^= 1;
+}
+
+// A product of role RO: dense (one k_gemv_n_role launch, or the two passes
+// of the upper-triangle product when a.sym is set) or structured.
 template <Role RO, class T, bool S3>
 static void launch_product(const Args& a, int& q, hipStream_t s)
 {
@@ -965,6 +1065,8 @@ static void launch_product(const Args& a, int& q, hipStream_t s)
             launch_t3_role<RO, 2>(a, q, s);
         else
             launch_t3_role<RO, 4>(a, q, s);
+    } else if (sizeof(T) == sizeof(d2) && a.sym.T > 0) {
+        launch_sym_role<RO>(a, q, s);
     } else {
         k_gemv_n_role<RO, T><<<blocks_n(a.n), kBlockN, 0, s>>>(a, q);
         q ^= 1;
@@ -1099,18 +1201,20 @@ static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_
 {
     int bad = check_common(n, A, lda, y, x, tol, maxit);
     if (bad) return bad;
-    if (flags & ~CCG_X0_ZERO) return -8;
+    if (flags & ~(CCG_X0_ZERO | CCG_A_SYM_UPPER)) return -8;
+    const bool sym = (flags & CCG_A_SYM_UPPER) != 0;
+    if (sym && M == M_CGNR) return -8;  // CGNR needs A^H
     const int method = ws_of(M);
     if (n > 0 && !work) return -9;
     if (n > 0 && ((uintptr_t)work & 255)) return -9;
-    if (n > 0 && work_bytes < layout(method, n).total) return -10;
+    if (n > 0 && work_bytes < layout(method, n, 0, sym).total) return -10;
     if (!res) return -11;
     if (n == 0) {
         std::memset(res, 0, sizeof *res);
         res->relres_rec = res->relres_true = 0.0;
         return 0;
     }
-    const Args a = make_args(method, n, A, lda, y, x, work, hist);
+    const Args a = make_args(method, n, A, lda, y, x, work, hist, sym);
     return run_solver<M>(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
 }
 
@@ -1143,7 +1247,7 @@ static int solve_short(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, c
 static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
                        ccg_z* y, void* work, size_t work_bytes, void* stream, bool own_ws)
 {
-    if (op != CCG_OP_N && op != CCG_OP_C) return -1;
+    if (op != CCG_OP_N && op != CCG_OP_C && op != CCG_OP_S) return -1;
     if (n < 0 || n > kMaxN) return -2;
     if (n > 0 && !A) return -3;
     if (lda < (n > 1 ? n : 1)) return -4;
@@ -1161,14 +1265,38 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
         e = hipGetLastError();
         return e == hipSuccess ? 0 : (int)e;
     }
+    if (op == CCG_OP_S) {
+        const size_t need = sym_part_bytes(n);
+        void* part = work;
+        if (own_ws) {
+            if ((e = hipMallocAsync(&part, need, s)) != hipSuccess) return (int)e;
+        } else {
+            if (!work) return -7;
+            if (work_bytes < need) return -8;
+        }
+        const SymGeom g = sym_geom(n, part);
+        const unsigned nb = (unsigned)sym_nblocks(g.T);
+        if (g.S == 2 * kWave)
+            k_symv_plain<2><<<nb, kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x, g);
+        else
+            k_symv_plain<1><<<nb, kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x, g);
+        k_symv_gather_plain<<<(unsigned)((n + kWave - 1) / kWave), kBlock, 0, s>>>(g, (int)n,
+                                                                                  (d2*)y);
+        e = hipGetLastError();
+        if (own_ws) {
+            hipError_t e2 = hipFreeAsync(part, s);
+            if (e == hipSuccess) e = e2;
+        }
+        return e == hipSuccess ? 0 : (int)e;
+    }
     const GemvCShape sh = gemv_c_shape(n);
     const size_t need = (size_t)sh.nbands * (size_t)n * sizeof(d2);
     void* part = work;
     if (own_ws) {
         if ((e = hipMallocAsync(&part, need, s)) != hipSuccess) return (int)e;
     } else {
-        if (!work) return -8;
-        if (work_bytes < need) return -9;
+        if (!work) return -7;
+        if (work_bytes < need) return -8;
     }
     k_gemv_c_band_plain<<<sh.blocks(), kBlock, 0, s>>>((const d2*)A, lda, (int)n,
                                                        (const d2*)x, (d2*)part, sh);
@@ -1598,6 +1726,10 @@ size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
     if (method == CCG_WS_BICGSTAB || method == CCG_WS_CGNR || method == CCG_WS_COCG ||
         method == CCG_WS_COCR)
         return ccg::layout(method, n).total;
+    if (method == CCG_WS_MATVEC_S) return ccg::sym_part_bytes(n);
+    if (method == (CCG_WS_BICGSTAB | CCG_WS_SYM) || method == (CCG_WS_COCG | CCG_WS_SYM) ||
+        method == (CCG_WS_COCR | CCG_WS_SYM))
+        return ccg::layout(method & ~CCG_WS_SYM, n, 0, true).total;
     if (method == CCG_WS_BICGSTAB_MIXED) return ccg::mix_layout(n).total;
     return 0;
 }

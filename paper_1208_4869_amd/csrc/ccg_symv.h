@@ -1,0 +1,236 @@
+// ccg_symv.h -- y = A x for a complex symmetric A (A^T = A, the matrices of
+// COCG and COCR, section 3.4) read from its upper triangle only (elements
+// A_ij with j >= i).  Each stored element is loaded once and used twice,
+// A_ij x_j for y_i and A_ij x_i for y_j, so a product moves half the bytes
+// of the dense one; below the diagonal nothing is read.
+//
+// Tiling.  The matrix is cut into S x S tiles, S = 64 CW; a block of four
+// wavefronts takes one tile (I, J) with J >= I.  Wavefront w streams the
+// RW = S / 4 rows I S + w RW, ... of the tile; lane l takes the columns
+// J S + l + 64 c (c < CW), so a wavefront reads coalesced 1 KB row segments
+// as in the dense product.  Per lane:
+//   row part:    v[r] += A_ij x_j   (one accumulator per row of a group)
+//   column part: u[c] += A_ij x_i   (one accumulator per column of the lane)
+// The rows are taken 8 at a time; the 8 row accumulators are summed over the
+// 64 lanes by a transposing butterfly: at each exchange a lane keeps half of
+// its rows and sends the other half to its partner, so three exchanges leave
+// every lane with a single row, and a plain butterfly over the 8 lanes that
+// share it finishes the total.  The column sums of the four wavefronts are
+// added in LDS in wavefront order.  In a diagonal tile the lower elements are not
+// loaded and the diagonal enters the row part only.
+//
+// Partials.  Element e of tile K receives one partial from each tile index
+// t = 0 .. T-1: the row part of tile (K, t) for t > K, the column part of
+// tile (t, K) for t < K, and for t = K the diagonal tile's row part plus its
+// column part.  They are stored at P[t n + e]; the product is the sum over t
+// in a fixed order, so results are reproducible bit for bit.
+//
+// Block order: the off-diagonal tiles first, the diagonal tiles (half the
+// elements each) last, so that the smallest pieces of work end the launch.
+#pragma once
+
+#include "ccg_device.h"
+
+namespace ccg {
+
+constexpr int kSymWaves = 4;  // wavefronts per tile block (kBlock threads)
+
+// Tile edge for an n x n matrix: 128 from n = 4096 on (fewer partials per
+// element), else 64 (more blocks for the smaller matrices).
+__host__ __device__ inline int sym_edge(int64_t n) { return n >= 4096 ? 128 : 64; }
+__host__ __device__ inline int64_t sym_ntiles(int64_t n, int S) { return (n + S - 1) / S; }
+__host__ __device__ inline int64_t sym_nblocks(int64_t T) { return T * (T + 1) / 2; }
+
+struct SymGeom {
+    int S;     // tile edge, 64 or 128
+    int T;     // tiles per edge
+    d2* part;  // T x n partials
+};
+
+// Tile (I, J) of block b: the strictly upper tiles row by row, then the
+// diagonal ones.
+__device__ __forceinline__ void sym_tile_of(int64_t b, int64_t T, int& I, int& J)
+{
+    const int64_t noff = T * (T - 1) / 2;
+    if (b >= noff) {
+        I = J = (int)(b - noff);
+        return;
+    }
+    // strictly upper row r starts at block r (2T - 1 - r) / 2
+    auto start = [T](int64_t r) { return r * (2 * T - 1 - r) / 2; };
+    const double tt = 2.0 * (double)T - 1.0;
+    int64_t r = (int64_t)((tt - sqrt(tt * tt - 8.0 * (double)b)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > T - 2) r = T - 2;
+    while (r > 0 && start(r) > b) --r;
+    while (r < T - 2 && start(r + 1) <= b) ++r;
+    I = (int)r;
+    J = (int)(r + 1 + (b - start(r)));
+}
+
+// Transposing butterfly (see above): on entry v[k] is this lane's partial
+// sum of row k; on return v[0] holds the wavefront total of row
+// lane / (64 / NV).  M rows are exchanged across lane distance H per step.
+template <int M, int H, int NV>
+__device__ __forceinline__ void transpose_sum_step(d2 (&v)[NV], int lane)
+{
+    if constexpr (M >= 1) {
+        const bool up = (lane & H) != 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const d2 send = up ? v[k] : v[k + M];
+            const d2 keep = up ? v[k + M] : v[k];
+            v[k] = keep + d2{__shfl_xor(send.x, H, kWave), __shfl_xor(send.y, H, kWave)};
+        }
+        transpose_sum_step<M / 2, H / 2, NV>(v, lane);
+    } else {
+#pragma unroll
+        for (int h = H; h >= 1; h >>= 1)
+            v[0] += d2{__shfl_xor(v[0].x, h, kWave), __shfl_xor(v[0].y, h, kWave)};
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_transpose_sum(d2 (&v)[NV], int lane)
+{
+    static_assert(NV >= 1 && NV <= kWave && (NV & (NV - 1)) == 0, "power of two rows");
+    transpose_sum_step<NV / 2, kWave / 2, NV>(v, lane);
+}
+
+// Value of lane src of a wavefront, in every lane.
+__device__ __forceinline__ double bcast_lane(double v, int src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// LDS of one tile block.
+template <int CW>
+struct SymTileLds {
+    d2 col[kSymWaves][kWave * CW];  // column sums per wavefront
+    d2 row[kWave * CW];             // row totals of the tile
+};
+
+constexpr int kSymGroup = 8;  // rows per step of a wavefront
+
+// Partials of tile (I, J), I <= J, of y = A x, into P (layout above).  FULL:
+// an off-diagonal tile with every row and column inside the matrix (no
+// masks).  Rows and columns past n - 1 are neither loaded nor stored.  A
+// wavefront takes its rows kSymGroup at a time (kSymGroup * CW loads in flight
+// per lane); each group's row sums go through the transposing butterfly and
+// land in LDS.
+template <int CW, bool FULL>
+__device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda, int n,
+                                          const d2* __restrict__ x, d2* __restrict__ P,
+                                          int I, int J, SymTileLds<CW>& lds)
+{
+    constexpr int S = kWave * CW;
+    constexpr int RW = S / kSymWaves;
+    constexpr int G = kSymGroup;
+    static_assert(RW % G == 0, "whole row groups");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int r0 = I * S + wave * RW;  // first row of this wavefront
+    const int c0 = J * S;              // first column of the tile
+    const d2 zero = d2{0.0, 0.0};
+
+    d2 xj[CW], u[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+        const int j = c0 + kWave * c + lane;
+        xj[c] = (FULL || j < n) ? x[j] : zero;
+        u[c] = zero;
+    }
+    const d2 xown = (lane < RW && (FULL || r0 + lane < n)) ? x[r0 + lane] : zero;
+    constexpr int kShare = kWave / G;  // lanes holding the same row total
+    const int rsel = lane / kShare;
+
+#pragma unroll 1
+    for (int g = 0; g < RW; g += G) {
+        d2 a[G][CW];
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const int i = r0 + g + r;
+            const d2* Ai = A + (int64_t)i * lda + c0 + lane;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int j = c0 + kWave * c + lane;
+                a[r][c] = zero;
+                if (FULL || (i < n && j < n && j >= i)) a[r][c] = ldnt(Ai + kWave * c);
+            }
+        }
+        d2 v[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const int i = r0 + g + r;
+            const d2 xi = d2{bcast_lane(xown.x, g + r), bcast_lane(xown.y, g + r)};
+            d2 acc = zero;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const int j = c0 + kWave * c + lane;
+                acc = cfma(a[r][c], xj[c], acc);
+                u[c] = cfma((FULL || j != i) ? a[r][c] : zero, xi, u[c]);
+            }
+            v[r] = acc;
+        }
+        wave_transpose_sum<G>(v, lane);
+        if ((lane & (kShare - 1)) == 0) lds.row[wave * RW + g + rsel] = v[0];
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) lds.col[wave][kWave * c + lane] = u[c];
+    __syncthreads();
+
+    const int t = threadIdx.x;
+    if (t < S) {
+        d2 s = lds.col[0][t];
+#pragma unroll
+        for (int w = 1; w < kSymWaves; ++w) s += lds.col[w][t];
+        if (I != J) {
+            if (FULL || c0 + t < n) P[(int64_t)I * n + c0 + t] = s;
+            if (FULL || I * S + t < n) P[(int64_t)J * n + I * S + t] = lds.row[t];
+        } else if (c0 + t < n) {
+            P[(int64_t)I * n + c0 + t] = lds.row[t] + s;
+        }
+    }
+}
+
+// The tile of block b (either form).
+template <int CW>
+__device__ __forceinline__ void symv_block(const d2* __restrict__ A, int64_t lda, int n,
+                                           const d2* __restrict__ x, const SymGeom& g,
+                                           int64_t b, SymTileLds<CW>& lds)
+{
+    int I, J;
+    sym_tile_of(b, g.T, I, J);
+    if (I != J && (int64_t)(J + 1) * (kWave * CW) <= n)
+        symv_tile<CW, true>(A, lda, n, x, g.part, I, J, lds);
+    else
+        symv_tile<CW, false>(A, lda, n, x, g.part, I, J, lds);
+}
+
+// Sum over t (in order) of the partials P[t n + e] of element
+// e = e0 + lane, e0 = the block's first element; every wavefront returns it.
+// The four wavefronts take consecutive quarters of t and are added in
+// wavefront order.  red: LDS of kSymWaves x 64 entries.
+__device__ __forceinline__ d2 symv_gather(const d2* __restrict__ P, int n, int T, int e,
+                                          d2 (*red)[kWave])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int qt = (T + kSymWaves - 1) / kSymWaves;
+    const int t0 = wave * qt < T ? wave * qt : T;
+    const int t1 = t0 + qt < T ? t0 + qt : T;
+    d2 s = d2{0.0, 0.0};
+    if (e < n)
+        for (int t = t0; t < t1; ++t) s += P[(int64_t)t * n + e];
+    red[wave][lane] = s;
+    __syncthreads();
+    d2 tot = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kSymWaves; ++w) tot += red[w][lane];
+    return tot;
+}
+
+}  // namespace ccg

@@ -23,9 +23,10 @@ def host_relres(A, x, y):
     return np.linalg.norm(r) / ny, bound / ny
 
 
-def gpu_solve(method, A, y, tol=1e-10, maxit=1000, x0=None, hist=True):
+def gpu_solve(method, A, y, tol=1e-10, maxit=1000, x0=None, hist=True, flags=0):
     """Run ccg_<method>_ex on the device copies of A and y.  x0 None means the
-    x0 = 0 flag.  Returns (x on the host, Result, hist array or None)."""
+    x0 = 0 flag; flags are added to it.  Returns (x on the host, Result, hist
+    array or None)."""
     import torch
 
     from paper_1208_4869_amd import ccg
@@ -34,10 +35,9 @@ def gpu_solve(method, A, y, tol=1e-10, maxit=1000, x0=None, hist=True):
     yd = y if isinstance(y, torch.Tensor) else dev(y)
     if x0 is None:
         x = torch.full((n,), float("nan"), dtype=torch.complex128, device="cuda")
-        flags = ccg.X0_ZERO
+        flags |= ccg.X0_ZERO
     else:
         x = dev(np.asarray(x0, dtype=np.complex128)).clone()
-        flags = 0
     h = ccg.new_hist(maxit) if hist else None
     fn = getattr(ccg, "ccg_%s_ex" % method)
     res = fn(Ad, yd, x, tol, maxit, flags=flags, hist=h)
@@ -46,7 +46,7 @@ def gpu_solve(method, A, y, tol=1e-10, maxit=1000, x0=None, hist=True):
 
 
 def assert_parity(orc, method, A, y, x_true=None, tol=1e-10, maxit=1000,
-                  Ad=None, yd=None, label=""):
+                  Ad=None, yd=None, label="", flags=0):
     """GPU vs oracle on the same realised A, y:
       * both converge (info 0);
       * the GPU's true relative residual, recomputed on the host in FP64, is
@@ -57,7 +57,7 @@ def assert_parity(orc, method, A, y, x_true=None, tol=1e-10, maxit=1000,
         residual is above 1e-8."""
     ref = getattr(orc, method)(A, y, tol=tol, maxit=maxit)
     x, res, h = gpu_solve(method, Ad if Ad is not None else A,
-                          yd if yd is not None else y, tol, maxit)
+                          yd if yd is not None else y, tol, maxit, flags=flags)
     rel, slack = host_relres(A, x, y)
     msg = "%s %s n=%d: gpu info %d iters %d relres %.3e | oracle info %d iters %d" % (
         label, method, A.shape[0], res.info, res.iters, rel, ref.info, ref.iters)

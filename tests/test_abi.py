@@ -69,12 +69,26 @@ def test_argument_errors_are_rejected_on_the_host(lib):
     res = _Result()
     for fn in (lib.ccg_bicgstab_ex, lib.ccg_cgnr_ex):
         args = [4, dummy, 4, dummy, dummy, 1e-10, 10]
-        assert fn(*args, 2, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
+        assert fn(*args, 4, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
         assert fn(*args, 0, None, 1 << 20, ctypes.byref(res), None, None) == -9
         assert fn(*args, 0, P(257), 1 << 20, ctypes.byref(res), None, None) == -9
         assert fn(*args, 0, dummy, 16, ctypes.byref(res), None, None) == -10
         assert fn(*args, 0, dummy, 1 << 20, None, None, None) == -11
-    for op, code in ((2, -1), (-1, -1)):
+    # the upper-triangle flag: CGNR rejects it; the other solvers need the
+    # larger workspace (both checked on the host before anything is enqueued)
+    args = [4, dummy, 4, dummy, dummy, 1e-10, 10]
+    assert lib.ccg_cgnr_ex(*args, 2, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
+    for fn, ws in ((lib.ccg_bicgstab_ex, 2), (lib.ccg_cocg_ex, 6), (lib.ccg_cocr_ex, 7)):
+        assert fn(*args, 4, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
+        n = 5000
+        plain = lib.ccg_workspace_bytes(ws, n, 1)
+        sym = lib.ccg_workspace_bytes(ws | 0x100, n, 1)
+        assert sym >= plain + n * 16 * ((n + 127) // 128)
+        big = [n, dummy, n, dummy, dummy, 1e-10, 10]
+        assert fn(*big, 2, dummy, plain, ctypes.byref(res), None, None) == -10
+    assert lib.ccg_workspace_bytes(12, 5000, 1) == 16 * 5000 * 40
+    assert lib.ccg_workspace_bytes(3 | 0x100, 5000, 1) == 0  # no CGNR form
+    for op, code in ((3, -1), (-1, -1)):
         assert lib.ccg_matvec(op, 4, dummy, 4, dummy, P(4096), None) == code
     assert lib.ccg_matvec(0, -3, dummy, 4, dummy, P(4096), None) == -2
     assert lib.ccg_matvec(0, 4, None, 4, dummy, P(4096), None) == -3
@@ -83,8 +97,8 @@ def test_argument_errors_are_rejected_on_the_host(lib):
     assert lib.ccg_matvec(0, 4, dummy, 4, dummy, None, None) == -6
     assert lib.ccg_matvec(0, 4, dummy, 4, dummy, P(256 + 16), None) == -6  # overlap
     assert lib.ccg_matvec(1, 0, None, 1, None, None, None) == 0
-    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), None, 0, None) == -8
-    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), dummy, 8, None) == -9
+    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), None, 0, None) == -7
+    assert lib.ccg_matvec_ex(1, 4, dummy, 4, dummy, P(4096), dummy, 8, None) == -8
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
