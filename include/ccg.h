@@ -101,7 +101,8 @@ enum {
 
 /* Added to CCG_WS_BICGSTAB, CCG_WS_COCG or CCG_WS_COCR: the workspace of that
  * solver run with the flag CCG_A_SYM_UPPER (room for the tile partials of
- * the upper-triangle product, about n * ceil(n / 128) * 16 bytes more). */
+ * the upper-triangle product, n * ceil(n / S) * 16 bytes more, S = 64, 128
+ * or 256 the product's tile edge). */
 #define CCG_WS_SYM 0x100
 
 /* Outcome of a mixed-precision solve (host struct). */

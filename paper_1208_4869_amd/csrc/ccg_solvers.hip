@@ -1044,7 +1044,9 @@ static void launch_sym_role(const Args& a, int& q, hipStream_t s)
     Args b = a;  // only the first pass reports a status word
     b.status = nullptr;
     const int64_t nb = sym_nblocks(a.sym.T);
-    if (a.sym.S == 2 * kWave)
+    if (a.sym.S == 4 * kWave)
+        k_sym_tile<RO, 4><<<(unsigned)nb, kBlock, 0, s>>>(a, q);
+    else if (a.sym.S == 2 * kWave)
         k_sym_tile<RO, 2><<<(unsigned)nb, kBlock, 0, s>>>(a, q);
     else
         k_sym_tile<RO, 1><<<(unsigned)nb, kBlock, 0, s>>>(a, q);
@@ -1276,7 +1278,9 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
         }
         const SymGeom g = sym_geom(n, part);
         const unsigned nb = (unsigned)sym_nblocks(g.T);
-        if (g.S == 2 * kWave)
+        if (g.S == 4 * kWave)
+            k_symv_plain<4><<<nb, kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x, g);
+        else if (g.S == 2 * kWave)
             k_symv_plain<2><<<nb, kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x, g);
         else
             k_symv_plain<1><<<nb, kBlock, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x, g);

@@ -35,14 +35,23 @@ namespace ccg {
 
 constexpr int kSymWaves = 4;  // wavefronts per tile block (kBlock threads)
 
-// Tile edge for an n x n matrix: 128 from n = 4096 on (fewer partials per
-// element), else 64 (more blocks for the smaller matrices).
-__host__ __device__ inline int sym_edge(int64_t n) { return n >= 4096 ? 128 : 64; }
 __host__ __device__ inline int64_t sym_ntiles(int64_t n, int S) { return (n + S - 1) / S; }
 __host__ __device__ inline int64_t sym_nblocks(int64_t T) { return T * (T + 1) / 2; }
 
+// Tile edge for an n x n matrix: the largest of 256 and 128 that still
+// gives at least 512 tile blocks (two per compute unit), else 64.  Larger
+// tiles write fewer partials (n^2 / S of them; the partial stores cost more
+// per byte than the streamed reads of A), smaller ones balance the load
+// across the compute units.
+__host__ __device__ inline int sym_edge(int64_t n)
+{
+    for (int S = 256; S >= 128; S /= 2)
+        if (sym_nblocks(sym_ntiles(n, S)) >= 512) return S;
+    return 64;
+}
+
 struct SymGeom {
-    int S;     // tile edge, 64 or 128
+    int S;     // tile edge, 64, 128 or 256
     int T;     // tiles per edge
     d2* part;  // T x n partials
 };
@@ -106,11 +115,11 @@ __device__ __forceinline__ double bcast_lane(double v, int src)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// LDS of one tile block.
-template <int CW>
+// LDS of one tile block of NW wavefronts.
+template <int CW, int NW = kSymWaves>
 struct SymTileLds {
-    d2 col[kSymWaves][kWave * CW];  // column sums per wavefront
-    d2 row[kWave * CW];             // row totals of the tile
+    d2 col[NW][kWave * CW];  // column sums per wavefront
+    d2 row[kWave * CW];      // row totals of the tile
 };
 
 constexpr int kSymGroup = 8;  // rows per step of a wavefront
@@ -118,17 +127,16 @@ constexpr int kSymGroup = 8;  // rows per step of a wavefront
 // Partials of tile (I, J), I <= J, of y = A x, into P (layout above).  FULL:
 // an off-diagonal tile with every row and column inside the matrix (no
 // masks).  Rows and columns past n - 1 are neither loaded nor stored.  A
-// wavefront takes its rows kSymGroup at a time (kSymGroup * CW loads in flight
-// per lane); each group's row sums go through the transposing butterfly and
-// land in LDS.
-template <int CW, bool FULL>
+// wavefront takes its rows G at a time (G * CW loads in flight
+// per lane, G = kSymGroup); each group's row sums go through the transposing
+// butterfly and land in LDS.
+template <int CW, bool FULL, int G = kSymGroup, int NW = kSymWaves>
 __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda, int n,
                                           const d2* __restrict__ x, d2* __restrict__ P,
-                                          int I, int J, SymTileLds<CW>& lds)
+                                          int I, int J, SymTileLds<CW, NW>& lds)
 {
     constexpr int S = kWave * CW;
-    constexpr int RW = S / kSymWaves;
-    constexpr int G = kSymGroup;
+    constexpr int RW = S / NW;
     static_assert(RW % G == 0, "whole row groups");
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -182,11 +190,10 @@ __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda,
     for (int c = 0; c < CW; ++c) lds.col[wave][kWave * c + lane] = u[c];
     __syncthreads();
 
-    const int t = threadIdx.x;
-    if (t < S) {
+    for (int t = threadIdx.x; t < S; t += NW * kWave) {
         d2 s = lds.col[0][t];
 #pragma unroll
-        for (int w = 1; w < kSymWaves; ++w) s += lds.col[w][t];
+        for (int w = 1; w < NW; ++w) s += lds.col[w][t];
         if (I != J) {
             if (FULL || c0 + t < n) P[(int64_t)I * n + c0 + t] = s;
             if (FULL || I * S + t < n) P[(int64_t)J * n + I * S + t] = lds.row[t];
@@ -197,17 +204,17 @@ __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda,
 }
 
 // The tile of block b (either form).
-template <int CW>
+template <int CW, int G = kSymGroup, int NW = kSymWaves>
 __device__ __forceinline__ void symv_block(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ x, const SymGeom& g,
-                                           int64_t b, SymTileLds<CW>& lds)
+                                           int64_t b, SymTileLds<CW, NW>& lds)
 {
     int I, J;
     sym_tile_of(b, g.T, I, J);
     if (I != J && (int64_t)(J + 1) * (kWave * CW) <= n)
-        symv_tile<CW, true>(A, lda, n, x, g.part, I, J, lds);
+        symv_tile<CW, true, G, NW>(A, lda, n, x, g.part, I, J, lds);
     else
-        symv_tile<CW, false>(A, lda, n, x, g.part, I, J, lds);
+        symv_tile<CW, false, G, NW>(A, lda, n, x, g.part, I, J, lds);
 }
 
 // Sum over t (in order) of the partials P[t n + e] of element

@@ -34,8 +34,9 @@ def full_from_upper(S):
 def test_product_integer_bitwise(orc, n):
     """Gaussian integers small enough that every partial sum is an exact
     integer: the product equals the oracle's bit for bit whatever the order
-    of the sums.  Covers one tile, several tiles, ragged last tiles, both tile
-    edges (64 below n = 4096, 128 from there on) and the benchmark's n."""
+    of the sums.  Covers one tile, several tiles, ragged last tiles, the
+    three tile edges (64 up to n = 3968, 128 up to 7936, 256 beyond) and the
+    benchmark's n."""
     A = inputs.gaussian_integer_matrix(n, 300 + n, bound=32)
     x = inputs.gaussian_integer_vector(n, 400 + n, bound=32)
     S = stored_upper(A)
