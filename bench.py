@@ -516,7 +516,7 @@ def structured_leg(steps):
 def sym_leg(A, A_h, y, y_h, steps):
     """The lattice matrix is complex symmetric: the upper-triangle product
     (CCG_OP_S, half the bytes of A x) timed with HIP events, and BiCGSTAB,
-    COCG and COCR run with it (flag A_SYM_UPPER) on the same system."""
+    CGNR, COCG and COCR run with it (flag A_SYM_UPPER) on the same system."""
     import torch
 
     from paper_1208_4869_amd import ccg
@@ -533,6 +533,7 @@ def sym_leg(A, A_h, y, y_h, steps):
                        "frac": tri / ts / 1e9 / HBM_PEAK_GBS,
                        "partials_bytes": float(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_S, n))}}
     for name, fn, wsid in (("bicgstab", ccg.ccg_bicgstab_ex, ccg.WS_BICGSTAB),
+                           ("cgnr", ccg.ccg_cgnr_ex, ccg.WS_CGNR),
                            ("cocg", ccg.ccg_cocg_ex, ccg.WS_COCG),
                            ("cocr", ccg.ccg_cocr_ex, ccg.WS_COCR)):
         wk = ccg.workspace(wsid | ccg.WS_SYM, n)

@@ -99,10 +99,10 @@ enum {
     CCG_WS_MATVEC_S = 12              /* scratch of ccg_matvec_ex, op = CCG_OP_S */
 };
 
-/* Added to CCG_WS_BICGSTAB, CCG_WS_COCG or CCG_WS_COCR: the workspace of that
- * solver run with the flag CCG_A_SYM_UPPER (room for the tile partials of
- * the upper-triangle product, n * ceil(n / S) * 16 bytes more, S = 64, 128
- * or 256 the product's tile edge). */
+/* Added to CCG_WS_BICGSTAB, CCG_WS_CGNR, CCG_WS_COCG or CCG_WS_COCR: the
+ * workspace of that solver run with the flag CCG_A_SYM_UPPER (room for the
+ * tile partials of the upper-triangle product, n * ceil(n / S) * 16 bytes
+ * more, S = 64, 128 or 256 the product's tile edge). */
 #define CCG_WS_SYM 0x100
 
 /* Outcome of a mixed-precision solve (host struct). */
@@ -121,9 +121,9 @@ typedef struct {
 /* A is complex symmetric (A^T = A, not checked; the matrices of COCG and
  * COCR, section 3.4): every product reads only the upper triangle (elements
  * (i, j) with j >= i), half the bytes of a dense product; what lies below the
- * diagonal is never read and may hold anything.  For ccg_bicgstab_ex,
- * ccg_cocg_ex and ccg_cocr_ex (ccg_cgnr_ex rejects it as argument 8); the
- * workspace is ccg_workspace_bytes(method | CCG_WS_SYM, n, 1). */
+ * diagonal is never read and may hold anything.  CGNR's A^H r is then
+ * conj(A) r from the same triangle.  The workspace is
+ * ccg_workspace_bytes(method | CCG_WS_SYM, n, 1). */
 #define CCG_A_SYM_UPPER 2u
 
 /*

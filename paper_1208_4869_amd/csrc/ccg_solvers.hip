@@ -584,6 +584,36 @@ __global__ __launch_bounds__(kBlock) void k_cgnr_z2(Args a, int q)
     publish(a, q, L, ph == PH_RESTART ? PK_Z_RESTART : PK_Z_RUN, gridDim.x);
 }
 
+// A^H r = conj(A) r from the upper triangle of a complex symmetric A: tile
+// partials (the upper-triangle form of k_cgnr_z1)
+template <int CW>
+__global__ __launch_bounds__(kBlock) void k_cgnr_z1_sym(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    __shared__ SymTileLds<CW> tl;
+    if (L.phase == PH_RUN || L.phase == PH_RESTART)
+        symv_block<CW, true>(a.A, a.lda, a.n, a.r, a.sym, blockIdx.x, tl);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+// z = sum of the tile partials, ||z||^2 (the upper-triangle form of k_cgnr_z2)
+__global__ __launch_bounds__(kBlock) void k_cgnr_z2_sym(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    const int ph = L.phase;
+    if (ph != PH_RUN && ph != PH_RESTART) { publish(a, q, L, PK_NONE, 0); return; }
+    __shared__ d2 red[kSymWaves][kWave];
+    const int j = blockIdx.x * kWave + (int)(threadIdx.x & (kWave - 1));
+    const d2 zj = symv_gather(a.sym.part, a.n, a.sym.T, j, red);
+    d2 v0 = d2{0.0, 0.0};
+    if (threadIdx.x < kWave && j < a.n) {
+        a.z[j] = zj;
+        v0.x = cabs2(zj);
+    }
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, ph == PH_RESTART ? PK_Z_RESTART : PK_Z_RUN, gridDim.x);
+}
+
 // p = z (new direction) or p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a, int q)
 {
@@ -1157,6 +1187,18 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                 k_bicg_s<T><<<gE, kBlock, 0, s>>>(a, flip());
                 launch_product<ROLE_T, T, S3>(a, q, s);
                 k_bicg_xr<T><<<gE, kBlock, 0, s>>>(a, flip());
+            } else if (M == M_CGNR && a.sym.T > 0) {
+                launch_sym_role<ROLE_W>(f, q, s);
+                k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
+                const unsigned nb = (unsigned)sym_nblocks(a.sym.T);
+                if (a.sym.S == 4 * kWave)
+                    k_cgnr_z1_sym<4><<<nb, kBlock, 0, s>>>(a, flip());
+                else if (a.sym.S == 2 * kWave)
+                    k_cgnr_z1_sym<2><<<nb, kBlock, 0, s>>>(a, flip());
+                else
+                    k_cgnr_z1_sym<1><<<nb, kBlock, 0, s>>>(a, flip());
+                k_cgnr_z2_sym<<<(unsigned)((a.n + kWave - 1) / kWave), kBlock, 0, s>>>(a, flip());
+                k_cgnr_p<<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR) {
                 k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(f, flip());
                 k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
@@ -1205,7 +1247,6 @@ static int solve_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_
     if (bad) return bad;
     if (flags & ~(CCG_X0_ZERO | CCG_A_SYM_UPPER)) return -8;
     const bool sym = (flags & CCG_A_SYM_UPPER) != 0;
-    if (sym && M == M_CGNR) return -8;  // CGNR needs A^H
     const int method = ws_of(M);
     if (n > 0 && !work) return -9;
     if (n > 0 && ((uintptr_t)work & 255)) return -9;
@@ -1731,8 +1772,8 @@ size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs)
         method == CCG_WS_COCR)
         return ccg::layout(method, n).total;
     if (method == CCG_WS_MATVEC_S) return ccg::sym_part_bytes(n);
-    if (method == (CCG_WS_BICGSTAB | CCG_WS_SYM) || method == (CCG_WS_COCG | CCG_WS_SYM) ||
-        method == (CCG_WS_COCR | CCG_WS_SYM))
+    if (method == (CCG_WS_BICGSTAB | CCG_WS_SYM) || method == (CCG_WS_CGNR | CCG_WS_SYM) ||
+        method == (CCG_WS_COCG | CCG_WS_SYM) || method == (CCG_WS_COCR | CCG_WS_SYM))
         return ccg::layout(method & ~CCG_WS_SYM, n, 0, true).total;
     if (method == CCG_WS_BICGSTAB_MIXED) return ccg::mix_layout(n).total;
     return 0;

@@ -124,13 +124,14 @@ struct SymTileLds {
 
 constexpr int kSymGroup = 8;  // rows per step of a wavefront
 
-// Partials of tile (I, J), I <= J, of y = A x, into P (layout above).  FULL:
+// Partials of tile (I, J), I <= J, of y = A x (CONJ: y = conj(A) x, which is
+// A^H x for a complex symmetric A), into P (layout above).  FULL:
 // an off-diagonal tile with every row and column inside the matrix (no
 // masks).  Rows and columns past n - 1 are neither loaded nor stored.  A
 // wavefront takes its rows G at a time (G * CW loads in flight
 // per lane, G = kSymGroup); each group's row sums go through the transposing
 // butterfly and land in LDS.
-template <int CW, bool FULL, int G = kSymGroup, int NW = kSymWaves>
+template <int CW, bool FULL, bool CONJ = false, int G = kSymGroup, int NW = kSymWaves>
 __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda, int n,
                                           const d2* __restrict__ x, d2* __restrict__ P,
                                           int I, int J, SymTileLds<CW, NW>& lds)
@@ -178,8 +179,14 @@ __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda,
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 const int j = c0 + kWave * c + lane;
-                acc = cfma(a[r][c], xj[c], acc);
-                u[c] = cfma((FULL || j != i) ? a[r][c] : zero, xi, u[c]);
+                const d2 au = (FULL || j != i) ? a[r][c] : zero;
+                if (CONJ) {
+                    acc = cfma_conj(a[r][c], xj[c], acc);
+                    u[c] = cfma_conj(au, xi, u[c]);
+                } else {
+                    acc = cfma(a[r][c], xj[c], acc);
+                    u[c] = cfma(au, xi, u[c]);
+                }
             }
             v[r] = acc;
         }
@@ -204,7 +211,7 @@ __device__ __forceinline__ void symv_tile(const d2* __restrict__ A, int64_t lda,
 }
 
 // The tile of block b (either form).
-template <int CW, int G = kSymGroup, int NW = kSymWaves>
+template <int CW, bool CONJ = false, int G = kSymGroup, int NW = kSymWaves>
 __device__ __forceinline__ void symv_block(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ x, const SymGeom& g,
                                            int64_t b, SymTileLds<CW, NW>& lds)
@@ -212,9 +219,9 @@ __device__ __forceinline__ void symv_block(const d2* __restrict__ A, int64_t lda
     int I, J;
     sym_tile_of(b, g.T, I, J);
     if (I != J && (int64_t)(J + 1) * (kWave * CW) <= n)
-        symv_tile<CW, true, G, NW>(A, lda, n, x, g.part, I, J, lds);
+        symv_tile<CW, true, CONJ, G, NW>(A, lda, n, x, g.part, I, J, lds);
     else
-        symv_tile<CW, false, G, NW>(A, lda, n, x, g.part, I, J, lds);
+        symv_tile<CW, false, CONJ, G, NW>(A, lda, n, x, g.part, I, J, lds);
 }
 
 // Sum over t (in order) of the partials P[t n + e] of element

@@ -74,11 +74,11 @@ def test_argument_errors_are_rejected_on_the_host(lib):
         assert fn(*args, 0, P(257), 1 << 20, ctypes.byref(res), None, None) == -9
         assert fn(*args, 0, dummy, 16, ctypes.byref(res), None, None) == -10
         assert fn(*args, 0, dummy, 1 << 20, None, None, None) == -11
-    # the upper-triangle flag: CGNR rejects it; the other solvers need the
-    # larger workspace (both checked on the host before anything is enqueued)
+    # the upper-triangle flag needs the larger workspace (checked on the host
+    # before anything is enqueued)
     args = [4, dummy, 4, dummy, dummy, 1e-10, 10]
-    assert lib.ccg_cgnr_ex(*args, 2, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
-    for fn, ws in ((lib.ccg_bicgstab_ex, 2), (lib.ccg_cocg_ex, 6), (lib.ccg_cocr_ex, 7)):
+    for fn, ws in ((lib.ccg_bicgstab_ex, 2), (lib.ccg_cgnr_ex, 3), (lib.ccg_cocg_ex, 6),
+                   (lib.ccg_cocr_ex, 7)):
         assert fn(*args, 4, dummy, 1 << 20, ctypes.byref(res), None, None) == -8
         n = 5000
         plain = lib.ccg_workspace_bytes(ws, n, 1)
@@ -87,7 +87,7 @@ def test_argument_errors_are_rejected_on_the_host(lib):
         big = [n, dummy, n, dummy, dummy, 1e-10, 10]
         assert fn(*big, 2, dummy, plain, ctypes.byref(res), None, None) == -10
     assert lib.ccg_workspace_bytes(12, 5000, 1) == 16 * 5000 * 40
-    assert lib.ccg_workspace_bytes(3 | 0x100, 5000, 1) == 0  # no CGNR form
+    assert lib.ccg_workspace_bytes(1 | 0x100, 5000, 1) == 0  # no such form
     for op, code in ((3, -1), (-1, -1)):
         assert lib.ccg_matvec(op, 4, dummy, 4, dummy, P(4096), None) == code
     assert lib.ccg_matvec(0, -3, dummy, 4, dummy, P(4096), None) == -2

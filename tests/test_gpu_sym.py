@@ -1,6 +1,7 @@
 """GPU tests of the upper-triangle product of a complex symmetric matrix
-(ccg_matvec with CCG_OP_S) and of BiCGSTAB / COCG / COCR run with it (flag
-CCG_A_SYM_UPPER), against the oracle on the same inputs.
+(ccg_matvec with CCG_OP_S) and of BiCGSTAB / CGNR / COCG / COCR run with it
+(flag CCG_A_SYM_UPPER; CGNR's A^H r is then conj(A) r from the same
+triangle), against the oracle on the same inputs.
 
 Every device matrix here holds NaN below the diagonal: a single read there
 would make a result non-finite, so finite results that match the oracle also
@@ -85,7 +86,7 @@ def test_product_lattice_matches_dense(orc):
     assert np.all(np.abs(ys - yd) <= 2 * bound)
 
 
-@pytest.mark.parametrize("method", ["bicgstab", "cocg", "cocr"])
+@pytest.mark.parametrize("method", ["bicgstab", "cgnr", "cocg", "cocr"])
 @pytest.mark.parametrize("m", [6, 12, 20])
 def test_solvers_lattice(orc, method, m):
     """Solves with the upper-triangle product (NaN below the diagonal on the
@@ -97,7 +98,7 @@ def test_solvers_lattice(orc, method, m):
                   label="lattice %d^3, upper triangle" % m, flags=ccg.A_SYM_UPPER)
 
 
-@pytest.mark.parametrize("method", ["cocg", "cocr", "bicgstab"])
+@pytest.mark.parametrize("method", ["cocg", "cocr", "bicgstab", "cgnr"])
 @pytest.mark.parametrize("n", [1, 3, 65, 700])
 def test_solvers_dense_symmetric(orc, method, n):
     rng = np.random.default_rng(900 + n)
@@ -118,7 +119,7 @@ def test_solver_edges(orc):
     n = m ** 3
     Sd = dev(stored_upper(A))
     x0 = inputs.cn01(np.random.default_rng(10), n)
-    for method in ("bicgstab", "cocg", "cocr"):
+    for method in ("bicgstab", "cgnr", "cocg", "cocr"):
         fn = getattr(ccg, "ccg_%s_ex" % method)
         x = dev(x0)
         res = fn(Sd, dev(y), x, flags=ccg.A_SYM_UPPER)
@@ -143,13 +144,25 @@ def test_solver_edges(orc):
         assert np.array_equal(xa, xb) and ra == rb
 
 
-def test_cgnr_rejects_flag_and_small_workspace():
+def test_small_workspace_is_rejected():
     A, _, y = inputs.lattice_system(4, 1)
     Sd = dev(stored_upper(A))
     import torch
     x = torch.zeros(A.shape[0], dtype=torch.complex128, device="cuda")
-    with pytest.raises(ValueError, match="argument 8"):
-        ccg.ccg_cgnr_ex(Sd, dev(y), x, flags=ccg.A_SYM_UPPER)
-    small = ccg.workspace(ccg.WS_COCG, A.shape[0])  # without the tile partials
-    with pytest.raises(ValueError, match="argument 10"):
-        ccg.ccg_cocg_ex(Sd, dev(y), x, flags=ccg.A_SYM_UPPER, work=small)
+    for method, ws in (("cgnr", ccg.WS_CGNR), ("cocg", ccg.WS_COCG)):
+        small = ccg.workspace(ws, A.shape[0])  # without the tile partials
+        with pytest.raises(ValueError, match="argument 10"):
+            getattr(ccg, "ccg_%s_ex" % method)(Sd, dev(y), x, flags=ccg.A_SYM_UPPER,
+                                               work=small)
+
+
+def test_cgnr_adjoint_product_matches_oracle(orc):
+    """CGNR's A^H product from the upper triangle: one iteration from x0 = 0
+    gives z = A^H y; compare the first iteration's alpha with the oracle's
+    (its A^H comes from the full matrix)."""
+    A, _, y = inputs.lattice_system(6, 3)
+    x, res, h = gpu_solve("cgnr", dev(stored_upper(A)), y, maxit=1, flags=ccg.A_SYM_UPPER)
+    ref = orc.cgnr(A, y, maxit=1)
+    assert res.info == ref.info == 1
+    assert abs(h[0, 0] - ref.hist[0, 0]) <= 1e-12 * abs(ref.hist[0, 0])
+    assert np.linalg.norm(x - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
