@@ -44,17 +44,18 @@ MAXIT = 1000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lattice20.md")
 
 
-def measured_traffic():
-    """HBM bytes per A x launch from the committed FETCH_SIZE / WRITE_SIZE
-    record, or None when the kernel sources changed since it was taken."""
+def measured_traffic(which="kernel"):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE record
+    (which = "kernel": the A x kernels; "sym": the upper-triangle product), or
+    None when the hashed kernel sources changed since it was taken."""
     import hashlib
     try:
         line = [ln for ln in open(TRAFFIC_FILE) if ln.startswith("traffic-json:")][0]
         rec = json.loads(line.split(":", 1)[1])
         h = hashlib.sha256()
-        for p in rec["kernel_sources"]:
+        for p in rec[which + "_sources"]:
             h.update(open(os.path.join(ROOT, p), "rb").read())
-        if h.hexdigest() != rec["kernel_sources_sha256"]:
+        if h.hexdigest() != rec[which + "_sources_sha256"]:
             return None
         return rec
     except (OSError, IndexError, KeyError, ValueError):
@@ -528,10 +529,12 @@ def sym_leg(A, A_h, y, y_h, steps):
     tri = 16.0 * n * (n + 1) / 2 + 32.0 * n
     log("upper-triangle product: %.1f us (%.0f GB/s of triangle bytes)"
         % (ts * 1e6, tri / ts / 1e9))
+    trec = measured_traffic("sym")
     out = {"product": {"kernel": "k_symv (tiles) + gather", "launch_us": ts * 1e6,
                        "bytes_per_launch": tri, "achieved_gbs": tri / ts / 1e9,
                        "frac": tri / ts / 1e9 / HBM_PEAK_GBS,
-                       "partials_bytes": float(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_S, n))}}
+                       "partials_bytes": float(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_S, n)),
+                       "traffic": trec["k_symv_traffic_bytes"] if trec else None}}
     for name, fn, wsid in (("bicgstab", ccg.ccg_bicgstab_ex, ccg.WS_BICGSTAB),
                            ("cgnr", ccg.ccg_cgnr_ex, ccg.WS_CGNR),
                            ("cocg", ccg.ccg_cocg_ex, ccg.WS_COCG),
