@@ -119,11 +119,12 @@ __device__ __forceinline__ void write_partials(d2 v0, d2 v1, d2* part, d2* lds)
 // Totals of the nblocks partial pairs written by the previous kernel.  Every
 // thread of the block takes part in the loads; the totals are valid in
 // thread 0.  Thread t adds blocks t, t + blockDim.x, ... in increasing order,
-// with the loads of eight of them in flight at a time.
+// with the loads of kInFlight of them in flight at a time (the order of the
+// additions does not depend on kInFlight).
+template <int kInFlight = 8>
 __device__ __forceinline__ void reduce_partials(const d2* part, int nblocks, d2* lds,
                                                 d2& t0, d2& t1)
 {
-    constexpr int kInFlight = 8;
     const int step = blockDim.x;
     d2 a0 = d2{0.0, 0.0}, a1 = d2{0.0, 0.0};
     for (int b0 = threadIdx.x; b0 < nblocks; b0 += kInFlight * step) {
@@ -146,6 +147,52 @@ __device__ __forceinline__ void reduce_partials(const d2* part, int nblocks, d2*
     }
     t0 = block_sum(a0, lds);
     t1 = block_sum(a1, lds);
+}
+
+// Three-term forms: the third block total goes to part3[b] (a separate
+// array, so the two-term layout is unchanged).
+__device__ __forceinline__ void write_partials3(d2 v0, d2 v1, d2 v2, d2* part, d2* part3,
+                                                d2* lds)
+{
+    const d2 s0 = block_sum(v0, lds);
+    const d2 s1 = block_sum(v1, lds);
+    const d2 s2 = block_sum(v2, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0;
+        part[2 * blockIdx.x + 1] = s1;
+        part3[blockIdx.x] = s2;
+    }
+}
+
+template <int kInFlight = 5>
+__device__ __forceinline__ void reduce_partials3(const d2* part, const d2* part3, int nblocks,
+                                                 d2* lds, d2& t0, d2& t1, d2& t2)
+{
+    const int step = blockDim.x;
+    d2 a0 = d2{0.0, 0.0}, a1 = d2{0.0, 0.0}, a2 = d2{0.0, 0.0};
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kInFlight * step) {
+        d2 u0[kInFlight], u1[kInFlight], u2[kInFlight];
+#pragma unroll
+        for (int m = 0; m < kInFlight; ++m) {
+            const int b = b0 + m * step;
+            if (b < nblocks) {
+                u0[m] = part[2 * b];
+                u1[m] = part[2 * b + 1];
+                u2[m] = part3[b];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kInFlight; ++m) {
+            if (b0 + m * step < nblocks) {
+                a0 += u0[m];
+                a1 += u1[m];
+                a2 += u2[m];
+            }
+        }
+    }
+    t0 = block_sum(a0, lds);
+    t1 = block_sum(a1, lds);
+    t2 = block_sum(a2, lds);
 }
 
 }  // namespace ccg

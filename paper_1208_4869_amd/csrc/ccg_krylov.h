@@ -50,6 +50,12 @@ enum Pending : int {
     PK_U,          // (r, A r)              -> beta, budget (COCR)
     PK_WW,         // (A p, A p)            -> alpha (COCR)
     PK_XR_R,       // ||r||^2               -> stop test (COCR)
+    // BiCGSTAB with the next direction formed in the x, r update (four
+    // launches per iteration): rho' = r^H s - omega r^H t, so beta is known
+    // before r is; its breakdown test waits for ||r||.
+    PK_S2,         // ||s||^2, r^H s        -> half-step test
+    PK_T3,         // t^H s, ||t||^2, r^H t -> omega, rho', beta
+    PK_XRP,        // ||r||^2               -> stop test, rho' breakdown, beta
 };
 
 // The solver's scalars in device memory.  Two copies alternate: a launch
@@ -63,6 +69,7 @@ struct alignas(16) SolverState {
     double ny2, thr2, rh2, rr;
     double relres_rec, relres_true, gamma, tol2;
     d2 rho, rho_old, alpha, omega, beta;
+    d2 rhs, rho_next;  // r^H s of this iteration; rho' for the next one (PK_T3)
 };
 static_assert(sizeof(SolverState) <= 512, "state block");
 
@@ -125,10 +132,12 @@ __device__ inline void cocg_rho_step(SolverState& L, d2 rho)
 }
 
 // The scalar step of the method that finishes the pending reduction with
-// totals t0, t1.  Runs in thread 0 of every block of the consuming kernel on
-// identical inputs, so every block takes the same decision; only block 0
-// writes the per-iteration record (hist non-null there).
-__device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
+// totals t0, t1 (and t2 for PK_T3).  Runs in thread 0 of every block of the
+// consuming kernel on identical inputs, so every block takes the same
+// decision; only block 0 writes the per-iteration record (hist non-null
+// there).
+__device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist,
+                                  d2 t2 = d2{0.0, 0.0})
 {
     const int k = L.pending;
     L.pending = PK_NONE;
@@ -232,6 +241,62 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist)
         if (hist) {
             hist[L.iters].beta_re = beta.x;
             hist[L.iters].beta_im = beta.y;
+        }
+        break;
+    }
+    case PK_S2: {  // half-step stop test on ||s||; keep r^H s
+        const double ss = t0.x;
+        if (!__builtin_isfinite(ss)) { finish(L, 4); break; }
+        if (hist) hist[L.iters].res_half = relres(ss, L.ny2);
+        L.rhs = t1;
+        if (ss <= L.thr2) {
+            L.relres_rec = relres(ss, L.ny2);
+            L.phase = PH_HALF;
+        }
+        break;
+    }
+    case PK_T3: {  // omega = t^H s / t^H t; rho' = r^H s - omega r^H t; beta
+        const d2 ts = t0;
+        const double tt = t1.x;
+        L.matvecs++;
+        if (!__builtin_isfinite(tt) || !cfinite(ts)) { finish(L, 4); break; }
+        if (tt == 0.0) { finish(L, 3); break; }
+        const d2 om = d2{ts.x / tt, ts.y / tt};
+        if (om.x == 0.0 && om.y == 0.0) { finish(L, 3); break; }
+        L.omega = om;
+        if (hist) {
+            hist[L.iters].omega_re = om.x;
+            hist[L.iters].omega_im = om.y;
+        }
+        const d2 nom = d2{-om.x, -om.y};
+        L.rho_next = cfma(nom, t2, L.rhs);
+        // beta is formed now (the x, r update also forms the next p); the
+        // tests on rho' and beta wait for ||r|| (PK_XRP)
+        L.beta = cmul(cdiv(L.rho_next, L.rho), cdiv(L.alpha, om));
+        break;
+    }
+    case PK_XRP: {  // stop test on ||r||, then the tests on rho' and beta
+        const double rr = t0.x;
+        const d2 rho_new = L.rho_next;
+        L.iters++;
+        if (!__builtin_isfinite(rr)) { finish(L, 4); break; }
+        if (hist) hist[L.iters - 1].res_full = relres(rr, L.ny2);
+        L.rr = rr;
+        L.relres_rec = relres(rr, L.ny2);
+        if (rr <= L.thr2) {
+            if (L.no_confirm) finish(L, 0);
+            else L.phase = PH_CONFIRM;
+            break;
+        }
+        if (L.iters >= L.maxit) { finish(L, 1); break; }
+        if (!cfinite(rho_new)) { finish(L, 4); break; }
+        if (cabs2(rho_new) <= 1e-28 * L.rh2 * rr) { finish(L, 2); break; }
+        if (!cfinite(L.beta)) { finish(L, 4); break; }
+        L.rho_old = L.rho;
+        L.rho = rho_new;
+        if (hist) {
+            hist[L.iters].beta_re = L.beta.x;
+            hist[L.iters].beta_im = L.beta.y;
         }
         break;
     }

@@ -56,6 +56,7 @@ struct Args {
     d2 *r, *rh, *p, *v, *s, *t;  // BiCGSTAB vectors
     d2 *z, *w, *zpart;           // CGNR vectors and A^H band partials
     d2* part[2];                 // per-block partial sums, alternating
+    d2* xpart[2];                // third per-block sums (PK_T3), alternating
     SolverState* st[2];          // state copies, alternating
     ccg_hist* hist;
     bool vec16;                  // complex64 A with 16-byte aligned rows
@@ -72,14 +73,26 @@ constexpr int kUC = 4;  // rows per step in A^H x
 
 // Start of every solver kernel: load state copy q into LDS and finish the
 // reduction the previous kernel left (same fixed order in every block).
+// kInFlight: partial loads in flight per thread.  Eight (five for three
+// terms) after a product (thousands of block partials); the product kernels,
+// which follow vector kernels of at most 512 blocks, take 2 so that the
+// prologue does not set their register count (the A x loop needs 64 VGPRs,
+// occupancy 8 with 512-thread blocks).
+template <int kInFlight = 8>
 __device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d2* lds)
 {
     if (threadIdx.x == 0) L = *a.st[q];
     __syncthreads();
     if (L.pending != PK_NONE) {
-        d2 t0 = d2{0.0, 0.0}, t1 = d2{0.0, 0.0};
-        if (L.pending_blocks > 0) reduce_partials(a.part[q], L.pending_blocks, lds, t0, t1);
-        if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr);
+        d2 t0 = d2{0.0, 0.0}, t1 = d2{0.0, 0.0}, t2 = d2{0.0, 0.0};
+        if (L.pending_blocks > 0) {
+            if (L.pending == PK_T3)
+                reduce_partials3<kInFlight == 8 ? 5 : kInFlight>(a.part[q], a.xpart[q],
+                                                                L.pending_blocks, lds, t0, t1, t2);
+            else
+                reduce_partials<kInFlight>(a.part[q], L.pending_blocks, lds, t0, t1);
+        }
+        if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
         __syncthreads();
     }
     // the first kernel of a slot reports where the previous slot left the
@@ -105,6 +118,12 @@ __device__ __forceinline__ void publish(const Args& a, int q, const SolverState&
     __shared__ SolverState L;              \
     __shared__ d2 lds[kMaxWaves];          \
     prologue(a, q, L, lds)
+
+// The same for the product kernels (see prologue).
+#define PRODUCT_PROLOGUE()                 \
+    __shared__ SolverState L;              \
+    __shared__ d2 lds[kMaxWaves];          \
+    prologue<2>(a, q, L, lds)
 
 // --------------------------------------------------------- common kernels
 
@@ -186,7 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
         if (ph == PH_RUN) {
             const d2 yi = ldv(y, i);
             stv(r, i, yi);
-            if (M == M_BICG) stv(rh, i, yi);
+            if (M == M_BICG) {
+                stv(rh, i, yi);
+                stv((T*)a.p, i, yi);  // first direction
+            }
             v0.x += cabs2(yi);
             if (M == M_COCG) v1 = cfma(yi, yi, v1);
         }
@@ -249,7 +271,7 @@ __device__ __forceinline__ const d2* role_input(const Args& a, int mode)
 // return its dot-product terms (in FP64; complex64 vectors are rounded on
 // store and the terms use the stored values).
 struct Terms {
-    d2 t0, t1;
+    d2 t0, t1, t2;  // t2: r^H t (BiCGSTAB's t = A s only)
 };
 
 template <Role RO, class T>
@@ -261,32 +283,36 @@ __device__ __forceinline__ Terms role_finish(const Args& a, int mode, int i, con
         T* r = (T*)a.r;
         stv(r, i, ldv((const T*)a.y, i) - val);
         const d2 ri = ldv(r, i);
-        if (RO == ROLE_SETUP_B || RO == ROLE_V) stv((T*)a.rh, i, ri);
+        if (RO == ROLE_SETUP_B || RO == ROLE_V) {
+            stv((T*)a.rh, i, ri);
+            stv((T*)a.p, i, ri);  // the direction of a (re)start
+        }
         const d2 b = (RO == ROLE_SETUP_G || RO == ROLE_Q) ? cfma(ri, ri, z) : z;
-        return Terms{d2{cabs2(ri), 0.0}, b};
+        return Terms{d2{cabs2(ri), 0.0}, b, z};
     }
     if (RO == ROLE_Q) {
         a.v[i] = val;  // q
-        return Terms{cfma(a.p[i], val, z), z};
+        return Terms{cfma(a.p[i], val, z), z, z};
     }
     if (RO == ROLE_U) {
         a.z[i] = val;  // u
-        return Terms{cfma(a.r[i], val, z), z};
+        return Terms{cfma(a.r[i], val, z), z, z};
     }
     if (RO == ROLE_V) {
         T* v = (T*)a.v;
         stv(v, i, val);
         const d2 vs = ldv(v, i);
-        return Terms{cfma_conj(ldv((const T*)a.rh, i), vs, z), d2{cabs2(vs), 0.0}};
+        return Terms{cfma_conj(ldv((const T*)a.rh, i), vs, z), d2{cabs2(vs), 0.0}, z};
     }
     if (RO == ROLE_T) {
         T* tv = (T*)a.t;
         stv(tv, i, val);
         const d2 ts = ldv(tv, i);
-        return Terms{cfma_conj(ts, ldv((const T*)a.s, i), z), d2{cabs2(ts), 0.0}};
+        return Terms{cfma_conj(ts, ldv((const T*)a.s, i), z), d2{cabs2(ts), 0.0},
+                     cfma_conj(ldv((const T*)a.rh, i), ts, z)};
     }
     a.w[i] = val;  // ROLE_W
-    return Terms{d2{cabs2(val), 0.0}, z};
+    return Terms{d2{cabs2(val), 0.0}, z, z};
 }
 
 // The reduction a product of role RO leaves for the next kernel.
@@ -298,14 +324,25 @@ __device__ __forceinline__ int role_kind(int mode)
     if (RO == ROLE_SETUP_G) return PK_SETUP_G1;
     if (mode == PH_CONFIRM)
         return RO == ROLE_V ? PK_CONFIRM_B : RO == ROLE_Q ? PK_CONFIRM_G : PK_CONFIRM_C;
-    return RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T : RO == ROLE_W ? PK_W
+    return RO == ROLE_V ? PK_V : RO == ROLE_T ? PK_T3 : RO == ROLE_W ? PK_W
          : RO == ROLE_Q ? PK_Q : PK_U;
+}
+
+// The block sums of a product of role RO (three for t = A s).
+template <Role RO>
+__device__ __forceinline__ void role_partials(const Args& a, int q, d2 v0, d2 v1, d2 v2,
+                                              d2* lds)
+{
+    if (RO == ROLE_T)
+        write_partials3(v0, v1, v2, a.part[q ^ 1], a.xpart[q ^ 1], lds);
+    else
+        write_partials(v0, v1, a.part[q ^ 1], lds);
 }
 
 template <Role RO, class T = d2>
 __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 {
-    SOLVER_PROLOGUE();
+    PRODUCT_PROLOGUE();
     const int mode = role_mode<RO>(L.phase);
     if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
     const int row0 = blockIdx.x * kR;
@@ -320,7 +357,7 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
     const d2* in = role_input<RO>(a, mode);
 
     __shared__ d2 red[kWN][kR];
-    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0}, pv2 = d2{0.0, 0.0};
     if constexpr (sizeof(T) == sizeof(f2))
         gemv_n_block_f<kR, kWN>((const f2*)a.A, a.lda, n, (const f2*)in, row0, red, a.vec16);
     else
@@ -331,8 +368,9 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
         const Terms tm = role_finish<RO, T>(a, mode, i, gemv_n_row_total<kR, kWN>(red, t));
         pv0 = tm.t0;
         pv1 = tm.t1;
+        pv2 = tm.t2;
     }
-    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
@@ -394,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
     }
     d2 v[R];
     const int line = t3_pass_xi<R>(a.t3, v);
-    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0}, pv2 = d2{0.0, 0.0};
     if (line >= 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -403,10 +441,11 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
                 const Terms tm = role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[r]);
                 pv0 += tm.t0;
                 pv1 += tm.t1;
+                pv2 += tm.t2;
             }
         }
     }
-    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
@@ -442,44 +481,20 @@ __global__ __launch_bounds__(kBlock) void k_sym_role(Args a, int q)
     }
     __shared__ d2 red[kSymWaves][kWave];
     const d2 val = symv_gather(a.sym.part, a.n, a.sym.T, e, red);
-    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0};
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0}, pv2 = d2{0.0, 0.0};
     if (wave0 && e < a.n) {
         const Terms tm = role_finish<RO, d2>(a, mode, e, val);
         pv0 = tm.t0;
         pv1 = tm.t1;
+        pv2 = tm.t2;
     }
-    write_partials(pv0, pv1, a.part[q ^ 1], lds);
+    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
 // ------------------------------------------------------- BiCGSTAB vectors
 
-// p = r (new direction) or p = r + beta (p - omega v)
-template <class T = d2>
-__global__ __launch_bounds__(kBlock) void k_bicg_p(Args a, int q)
-{
-    SOLVER_PROLOGUE();
-    if (L.phase == PH_RUN || L.phase == PH_RESTART) {
-        T* p = (T*)a.p;
-        const T* r = (const T*)a.r;
-        const T* v = (const T*)a.v;
-        const bool fresh = L.restart != 0;
-        const d2 beta = L.beta;
-        const d2 nom = d2{-L.omega.x, -L.omega.y};
-        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-            const d2 ri = ldv(r, i);
-            if (fresh) {
-                stv(p, i, ri);
-            } else {
-                const d2 d = cfma(nom, ldv(v, i), ldv(p, i));  // p - omega v
-                stv(p, i, cfma(beta, d, ri));
-            }
-        }
-    }
-    publish(a, q, L, PK_NONE, 0);
-}
-
-// s = r - alpha v, ||s||^2
+// s = r - alpha v, ||s||^2, r^H s
 template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 {
@@ -488,49 +503,56 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
     T* s = (T*)a.s;
     const T* r = (const T*)a.r;
     const T* v = (const T*)a.v;
+    const T* rh = (const T*)a.rh;
     const d2 nal = d2{-L.alpha.x, -L.alpha.y};
-    d2 v0 = d2{0.0, 0.0};
+    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         stv(s, i, cfma(nal, ldv(v, i), ldv(r, i)));
-        v0.x += cabs2(ldv(s, i));
+        const d2 si = ldv(s, i);
+        v0.x += cabs2(si);
+        v1 = cfma_conj(ldv(rh, i), si, v1);
     }
-    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
-    publish(a, q, L, PK_S, gridDim.x);
+    write_partials(v0, v1, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_S2, gridDim.x);
 }
 
-// x += alpha p + omega s, r = s - omega t, ||r||^2, r^H r; or, after a
-// half-step exit, x += alpha p.
+// x += alpha p + omega s, r = s - omega t, ||r||^2, and the next direction
+// p = r + beta (p - omega v) with the beta of PK_T3; or, after a half-step
+// exit, x += alpha p.
 template <class T = d2>
-__global__ __launch_bounds__(kBlock) void k_bicg_xr(Args a, int q)
+__global__ __launch_bounds__(kBlock) void k_bicg_xrp(Args a, int q)
 {
     SOLVER_PROLOGUE();
     const int ph = L.phase;
     if (ph != PH_RUN && ph != PH_HALF) { publish(a, q, L, PK_NONE, 0); return; }
     T* x = (T*)a.x;
     T* r = (T*)a.r;
-    const T* p = (const T*)a.p;
+    T* p = (T*)a.p;
     const T* s = (const T*)a.s;
     const T* tv = (const T*)a.t;
-    const T* rh = (const T*)a.rh;
+    const T* v = (const T*)a.v;
     const d2 alpha = L.alpha;
     const d2 omega = L.omega;
+    const d2 beta = L.beta;
     const d2 nom = d2{-omega.x, -omega.y};
-    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
+    d2 v0 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        d2 xi = cfma(alpha, ldv(p, i), ldv(x, i));
+        const d2 pi = ldv(p, i);
+        d2 xi = cfma(alpha, pi, ldv(x, i));
         if (ph == PH_RUN) {
             const d2 si = ldv(s, i);
             xi = cfma(omega, si, xi);
             stv(r, i, cfma(nom, ldv(tv, i), si));
             const d2 ri = ldv(r, i);
             v0.x += cabs2(ri);
-            v1 = cfma_conj(ldv(rh, i), ri, v1);
+            const d2 d = cfma(nom, ldv(v, i), pi);  // p - omega v
+            stv(p, i, cfma(beta, d, ri));
         }
         stv(x, i, xi);
     }
     if (ph == PH_HALF) { publish(a, q, L, PK_HALF, 0); return; }
-    write_partials(v0, v1, a.part[q ^ 1], lds);
-    publish(a, q, L, PK_XR, gridDim.x);
+    write_partials(v0, d2{0.0, 0.0}, a.part[q ^ 1], lds);
+    publish(a, q, L, PK_XRP, gridDim.x);
 }
 
 // ----------------------------------------------------------- CGNR vectors
@@ -925,7 +947,7 @@ static inline bool rows16(const void* A, int64_t lda)
 }
 
 struct Layout {
-    size_t state, partials, part_bytes, vec, zpart, spart, total;
+    size_t state, partials, part_bytes, xpartials, xpart_bytes, vec, zpart, spart, total;
     int nvec;
 };
 
@@ -962,6 +984,9 @@ static Layout layout(int method, int64_t n, int64_t min_partials = 0, bool sym =
     L.partials = off;  // two buffers of pb partial pairs
     L.part_bytes = align256((size_t)pb * 2 * sizeof(d2));
     off += 2 * L.part_bytes;
+    L.xpartials = off;  // two buffers of pb third sums
+    L.xpart_bytes = align256((size_t)pb * sizeof(d2));
+    off += 2 * L.xpart_bytes;
     L.nvec = method == CCG_WS_BICGSTAB ? 6 : method == CCG_WS_CGNR ? 4
            : method == CCG_WS_COCG ? 3 : method == CCG_WS_COCR ? 4 : 0;
     L.vec = off;
@@ -1019,6 +1044,8 @@ static Args make_args(int method, int64_t n, const ccg_z* A, int64_t lda, const 
     }
     a.part[0] = (d2*)(base + L.partials);
     a.part[1] = (d2*)(base + L.partials + L.part_bytes);
+    a.xpart[0] = (d2*)(base + L.xpartials);
+    a.xpart[1] = (d2*)(base + L.xpartials + L.xpart_bytes);
     a.st[0] = (SolverState*)(base + L.state);
     a.st[1] = (SolverState*)(base + L.state + 512);
     a.hist = hist;
@@ -1182,11 +1209,10 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                 f.status = sc->ring_d + w;
             }
             if (M == M_BICG) {
-                k_bicg_p<T><<<gE, kBlock, 0, s>>>(f, flip());
-                launch_product<ROLE_V, T, S3>(a, q, s);
+                launch_product<ROLE_V, T, S3>(f, q, s);
                 k_bicg_s<T><<<gE, kBlock, 0, s>>>(a, flip());
                 launch_product<ROLE_T, T, S3>(a, q, s);
-                k_bicg_xr<T><<<gE, kBlock, 0, s>>>(a, flip());
+                k_bicg_xrp<T><<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR && a.sym.T > 0) {
                 launch_sym_role<ROLE_W>(f, q, s);
                 k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
@@ -1739,6 +1765,8 @@ static int t3_solve(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double 
     char* base = (char*)work;
     a.part[0] = (d2*)(base + L.partials);
     a.part[1] = (d2*)(base + L.partials + L.part_bytes);
+    a.xpart[0] = (d2*)(base + L.xpartials);
+    a.xpart[1] = (d2*)(base + L.xpartials + L.xpart_bytes);
     const size_t vbytes = align256((size_t)n * sizeof(d2));
     d2* vec[6] = {};
     for (int k = 0; k < L.nvec; ++k) vec[k] = (d2*)(base + L.vec + k * vbytes);
