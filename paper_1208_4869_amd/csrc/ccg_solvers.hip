@@ -10,9 +10,9 @@
 // van der Vorst's BiCGSTAB and CG on the normal equations, each written as a
 // short fixed sequence of kernels per iteration:
 //
-//   BiCGSTAB slot: p-update | v = A p (+ r^H v, |v|^2) | s = r - alpha v
-//                  (+ |s|^2) | t = A s (+ t^H s, |t|^2) | x, r update
-//                  (+ |r|^2, r^H r)
+//   BiCGSTAB slot: v = A p (+ r^H v, |v|^2) | s = r - alpha v (+ |s|^2,
+//                  r^H s) | t = A s (+ t^H s, |t|^2, r^H t) | x, r and next
+//                  p update (+ |r|^2; beta from rho' = r^H s - omega r^H t)
 //   CGNR slot:     w = A p (+ |w|^2) | x, r update (+ |r|^2) | A^H r band
 //                  partials | z = band sum (+ |z|^2) | p-update
 //
@@ -25,8 +25,8 @@
 // no scalar crosses to the host during a solve.  A device phase word drives
 // the control flow: every kernel reads it on entry and does its part only in
 // the phases where it has one, so the host enqueues the same slot over and
-// over and learns that the solve is over from a one-word status copied to
-// pinned host memory at the end of each slot, a slot or two behind the device.
+// over and learns that the solve is over from a one-word status that the
+// first kernel of the next slot stores to pinned host memory.
 #include <hip/hip_runtime.h>
 
 #include <climits>
