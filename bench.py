@@ -410,6 +410,18 @@ def serve_leg(nreq, rate):
     log("serving: capacity %.0f req/s, Poisson %.0f req/s: p50 %.2f ms p99 %.2f ms; "
         "one at a time %.0f req/s" % (cap, rate, np.percentile(lat_p, 50) * 1e3,
                                       np.percentile(lat_p, 99) * 1e3, nreq / t_seq))
+    # latency against offered load: Poisson arrivals at 50%, 90% and 120% of
+    # the measured capacity (above 100% the queue grows over the run)
+    sweep = []
+    for i, load in enumerate((0.5, 0.9, 1.2)):
+        g = np.random.default_rng(SERVE_SEED + 10 + i).exponential(1.0 / (load * cap), nreq)
+        mk_s, lat_s, res_s, _ = run_server(reqs, np.cumsum(g) - g[0])
+        ok = ok and all(a.info == 0 and a.relres_true <= TOL for r in res_s for a in r)
+        sweep.append({"load": load, "rate_per_s": load * cap, "requests_per_s": nreq / mk_s,
+                      "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                      "p99_ms": float(np.percentile(lat_s, 99) * 1e3)})
+        log("serving at %.0f%% of capacity: p50 %.2f ms p99 %.2f ms" % (
+            100 * load, sweep[-1]["p50_ms"], sweep[-1]["p99_ms"]))
     # the mixed-precision variant on the same requests and arrivals
     X64 = [X.clone() for _, _, X in reqs]
     run_server(reqs[:8], np.zeros(8), mixed=True)  # warm-up
@@ -436,6 +448,7 @@ def serve_leg(nreq, rate):
                         "p50_ms": float(np.percentile(lat_p, 50) * 1e3),
                         "p99_ms": float(np.percentile(lat_p, 99) * 1e3),
                         "ticks": st_p["ticks"], "peak_active": st_p["peak_active"]},
+            "load_sweep": sweep,
             "one_at_a_time": {"requests_per_s": nreq / t_seq,
                               "rhs_solves_per_s": rhs / t_seq},
             "mixed": {"capacity_requests_per_s": nreq / mk_mc,
