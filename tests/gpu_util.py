@@ -53,7 +53,7 @@ def assert_parity(orc, method, A, y, x_true=None, tol=1e-10, maxit=1000,
         <= tol (plus the rounding bound of that recomputation);
       * forward error <= 100 x max(oracle forward error, 1e-13);
       * iteration counts within 1;
-      * the scalar histories (alpha, omega) agree to 1e-6 relative while the
+      * the scalar histories (alpha, omega, beta) agree to 1e-6 relative while the
         residual is above 1e-8."""
     ref = getattr(orc, method)(A, y, tol=tol, maxit=maxit)
     x, res, h = gpu_solve(method, Ad if Ad is not None else A,
@@ -73,7 +73,7 @@ def assert_parity(orc, method, A, y, x_true=None, tol=1e-10, maxit=1000,
     for it in range(k):
         if not (ref.hist[it, 7] > 1e-8 or np.isnan(ref.hist[it, 7])):
             break
-        for col in (0, 2):  # alpha, omega
+        for col in (0, 2, 4):  # alpha, omega, beta
             a = h[it, col] + 1j * h[it, col + 1]
             b = ref.hist[it, col] + 1j * ref.hist[it, col + 1]
             if np.isnan(b):
