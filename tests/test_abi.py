@@ -222,3 +222,15 @@ def test_server_mixed_argument_errors_are_rejected_on_the_host(lib):
         bm = ccg.ccg_server_request_bytes(n, k, mixed=True)
         assert bm >= b + 8 * n * n  # the complex64 copy of A on top
     assert ccg.ccg_server_request_bytes(10, 17, mixed=True) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so,
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    proc = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                          capture_output=True, text=True, timeout=120)
+    assert proc.returncode == 2
+    assert "one GPU" in proc.stderr
