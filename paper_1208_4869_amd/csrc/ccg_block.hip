@@ -181,6 +181,71 @@ __global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int6
     zgemm_body<NT>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
+// Slice s of Z = A B for at most kVCols columns, on the vector units.  With
+// four or fewer right-hand sides the product is HBM bound and a 16-wide
+// matrix-core tile would spend most of its work and of its B traffic on
+// padding; here wavefront w takes kVRows rows, lane l the columns
+// k0 + 64 c + l of the slice, and each lane accumulates kVRows x KP complex
+// sums in FP64 (one load of A feeds KP complex FMAs; the lane's B row segment
+// serves kVRows rows).  The sums cross the 64 lanes in the transposing
+// butterfly.  Same slice split and output layout as zgemm_body: block b takes
+// slice b mod 8 (the XCD it runs on) and rows (b / 8) * kVRowsPerBlock ...
+constexpr int kVCols = 4;                   // most columns of this product
+constexpr int kVRows = 4;                   // rows per wavefront
+constexpr int kVRowsPerBlock = kWavesPerBlock * kVRows;
+
+template <int KP>
+__device__ __forceinline__ void vgemm_body(const d2* __restrict__ A, int64_t lda, int n,
+                                           const d2* __restrict__ B, int64_t ldb, int ncols,
+                                           d2* __restrict__ Zp, int kslice, int bid)
+{
+    const int s = bid % kSlices;
+    const int rb = bid / kSlices;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int r0 = rb * kVRowsPerBlock + w * kVRows;
+    const int k0 = s * kslice;
+    const int k1 = k0 + kslice < n ? k0 + kslice : n;
+    constexpr int NV = kVRows * KP;
+    d2 acc[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) acc[e] = d2{0.0, 0.0};
+    const d2* Ar[kVRows];
+#pragma unroll
+    for (int r = 0; r < kVRows; ++r) Ar[r] = A + (int64_t)(r0 + r < n ? r0 + r : n - 1) * lda;
+    for (int j = k0 + lane; j < k1; j += kWave) {
+        d2 b[KP], a[kVRows];
+#pragma unroll
+        for (int c = 0; c < KP; ++c) b[c] = c < ncols ? B[(int64_t)j * ldb + c] : d2{0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < kVRows; ++r) a[r] = ldnt(Ar[r] + j);
+#pragma unroll
+        for (int r = 0; r < kVRows; ++r)
+#pragma unroll
+            for (int c = 0; c < KP; ++c) acc[r * KP + c] = cfma(a[r], b[c], acc[r * KP + c]);
+    }
+    wave_transpose_sum<NV>(acc, lane);
+    constexpr int kShare = kWave / NV;  // lanes holding the same total
+    if ((lane & (kShare - 1)) == 0) {
+        const int e = lane / kShare;
+        const int r = e / KP, c = e % KP;
+        if (r0 + r < n && c < ncols) Zp[((int64_t)s * n + r0 + r) * ncols + c] = acc[0];
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_vgemm(const d2* __restrict__ A, int64_t lda, int n,
+                                                  const d2* __restrict__ B, int64_t ldb,
+                                                  int ncols, d2* __restrict__ Zp, int kslice)
+{
+    vgemm_body<KP>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+}
+
+static inline int vgemm_blocks(int64_t n)
+{
+    return (int)((n + kVRowsPerBlock - 1) / kVRowsPerBlock) * kSlices;
+}
+
 // Z[i][c] = sum over slices s (in order) of Zp[s][i][c]
 __device__ __forceinline__ d2 slice_sum(const d2* __restrict__ Zp, int64_t n, int ncols,
                                         int64_t i, int c)
@@ -211,9 +276,21 @@ static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ld
     k_zgemm<NT><<<rblocks * kSlices, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, kslice_of(n));
 }
 
+// Z slices = A B: vector units for up to kVCols columns, FP64 matrix cores
+// beyond.
 static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,
                  hipStream_t s)
 {
+    if (ncols <= kVCols) {
+        const int g = vgemm_blocks(n), ks = kslice_of(n);
+        if (ncols == 1)
+            k_vgemm<1><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+        else if (ncols == 2)
+            k_vgemm<2><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+        else
+            k_vgemm<4><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+        return;
+    }
     switch ((ncols + 15) / 16) {
     case 1: launch_gemm<1>(A, lda, n, B, ldb, ncols, Zp, s); break;
     case 2: launch_gemm<2>(A, lda, n, B, ldb, ncols, Zp, s); break;
@@ -1165,23 +1242,30 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
 // whatever else is in the batch.  Product shares start at multiples of 8, so
 // the slice of a product block is still the XCD it runs on.
 
-constexpr int kServeCols = 16;  // one 16-wide product tile per request
+constexpr int kServeCols = 16;  // one 16-wide matrix-core tile (or the vector-unit
+                                // product for kp <= kVCols) per request
 constexpr int kMaxActive = 128;
 
 struct SlotRec {
     BArgs a;
     int c0, gC;  // column-kernel blocks [c0, c0 + gC) of the batched grid
-    int g0, gG;  // product blocks [g0, g0 + gG)
+    int g0, gG;  // matrix-core product blocks [g0, g0 + gG) (0 blocks if none)
+    int v0, vG;  // vector-unit product blocks [v0, v0 + vG) (FP64, kp <= kVCols)
     int kslice;
     int slot;    // index of the request's done word
 };
 
-__device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, int b, bool prod)
+enum RecGrid { RG_COL, RG_MFMA, RG_VALU };
+
+// The record whose blocks of grid `which` contain block b: the last record
+// starting at or before b (records with no blocks in that grid are skipped).
+__device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, int b, int which)
 {
     int lo = 0, hi = m - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int start = prod ? tab[mid].g0 : tab[mid].c0;
+        const int start = which == RG_MFMA ? tab[mid].g0 : which == RG_VALU ? tab[mid].v0
+                        : tab[mid].c0;
         if (start <= b)
             lo = mid;
         else
@@ -1196,7 +1280,7 @@ __device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, 
     __global__ __launch_bounds__(kBlock) void kv_##name(                              \
         const SlotRec* __restrict__ tab, int m, const int* __restrict__ sdone)        \
     {                                                                                 \
-        const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, false)];                  \
+        const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];                 \
         if (sdone[r.slot]) return;                                                    \
         const BArgs a = r.a;                                                          \
         kb_##name##_body(a, blockIdx.x - r.c0, r.gC);                                 \
@@ -1214,17 +1298,35 @@ SERVE_COL_KERNEL(xr)
 __global__ __launch_bounds__(kBlock) void kv_gemm(const SlotRec* __restrict__ tab, int m,
                                                   const int* __restrict__ sdone, int use_s)
 {
-    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
-    if (sdone[r.slot] || r.a.A32) return;
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_MFMA)];
+    if (sdone[r.slot] || r.a.A32 || r.gG == 0) return;
     const BArgs a = r.a;
     zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
                   blockIdx.x - r.g0);
 }
 
+// The FP64 requests of at most kVCols columns: the vector-unit product, as
+// gemm() gives it to ccg_bicgstab_block_ex.
+__global__ __launch_bounds__(kBlock) void kv_vgemm(const SlotRec* __restrict__ tab, int m,
+                                                   const int* __restrict__ sdone, int use_s)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_VALU)];
+    if (sdone[r.slot] || r.vG == 0) return;
+    const BArgs a = r.a;
+    const d2* Bm = use_s ? a.S : a.B;
+    const int bid = blockIdx.x - r.v0;
+    if (a.kp == 1)
+        vgemm_body<1>(a.A, a.lda, a.n, Bm, a.kp, a.kp, a.Zp, r.kslice, bid);
+    else if (a.kp == 2)
+        vgemm_body<2>(a.A, a.lda, a.n, Bm, a.kp, a.kp, a.Zp, r.kslice, bid);
+    else
+        vgemm_body<4>(a.A, a.lda, a.n, Bm, a.kp, a.kp, a.Zp, r.kslice, bid);
+}
+
 __global__ __launch_bounds__(kBlock) void kv_cgemm(const SlotRec* __restrict__ tab, int m,
                                                    const int* __restrict__ sdone, int use_s)
 {
-    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, true)];
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_MFMA)];
     if (sdone[r.slot] || !r.a.A32) return;
     const BArgs a = r.a;
     cgemm_body<1>(a.A32, a.lda32, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
@@ -1380,7 +1482,7 @@ struct ccg_server {
     bool stage_pending[ccg::kRing] = {};
     int stage_next = 0;
     std::vector<std::pair<int, int64_t>> table;  // (slot, solve id) of the device table
-    int tot_c = 0, tot_g = 0;
+    int tot_c = 0, tot_g = 0, tot_v = 0;
     // copy-out: pinned column records [kMaxActive][kServeCols]
     char* res_h = nullptr;
     double* norms_h = nullptr;  // pinned column norms of mixed requests
@@ -1498,7 +1600,9 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
         return (int)e;
     r->rec.a = a;
     r->rec.gC = col_blocks(n, kp);
-    r->rec.gG = (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
+    const bool valu = !r->mixed && kp <= kVCols;
+    r->rec.gG = valu ? 0 : (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
+    r->rec.vG = valu ? vgemm_blocks(n) : 0;
     r->rec.kslice = r->mixed ? kslice32_of(n) : kslice_of(n);
     r->rec.slot = slot;
     r->slot = slot;
@@ -1737,17 +1841,20 @@ static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, in
         S->stage_pending[u] = false;
     }
     SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
-    int c = 0, g = 0;
+    int c = 0, g = 0, v = 0;
     for (size_t i = 0; i < want.size(); ++i) {
         SlotRec rec = S->slots[want[i].first]->rec;
         rec.c0 = c;
         rec.g0 = g;
+        rec.v0 = v;
         c += rec.gC;
         g += rec.gG;
+        v += rec.vG;
         h[i] = rec;
     }
     S->tot_c = c;
     S->tot_g = g;
+    S->tot_v = v;
     S->table = want;
     if (want.empty()) return 0;
     hipError_t e = hipMemcpyAsync(S->tab_d, h, want.size() * sizeof(SlotRec),
@@ -1797,11 +1904,12 @@ static int serve_step(ccg_server* S)
     // 2. the table of this iteration: admitted requests still iterating (a
     //    slot may hold another request than in the last table: compare tickets)
     std::vector<std::pair<int, int64_t>> want;
-    bool any64 = false, any32 = false;
+    bool any64 = false, any32 = false, anyv = false;
     for (int q = 0; q < S->max_active; ++q)
         if (serve_iterating(S->slots[q])) {
             want.emplace_back(q, S->slots[q]->solve_id);
-            (S->slots[q]->mixed ? any32 : any64) = true;
+            const SlotRec& rec = S->slots[q]->rec;
+            (S->slots[q]->mixed ? any32 : rec.vG > 0 ? anyv : any64) = true;
         }
     if (want != S->table && (rc = serve_upload_table(S, want))) return rc;
     // 3. one batched iteration
@@ -1815,12 +1923,14 @@ static int serve_step(ccg_server* S)
         kv_p<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         if (any64) kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
         if (any32) kv_cgemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
+        if (anyv) kv_vgemm<<<S->tot_v, kBlock, 0, s>>>(tab, m, S->sdone_d, 0);
         kv_red1<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_P1, nullptr);
         kv_s<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_S, nullptr);
         if (any64) kv_gemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
         if (any32) kv_cgemm<<<S->tot_g, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
+        if (anyv) kv_vgemm<<<S->tot_v, kBlock, 0, s>>>(tab, m, S->sdone_d, 1);
         kv_red2<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_T, nullptr);
         kv_xr<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);

@@ -84,6 +84,40 @@ __device__ __forceinline__ double wave_sum(double v)
 
 __device__ __forceinline__ d2 wave_sum(d2 v) { return d2{wave_sum(v.x), wave_sum(v.y)}; }
 
+// Transposing butterfly: the wavefront totals of NV per-lane partial sums
+// with about one exchange per value instead of six.  On entry v[k] is this
+// lane's partial sum of value k; at each step a lane keeps half of its values
+// and sends the other half to its partner at lane distance H (M values per
+// step), so log2(NV) steps leave one value per lane and a plain butterfly
+// over the 64 / NV lanes that share it finishes the total: on return v[0]
+// holds the total of value lane / (64 / NV).  Fixed order: every run gives
+// the same bits.
+template <int M, int H, int NV>
+__device__ __forceinline__ void transpose_sum_step(d2 (&v)[NV], int lane)
+{
+    if constexpr (M >= 1) {
+        const bool up = (lane & H) != 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const d2 send = up ? v[k] : v[k + M];
+            const d2 keep = up ? v[k + M] : v[k];
+            v[k] = keep + d2{__shfl_xor(send.x, H, kWave), __shfl_xor(send.y, H, kWave)};
+        }
+        transpose_sum_step<M / 2, H / 2, NV>(v, lane);
+    } else {
+#pragma unroll
+        for (int h = H; h >= 1; h >>= 1)
+            v[0] += d2{__shfl_xor(v[0].x, h, kWave), __shfl_xor(v[0].y, h, kWave)};
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_transpose_sum(d2 (&v)[NV], int lane)
+{
+    static_assert(NV >= 1 && NV <= kWave && (NV & (NV - 1)) == 0, "power of two rows");
+    transpose_sum_step<NV / 2, kWave / 2, NV>(v, lane);
+}
+
 // Sum of one value per thread over the block, in a fixed order (64-lane
 // butterfly, then wavefronts in index order).  Valid in thread 0.  `lds` must
 // hold one entry per wavefront.

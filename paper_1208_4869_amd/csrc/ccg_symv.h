@@ -77,35 +77,6 @@ __device__ __forceinline__ void sym_tile_of(int64_t b, int64_t T, int& I, int& J
     J = (int)(r + 1 + (b - start(r)));
 }
 
-// Transposing butterfly (see above): on entry v[k] is this lane's partial
-// sum of row k; on return v[0] holds the wavefront total of row
-// lane / (64 / NV).  M rows are exchanged across lane distance H per step.
-template <int M, int H, int NV>
-__device__ __forceinline__ void transpose_sum_step(d2 (&v)[NV], int lane)
-{
-    if constexpr (M >= 1) {
-        const bool up = (lane & H) != 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const d2 send = up ? v[k] : v[k + M];
-            const d2 keep = up ? v[k + M] : v[k];
-            v[k] = keep + d2{__shfl_xor(send.x, H, kWave), __shfl_xor(send.y, H, kWave)};
-        }
-        transpose_sum_step<M / 2, H / 2, NV>(v, lane);
-    } else {
-#pragma unroll
-        for (int h = H; h >= 1; h >>= 1)
-            v[0] += d2{__shfl_xor(v[0].x, h, kWave), __shfl_xor(v[0].y, h, kWave)};
-    }
-}
-
-template <int NV>
-__device__ __forceinline__ void wave_transpose_sum(d2 (&v)[NV], int lane)
-{
-    static_assert(NV >= 1 && NV <= kWave && (NV & (NV - 1)) == 0, "power of two rows");
-    transpose_sum_step<NV / 2, kWave / 2, NV>(v, lane);
-}
-
 // Value of lane src of a wavefront, in every lane.
 __device__ __forceinline__ double bcast_lane(double v, int src)
 {
