@@ -155,7 +155,20 @@ def cpu_baseline(A, y, budget_s):
             "sample": "%d complete BiCGSTAB solve(s) of the same 20^3 lattice "
                       "system (n=8000) by the single-threaded C oracle, %.1f s"
                       % (k, el),
-            "iters": res.iters, "relres_true": res.relres_true}
+            "iters": res.iters, "relres_true": res.relres_true,
+            "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+
+def host_cpu():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def mixed_leg(steps):
