@@ -71,6 +71,22 @@ constexpr int kWN = 8;  // wavefronts per block in A x
 constexpr int kBlockN = kWN * kWave;
 constexpr int kUC = 4;  // rows per step in A^H x
 
+// Status word of a slot: the phase in the low 4 bits and, above them,
+// -16 log2 of the recursive relative residual (0 when unknown or >= 1), which
+// the host uses to stop enqueueing slots ahead when the next one is likely
+// to be the last.
+constexpr int kStatusPhaseBits = 4;
+
+__device__ __forceinline__ int status_word(int phase, double relres)
+{
+    int code = 0;
+    if (relres > 0.0 && relres < 1.0) {
+        const double c = -16.0 * log2(relres);
+        code = c < (double)(1 << 26) ? (int)c : (1 << 26) - 1;
+    }
+    return (code << kStatusPhaseBits) | phase;
+}
+
 // Start of every solver kernel: load state copy q into LDS and finish the
 // reduction the previous kernel left (same fixed order in every block).
 // kInFlight: partial loads in flight per thread.  Eight (five for three
@@ -98,7 +114,8 @@ __device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d
     // the first kernel of a slot reports where the previous slot left the
     // method (a plain store to pinned host memory, system scope)
     if (a.status && blockIdx.x == 0 && threadIdx.x == 0)
-        __hip_atomic_store(a.status, L.phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.status, status_word(L.phase, L.relres_rec), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // End of every solver kernel: block 0 writes the state for the next kernel,
@@ -160,7 +177,8 @@ __global__ void k_status(Args a, int q, int* ring_slot)
 {
     SOLVER_PROLOGUE();
     if (threadIdx.x == 0)
-        __hip_atomic_store(ring_slot, L.phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(ring_slot, status_word(L.phase, L.relres_rec), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
     publish(a, q, L, PK_NONE, 0);
 }
 
@@ -1140,26 +1158,27 @@ static void launch_product(const Args& a, int& q, hipStream_t s)
 // invalidation, a few microseconds per slot, so the fast path makes none.)
 constexpr int kStatusEmpty = -1;
 
-static int wait_status(SyncCtx* sc, int idx, hipStream_t s, int* phase)
+static int wait_status(SyncCtx* sc, int idx, hipStream_t s, int* phase, double* relres)
 {
+    int v = kStatusEmpty;
     for (uint64_t spin = 1;; ++spin) {
-        const int v = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
-        if (v != kStatusEmpty) {
-            *phase = v;
-            return 0;
-        }
+        v = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
+        if (v != kStatusEmpty) break;
         if (spin >= (1u << 14) && (spin & 1023) == 0) {
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {  // drained: the word must be there now
-                const int w = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
-                if (w == kStatusEmpty) return (int)hipErrorUnknown;
-                *phase = w;
-                return 0;
+                v = __atomic_load_n(&sc->ring_h[idx], __ATOMIC_ACQUIRE);
+                if (v == kStatusEmpty) return (int)hipErrorUnknown;
+                break;
             }
             if (e != hipErrorNotReady) return (int)e;
         }
         __builtin_ia32_pause();
     }
+    *phase = v & ((1 << kStatusPhaseBits) - 1);
+    const int code = v >> kStatusPhaseBits;
+    *relres = code > 0 ? std::exp2(-code / 16.0) : -1.0;
+    return 0;
 }
 
 // Enqueue set-up, then slots until the status word of a slot reads PH_DONE.
@@ -1197,14 +1216,29 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     // Each slot advances the method by at most one iteration or one
     // confirmation; a confirmation is always preceded by an iteration or
     // by the set-up, so 2 * maxit + 4 slots always suffice.
+    //
+    // Look-ahead: the host keeps `ahead` slots queued beyond the one whose
+    // status it reads, except past the slot that is likely to be the last:
+    // when a status reads CONFIRM (the next slot confirms) or the residual
+    // ratio of the last two statuses predicts convergence within the next
+    // slot, nothing is enqueued after the presumed confirmation slot, and a
+    // one-block status kernel reports that slot instead of the first kernel
+    // of a slot that would have run for nothing.  A wrong guess costs one such
+    // status kernel; the slots then continue as before.
     const int64_t max_slots = 2 * (int64_t)maxit + 4;
     const int ahead = S3 ? 2 : lookahead(a.n);  // structured slots are short
-    for (int64_t slot = 0; slot < max_slots + ahead; ++slot) {
-        if (slot < max_slots) {
+    const double tol = std::sqrt(tol2);
+    int64_t next = 0;                 // next slot to enqueue
+    int64_t seen = 0;                 // next slot whose status the host reads
+    int64_t reported = -1;            // last slot followed by a status kernel
+    int64_t stop_at = INT64_MAX;      // enqueue nothing past this slot
+    double prev_rr = -1.0;
+    for (;;) {
+        while (next < max_slots && next <= seen + ahead && next <= stop_at) {
             Args f = a;  // the slot's first kernel reports slot - 1
             f.status = nullptr;
-            if (slot > 0) {
-                const int w = (int)((slot - 1) % kRing);
+            if (next > 0 && reported != next - 1) {
+                const int w = (int)((next - 1) % kRing);
                 __atomic_store_n(&sc->ring_h[w], kStatusEmpty, __ATOMIC_RELEASE);
                 f.status = sc->ring_d + w;
             }
@@ -1240,20 +1274,33 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                 k_cocr_pw<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cocr_xr<<<gE, kBlock, 0, s>>>(a, flip());
             }
-            if (slot == max_slots - 1) {
-                const int w = (int)(slot % kRing);
-                __atomic_store_n(&sc->ring_h[w], kStatusEmpty, __ATOMIC_RELEASE);
-                k_status<<<1, kBlock, 0, s>>>(a, flip(), sc->ring_d + w);
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+            ++next;
         }
-        const int64_t seen = slot - ahead;
-        if (seen >= 0) {
-            int phase = 0;
-            int rc = wait_status(sc, (int)(seen % kRing), s, &phase);
-            if (rc) return rc;
-            if (phase == PH_DONE) break;
+        // the last enqueued slot has no follower for now: a status kernel
+        // reports it
+        if (next > seen && reported != next - 1 && (next == max_slots || next > stop_at)) {
+            const int w = (int)((next - 1) % kRing);
+            __atomic_store_n(&sc->ring_h[w], kStatusEmpty, __ATOMIC_RELEASE);
+            k_status<<<1, kBlock, 0, s>>>(a, flip(), sc->ring_d + w);
+            reported = next - 1;
         }
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        if (seen >= next) break;  // slot budget spent (defensive)
+        int phase = 0;
+        double rr = -1.0;
+        int rc = wait_status(sc, (int)(seen % kRing), s, &phase, &rr);
+        if (rc) return rc;
+        if (phase == PH_DONE) break;
+        if (phase == PH_CONFIRM || phase == PH_HALF) {
+            stop_at = seen + 1;
+        } else {
+            stop_at = INT64_MAX;
+            if (phase == PH_RUN && prev_rr > 0.0 && rr > 0.0 && rr < prev_rr &&
+                rr * (rr / prev_rr) <= 2.0 * tol)
+                stop_at = seen + 2;  // slot seen + 1 is predicted to converge
+        }
+        prev_rr = rr;
+        ++seen;
     }
     SolverState hs;
     if ((e = hipMemcpyAsync(&hs, a.st[q], sizeof hs, hipMemcpyDeviceToHost, s)) != hipSuccess)
