@@ -396,9 +396,9 @@ __global__ __launch_bounds__(kBlockN) void k_gemv_n_role(Args a, int q)
 //
 // The same roles with the product computed by the five FFT passes of
 // ccg_t3.h.  The first pass applies the pending scalar step (and so learns
-// the phase and the input vector); the passes in between only carry the
-// state; the last pass finishes the product and does what k_gemv_n_role does
-// with each element.
+// the phase and the input vector); the passes in between are the plain ones
+// (k_t3p_*); the last pass finishes the product and does what k_gemv_n_role
+// does with each element.
 
 template <Role RO, int R>
 __global__ __launch_bounds__(kBlock) void k_t3_x(Args a, int q)
@@ -406,33 +406,6 @@ __global__ __launch_bounds__(kBlock) void k_t3_x(Args a, int q)
     SOLVER_PROLOGUE();
     const int mode = role_mode<RO>(L.phase);
     if (mode >= 0 && mode != PH_ZERO) t3_pass_x<R>(a.t3, role_input<RO>(a, mode));
-    publish(a, q, L, PK_NONE, 0);
-}
-
-template <Role RO, int R>
-__global__ __launch_bounds__(kBlock) void k_t3_y(Args a, int q)
-{
-    SOLVER_PROLOGUE();
-    const int mode = role_mode<RO>(L.phase);
-    if (mode >= 0 && mode != PH_ZERO) t3_pass_y<R>(a.t3);
-    publish(a, q, L, PK_NONE, 0);
-}
-
-template <Role RO, int R>
-__global__ __launch_bounds__(kBlock) void k_t3_z(Args a, int q)
-{
-    SOLVER_PROLOGUE();
-    const int mode = role_mode<RO>(L.phase);
-    if (mode >= 0 && mode != PH_ZERO) t3_pass_z<R>(a.t3);
-    publish(a, q, L, PK_NONE, 0);
-}
-
-template <Role RO, int R>
-__global__ __launch_bounds__(kBlock) void k_t3_yi(Args a, int q)
-{
-    SOLVER_PROLOGUE();
-    const int mode = role_mode<RO>(L.phase);
-    if (mode >= 0 && mode != PH_ZERO) t3_pass_yi<R>(a.t3);
     publish(a, q, L, PK_NONE, 0);
 }
 
@@ -1093,7 +1066,11 @@ static inline int t3_blocks(int64_t lines)
 }
 
 // The five passes of a structured product of role RO (state copy q in, q
-// advanced past them).
+// advanced past them).  Only the first and the last pass take part in the
+// state chain; the three middle passes run unconditionally on the grids
+// (when the first pass had nothing to transform they work on stale grid
+// data that the last pass then ignores), which spares each of them the
+// dependent load of the state at its start.
 template <Role RO, int R>
 static void launch_t3_role(const Args& a, int& q, hipStream_t s)
 {
@@ -1102,12 +1079,9 @@ static void launch_t3_role(const Args& a, int& q, hipStream_t s)
     b.status = nullptr;
     k_t3_x<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
     q ^= 1;
-    k_t3_y<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(b, q);
-    q ^= 1;
-    k_t3_z<RO, R><<<t3_blocks(M * M), kBlock, 0, s>>>(b, q);
-    q ^= 1;
-    k_t3_yi<RO, R><<<t3_blocks(M * m), kBlock, 0, s>>>(b, q);
-    q ^= 1;
+    k_t3p_y<R><<<t3_blocks(M * m), kBlock, 0, s>>>(a.t3);
+    k_t3p_z<R><<<t3_blocks(M * M), kBlock, 0, s>>>(a.t3);
+    k_t3p_yi<R><<<t3_blocks(M * m), kBlock, 0, s>>>(a.t3);
     k_t3_role<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(b, q);
     q ^= 1;
 }
