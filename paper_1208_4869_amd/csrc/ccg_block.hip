@@ -512,7 +512,9 @@ __device__ __forceinline__ void col_partials(const BArgs& a, int bid, d2 v0, d2 
     }
 }
 
-__global__ void kb_init(BArgs a, int maxit, double tol2, int no_confirm)
+// Column records of a new solve: thread j (of at least kp) writes record j.
+__device__ __forceinline__ void kb_init_body(const BArgs& a, int maxit, double tol2,
+                                             int no_confirm)
 {
     const int j = threadIdx.x;
     if (j >= a.kp) return;
@@ -532,6 +534,11 @@ __global__ void kb_init(BArgs a, int maxit, double tol2, int no_confirm)
     o.relres_rec = o.relres_true = __builtin_nan("");
     o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
     col_state(a, j) = o;
+}
+
+__global__ void kb_init(BArgs a, int maxit, double tol2, int no_confirm)
+{
+    kb_init_body(a, maxit, tol2, no_confirm);
 }
 
 // Column step: finish the column reductions of the previous kernel (nparts
@@ -1253,6 +1260,9 @@ struct SlotRec {
     int v0, vG;  // vector-unit product blocks [v0, v0 + vG) (FP64, kp <= kVCols)
     int kslice;
     int slot;    // index of the request's done word
+    // set-up of the request's current solve (read by the batched set-up only)
+    int maxit, no_confirm;
+    double tol2;
 };
 
 enum RecGrid { RG_COL, RG_MFMA, RG_VALU };
@@ -1285,6 +1295,8 @@ __device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, 
         const BArgs a = r.a;                                                          \
         kb_##name##_body(a, blockIdx.x - r.c0, r.gC);                                 \
     }
+SERVE_COL_KERNEL(normy)
+SERVE_COL_KERNEL(setup0)
 SERVE_COL_KERNEL(p)
 SERVE_COL_KERNEL(red1)
 SERVE_COL_KERNEL(s)
@@ -1357,9 +1369,18 @@ __global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restric
     kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
 }
 
-__global__ void kv_clear(int* sdone, int slot)
+// First kernel of the batched set-up of the solves that start in a step (a
+// table of their records, one block each): the request's done word is
+// cleared and its column records written, as kb_init does for a solve alone.
+// The set-up continues with kv_normy, kv_step (CS_NORMY), kv_setup0 and
+// kv_step (CS_SETUP0) over the same table.
+__global__ __launch_bounds__(kMaxCols) void kv_setup_init(const SlotRec* __restrict__ tab,
+                                                          int* sdone)
 {
-    if (threadIdx.x == 0) sdone[slot] = 0;
+    const SlotRec& r = tab[blockIdx.x];
+    if (threadIdx.x == 0) sdone[r.slot] = 0;
+    const BArgs a = r.a;
+    kb_init_body(a, r.maxit, r.tol2, r.no_confirm);
 }
 
 // First-fit allocator over the pool (offsets and sizes are multiples of 256).
@@ -1417,6 +1438,7 @@ struct ServeReq {
     int slot = -1;
     int state = CCG_REQ_QUEUED;
     bool retiring = false;      // copy-out enqueued
+    bool setup_pending = false; // a solve starts: set-up not yet enqueued
     int64_t ticks = 0, max_ticks = 0, last_tick = -1;
     SlotRec rec{};
     std::vector<ccg_result> res;
@@ -1482,6 +1504,13 @@ struct ccg_server {
     bool stage_pending[ccg::kRing] = {};
     int stage_next = 0;
     std::vector<std::pair<int, int64_t>> table;  // (slot, solve id) of the device table
+    // batched set-up: device table of the solves starting in a step, its
+    // pinned staging [kRing][kMaxActive] and events
+    ccg::SlotRec* stab_d = nullptr;
+    ccg::SlotRec* sstage_h = nullptr;
+    hipEvent_t sstage_ev[ccg::kRing] = {};
+    bool sstage_pending[ccg::kRing] = {};
+    int sstage_next = 0;
     int tot_c = 0, tot_g = 0, tot_v = 0;
     // copy-out: pinned column records [kMaxActive][kServeCols]
     char* res_h = nullptr;
@@ -1492,22 +1521,16 @@ struct ccg_server {
 
 namespace ccg {
 
-// Enqueue the set-up of a block solve of request r (inner solve of a mixed
-// request, or the whole solve of an FP64 one) and make it iterate.
+// Start a block solve of request r (inner solve of a mixed request, or the
+// whole solve of an FP64 one): its set-up joins the batched set-up of the
+// next step (serve_setup_batch), after which it iterates.
 static int serve_start_solve(ccg_server* S, ServeReq* r, int32_t maxit, double tol2,
                              int no_confirm)
 {
-    hipStream_t s = S->s;
-    const BArgs& a = r->rec.a;
-    const int gC = r->rec.gC;
-    kv_clear<<<1, kWave, 0, s>>>(S->sdone_d, r->slot);
-    kb_init<<<1, kMaxCols, 0, s>>>(a, maxit, tol2, no_confirm);
-    kb_normy<<<gC, kBlock, 0, s>>>(a);
-    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_NORMY, gC, nullptr);
-    kb_setup0<<<gC, kBlock, 0, s>>>(a);
-    kb_step<<<1, kStepThreads, 0, s>>>(a, CS_SETUP0, gC, nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return (int)e;
+    r->rec.maxit = maxit;
+    r->rec.tol2 = tol2;
+    r->rec.no_confirm = no_confirm;
+    r->setup_pending = true;
     r->phase = MP_INNER;
     r->solve_id = S->next_solve++;
     r->ticks = 0;
@@ -1868,7 +1891,48 @@ static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, in
 static bool serve_iterating(const ServeReq* r)
 {
     return r && r->state == CCG_REQ_RUNNING && !r->retiring && r->phase == MP_INNER &&
-           r->ticks < r->max_ticks;
+           !r->setup_pending && r->ticks < r->max_ticks;
+}
+
+// Enqueue the set-up of every solve that starts now, as one batch: a table of
+// their records (column-kernel shares laid out as in the iteration table) and
+// five kernels over it, each request's set-up being the one a solve alone runs
+// (same block partition, same reduction order).
+static int serve_setup_batch(ccg_server* S)
+{
+    const int u = S->sstage_next;
+    SlotRec* h = S->sstage_h + (size_t)u * kMaxActive;
+    int m = 0, c = 0;
+    for (int q = 0; q < S->max_active; ++q) {
+        ServeReq* r = S->slots[q];
+        if (!r || !r->setup_pending) continue;
+        if (m == 0 && S->sstage_pending[u]) {  // staging u is free once its copy ran
+            hipError_t e = hipEventSynchronize(S->sstage_ev[u]);
+            if (e != hipSuccess) return (int)e;
+            S->sstage_pending[u] = false;
+        }
+        SlotRec rec = r->rec;
+        rec.c0 = c;
+        c += rec.gC;
+        h[m++] = rec;
+        r->setup_pending = false;
+    }
+    if (m == 0) return 0;
+    S->sstage_next = (S->sstage_next + 1) % kRing;
+    hipStream_t s = S->s;
+    hipError_t e = hipMemcpyAsync(S->stab_d, h, (size_t)m * sizeof(SlotRec),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return (int)e;
+    if ((e = hipEventRecord(S->sstage_ev[u], s)) != hipSuccess) return (int)e;
+    S->sstage_pending[u] = true;
+    const SlotRec* tab = S->stab_d;
+    kv_setup_init<<<m, kMaxCols, 0, s>>>(tab, S->sdone_d);
+    kv_normy<<<c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+    kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_NORMY, nullptr);
+    kv_setup0<<<c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+    kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_SETUP0, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    return 0;
 }
 
 // Admission in arrival order while a slot is free and the head fits the pool.
@@ -1901,6 +1965,7 @@ static int serve_step(ccg_server* S)
     // 1. finished copy-outs free their slots and pool blocks; admit
     if ((rc = serve_collect(S, false))) return rc;
     if ((rc = serve_admit_queue(S))) return rc;
+    if ((rc = serve_setup_batch(S))) return rc;
     // 2. the table of this iteration: admitted requests still iterating (a
     //    slot may hold another request than in the last table: compare tickets)
     std::vector<std::pair<int, int64_t>> want;
@@ -1954,7 +2019,9 @@ static int serve_step(ccg_server* S)
         if ((rc = serve_read_tick(S))) return rc;
     // 5. with nothing left iterating, wait for the copy-outs
     bool iterating = false;
-    for (int q = 0; q < S->max_active; ++q) iterating = iterating || serve_iterating(S->slots[q]);
+    for (int q = 0; q < S->max_active; ++q)
+        iterating = iterating || serve_iterating(S->slots[q]) ||
+                    (S->slots[q] && S->slots[q]->setup_pending);
     if (!iterating && (rc = serve_collect(S, true))) return rc;
     int act = 0;
     for (int q = 0; q < S->max_active; ++q)
@@ -2143,7 +2210,8 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
 {
     using namespace ccg;
     if (!pool || ((uintptr_t)pool & 255)) return -1;
-    const size_t head = align256(kMaxActive * sizeof(int)) + align256(kMaxActive * sizeof(SlotRec));
+    const size_t head =
+        align256(kMaxActive * sizeof(int)) + 2 * align256(kMaxActive * sizeof(SlotRec));
     if (pool_bytes < head) return -2;
     if (max_active < 1 || max_active > kMaxActive) return -3;
     if (!out) return -5;
@@ -2157,6 +2225,7 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
     S->max_active = max_active;
     S->sdone_d = (int*)pool;
     S->tab_d = (SlotRec*)((char*)pool + align256(kMaxActive * sizeof(int)));
+    S->stab_d = (SlotRec*)((char*)S->tab_d + align256(kMaxActive * sizeof(SlotRec)));
     S->alloc.init(head, (pool_bytes - head) & ~(size_t)255);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&S->ring_h, (size_t)kRing * kMaxActive * sizeof(int),
@@ -2164,6 +2233,9 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&S->ring_d, S->ring_h, 0);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&S->stage_h, (size_t)kRing * kMaxActive * sizeof(SlotRec),
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&S->sstage_h, (size_t)kRing * kMaxActive * sizeof(SlotRec),
                           hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&S->res_h, (size_t)kMaxActive * kServeCols * kStateStride,
@@ -2174,6 +2246,7 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
     for (int q = 0; q < kRing && e == hipSuccess; ++q) {
         e = hipEventCreateWithFlags(&S->tick_ev[q], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&S->stage_ev[q], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S->sstage_ev[q], hipEventDisableTiming);
     }
     for (int q = 0; q < kMaxActive && e == hipSuccess; ++q)
         e = hipEventCreateWithFlags(&S->slot_ev[q], hipEventDisableTiming);
@@ -2196,11 +2269,13 @@ int ccg_server_destroy(ccg_server* S)
     for (int q = 0; q < ccg::kRing; ++q) {
         if (S->tick_ev[q]) keep(hipEventDestroy(S->tick_ev[q]));
         if (S->stage_ev[q]) keep(hipEventDestroy(S->stage_ev[q]));
+        if (S->sstage_ev[q]) keep(hipEventDestroy(S->sstage_ev[q]));
     }
     for (int q = 0; q < ccg::kMaxActive; ++q)
         if (S->slot_ev[q]) keep(hipEventDestroy(S->slot_ev[q]));
     if (S->ring_h) keep(hipHostFree(S->ring_h));
     if (S->stage_h) keep(hipHostFree(S->stage_h));
+    if (S->sstage_h) keep(hipHostFree(S->sstage_h));
     if (S->res_h) keep(hipHostFree(S->res_h));
     if (S->norms_h) keep(hipHostFree(S->norms_h));
     delete S;
