@@ -385,8 +385,9 @@ int ccg_t3_cocr_ex(int64_t m, const void* op, const ccg_z* y, ccg_z* x,
  * request is admitted, in arrival order, when a slot is free (at most
  * max_active at once) and its footprint (A, Y, X and the block-solver
  * workspace, ccg_server_request_bytes) fits in the free pool; admission
- * copies A and Y into the pool (hipMemcpyDefault: host or device sources)
- * and runs the solver set-up.  Every ccg_server_step enqueues one iteration
+ * copies Y, and A when it is in host memory, into the pool (hipMemcpyDefault)
+ * and runs the solver set-up; an A in device memory of the server's GPU is
+ * read in place (its pool region stays reserved).  Every ccg_server_step enqueues one iteration
  * of every admitted request as one batch of kernels (the grid of each kernel
  * covers all requests; each request keeps its own scalars, stop tests and
  * reduction order), so a request's result is bit for bit the result of

@@ -1450,7 +1450,9 @@ struct ServeReq {
     int64_t solve_id = 0;       // id of the block solve now iterating
     bool waiting = false;       // an event of this phase is outstanding
     int outer = 0;              // FP64 residuals evaluated after the first
-    d2 *Ad = nullptr, *Yd = nullptr, *Xd = nullptr;  // pool copies
+    const d2* Ad = nullptr;     // A as the products read it (the caller's or the pool copy)
+    int64_t ald = 0;
+    d2 *Yd = nullptr, *Xd = nullptr;  // pool copies
     d2 *R = nullptr, *Ys = nullptr, *D = nullptr;
     double* norms_d = nullptr;
     std::vector<double> ny2, relres;
@@ -1555,6 +1557,18 @@ static int serve_norms(ccg_server* S, ServeReq* r, const d2* M, int64_t ld)
     return 0;
 }
 
+// True when p is device memory of `device` (then kernels on the server's
+// stream may read it in place).
+static bool on_device(const void* p, int device)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // pageable host memory: not an error here
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
 static int serve_admit(ccg_server* S, ServeReq* r, int slot)
 {
     const int64_t n = r->n;
@@ -1576,9 +1590,17 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
     char* w = base + o;
     const BLayout L = block_layout(n, k);
     const int kp = pow2_at_least(k);
+    // A in device memory of this GPU is read where it is (the caller keeps it
+    // valid and unchanged until the request is done); only host memory is
+    // copied into the pool, whose A region stays reserved either way.
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    const bool borrow = on_device(r->A, S->device);
+    const d2* Asrc = borrow ? r->A : A;
+    const int64_t lda = borrow ? r->lda : n;
     BArgs a{};
-    a.A = A;
-    a.lda = n;
+    a.A = Asrc;
+    a.lda = lda;
     a.n = (int)n;
     a.k = k;
     a.kp = kp;
@@ -1592,7 +1614,8 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
     a.Zp = (d2*)(w + L.zp);
     a.cpart = (d2*)(w + L.cpart);
     a.cst = (SolverState*)(w + L.cst);
-    r->Ad = A;
+    r->Ad = Asrc;
+    r->ald = lda;
     r->Yd = Y;
     r->Xd = X;
     if (r->mixed) {
@@ -1610,8 +1633,8 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
         a.ldx = kp;
     }
     const size_t row = (size_t)k * sizeof(d2);
-    hipError_t e;
-    if ((e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
+    if (!borrow &&
+        (e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
                               hipMemcpyDefault, s)) != hipSuccess)
         return (int)e;
     if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
@@ -1636,7 +1659,7 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
     if (S->st.pool_used > S->st.pool_peak) S->st.pool_peak = S->st.pool_used;
     int rc;
     if (r->mixed) {
-        km_round<<<elem_blocks(n * n), kBlock, 0, s>>>(A, n, (int)n, A32);
+        km_round<<<elem_blocks(n * n), kBlock, 0, s>>>(Asrc, lda, (int)n, A32);
         r->ny2.assign(k, 0.0);
         r->relres.assign(k, 0.0);
         r->info.assign(k, 0);
@@ -1767,7 +1790,7 @@ static int serve_mixed_outer(ccg_server* S, ServeReq* r)
         return (int)e;
     km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp, r->D,
                                                            r->nr, ColScale{});
-    gemm(r->Ad, r->n, (int)r->n, r->Xd, r->k, r->k, r->rec.a.Zp, s);
+    gemm(r->Ad, r->ald, (int)r->n, r->Xd, r->k, r->k, r->rec.a.Zp, s);
     km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, r->rec.a.Zp, (int)r->n, r->k,
                                                        kp, r->R);
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
