@@ -1263,6 +1263,10 @@ struct SlotRec {
     // set-up of the request's current solve (read by the batched set-up only)
     int maxit, no_confirm;
     double tol2;
+    // device sources of Y and X still to be copied into the pool by the
+    // batched set-up (null when admission copied them)
+    const d2 *ysrc, *xsrc;
+    int64_t ldys, ldxs;
 };
 
 enum RecGrid { RG_COL, RG_MFMA, RG_VALU };
@@ -1367,6 +1371,25 @@ __global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restric
     if (sdone[r.slot]) return;
     const BArgs a = r.a;
     kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
+}
+
+// Copy of Y and X (n x k, device sources) into a request's pool matrices
+// (leading dimension k), for the records of the batched set-up that have
+// them; the column-kernel shares of the set-up table split the elements.
+__global__ __launch_bounds__(kBlock) void kv_copy_in(const SlotRec* __restrict__ tab, int m)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    if (!r.ysrc) return;
+    const int bid = blockIdx.x - r.c0;
+    const int k = r.a.k;
+    const int64_t total = (int64_t)r.a.n * k;
+    for (int64_t e = (int64_t)bid * kBlock + threadIdx.x; e < total;
+         e += (int64_t)r.gC * kBlock) {
+        const int64_t i = e / k;
+        const int64_t j = e - i * k;
+        r.a.X[e] = r.xsrc[i * r.ldxs + j];
+        const_cast<d2*>(r.a.Y)[e] = r.ysrc[i * r.ldys + j];
+    }
 }
 
 // First kernel of the batched set-up of the solves that start in a step (a
@@ -1637,14 +1660,24 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
         (e = hipMemcpy2DAsync(A, n * sizeof(d2), r->A, r->lda * sizeof(d2), n * sizeof(d2), n,
                               hipMemcpyDefault, s)) != hipSuccess)
         return (int)e;
-    if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
-        hipSuccess)
-        return (int)e;
-    // x keeps the caller's values in columns the solver never writes
-    if ((e = hipMemcpy2DAsync(X, row, r->X, r->ldx * sizeof(d2), row, n, hipMemcpyDefault, s)) !=
-        hipSuccess)
-        return (int)e;
+    // x keeps the caller's values in columns the solver never writes.  Y and X
+    // in device memory of this GPU (FP64 requests) are copied by the batched
+    // set-up, in one kernel for all requests starting in the step; mixed
+    // requests need Y at once (its column norms).
+    const bool yx_dev = !r->mixed && on_device(r->Y, S->device) && on_device(r->X, S->device);
+    if (!yx_dev) {
+        if ((e = hipMemcpy2DAsync(Y, row, r->Y, r->ldy * sizeof(d2), row, n, hipMemcpyDefault,
+                                  s)) != hipSuccess)
+            return (int)e;
+        if ((e = hipMemcpy2DAsync(X, row, r->X, r->ldx * sizeof(d2), row, n, hipMemcpyDefault,
+                                  s)) != hipSuccess)
+            return (int)e;
+    }
     r->rec.a = a;
+    r->rec.ysrc = yx_dev ? r->Y : nullptr;
+    r->rec.xsrc = yx_dev ? r->X : nullptr;
+    r->rec.ldys = r->ldy;
+    r->rec.ldxs = r->ldx;
     r->rec.gC = col_blocks(n, kp);
     const bool valu = !r->mixed && kp <= kVCols;
     r->rec.gG = valu ? 0 : (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
@@ -1926,6 +1959,7 @@ static int serve_setup_batch(ccg_server* S)
     const int u = S->sstage_next;
     SlotRec* h = S->sstage_h + (size_t)u * kMaxActive;
     int m = 0, c = 0;
+    bool copy_in = false;
     for (int q = 0; q < S->max_active; ++q) {
         ServeReq* r = S->slots[q];
         if (!r || !r->setup_pending) continue;
@@ -1938,6 +1972,8 @@ static int serve_setup_batch(ccg_server* S)
         rec.c0 = c;
         c += rec.gC;
         h[m++] = rec;
+        copy_in = copy_in || rec.ysrc;
+        r->rec.ysrc = r->rec.xsrc = nullptr;  // copied once
         r->setup_pending = false;
     }
     if (m == 0) return 0;
@@ -1949,6 +1985,7 @@ static int serve_setup_batch(ccg_server* S)
     if ((e = hipEventRecord(S->sstage_ev[u], s)) != hipSuccess) return (int)e;
     S->sstage_pending[u] = true;
     const SlotRec* tab = S->stab_d;
+    if (copy_in) kv_copy_in<<<c, kBlock, 0, s>>>(tab, m);
     kv_setup_init<<<m, kMaxCols, 0, s>>>(tab, S->sdone_d);
     kv_normy<<<c, kBlock, 0, s>>>(tab, m, S->sdone_d);
     kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_NORMY, nullptr);
