@@ -194,6 +194,41 @@ def test_serve_host_memory_sources(mix, mix_alone):
     check_equal(got, [mix_alone[i] for i in sub])
 
 
+def test_serve_strided_and_mixed_residency_sources(mix, mix_alone):
+    """Sources given as views with padded leading dimensions: a device A is
+    read in place, device Y and X are copied into the pool by the batched
+    set-up; requests whose X is in host memory take the copy path.  Results
+    equal the solves alone and the padding of the caller's X is untouched."""
+    import torch
+    sub = [1, 3, 4, 6]
+    pad = complex(3.0, 4.0)
+    pool = 64 * 2 ** 20 + sum(ccg.ccg_server_request_bytes(mix[i][0].shape[0],
+                                                           mix[i][1].shape[1]) for i in sub)
+    with ccg.Server(pool, max_active=8) as srv:
+        tickets, held = [], []
+        for j, i in enumerate(sub):
+            A, Y, _ = mix[i]
+            n, k = Y.shape
+            Ab = torch.full((n, n + 3), pad, dtype=torch.complex128, device="cuda")
+            Ab[:, :n] = dev(A)
+            Yb = torch.full((n, k + 2), pad, dtype=torch.complex128, device="cuda")
+            Yb[:, :k] = dev(Y)
+            Xb = torch.full((n, k + 5), pad, dtype=torch.complex128,
+                            device="cuda" if j % 2 == 0 else "cpu")
+            Xb[:, :k] = float("nan")
+            tickets.append(srv.submit(Ab[:, :n], Yb[:, :k], Xb[:, :k], 1e-10, 1000))
+            held.append((Ab, Yb, Xb))
+        res = srv.run_all(tickets)
+        torch.cuda.synchronize()
+    for t, i, (_, _, Xb) in zip(tickets, sub, held):
+        Xr, resr = mix_alone[i]
+        k = Xr.shape[1]
+        X = Xb.cpu().numpy()
+        assert np.array_equal(X[:, :k], Xr, equal_nan=True), i
+        assert np.all(X[:, k:] == pad), i
+        assert all(same_result(a, b) for a, b in zip(res[t], resr)), i
+
+
 def test_serve_server_reuse_many_rounds():
     """Slots and pool blocks are reused across many requests (more requests
     than slots, several waves), results as alone."""
