@@ -371,6 +371,27 @@ __device__ __forceinline__ void role_partials(const Args& a, int q, d2 v0, d2 v1
         write_partials(v0, v1, a.part[q ^ 1], lds);
 }
 
+// role_partials when only the first wavefront holds nonzero terms (the
+// dense product's R rows): the block totals are that wavefront's sums, so no
+// block-wide reduction is needed.  Adding +0 keeps the bits of block_sum,
+// which adds the other wavefronts' +0 sums to it.
+template <Role RO>
+__device__ __forceinline__ void role_partials_wave0(const Args& a, int q, d2 v0, d2 v1, d2 v2)
+{
+    if (threadIdx.x >= kWave) return;
+    const d2 z = d2{0.0, 0.0};
+    const d2 s0 = wave_sum(v0) + z;
+    const d2 s1 = wave_sum(v1) + z;
+    d2 s2 = z;
+    if (RO == ROLE_T) s2 = wave_sum(v2) + z;
+    if (threadIdx.x == 0) {
+        d2* part = a.part[q ^ 1];
+        part[2 * blockIdx.x] = s0;
+        part[2 * blockIdx.x + 1] = s1;
+        if (RO == ROLE_T) a.xpart[q ^ 1][blockIdx.x] = s2;
+    }
+}
+
 template <Role RO, class T = d2>
 __global__ __launch_bounds__(GemvShape<T>::threads) void k_gemv_n_role(Args a, int q)
 {
@@ -403,7 +424,7 @@ __global__ __launch_bounds__(GemvShape<T>::threads) void k_gemv_n_role(Args a, i
         pv1 = tm.t1;
         pv2 = tm.t2;
     }
-    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
+    role_partials_wave0<RO>(a, q, pv0, pv1, pv2);  // the terms sit in the first wavefront
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
@@ -494,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_sym_role(Args a, int q)
         pv1 = tm.t1;
         pv2 = tm.t2;
     }
-    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
+    role_partials_wave0<RO>(a, q, pv0, pv1, pv2);  // the terms sit in the first wavefront
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
