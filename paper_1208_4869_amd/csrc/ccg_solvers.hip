@@ -114,15 +114,37 @@ __device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d
     if (threadIdx.x == 0) L = *a.st[q];
     __syncthreads();
     if (L.pending != PK_NONE) {
-        d2 t0 = d2{0.0, 0.0}, t1 = d2{0.0, 0.0}, t2 = d2{0.0, 0.0};
-        if (L.pending_blocks > 0) {
+        const d2 z = d2{0.0, 0.0};
+        d2 t0 = z, t1 = z, t2 = z;
+        const int nb = L.pending_blocks;
+        if (nb <= kWave) {
+            // at most one partial per thread, all in the first wavefront: the
+            // totals are its sums plus +0 (the bits of the block-wide sum,
+            // which adds the other wavefronts' +0 sums), with no barrier
+            if (threadIdx.x < kWave) {
+                if (nb > 0) {
+                    const int b = threadIdx.x;
+                    d2 a0 = z, a1 = z, a2 = z;
+                    if (b < nb) {
+                        a0 += a.part[q][2 * b];
+                        a1 += a.part[q][2 * b + 1];
+                        if (L.pending == PK_T3) a2 += a.xpart[q][b];
+                    }
+                    t0 = wave_sum(a0) + z;
+                    t1 = wave_sum(a1) + z;
+                    if (L.pending == PK_T3) t2 = wave_sum(a2) + z;
+                }
+                if (threadIdx.x == 0)
+                    apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
+            }
+        } else {
             if (L.pending == PK_T3)
-                reduce_partials3<kInFlight == 8 ? 5 : kInFlight>(a.part[q], a.xpart[q],
-                                                                L.pending_blocks, lds, t0, t1, t2);
+                reduce_partials3<kInFlight == 8 ? 5 : kInFlight>(a.part[q], a.xpart[q], nb, lds,
+                                                                t0, t1, t2);
             else
-                reduce_partials<kInFlight>(a.part[q], L.pending_blocks, lds, t0, t1);
+                reduce_partials<kInFlight>(a.part[q], nb, lds, t0, t1);
+            if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
         }
-        if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
         __syncthreads();
     }
     // the first kernel of a slot reports where the previous slot left the
