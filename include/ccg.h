@@ -33,7 +33,8 @@
  *      a zero bilinear form (r, r), (p, A p), (r, A r) or (A p, A p) (COCG,
  *      COCR)
  *   3  breakdown: t^H t or omega zero (BiCGSTAB)
- *   4  a non-finite value was met (x is left at the last finite iterate)
+ *   4  a non-finite value was met (x is left at the last finite iterate:
+ *      x0 as given, or x = 0 under CCG_X0_ZERO when y itself is not finite)
  *   n == 0 is a no-op with info 0; y == 0 gives x = 0 with info 0.
  *
  * Concurrency: calls on different streams with different workspaces are

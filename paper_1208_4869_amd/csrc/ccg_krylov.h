@@ -26,9 +26,8 @@ enum Phase : int {
 enum Pending : int {
     PK_NONE = 0,
     PK_NORMY,      // ||y||^2
-    PK_SETUP_B0,   // BiCGSTAB set-up, r = y (x0 = 0): ||r||^2
+    PK_SETUP_B0,   // block BiCGSTAB set-up, r = y (x0 = 0): ||r||^2
     PK_SETUP_B1,   // BiCGSTAB set-up, r = y - A x: ||r||^2
-    PK_SETUP_C0,   // CGNR set-up, r = y
     PK_SETUP_C1,   // CGNR set-up, r = y - A x
     PK_ZERO,       // y == 0: x has been zeroed
     PK_V,          // r^H v, ||v||^2        -> alpha
@@ -42,7 +41,6 @@ enum Pending : int {
     PK_XR2,        // ||r||^2               -> stop test (CGNR)
     PK_Z_RUN,      // ||z||^2               -> beta (CGNR)
     PK_Z_RESTART,  // ||z||^2               -> gamma of a new direction (CGNR)
-    PK_SETUP_G0,   // COCG set-up, r = y: ||r||^2, (r, r)
     PK_SETUP_G1,   // COCG set-up, r = y - A x: ||r||^2, (r, r)
     PK_CONFIRM_G,  // ||y - A x||^2, (r, r) of the true residual (COCG)
     PK_Q,          // (p, A p)              -> alpha (COCG)
@@ -56,6 +54,11 @@ enum Pending : int {
     PK_S2,         // ||s||^2, r^H s        -> half-step test
     PK_T3,         // t^H s, ||t||^2, r^H t -> omega, rho', beta
     PK_XRP,        // ||r||^2               -> stop test, rho' breakdown, beta
+    // x0 = 0: ||y||^2 and the set-up sums come from one kernel (r = y, so
+    // ||r||^2 = ||y||^2): the ||y|| step, then the set-up step
+    PK_NY_SETUP_B0,  // BiCGSTAB
+    PK_NY_SETUP_C0,  // CGNR, COCR
+    PK_NY_SETUP_G0,  // COCG (+ (r, r))
 };
 
 // The solver's scalars in device memory.  Two copies alternate: a launch
@@ -131,6 +134,28 @@ __device__ inline void cocg_rho_step(SolverState& L, d2 rho)
     L.restart = 1;
 }
 
+// ||y||^2: the stop threshold, or y == 0 (x = 0), or a non-finite y.
+__device__ inline void normy_step(SolverState& L, double ny2)
+{
+    L.ny2 = ny2;
+    if (!__builtin_isfinite(ny2)) finish(L, 4);
+    else if (ny2 == 0.0) L.phase = PH_ZERO;
+    else L.thr2 = L.tol2 * ny2;
+}
+
+// COCG set-up on ||r||^2 and (r, r).
+__device__ inline void cocg_setup_step(SolverState& L, double rr, d2 rho)
+{
+    if (!__builtin_isfinite(rr)) { finish(L, 4); return; }
+    L.rr = rr;
+    L.relres_rec = relres(rr, L.ny2);
+    if (rr <= L.thr2) { L.phase = PH_CONFIRM; return; }
+    cocg_rho_step(L, rho);
+    if (L.phase == PH_DONE) return;
+    if (L.maxit <= 0) { finish(L, 1); return; }
+    L.phase = PH_RESTART;
+}
+
 // The scalar step of the method that finishes the pending reduction with
 // totals t0, t1 (and t2 for PK_T3).  Runs in thread 0 of every block of the
 // consuming kernel on identical inputs, so every block takes the same
@@ -143,14 +168,23 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist,
     L.pending = PK_NONE;
     L.pending_blocks = 0;
     switch (k) {
-    case PK_NORMY: {
-        const double ny2 = t0.x;
-        L.ny2 = ny2;
-        if (!__builtin_isfinite(ny2)) finish(L, 4);
-        else if (ny2 == 0.0) L.phase = PH_ZERO;
-        else L.thr2 = L.tol2 * ny2;
+    case PK_NORMY:
+        normy_step(L, t0.x);
         break;
-    }
+    case PK_NY_SETUP_B0:
+    case PK_NY_SETUP_C0:
+    case PK_NY_SETUP_G0:
+        normy_step(L, t0.x);
+        if (L.phase == PH_ZERO) {  // y == 0: x has been zeroed
+            L.relres_rec = L.relres_true = 0.0;
+            finish(L, 0);
+        } else if (L.phase == PH_RUN) {
+            if (k == PK_NY_SETUP_G0)
+                cocg_setup_step(L, t0.x, t1);
+            else
+                setup_step(L, t0.x, k == PK_NY_SETUP_B0);
+        }
+        break;
     case PK_ZERO:
         L.relres_rec = L.relres_true = 0.0;
         finish(L, 0);
@@ -164,9 +198,6 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist,
         break;
     case PK_SETUP_C1:
         L.matvecs++;
-        setup_step(L, t0.x, false);
-        break;
-    case PK_SETUP_C0:
         setup_step(L, t0.x, false);
         break;
     case PK_CONFIRM_B:
@@ -352,16 +383,8 @@ __device__ inline void apply_step(SolverState& L, d2 t0, d2 t1, ccg_hist* hist,
         break;
     }
     case PK_SETUP_G1:
-    case PK_SETUP_G0:
-        if (k == PK_SETUP_G1) L.matvecs++;
-        if (!__builtin_isfinite(t0.x)) { finish(L, 4); break; }
-        L.rr = t0.x;
-        L.relres_rec = relres(t0.x, L.ny2);
-        if (t0.x <= L.thr2) { L.phase = PH_CONFIRM; break; }
-        cocg_rho_step(L, t1);
-        if (L.phase == PH_DONE) break;
-        if (L.maxit <= 0) { finish(L, 1); break; }
-        L.phase = PH_RESTART;
+        L.matvecs++;
+        cocg_setup_step(L, t0.x, t1);
         break;
     case PK_CONFIRM_G:
         confirm_step(L, t0.x, false);

@@ -241,14 +241,20 @@ __global__ __launch_bounds__(kBlock) void k_norm_y(Args a, int q, int maxit, dou
 // Methods sharing the set-up kernels.
 enum Method { M_BICG = 0, M_CGNR = 1, M_COCG = 2, M_COCR = 3 };
 
-// Set-up when the caller says x0 = 0: x = 0, r = y (and r^ = y for BiCGSTAB;
-// COCG also needs the bilinear (r, r)).
+// First kernel of a solve when the caller says x0 = 0: the initial state
+// (every block builds the same record; block 0 publishes it), x = 0, r = y
+// (and r^ = p = y for BiCGSTAB), and the partials of ||y||^2 (= ||r||^2; COCG
+// also (r, r)), which the next kernel's step takes as both the norm of y and
+// the set-up sums.  x is zeroed whatever y holds: with a non-finite y the
+// solve ends with info 4 at the iterate x0 = 0.
 template <int M, class T = d2>
-__global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
+__global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q, int maxit, double tol2,
+                                                         int no_confirm)
 {
-    SOLVER_PROLOGUE();
-    const int ph = L.phase;
-    if (ph != PH_RUN && ph != PH_ZERO) { publish(a, q, L, PK_NONE, 0); return; }
+    __shared__ SolverState L;
+    __shared__ d2 lds[kMaxWaves];
+    if (threadIdx.x == 0) init_state(L, maxit, tol2, no_confirm);
+    __syncthreads();
     T* x = (T*)a.x;
     T* r = (T*)a.r;
     T* rh = (T*)a.rh;
@@ -256,20 +262,17 @@ __global__ __launch_bounds__(kBlock) void k_setup_x0zero(Args a, int q)
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
         stv(x, i, d2{0.0, 0.0});
-        if (ph == PH_RUN) {
-            const d2 yi = ldv(y, i);
-            stv(r, i, yi);
-            if (M == M_BICG) {
-                stv(rh, i, yi);
-                stv((T*)a.p, i, yi);  // first direction
-            }
-            v0.x += cabs2(yi);
-            if (M == M_COCG) v1 = cfma(yi, yi, v1);
+        const d2 yi = ldv(y, i);
+        stv(r, i, yi);
+        if (M == M_BICG) {
+            stv(rh, i, yi);
+            stv((T*)a.p, i, yi);  // first direction
         }
+        v0.x += cabs2(yi);
+        if (M == M_COCG) v1 = cfma(yi, yi, v1);
     }
-    if (ph == PH_ZERO) { publish(a, q, L, PK_ZERO, 0); return; }
     write_partials(v0, v1, a.part[q ^ 1], lds);
-    publish(a, q, L, M == M_BICG ? PK_SETUP_B0 : M == M_COCG ? PK_SETUP_G0 : PK_SETUP_C0,
+    publish(a, q, L, M == M_BICG ? PK_NY_SETUP_B0 : M == M_COCG ? PK_NY_SETUP_G0 : PK_NY_SETUP_C0,
             gridDim.x);
 }
 
@@ -1235,15 +1238,18 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     int q = 0;
     auto flip = [&q]() { const int cur = q; q ^= 1; return cur; };
 
-    k_norm_y<T><<<gE, kBlock, 0, s>>>(a, flip(), maxit, tol2, no_confirm);
-    if (flags & CCG_X0_ZERO)
-        k_setup_x0zero<M == M_COCR ? M_CGNR : M, T><<<gE, kBlock, 0, s>>>(a, flip());
-    else if (M == M_BICG)
-        launch_product<ROLE_SETUP_B, T, S3>(a, q, s);
-    else if (M == M_COCG)
-        launch_product<ROLE_SETUP_G, T, S3>(a, q, s);
-    else
-        launch_product<ROLE_SETUP_C, T, S3>(a, q, s);
+    if (flags & CCG_X0_ZERO) {
+        k_setup_x0zero<M == M_COCR ? M_CGNR : M, T>
+            <<<gE, kBlock, 0, s>>>(a, flip(), maxit, tol2, no_confirm);
+    } else {
+        k_norm_y<T><<<gE, kBlock, 0, s>>>(a, flip(), maxit, tol2, no_confirm);
+        if (M == M_BICG)
+            launch_product<ROLE_SETUP_B, T, S3>(a, q, s);
+        else if (M == M_COCG)
+            launch_product<ROLE_SETUP_G, T, S3>(a, q, s);
+        else
+            launch_product<ROLE_SETUP_C, T, S3>(a, q, s);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
 
     // Each slot advances the method by at most one iteration or one

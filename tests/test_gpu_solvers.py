@@ -150,3 +150,18 @@ def test_hist_and_result_fields(orc, method):
     finite_g = ~np.isnan(h[:k])
     finite_o = ~np.isnan(ref.hist[:k])
     assert np.array_equal(finite_g, finite_o)  # same fields produced
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "cgnr", "cocg", "cocr"])
+def test_x0_zero_with_special_y(orc, method):
+    """With the x0 = 0 flag the first kernel zeroes x, copies y and forms
+    ||y||^2: a non-finite y ends with info 4 at x = 0 (the last finite
+    iterate), y = 0 with info 0 and x = 0; neither spends a product."""
+    A, _, y = inputs.dense_system(96, 5)
+    ybad = y.copy()
+    ybad[11] = complex(np.inf, 0.0)
+    x, res, _ = gpu_solve(method, A, ybad)
+    assert res.info == 4 and res.iters == 0 and res.matvecs == 0 and np.all(x == 0)
+    assert getattr(orc, method)(A, ybad).info == 4
+    x, res, _ = gpu_solve(method, A, np.zeros(96, dtype=np.complex128))
+    assert res.info == 0 and res.iters == 0 and res.matvecs == 0 and np.all(x == 0)
