@@ -619,10 +619,9 @@ def profile_kernels(A, y):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single "
-              "MI355X (--gpus 1); a system larger than one GPU would be "
-              "row-sharded as described in DESIGN.md, not measured here.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1, one MI355X); a "
+              "system larger than one GPU would be row-sharded across GPUs, "
+              "which is not measured here.", file=sys.stderr)
         sys.exit(2)
     import torch
 
