@@ -108,15 +108,24 @@ __device__ __forceinline__ int status_word(int phase, double relres)
 // which follow vector kernels of at most 512 blocks, take 2 so that the
 // prologue does not set their register count (the A x loop needs 64 VGPRs,
 // occupancy 8 with 512-thread blocks).
+//
+// Two LDS records: Ls[0] holds the state as loaded, Ls[1] the state after the
+// pending step.  Thread 0 writes only Ls[1], so every thread's read of the
+// loaded record (the pending kind and block count that steer it through the
+// prologue) is free of that write even where no barrier separates them (the
+// first-wavefront path below); the barrier that ends the step orders the
+// write before any thread reads Ls[1].  Returns the record the kernel uses.
 template <int kInFlight = 8>
-__device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d2* lds)
+__device__ __forceinline__ SolverState& prologue(const Args& a, int q, SolverState* Ls, d2* lds)
 {
-    if (threadIdx.x == 0) L = *a.st[q];
+    if (threadIdx.x == 0) Ls[0] = *a.st[q];
     __syncthreads();
-    if (L.pending != PK_NONE) {
+    const int pending = Ls[0].pending;
+    SolverState* L = Ls;
+    if (pending != PK_NONE) {
         const d2 z = d2{0.0, 0.0};
         d2 t0 = z, t1 = z, t2 = z;
-        const int nb = L.pending_blocks;
+        const int nb = Ls[0].pending_blocks;
         if (nb <= kWave) {
             // at most one partial per thread, all in the first wavefront: the
             // totals are its sums plus +0 (the bits of the block-wide sum,
@@ -128,30 +137,33 @@ __device__ __forceinline__ void prologue(const Args& a, int q, SolverState& L, d
                     if (b < nb) {
                         a0 += a.part[q][2 * b];
                         a1 += a.part[q][2 * b + 1];
-                        if (L.pending == PK_T3) a2 += a.xpart[q][b];
+                        if (pending == PK_T3) a2 += a.xpart[q][b];
                     }
                     t0 = wave_sum(a0) + z;
                     t1 = wave_sum(a1) + z;
-                    if (L.pending == PK_T3) t2 = wave_sum(a2) + z;
+                    if (pending == PK_T3) t2 = wave_sum(a2) + z;
                 }
-                if (threadIdx.x == 0)
-                    apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
             }
         } else {
-            if (L.pending == PK_T3)
+            if (pending == PK_T3)
                 reduce_partials3<kInFlight == 8 ? 5 : kInFlight>(a.part[q], a.xpart[q], nb, lds,
                                                                 t0, t1, t2);
             else
                 reduce_partials<kInFlight>(a.part[q], nb, lds, t0, t1);
-            if (threadIdx.x == 0) apply_step(L, t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
+        }
+        if (threadIdx.x == 0) {
+            Ls[1] = Ls[0];
+            apply_step(Ls[1], t0, t1, blockIdx.x == 0 ? a.hist : nullptr, t2);
         }
         __syncthreads();
+        L = Ls + 1;
     }
     // the first kernel of a slot reports where the previous slot left the
     // method (a plain store to pinned host memory, system scope)
     if (a.status && blockIdx.x == 0 && threadIdx.x == 0)
-        __hip_atomic_store(a.status, status_word(L.phase, L.relres_rec), __ATOMIC_RELAXED,
+        __hip_atomic_store(a.status, status_word(L->phase, L->relres_rec), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
+    return *L;
 }
 
 // End of every solver kernel: block 0 writes the state for the next kernel,
@@ -167,16 +179,16 @@ __device__ __forceinline__ void publish(const Args& a, int q, const SolverState&
     }
 }
 
-#define SOLVER_PROLOGUE()                  \
-    __shared__ SolverState L;              \
-    __shared__ d2 lds[kMaxWaves];          \
-    prologue(a, q, L, lds)
+#define SOLVER_PROLOGUE()                           \
+    __shared__ SolverState Ls_[2];                  \
+    __shared__ d2 lds[kMaxWaves];                   \
+    SolverState& L = prologue(a, q, Ls_, lds)
 
 // The same for the product kernels (see prologue).
-#define PRODUCT_PROLOGUE()                 \
-    __shared__ SolverState L;              \
-    __shared__ d2 lds[kMaxWaves];          \
-    prologue<2>(a, q, L, lds)
+#define PRODUCT_PROLOGUE()                          \
+    __shared__ SolverState Ls_[2];                  \
+    __shared__ d2 lds[kMaxWaves];                   \
+    SolverState& L = prologue<2>(a, q, Ls_, lds)
 
 // --------------------------------------------------------- common kernels
 
