@@ -149,6 +149,25 @@ int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda,
                   const ccg_z* x, ccg_z* y, void* work, size_t work_bytes,
                   void* stream);
 
+/*
+ * As ccg_matvec, allocating nothing: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The partial sums of CCG_OP_C and CCG_OP_S go to a
+ * fixed device array of CCG_NOALLOC_SCRATCH_BYTES, one per GPU, held from the
+ * library's loading until the process ends; CCG_OP_N needs none.  Returns -2
+ * when n is out of range or its partials exceed that array (CCG_OP_C needs
+ * at most 16 n + 1 MiB bytes, so any n below 2^20; CCG_OP_S needs
+ * n * ceil(n / S) * 16 bytes for its tile edge S, so n <= 16384), with no
+ * work enqueued.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race.  The results are bitwise those of ccg_matvec.  Enqueued on stream,
+ * no wait.  Arguments as ccg_matvec: 1 op, 2 n, 3 A, 4 lda, 5 x, 6 y,
+ * 7 stream.
+ */
+#define CCG_NOALLOC_SCRATCH_BYTES (16u << 20)
+int ccg_matvec_noalloc(int op, int64_t n, const ccg_z* A, int64_t lda,
+                       const ccg_z* x, ccg_z* y, void* stream);
+
 /* Bytes of device workspace the _ex entry points need (256-byte aligned
  * start required).  nrhs is 1 for the single right-hand-side solvers. */
 size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs);

@@ -114,6 +114,7 @@ def load() -> ctypes.CDLL:
     S = ctypes.c_size_t
     lib.ccg_matvec.argtypes = [ctypes.c_int, I64, P, I64, P, P, P]
     lib.ccg_matvec_ex.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, S, P]
+    lib.ccg_matvec_noalloc.argtypes = [ctypes.c_int, I64, P, I64, P, P, P]
     lib.ccg_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
     lib.ccg_workspace_bytes.restype = S
     for name in ("ccg_bicgstab", "ccg_cgnr", "ccg_cocg", "ccg_cocr"):
@@ -249,6 +250,18 @@ def ccg_matvec_ex(op: int, A, x, y, work, stream=None):
     _check(load().ccg_matvec_ex(op, n, A.data_ptr(), lda, x.data_ptr(),
                                 y.data_ptr(), wp, wb, _stream(stream)),
            "ccg_matvec_ex")
+    return y
+
+
+def ccg_matvec_noalloc(op: int, A, x, y, stream=None):
+    """ccg_matvec with its partial sums in the library's fixed device array
+    (no allocation); returns y."""
+    n, lda = _mat(A)
+    _vec(x, n, "x")
+    _vec(y, n, "y")
+    _check(load().ccg_matvec_noalloc(op, n, A.data_ptr(), lda, x.data_ptr(),
+                                     y.data_ptr(), _stream(stream)),
+           "ccg_matvec_noalloc")
     return y
 
 

@@ -32,6 +32,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ccg.h"
@@ -1479,6 +1480,70 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
     return e == hipSuccess ? 0 : (int)e;
 }
 
+// --------------------------------------------- allocation-free products
+//
+// ccg_matvec_noalloc: the products of ccg_matvec for callers that cannot
+// allocate device memory.  The partial sums of the A^H x band walk and of the
+// upper-triangle tiles go to a fixed device array instead of a stream-ordered
+// allocation.  Every GPU holds its own copy of a __device__ array (the loader
+// places one per device) until the process ends; host code never passes the
+// array's name to a kernel (on the host that name is a stand-in, not a device
+// address) but the address hipGetSymbolAddress returns for the current
+// device, looked up once per device on the first call there.  Both partial
+// kinds are written in full before they are read (every band or tile writes
+// its partial of every element it covers), so nothing needs clearing between
+// calls; calls that overlap on one GPU share the array and race.
+constexpr size_t kNoAllocScratchBytes = (size_t)CCG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device.
+static int noalloc_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!ptr) return (int)hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+// Bytes of partial sums a product of kind op needs at size n (0 for A x).
+static size_t noalloc_need(int op, int64_t n)
+{
+    if (op == CCG_OP_C) {
+        const GemvCShape sh = gemv_c_shape(n);
+        return (size_t)sh.nbands * (size_t)n * sizeof(d2);
+    }
+    if (op == CCG_OP_S) return sym_part_bytes(n);
+    return 0;
+}
+
+static int matvec_noalloc_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
+                               ccg_z* y, void* stream)
+{
+    if (op != CCG_OP_N && op != CCG_OP_C && op != CCG_OP_S) return -1;
+    if (n < 0 || n > kMaxN) return -2;
+    if (n == 0 || op == CCG_OP_N)
+        return matvec_impl(op, n, A, lda, x, y, nullptr, 0, stream, false);
+    if (noalloc_need(op, n) > kNoAllocScratchBytes) return -2;  // beyond the fixed array
+    void* ptr = nullptr;
+    const int rc = noalloc_scratch(&ptr);
+    if (rc) return rc;
+    return matvec_impl(op, n, A, lda, x, y, ptr, kNoAllocScratchBytes, stream, false);
+}
+
 // ------------------------------------------------------- mixed precision
 //
 // FP64 iterative refinement around an inner complex64 BiCGSTAB (the single /
@@ -1915,6 +1980,12 @@ int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x
                   void* work, size_t work_bytes, void* stream)
 {
     return ccg::matvec_impl(op, n, A, lda, x, y, work, work_bytes, stream, false);
+}
+
+int ccg_matvec_noalloc(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
+                       ccg_z* y, void* stream)
+{
+    return ccg::matvec_noalloc_impl(op, n, A, lda, x, y, stream);
 }
 
 int ccg_bicgstab(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x, double tol,

@@ -234,3 +234,20 @@ def test_bench_refuses_more_than_one_gpu():
                           capture_output=True, text=True, timeout=120)
     assert proc.returncode == 2
     assert "one GPU" in proc.stderr
+
+
+def test_noalloc_product_rejects_sizes_beyond_its_array_on_the_host(lib):
+    """ccg_matvec_noalloc refuses, before any HIP call, a product whose
+    partial sums would not fit its fixed device array (CCG_OP_S beyond
+    n = 16384, CCG_OP_C from n = 2^20 on), an unknown op and a negative n."""
+    P = ctypes.c_void_p
+    dummy = P(256)  # never dereferenced: the checks fail first
+    fn = lib.ccg_matvec_noalloc
+    assert fn(7, 4, dummy, 4, dummy, P(512), None) == -1
+    assert fn(0, -1, dummy, 4, dummy, P(512), None) == -2
+    assert fn(2, 16385, dummy, 16385, dummy, P(512), None) == -2
+    assert fn(2, 40000, dummy, 40000, dummy, P(512), None) == -2
+    assert fn(1, 1 << 21, dummy, 1 << 21, dummy, P(512), None) == -2
+    assert fn(1, (1 << 30) + 1, dummy, (1 << 30) + 1, dummy, P(512), None) == -2
+    # n = 0 is a no-op
+    assert fn(1, 0, None, 1, None, None, None) == 0
