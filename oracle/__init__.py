@@ -115,6 +115,11 @@ class Oracle:
             ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
             ctypes.POINTER(_MixedStats), P]
         self.lib.oracle_bicgstab_mixed.restype = ctypes.c_int
+        self.lib.oracle_bicgstab_mixed_wide.argtypes = \
+            self.lib.oracle_bicgstab_mixed.argtypes
+        self.lib.oracle_bicgstab_mixed_wide.restype = ctypes.c_int
+        self.lib.oracle_matvec_c64_wide.argtypes = [I64, P, I64, P, P]
+        self.lib.oracle_matvec_c64_wide.restype = None
         for name in ("oracle_matvec", "oracle_matvec_h", "oracle_matvec_sym_upper"):
             f = getattr(self.lib, name)
             f.argtypes = [I64, P, I64, P, P]
@@ -210,10 +215,45 @@ class Oracle:
                                    x.ctypes.data, y.ctypes.data)
         return y
 
+    def matvec_c64_wide(self, A32, x):
+        """The complex64 product of a complex128 vector (x rounded to
+        complex64, FP32 row sums widened to complex128)."""
+        A32 = np.asarray(A32)
+        if A32.dtype != np.complex64 or A32.strides[1] != 8:
+            raise TypeError("A32 must be a row-major complex64 matrix")
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.empty(A32.shape[0], dtype=np.complex128)
+        self.lib.oracle_matvec_c64_wide(A32.shape[0], A32.ctypes.data, A32.strides[0] // 8,
+                                        x.ctypes.data, y.ctypes.data)
+        return y
+
     def bicgstab_mixed(self, A, y, A32=None, x0=None, tol=1e-10, maxit=10,
                        tol_inner=1e-5, maxit_inner=1000):
         """FP64 refinement around an inner complex64 BiCGSTAB.  A32 defaults
         to A rounded to complex64."""
+        return self._mixed(self.lib.oracle_bicgstab_mixed, A, y, A32, x0, tol, maxit,
+                           tol_inner, maxit_inner)
+
+    def bicgstab_mixed_wide(self, A, y, A32=None, x0=None, tol=1e-10, maxit=10,
+                            tol_inner=1e-5, maxit_inner=1000):
+        """FP64 refinement around an inner BiCGSTAB whose Krylov vectors stay
+        complex128 and whose products are complex64 (the form of the solver
+        for many right-hand sides)."""
+        return self._mixed(self.lib.oracle_bicgstab_mixed_wide, A, y, A32, x0, tol, maxit,
+                           tol_inner, maxit_inner)
+
+    def bicgstab_block_mixed(self, A, Y, A32=None, X0=None, tol=1e-10, maxit=10,
+                             tol_inner=1e-5, maxit_inner=1000, cols=None):
+        """Each column of Y by its own bicgstab_mixed_wide (per-column
+        refinement decisions); cols selects a subset."""
+        Y = np.asarray(Y)
+        cols = range(Y.shape[1]) if cols is None else cols
+        if A32 is None:
+            A32 = np.asarray(A).astype(np.complex64)
+        return [self.bicgstab_mixed_wide(A, Y[:, c], A32, None if X0 is None else X0[:, c],
+                                         tol, maxit, tol_inner, maxit_inner) for c in cols]
+
+    def _mixed(self, fn, A, y, A32, x0, tol, maxit, tol_inner, maxit_inner):
         A, lda = self._mat(A)
         n = A.shape[0]
         if A32 is None:
@@ -228,7 +268,7 @@ class Oracle:
             x = np.array(x0, dtype=np.complex128, copy=True)
         outer_res = np.full(max(maxit, 0) + 1, np.nan)
         st = _MixedStats()
-        rc = self.lib.oracle_bicgstab_mixed(
+        rc = fn(
             n, A.ctypes.data, lda, A32.ctypes.data, max(n, 1), y.ctypes.data,
             x.ctypes.data, float(tol), int(maxit), float(tol_inner),
             int(maxit_inner), flags, ctypes.byref(st), outer_res.ctypes.data)

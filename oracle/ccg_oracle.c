@@ -26,7 +26,10 @@
  *     complex64 BiCGSTAB -- the single/double precision switch of the
  *     ddprecision module (Abstract; Usage section) used inside one solve.
  *     The inner products accumulate in FP32; the inner dot products and
- *     scalars are FP64; the outer residual and update are FP64.
+ *     scalars are FP64; the outer residual and update are FP64.  A second
+ *     form keeps the inner Krylov vectors in complex128 (the form the solver
+ *     for many right-hand sides uses): only the product is complex64, its
+ *     input rounded to complex64 and its FP32 sums widened back.
  *   - CG: Hestenes-Stiefel conjugate gradients for Hermitian positive-definite
  *     A.  Not in the paper's list; kept only as a pinned reference that other
  *     tests compare CGNR and BiCGSTAB against.
@@ -956,11 +959,192 @@ int oracle_bicgstab_mixed(int64_t n, const zc* A, int64_t lda, const fc* A32, in
             st->info = 4;
             break;
         }
+        if ((info_in == 2 || info_in == 3) && it == 0) {
+            /* breakdown before the first inner update: d = 0, and the next
+             * step would repeat this one exactly */
+            st->info = info_in;
+            break;
+        }
         for (int64_t i = 0; i < n; ++i)
             x[i] = x[i] + nr * (zc)d32[i];
     }
     free(r);
     free(f);
+    return 0;
+}
+
+/* ----------------------------------- mixed precision, FP64 inner vectors */
+
+/* The complex64 product applied to a complex128 vector: x rounded to
+ * complex64, each row summed left to right in FP32, the sum widened to
+ * complex128 (the inner product of the mixed solver for many right-hand
+ * sides, whose Krylov vectors stay complex128). */
+void oracle_matvec_c64_wide(int64_t n, const fc* A, int64_t lda, const zc* x, zc* y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        fc s = 0.0f;
+        for (int64_t j = 0; j < n; ++j)
+            s += A[i * lda + j] * (fc)x[j];
+        y[i] = (zc)s;
+    }
+}
+
+/* Inner BiCGSTAB for A32 d = b from d = 0: the steps of oracle_bicgstab on
+ * complex128 vectors with FP64 dot products and scalars, every product
+ * oracle_matvec_c64_wide, stop on the recursive residual (no confirmation).
+ * Returns info; *iters, *matvecs. */
+static int inner_bicgstab_wide(int64_t n, const fc* A, int64_t lda, const zc* b, zc* x,
+                               double tol, int32_t maxit, int32_t* iters, int32_t* matvecs,
+                               zc* w)
+{
+    zc *r = w, *rh = r + n, *p = rh + n, *v = p + n, *s = v + n, *t = s + n;
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = 0.0;
+        r[i] = b[i];
+        rh[i] = b[i];
+    }
+    const double nb2 = norm2sq(n, b);
+    const double thr2 = tol * tol * nb2;
+    double rr = nb2, rh2 = nb2;
+    zc rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int first = 1;
+    int32_t k = 0;
+    *iters = 0;
+    if (!isfinite(rr)) return 4;
+    if (rr <= thr2) return 0;
+    while (k < maxit) {
+        zc rho = dotc(n, rh, r);
+        if (!zfinite(rho)) return 4;
+        if (abs2(rho) <= 1e-28 * rh2 * rr) return 2;
+        if (first) {
+            zcopy(n, r, p);
+            first = 0;
+        } else {
+            zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);
+            if (!zfinite(beta)) return 4;
+            for (int64_t i = 0; i < n; ++i)
+                p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        oracle_matvec_c64_wide(n, A, lda, p, v);
+        (*matvecs)++;
+        zc sigma = dotc(n, rh, v);
+        double vv = norm2sq(n, v);
+        if (!zfinite(sigma) || !isfinite(vv)) return 4;
+        if (abs2(sigma) <= 1e-28 * rh2 * vv) return 2;
+        alpha = zdiv(rho, sigma);
+        if (!zfinite(alpha)) return 4;
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        double ss = norm2sq(n, s);
+        if (!isfinite(ss)) return 4;
+        if (ss <= thr2) {
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            *iters = k + 1;
+            return 0;
+        }
+        oracle_matvec_c64_wide(n, A, lda, s, t);
+        (*matvecs)++;
+        double tt = norm2sq(n, t);
+        zc ts = dotc(n, t, s);
+        if (!isfinite(tt) || !zfinite(ts)) return 4;
+        if (tt == 0.0) return 3;
+        omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);
+        if (omega == 0.0) return 3;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        rr = norm2sq(n, r);
+        k++;
+        *iters = k;
+        if (!isfinite(rr)) return 4;
+        rho_old = rho;
+        if (rr <= thr2) return 0;
+    }
+    return 1;
+}
+
+/* FP64 iterative refinement as oracle_bicgstab_mixed, with the inner solve
+ * keeping its Krylov vectors in complex128: r = y - A x (FP64, complex128 A);
+ * stop when ||r|| <= tol ||y|| (info 0) or after maxit steps (info 1);
+ * otherwise solve A32 d = r / ||r|| (the scaling in FP64, no rounding of the
+ * right-hand side) with inner_bicgstab_wide to tol_inner, and set
+ * x += ||r|| d in FP64.  An inner non-finite value ends the refinement with
+ * info 4, an inner breakdown before the first inner update (d = 0) with the
+ * inner info 2 or 3; x is then left as it was.  outer_res (maxit + 1 entries
+ * or NULL) receives ||r|| / ||y|| at every outer check. */
+int oracle_bicgstab_mixed_wide(int64_t n, const zc* A, int64_t lda, const fc* A32,
+                               int64_t lda32, const zc* y, zc* x, double tol, int32_t maxit,
+                               double tol_inner, int32_t maxit_inner, uint32_t flags,
+                               oracle_mixed_stats* st, double* outer_res)
+{
+    memset(st, 0, sizeof *st);
+    st->relres_true = NAN;
+    if (n < 0) return -1;
+    if (lda < (n > 1 ? n : 1) || lda32 < (n > 1 ? n : 1)) return -3;
+    if (!(tol > 0.0) || !isfinite(tol) || maxit < 0) return -6;
+    if (!(tol_inner > 0.0) || !(tol_inner < 1.0) || maxit_inner < 1) return -10;
+    if (n == 0) {
+        st->relres_true = 0.0;
+        return 0;
+    }
+    double ny2 = norm2sq(n, y);
+    if (!isfinite(ny2)) {
+        st->info = 4;
+        return 0;
+    }
+    if (ny2 == 0.0) {
+        zzero(n, x);
+        st->relres_true = 0.0;
+        return 0;
+    }
+    zc* w = (zc*)malloc(sizeof(zc) * (size_t)(9 * n));
+    if (!w) return -100;
+    zc *r = w, *b = w + n, *d = w + 2 * n, *inner = w + 3 * n;
+    const double thr2 = tol * tol * ny2;
+    for (int32_t outer = 0;; ++outer) {
+        if (outer == 0 && (flags & ORACLE_X0_ZERO)) {
+            zzero(n, x);
+            zcopy(n, y, r);
+        } else {
+            residual(n, A, lda, y, x, r);
+            st->matvecs64++;
+        }
+        double rr = norm2sq(n, r);
+        st->relres_true = sqrt(rr / ny2);
+        if (outer_res) outer_res[outer] = st->relres_true;
+        if (!isfinite(rr)) {
+            st->info = 4;
+            break;
+        }
+        if (rr <= thr2) {
+            st->info = 0;
+            break;
+        }
+        if (outer >= maxit) {
+            st->info = 1;
+            break;
+        }
+        const double nr = sqrt(rr);
+        const double scale = 1.0 / nr;
+        for (int64_t i = 0; i < n; ++i)
+            b[i] = CMPLX(creal(r[i]) * scale, cimag(r[i]) * scale);
+        int32_t it = 0;
+        int info_in = inner_bicgstab_wide(n, A32, lda32, b, d, tol_inner, maxit_inner, &it,
+                                          &st->matvecs32, inner);
+        st->outer++;
+        st->inner_iters += it;
+        if (info_in == 4) {
+            st->info = 4;
+            break;
+        }
+        if ((info_in == 2 || info_in == 3) && it == 0) {
+            st->info = info_in;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = x[i] + CMPLX(nr * creal(d[i]), nr * cimag(d[i]));
+    }
+    free(w);
     return 0;
 }
 

@@ -807,4 +807,96 @@ def pin_mixed_trivial(orc):
     assert r.info == 1 and r.outer == 0 and r.relres_true == 1.0
 
 
+def pin_mixed_inner_breakdown_ends_refinement(orc):
+    """Both refinement forms: an inner breakdown before the first inner update
+    leaves d = 0, so the refinement ends with that inner info instead of
+    repeating the same step until its budget.  The rotation A = [[0, 1],
+    [-1, 0]] with y = e1 gives sigma = r^H A r = 0 exactly at the first inner
+    iteration (info 2, x = 0); from x0 = (1/2, 1/2) the residual is (1, 1)/2
+    and sigma is again exactly zero (x left at x0)."""
+    A = np.array([[0, 1], [-1, 0]], dtype=np.complex128)
+    y = np.array([1, 0], dtype=np.complex128)
+    x0 = np.array([0.5, 0.5], dtype=np.complex128)
+    for fn in (orc.bicgstab_mixed, orc.bicgstab_mixed_wide):
+        r = fn(A, y, maxit=10)
+        assert (r.info, r.outer, r.inner_iters) == (2, 1, 0) and np.all(r.x == 0)
+        r = fn(A, y, x0=x0, maxit=10)
+        assert (r.info, r.outer, r.inner_iters) == (2, 1, 0) and np.array_equal(r.x, x0)
+
+
+def pin_mixed_scaled_identity(orc):
+    """A = c I with c exact in complex64, both refinement forms: every inner
+    solve leaves at the half step of its first iteration (the complex64
+    product is c times the input up to FP32 rounding), so each refinement step
+    gains a factor of about 2^-24: two steps reach 1e-10, with two complex64
+    and two FP64 products, and x = y / c to FP64 rounding."""
+    c = 2.0 - 3.0j
+    A = c * np.eye(40, dtype=np.complex128)
+    y = inputs.cn01(np.random.default_rng(51), 40)
+    for fn in (orc.bicgstab_mixed, orc.bicgstab_mixed_wide):
+        r = fn(A, y)
+        assert r.info == 0 and (r.outer, r.inner_iters, r.matvecs32, r.matvecs64) == \
+            (2, 2, 2, 2), (r.outer, r.inner_iters, r.matvecs32, r.matvecs64)
+        assert r.outer_res[1] <= 1e-6 and r.relres_true <= 1e-13
+        assert relerr(r.x, y / c) <= 1e-13
+
+
+# -------------------------------- mixed precision, complex128 inner vectors
+
+def pin_mixed_wide_matvec_integer_exact(orc):
+    """The complex64 product of a complex128 vector on small Gaussian
+    integers: the vector rounds to itself, every FP32 partial sum is an
+    integer below 2^24, so the widened result equals the exact integer
+    product (a non-symmetric A also fixes the orientation)."""
+    for n, seed in ((1, 0), (9, 1), (40, 2)):
+        A = inputs.gaussian_integer_matrix(n, seed, bound=16)
+        x = inputs.gaussian_integer_vector(n, seed + 7, bound=16)
+        want = exact_matvec_int(A, x)
+        got = orc.matvec_c64_wide(A.astype(np.complex64), x)
+        assert got.dtype == np.complex128 and np.array_equal(got, want), n
+
+
+def pin_mixed_wide_solution(orc):
+    """The complex128-vector refinement reaches the FP64 tolerance: true
+    residual <= 1e-10 and the LU solution within the conditioning bound."""
+    systems = [inputs.lattice_matrix(5), inputs.lattice_matrix(6),
+               inputs.dense_matrix(64, 12), inputs.dense_matrix(3, 2)]
+    rng = np.random.default_rng(52)
+    for A in systems:
+        y = inputs.cn01(rng, A.shape[0])
+        r = orc.bicgstab_mixed_wide(A, y)
+        assert r.info == 0 and r.relres_true <= 1e-10 and r.outer <= 4
+        kappa = np.linalg.cond(A)
+        assert relerr(r.x, lu_solve(A, y)) <= 10 * kappa * 1e-10
+
+
+def pin_mixed_wide_refinement_contracts(orc):
+    """Each refinement step multiplies the FP64 residual by about the inner
+    tolerance (plus kappa times the complex64 rounding of A and of the
+    product's input)."""
+    A = inputs.lattice_matrix(6)
+    y = inputs.cn01(np.random.default_rng(53), A.shape[0])
+    for tin, bound in ((1e-5, 1e-4), (1e-3, 1e-2)):
+        r = orc.bicgstab_mixed_wide(A, y, tol=1e-12, tol_inner=tin)
+        res = r.outer_res[:r.outer + 1]
+        assert r.info == 0 and len(res) >= 2
+        assert np.all(res[1:] <= bound * res[:-1]), res
+
+
+def pin_mixed_wide_trivial(orc):
+    """Non-finite y: info 4 with x as given; y = 0: x = 0 with no step;
+    maxit = 0: info 1 after the first check."""
+    A = inputs.lattice_matrix(3)
+    y = inputs.cn01(np.random.default_rng(54), 27)
+    x0 = np.full(27, 1.0 + 1.0j)
+    ybad = y.copy()
+    ybad[4] = np.nan
+    r = orc.bicgstab_mixed_wide(A, ybad, x0=x0)
+    assert r.info == 4 and np.array_equal(r.x, x0)
+    r = orc.bicgstab_mixed_wide(A, np.zeros(27, dtype=np.complex128), x0=x0)
+    assert r.info == 0 and np.all(r.x == 0) and r.outer == 0
+    r = orc.bicgstab_mixed_wide(A, y, maxit=0)
+    assert r.info == 1 and r.outer == 0 and r.relres_true == 1.0
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

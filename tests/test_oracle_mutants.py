@@ -18,15 +18,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MUTANTS = [
     ("beta_drops_alpha_over_omega",
      "zc beta = zdiv(rho, rho_old) * zdiv(alpha, omega);",
-     "zc beta = zdiv(rho, rho_old);", 2),
+     "zc beta = zdiv(rho, rho_old);", 3),
     ("omega_conjugated",
      "omega = CMPLX(creal(ts) / tt, cimag(ts) / tt);",
-     "omega = CMPLX(creal(ts) / tt, -cimag(ts) / tt);", 2),
+     "omega = CMPLX(creal(ts) / tt, -cimag(ts) / tt);", 3),
     ("p_update_sign",
      "p[i] = r[i] + beta * (p[i] - omega * v[i]);",
-     "p[i] = r[i] + beta * (p[i] + omega * v[i]);", 1),
+     "p[i] = r[i] + beta * (p[i] + omega * v[i]);", 2),
     ("s_update_sign",
-     "s[i] = r[i] - alpha * v[i];", "s[i] = r[i] + alpha * v[i];", 1),
+     "s[i] = r[i] - alpha * v[i];", "s[i] = r[i] + alpha * v[i];", 2),
     ("adjoint_without_conj",
      "y[j] += conj(A[i * lda + j]) * xi;", "y[j] += A[i * lda + j] * xi;", 1),
     ("cgnr_beta_inverted",
@@ -37,24 +37,24 @@ MUTANTS = [
     ("dot_unconjugated",
      "s += conj(a[i]) * b[i];", "s += a[i] * b[i];", 1),
     ("stop_test_not_squared",
-     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 6),
+     "const double thr2 = tol * tol * ny2;", "const double thr2 = tol * ny2;", 7),
     ("residual_sign",
      "rt[i] = y[i] - rt[i];", "rt[i] = y[i] + rt[i];", 1),
     ("division_without_conj",
      "zc q = a * conj(b);", "zc q = a * b;", 1),
     ("x_update_drops_omega_s",
      "x[i] = x[i] + alpha * p[i] + omega * s[i];", "x[i] = x[i] + alpha * p[i];",
-     1),
+     2),
     ("r_update_wrong_vector",
-     "r[i] = s[i] - omega * t[i];", "r[i] = s[i] - omega * s[i];", 1),
+     "r[i] = s[i] - omega * t[i];", "r[i] = s[i] - omega * s[i];", 2),
     ("cgnr_p_update_drops_beta",
      "p[i] = z[i] + beta * p[i];", "p[i] = z[i];", 1),
     ("rho_without_shadow",
-     "rho = dotc(n, rh, r);", "rho = dotc(n, r, r);", 1),
+     "rho = dotc(n, rh, r);", "rho = dotc(n, r, r);", 2),
     ("sigma_without_shadow",
-     "zc sigma = dotc(n, rh, v);", "zc sigma = dotc(n, r, v);", 1),
+     "zc sigma = dotc(n, rh, v);", "zc sigma = dotc(n, r, v);", 2),
     ("ts_operands_swapped",
-     "zc ts = dotc(n, t, s);", "zc ts = dotc(n, s, t);", 1),
+     "zc ts = dotc(n, t, s);", "zc ts = dotc(n, s, t);", 2),
     ("norm_drops_imaginary",
      "s += creal(v[i]) * creal(v[i]) + cimag(v[i]) * cimag(v[i]);",
      "s += creal(v[i]) * creal(v[i]);", 1),
@@ -82,7 +82,7 @@ MUTANTS = [
     ("mixed_update_unscaled",
      "x[i] = x[i] + nr * (zc)d32[i];", "x[i] = x[i] + (zc)d32[i];", 1),
     ("mixed_residual_not_normalised",
-     "const double scale = 1.0 / nr;", "const double scale = 1.0;", 1),
+     "const double scale = 1.0 / nr;", "const double scale = 1.0;", 2),
     ("c64_product_transposed",
      "s += A[i * lda + j] * x[j];\n        y[i] = s;\n    }\n}\n\nstatic double norm2sq_c64",
      "s += A[j * lda + i] * x[j];\n        y[i] = s;\n    }\n}\n\nstatic double norm2sq_c64", 1),
@@ -95,6 +95,14 @@ MUTANTS = [
     ("sym_diagonal_dropped",
      "for (int64_t j = i; j < n; ++j)\n            s += A[i * lda + j] * x[j];",
      "for (int64_t j = i + 1; j < n; ++j)\n            s += A[i * lda + j] * x[j];", 1),
+    ("wide_product_transposed",
+     "s += A[i * lda + j] * (fc)x[j];", "s += A[j * lda + i] * (fc)x[j];", 1),
+    ("wide_update_unscaled",
+     "x[i] = x[i] + CMPLX(nr * creal(d[i]), nr * cimag(d[i]));", "x[i] = x[i] + d[i];", 1),
+    ("wide_rhs_not_normalised",
+     "b[i] = CMPLX(creal(r[i]) * scale, cimag(r[i]) * scale);", "b[i] = r[i];", 1),
+    ("inner_breakdown_ignored",
+     "if ((info_in == 2 || info_in == 3) && it == 0) {", "if (0) {", 2),
 ]
 
 
