@@ -168,6 +168,91 @@ int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda,
 int ccg_matvec_noalloc(int op, int64_t n, const ccg_z* A, int64_t lda,
                        const ccg_z* x, ccg_z* y, void* stream);
 
+/*
+ * Many small systems at once: BiCGSTAB (method CCG_WS_BICGSTAB) or CGNR
+ * (CCG_WS_CGNR) on batch independent dense systems A_b x_b = y_b of one size
+ * n <= CCG_SMALL_MAX_N (the problem "Ax = y" of the Introduction, solved by
+ * section 2.1's bicgstab and cgnr for many right-hand sides and matrices at
+ * once).  Same methods, stop rule, confirmation, restart and info codes as
+ * ccg_bicgstab_ex / ccg_cgnr_ex; every system takes its own decisions, and
+ * its result does not depend on the rest of the batch (bitwise).  One
+ * workgroup per system runs its whole solve inside one kernel launch, with
+ * the Krylov vectors in LDS, so a batch is one launch bound by the HBM
+ * stream of the matrices.
+ * Layout: system b's matrix at A + b * strideA (row-major, lda >= n), its
+ * right-hand side at Y + b * strideY and its x at X + b * strideX (n
+ * contiguous elements each; strides are in elements and only checked when
+ * batch > 1).  X holds the initial guesses (ignored under CCG_X0_ZERO).
+ * res: device array of batch ccg_result, written by the kernel.  All
+ * pointers are device pointers.  Asynchronous: nothing is waited for, res
+ * is valid once the stream has passed the launch.
+ * Arguments: 1 method, 2 n (0..CCG_SMALL_MAX_N), 3 batch >= 0, 4 A, 5 lda,
+ * 6 strideA >= (n - 1) lda + n, 7 Y, 8 strideY >= n, 9 X, 10 strideX >= n,
+ * 11 tol (> 0, finite), 12 maxit >= 0, 13 flags (CCG_X0_ZERO or 0), 14 res,
+ * 15 stream.
+ */
+#define CCG_SMALL_MAX_N 1024
+int ccg_solve_small_batched(int method, int64_t n, int64_t batch,
+                            const ccg_z* A, int64_t lda, int64_t strideA,
+                            const ccg_z* Y, int64_t strideY, ccg_z* X,
+                            int64_t strideX, double tol, int32_t maxit,
+                            uint32_t flags, ccg_result* res, void* stream);
+
+/*
+ * Measurement aid, outside the method: HIP events around the solvers' dense
+ * complex128 products, so that a caller can time the product kernel inside
+ * its solves (the A x that dominates their bytes) rather than apart from
+ * them.  events holds 2 * capacity hipEvent_t (as void*) created by the
+ * caller with timing enabled; count is the number of (start, end) pairs
+ * recorded so far and seen the number of products counted while attached,
+ * both advanced by the library.  While a log is attached, the dense
+ * complex128 A x launches of ccg_bicgstab*, ccg_cgnr*, ccg_cocg* and
+ * ccg_cocr* that the calling host thread makes, of the kinds in the mask
+ * roles (CCG_PROD_*; 0: every kind), are counted, and every stride-th of
+ * them (seen % stride == 0; stride <= 1: all) is bracketed by
+ * hipEventRecord(events[2 count]) and hipEventRecord(events[2 count + 1]) on
+ * the solve's stream, until capacity pairs are used.  (Each record costs a
+ * few microseconds of stream time; a stride spreads a few samples over many
+ * solves.)  The log is per host thread; the library keeps the pointer until
+ * ccg_set_event_log(NULL), so the caller keeps the struct alive until then.
+ * Returns -1 for a negative capacity or a null events array with
+ * capacity > 0.
+ */
+typedef struct {
+    void** events;    /* 2 * capacity hipEvent_t, caller-created and -owned */
+    int32_t capacity; /* event pairs */
+    int32_t count;    /* pairs recorded; advanced by the library */
+    int32_t stride;   /* record every stride-th counted product (<= 1: each) */
+    int32_t seen;     /* products counted while attached; advanced by the library */
+    uint32_t roles;   /* CCG_PROD_* mask of the products counted; 0: all */
+    int32_t pad;
+} ccg_event_log;
+/* Kinds of the solvers' dense products (ccg_event_log.roles). */
+enum {
+    CCG_PROD_SETUP = 1, /* set-up residuals y - A x */
+    CCG_PROD_V = 2,     /* BiCGSTAB v = A p, and its confirming residuals */
+    CCG_PROD_T = 4,     /* BiCGSTAB t = A s */
+    CCG_PROD_W = 8,     /* CGNR w = A p, and its confirming residuals */
+    CCG_PROD_Q = 16,    /* COCG q = A p, and its confirming residuals */
+    CCG_PROD_U = 32     /* COCR u = A r, and its confirming residuals */
+};
+int ccg_set_event_log(ccg_event_log* log);
+
+/*
+ * Measurement aid, outside the method: one pass that reads bytes bytes at src
+ * (device; 16-byte aligned, bytes a multiple of 16) with the 16-byte
+ * nontemporal loads the products use, and nothing else -- the HBM read rate
+ * the chip delivers to that load pattern, beside which the products' rates
+ * are set.  One block per slab of CCG_READ_STREAM_SLAB bytes writes the
+ * 16-byte sum of what it read to out (device, 16-byte aligned, out_bytes >=
+ * 16 * ceil(bytes / CCG_READ_STREAM_SLAB)), so no load can be dropped.
+ * Asynchronous on stream.  Returns -1 null src, -2 misaligned src or bytes,
+ * -3 bad out, -4 out too small.
+ */
+#define CCG_READ_STREAM_SLAB 262144
+int ccg_read_stream(const void* src, size_t bytes, void* out, size_t out_bytes,
+                    void* stream);
+
 /* Bytes of device workspace the _ex entry points need (256-byte aligned
  * start required).  nrhs is 1 for the single right-hand-side solvers. */
 size_t ccg_workspace_bytes(int method, int64_t n, int64_t nrhs);
@@ -243,20 +328,25 @@ int ccg_cocr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y,
  * alpha / omega / beta / rho scalars stay FP64) to the relative tolerance
  * tol_inner, stopping on its recursive residual, and applies x += ||r|| d in
  * FP64.  The outer loop stops when the FP64 true residual meets tol (info 0)
- * or after maxit steps (info 1); an inner breakdown or budget only ends that
- * inner solve.  A32 is the complex64 copy of A (ccg_round_c64), lda32 >= n.
+ * or after maxit steps (info 1).  An inner budget or a later inner breakdown
+ * only ends that inner solve; an inner non-finite value ends the refinement
+ * with info 4, and an inner breakdown before the first inner update (d = 0,
+ * so the next step would repeat this one) ends it with the inner info 2 or
+ * 3; x is then left as it was.  A32 is the complex64 copy of A
+ * (ccg_round_c64), lda32 >= n.
  * Arguments: 1 n, 2 A, 3 lda, 4 A32, 5 lda32, 6 y, 7 x, 8 tol, 9 maxit
  * (outer steps), 10 tol_inner (0 < tol_inner < 1), 11 maxit_inner >= 1,
  * 12 flags (CCG_X0_ZERO or 0), 13 work, 14 work_bytes (>=
- * ccg_workspace_bytes(CCG_WS_BICGSTAB_MIXED, n, 1)), 15 res (host), 16 stream.
- * Waits on stream.
+ * ccg_workspace_bytes(CCG_WS_BICGSTAB_MIXED, n, 1)), 15 res (host),
+ * 16 outer_res (host array of maxit + 1 doubles or NULL: ||r|| / ||y|| at
+ * every outer check, NaN past the last), 17 stream.  Waits on stream.
  */
 int ccg_bicgstab_mixed_ex(int64_t n, const ccg_z* A, int64_t lda,
                           const ccg_c* A32, int64_t lda32, const ccg_z* y,
                           ccg_z* x, double tol, int32_t maxit, double tol_inner,
                           int32_t maxit_inner, uint32_t flags, void* work,
                           size_t work_bytes, ccg_mixed_result* res,
-                          void* stream);
+                          double* outer_res, void* stream);
 
 /* y = A x in complex64, the inner product of the mixed-precision solver: each
  * lane accumulates in FP32 with fused multiply-adds, lanes and wavefronts are
@@ -336,13 +426,16 @@ int ccg_matmat_c64(int64_t n, int64_t k, const ccg_c* A32, int64_t lda32,
  * (ccg_matmat_c64) to tol_inner (recursive residual) and takes
  * X += ||R|| D in FP64.  The inner Krylov vectors stay complex128 (O(n k)
  * bytes; the complex64 copy halves the O(n^2) bytes of A).  Per column: info
- * 0 within tol, 1 after maxit outer steps, 4 non-finite (x left as given);
+ * 0 within tol, 1 after maxit outer steps, 4 non-finite (x left as given),
+ * and the inner-breakdown rule of ccg_bicgstab_mixed_ex (info 4, 2 or 3);
  * y = 0 gives x = 0.  Arguments: 1 n, 2 k, 3 A, 4 lda, 5 A32, 6 lda32, 7 Y,
  * 8 ldy >= k, 9 X, 10 ldx >= k, 11 tol, 12 maxit (outer), 13 tol_inner
  * (0 < tol_inner < 1), 14 maxit_inner >= 1, 15 flags (CCG_X0_ZERO or 0),
  * 16 work (>= ccg_workspace_bytes(CCG_WS_BICGSTAB_BLOCK_MIXED, n, k)),
- * 17 work_bytes, 18 res (host array of k ccg_mixed_result), 19 stream.
- * Waits on stream.
+ * 17 work_bytes, 18 res (host array of k ccg_mixed_result), 19 outer_res
+ * (host array of k * (maxit + 1) doubles or NULL: column c's ||r|| / ||y||
+ * at outer check j in outer_res[c * (maxit + 1) + j], NaN where not
+ * reached), 20 stream.  Waits on stream.
  */
 int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A,
                                 int64_t lda, const ccg_c* A32, int64_t lda32,
@@ -350,7 +443,8 @@ int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A,
                                 int64_t ldx, double tol, int32_t maxit,
                                 double tol_inner, int32_t maxit_inner,
                                 uint32_t flags, void* work, size_t work_bytes,
-                                ccg_mixed_result* res, void* stream);
+                                ccg_mixed_result* res, double* outer_res,
+                                void* stream);
 
 /*
  * Structured product: A is a three-level Toeplitz matrix on an m x m x m

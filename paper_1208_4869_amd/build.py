@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libccg.so")
-SOURCES = ["ccg_solvers.hip", "ccg_block.hip"]
+SOURCES = ["ccg_solvers.hip", "ccg_block.hip", "ccg_small.hip"]
 HEADERS = ["ccg_device.h", "ccg_gemv.h", "ccg_krylov.h", "ccg_host.h", "ccg_t3.h"]
 ARCH = "gfx950"
 

@@ -70,6 +70,16 @@ class _ServerStats(ctypes.Structure):
                 ("pool_used", ctypes.c_uint64), ("pool_peak", ctypes.c_uint64)]
 
 
+class _EventLog(ctypes.Structure):
+    _fields_ = [("events", ctypes.POINTER(ctypes.c_void_p)),
+                ("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("seen", ctypes.c_int32),
+                ("roles", ctypes.c_uint32), ("pad", ctypes.c_int32)]
+
+
+PROD_SETUP, PROD_V, PROD_T, PROD_W, PROD_Q, PROD_U = 1, 2, 4, 8, 16, 32
+
+
 @dataclass
 class MixedResult:
     info: int
@@ -78,6 +88,7 @@ class MixedResult:
     matvecs64: int
     matvecs32: int
     relres_true: float
+    outer_res: np.ndarray = None  # ||r|| / ||y|| at every outer check (NaN past the last)
 
 
 @dataclass
@@ -115,6 +126,10 @@ def load() -> ctypes.CDLL:
     lib.ccg_matvec.argtypes = [ctypes.c_int, I64, P, I64, P, P, P]
     lib.ccg_matvec_ex.argtypes = [ctypes.c_int, I64, P, I64, P, P, P, S, P]
     lib.ccg_matvec_noalloc.argtypes = [ctypes.c_int, I64, P, I64, P, P, P]
+    lib.ccg_read_stream.argtypes = [P, S, P, S, P]
+    lib.ccg_solve_small_batched.argtypes = [ctypes.c_int, I64, I64, P, I64, I64, P, I64,
+                                            P, I64, D, I32, U32, P, P]
+    lib.ccg_set_event_log.argtypes = [ctypes.POINTER(_EventLog)]
     lib.ccg_workspace_bytes.argtypes = [ctypes.c_int, I64, I64]
     lib.ccg_workspace_bytes.restype = S
     for name in ("ccg_bicgstab", "ccg_cgnr", "ccg_cocg", "ccg_cocr"):
@@ -124,7 +139,7 @@ def load() -> ctypes.CDLL:
         getattr(lib, name).argtypes = [I64, P, I64, P, P, D, I32, U32, P, S,
                                        ctypes.POINTER(_Result), P, P]
     lib.ccg_bicgstab_mixed_ex.argtypes = [I64, P, I64, P, I64, P, P, D, I32, D, I32,
-                                          U32, P, S, ctypes.POINTER(_MixedResult), P]
+                                          U32, P, S, ctypes.POINTER(_MixedResult), P, P]
     lib.ccg_round_c64.argtypes = [I64, I64, P, I64, P, I64, P]
     lib.ccg_matvec_c64.argtypes = [I64, P, I64, P, P, P]
     lib.ccg_matmat.argtypes = [I64, I64, P, I64, P, I64, P, I64, P]
@@ -138,7 +153,7 @@ def load() -> ctypes.CDLL:
     lib.ccg_matmat_c64.restype = ctypes.c_int
     lib.ccg_bicgstab_block_mixed_ex.argtypes = [I64, I64, P, I64, P, I64, P, I64, P, I64,
                                                 D, I32, D, I32, U32, P, S,
-                                                ctypes.POINTER(_MixedResult), P]
+                                                ctypes.POINTER(_MixedResult), P, P]
     lib.ccg_bicgstab_block_mixed_ex.restype = ctypes.c_int
     lib.ccg_t3_op_bytes.argtypes = [I64]
     lib.ccg_t3_op_bytes.restype = S
@@ -263,6 +278,111 @@ def ccg_matvec_noalloc(op: int, A, x, y, stream=None):
                                      y.data_ptr(), _stream(stream)),
            "ccg_matvec_noalloc")
     return y
+
+
+SMALL_MAX_N = 1024
+
+
+def ccg_solve_small_batched(method: int, A, Y, X, tol=1e-10, maxit=1000, flags=0,
+                            res=None, stream=None):
+    """BiCGSTAB (method WS_BICGSTAB) or CGNR (WS_CGNR) on a batch of
+    independent systems: A (batch, n, n), Y and X (batch, n) complex128
+    device tensors (each system's matrix row-major).  res: an optional device
+    buffer of batch result records (uint8 tensor of batch * 32 bytes).
+    Asynchronous; returns res (read it with small_results)."""
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.complex128 or A.dim() != 3 \
+            or A.shape[1] != A.shape[2] or not A.is_cuda:
+        raise TypeError("A must be a (batch, n, n) complex128 CUDA tensor")
+    batch, n = A.shape[0], A.shape[1]
+    for M, what in ((Y, "Y"), (X, "X")):
+        if not isinstance(M, torch.Tensor) or M.dtype != torch.complex128 or \
+                not M.is_cuda or tuple(M.shape) != (batch, n) or \
+                (n > 0 and M.stride(1) != 1):
+            raise TypeError("%s must be a (batch, n) complex128 CUDA tensor with "
+                            "contiguous rows" % what)
+    if n > 0 and A.stride(2) != 1:
+        raise TypeError("A must be row-major within each system")
+    lda = max(A.stride(1), 1) if n > 0 else 1
+    if res is None:
+        res = torch.empty(max(batch, 1) * ctypes.sizeof(_Result), dtype=torch.uint8,
+                          device=A.device)
+    _check(load().ccg_solve_small_batched(
+        int(method), n, batch, A.data_ptr(), lda, A.stride(0), Y.data_ptr(), Y.stride(0),
+        X.data_ptr(), X.stride(0), float(tol), int(maxit), int(flags), res.data_ptr(),
+        _stream(stream)), "ccg_solve_small_batched")
+    return res
+
+
+def small_results(res, batch):
+    """The result records of ccg_solve_small_batched as a list of Result."""
+    raw = res[:batch * ctypes.sizeof(_Result)].cpu().numpy().tobytes()
+    out = []
+    for b in range(batch):
+        r = _Result.from_buffer_copy(raw, b * ctypes.sizeof(_Result))
+        out.append(Result(r.info, r.iters, r.matvecs, r.confirms, r.relres_rec,
+                          r.relres_true))
+    return out
+
+
+READ_STREAM_SLAB = 262144
+
+
+def ccg_read_stream(src, out=None, stream=None):
+    """One read pass over the device tensor src (measurement aid); out: the
+    per-slab sums (a complex128 tensor of at least ceil(bytes / slab)
+    elements)."""
+    torch = _torch()
+    if not src.is_cuda or not src.is_contiguous():
+        raise TypeError("src must be a contiguous CUDA tensor")
+    nbytes = src.numel() * src.element_size()
+    if out is None:
+        out = torch.empty(max((nbytes + READ_STREAM_SLAB - 1) // READ_STREAM_SLAB, 1),
+                          dtype=torch.complex128, device=src.device)
+    _check(load().ccg_read_stream(src.data_ptr(), nbytes, out.data_ptr(),
+                                  out.numel() * out.element_size(), _stream(stream)),
+           "ccg_read_stream")
+    return out
+
+
+class EventLog:
+    """Pairs of timing events recorded by the library around the dense
+    complex128 products of the solves this host thread runs while attached
+    (ccg_set_event_log); durations() gives each product's time in seconds."""
+
+    def __init__(self, capacity: int, stride: int = 1, roles: int = 0):
+        torch = _torch()
+        self.pairs = [(torch.cuda.Event(enable_timing=True),
+                       torch.cuda.Event(enable_timing=True)) for _ in range(capacity)]
+        for a, b in self.pairs:  # torch creates its events on first record
+            a.record()
+            b.record()
+        torch.cuda.synchronize()
+        self._arr = (ctypes.c_void_p * (2 * capacity))(
+            *[e.cuda_event for pair in self.pairs for e in pair])
+        self._log = _EventLog(ctypes.cast(self._arr, ctypes.POINTER(ctypes.c_void_p)),
+                              capacity, 0, int(stride), 0, int(roles), 0)
+
+    def __enter__(self):
+        self._log.count = 0
+        self._log.seen = 0
+        _check(load().ccg_set_event_log(ctypes.byref(self._log)), "ccg_set_event_log")
+        return self
+
+    def __exit__(self, *exc):
+        load().ccg_set_event_log(None)
+
+    @property
+    def count(self) -> int:
+        return int(self._log.count)
+
+    @property
+    def seen(self) -> int:
+        return int(self._log.seen)
+
+    def durations(self):
+        _torch().cuda.synchronize()
+        return [a.elapsed_time(b) / 1e3 for a, b in self.pairs[:self.count]]
 
 
 def _short(name, A, y, x, tol, maxit, stream):
@@ -408,13 +528,14 @@ def ccg_bicgstab_mixed_ex(A, A32, y, x, tol=1e-10, maxit=10, tol_inner=1e-5,
         nbytes = max(ccg_workspace_bytes(WS_BICGSTAB_MIXED, n), 256)
         work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
     res = _MixedResult()
+    orr = np.full(max(int(maxit), 0) + 1, np.nan)
     _check(load().ccg_bicgstab_mixed_ex(
         n, A.data_ptr(), lda, A32.data_ptr(), lda32, y.data_ptr(), x.data_ptr(),
         float(tol), int(maxit), float(tol_inner), int(maxit_inner), int(flags),
         work.data_ptr(), work.numel() * work.element_size(), ctypes.byref(res),
-        _stream(stream)), "ccg_bicgstab_mixed_ex")
+        orr.ctypes.data if maxit >= 0 else None, _stream(stream)), "ccg_bicgstab_mixed_ex")
     return MixedResult(res.info, res.outer, res.inner_iters, res.matvecs64,
-                       res.matvecs32, res.relres_true)
+                       res.matvecs32, res.relres_true, orr)
 
 
 def hist_numpy(hist) -> np.ndarray:
@@ -665,13 +786,15 @@ def ccg_bicgstab_block_mixed_ex(A, A32, Y, X, tol=1e-10, maxit=10, tol_inner=1e-
         work = torch.empty(max(ccg_workspace_bytes(WS_BICGSTAB_BLOCK_MIXED, n, max(k, 1)), 256),
                            dtype=torch.uint8, device=A.device)
     res = (_MixedResult * max(k, 1))()
+    orr = np.full((max(k, 1), max(int(maxit), 0) + 1), np.nan)
     _check(load().ccg_bicgstab_block_mixed_ex(
         n, k, A.data_ptr(), lda, A32.data_ptr(), lda32, Y.data_ptr(), ldy, X.data_ptr(), ldx,
         float(tol), int(maxit), float(tol_inner), int(maxit_inner), int(flags),
-        work.data_ptr(), work.numel() * work.element_size(), res, _stream(stream)),
+        work.data_ptr(), work.numel() * work.element_size(), res,
+        orr.ctypes.data if maxit >= 0 else None, _stream(stream)),
         "ccg_bicgstab_block_mixed_ex")
     return [MixedResult(r.info, r.outer, r.inner_iters, r.matvecs64, r.matvecs32,
-                        r.relres_true) for r in list(res)[:k]]
+                        r.relres_true, orr[c]) for c, r in enumerate(list(res)[:k])]
 
 
 # ------------------------------------------------ structured lattice operator

@@ -75,15 +75,15 @@ static inline int kslice_of(int64_t n)
 // 16w..16w+15 of the tile by all 16 NT columns.
 constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
 
-template <int NT>
+template <int NT, int KS = kKS>
 __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid)
 {
-    constexpr int AP = kKS + 1;                       // padded A-tile row (LDS banks)
-    constexpr int AE = kRowsPerBlock * kKS / kBlock;  // A elements per thread
+    constexpr int AP = KS + 1;                        // padded A-tile row (LDS banks)
+    constexpr int AE = kRowsPerBlock * KS / kBlock;   // A elements per thread
     constexpr int BW = 16 * NT;                       // B-tile width
-    constexpr int BN = kKS * BW;                      // B-tile elements
+    constexpr int BN = KS * BW;                       // B-tile elements
     constexpr int BPT = (BN + kBlock - 1) / kBlock;   // B elements per thread
     __shared__ d2 As[2][kRowsPerBlock * AP];
     __shared__ d2 Bs[2][BN];
@@ -103,38 +103,42 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         cim[q] = d4{0.0, 0.0, 0.0, 0.0};
     }
     // this thread's share of the global tiles
-    const int arow = t / (kKS / AE);
-    const int aseg = (t % (kKS / AE)) * AE;
+    const int arow = t / (KS / AE);
+    const int aseg = (t % (KS / AE)) * AE;
     const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
     const d2* Ar = A + (int64_t)grow * lda;
+    // The loads of the next stage only issue here; what falls outside the
+    // slice is zeroed when the values go to LDS (after this stage's matrix
+    // products), so nothing waits for the loads before the products.
     d2 ra[AE], rbv[BPT];
+    bool aok[AE], bok[BPT];
     auto gload = [&](int kk) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int kc = kk + aseg + e;
+            aok[e] = kc < k1;
             ra[e] = Ar[kc < n ? kc : n - 1];
-            if (kc >= k1) ra[e] = d2{0.0, 0.0};
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * kBlock;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
-            const bool ok = idx < BN && kc < k1 && c < ncols;
-            rbv[m] = B[(int64_t)(ok ? kc : k0) * ldb + (ok ? c : 0)];
-            if (!ok) rbv[m] = d2{0.0, 0.0};
+            bok[m] = idx < BN && kc < k1 && c < ncols;
+            rbv[m] = B[(int64_t)(bok[m] ? kc : k0) * ldb + (bok[m] ? c : 0)];
         }
     };
     auto lstore = [&](int buf) {
+        const d2 z = d2{0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = ra[e];
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * kBlock;
-            if (idx < BN) Bs[buf][idx] = rbv[m];
+            if (idx < BN) Bs[buf][idx] = bok[m] ? rbv[m] : z;
         }
     };
-    const int nst = k1 > k0 ? (k1 - k0 + kKS - 1) / kKS : 0;
+    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
     if (nst > 0) {
         gload(k0);
         lstore(0);
@@ -142,9 +146,9 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
         const int cur = st & 1;
-        if (st + 1 < nst) gload(k0 + (st + 1) * kKS);
+        if (st + 1 < nst) gload(k0 + (st + 1) * KS);
 #pragma unroll
-        for (int ks = 0; ks < kKS; ks += 4) {
+        for (int ks = 0; ks < KS; ks += 4) {
             const d2 a = As[cur][(w * 16 + li) * AP + ks + lk];
             d2 b[NT];
 #pragma unroll
@@ -178,12 +182,12 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     }
 }
 
-template <int NT>
+template <int NT, int KS = kKS>
 __global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int64_t lda, int n,
                                                   const d2* __restrict__ B, int64_t ldb,
                                                   int ncols, d2* __restrict__ Zp, int kslice)
 {
-    zgemm_body<NT>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    zgemm_body<NT, KS>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 // Slice s of Z = A B for at most kVCols columns, on the vector units.  With
@@ -324,15 +328,15 @@ static inline int kslice32_of(int64_t n)
     return (int)(((per + kKS32 - 1) / kKS32) * kKS32);
 }
 
-template <int NT>
+template <int NT, int KS = kKS32>
 __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid)
 {
-    constexpr int AP = kKS32 + 1;
-    constexpr int AE = kRowsPerBlock * kKS32 / kBlock;  // 4
+    constexpr int AP = KS + 1;
+    constexpr int AE = kRowsPerBlock * KS / kBlock;  // 4
     constexpr int BW = 16 * NT;
-    constexpr int BN = kKS32 * BW;
+    constexpr int BN = KS * BW;
     constexpr int BPT = (BN + kBlock - 1) / kBlock;
     __shared__ f2 As[2][kRowsPerBlock * AP];
     __shared__ f2 Bs[2][BN];
@@ -351,38 +355,43 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
         cre[q] = f4v{0.f, 0.f, 0.f, 0.f};
         cim[q] = f4v{0.f, 0.f, 0.f, 0.f};
     }
-    const int arow = t / (kKS32 / AE);
-    const int aseg = (t % (kKS32 / AE)) * AE;
+    const int arow = t / (KS / AE);
+    const int aseg = (t % (KS / AE)) * AE;
     const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
     const f2* Ar = A + (int64_t)grow * lda;
-    f2 ra[AE], rbv[BPT];
+    // as in zgemm_body: the loads only issue here; zeroing outside the slice
+    // and the rounding of B to complex64 happen on the way to LDS
+    f2 ra[AE];
+    d2 rbv[BPT];
+    bool aok[AE], bok[BPT];
     auto gload = [&](int kk) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int kc = kk + aseg + e;
+            aok[e] = kc < k1;
             ra[e] = Ar[kc < n ? kc : n - 1];
-            if (kc >= k1) ra[e] = f2{0.f, 0.f};
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * kBlock;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
-            const bool ok = idx < BN && kc < k1 && c < ncols;
-            const d2 bv = B[(int64_t)(ok ? kc : k0) * ldb + (ok ? c : 0)];
-            rbv[m] = ok ? f2{(float)bv.x, (float)bv.y} : f2{0.f, 0.f};
+            bok[m] = idx < BN && kc < k1 && c < ncols;
+            rbv[m] = B[(int64_t)(bok[m] ? kc : k0) * ldb + (bok[m] ? c : 0)];
         }
     };
     auto lstore = [&](int buf) {
+        const f2 z = f2{0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = ra[e];
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * kBlock;
-            if (idx < BN) Bs[buf][idx] = rbv[m];
+            if (idx < BN)
+                Bs[buf][idx] = bok[m] ? f2{(float)rbv[m].x, (float)rbv[m].y} : z;
         }
     };
-    const int nst = k1 > k0 ? (k1 - k0 + kKS32 - 1) / kKS32 : 0;
+    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
     if (nst > 0) {
         gload(k0);
         lstore(0);
@@ -390,9 +399,9 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
         const int cur = st & 1;
-        if (st + 1 < nst) gload(k0 + (st + 1) * kKS32);
+        if (st + 1 < nst) gload(k0 + (st + 1) * KS);
 #pragma unroll
-        for (int ks = 0; ks < kKS32; ks += 4) {
+        for (int ks = 0; ks < KS; ks += 4) {
             const f2 a = As[cur][(w * 16 + li) * AP + ks + lk];
             f2 b[NT];
 #pragma unroll
@@ -424,12 +433,12 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     }
 }
 
-template <int NT>
+template <int NT, int KS = kKS32>
 __global__ __launch_bounds__(kBlock) void k_cgemm(const f2* __restrict__ A, int64_t lda, int n,
                                                   const d2* __restrict__ B, int64_t ldb,
                                                   int ncols, d2* __restrict__ Zp, int kslice)
 {
-    cgemm_body<NT>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    cgemm_body<NT, KS>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 template <int NT>
@@ -1048,11 +1057,21 @@ __global__ __launch_bounds__(kBlock) void km_scale(const d2* __restrict__ R, int
     }
 }
 
-// X[:, c] += nr[c] D[:, c] for the columns with nr[c] != 0; zero: X[:, c] = 0
-// first where zero.v[c] != 0
+// An inner solve that met a non-finite value, or broke down before its
+// first update (its correction is zero, and the next outer step would repeat
+// it), ends the column's refinement: its correction is not applied.
+__host__ __device__ __forceinline__ bool inner_ends_refinement(int info, int iters)
+{
+    return info == 4 || ((info == 2 || info == 3) && iters == 0);
+}
+
+// X[:, c] += nr[c] D[:, c] for the columns with nr[c] != 0 (and, when inner
+// is not null, whose inner record does not end the refinement); zero:
+// X[:, c] = 0 first where zero.v[c] != 0
 __global__ __launch_bounds__(kBlock) void km_update(d2* __restrict__ X, int64_t ldx, int n, int k,
                                                     int kp, const d2* __restrict__ D, ColScale nr,
-                                                    ColScale zero)
+                                                    ColScale zero,
+                                                    const char* __restrict__ inner = nullptr)
 {
     const int64_t total = (int64_t)n * k;
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
@@ -1061,7 +1080,11 @@ __global__ __launch_bounds__(kBlock) void km_update(d2* __restrict__ X, int64_t 
         const int c = (int)(e - i * k);
         d2* xp = X + i * ldx + c;
         if (zero.v[c] != 0.0) *xp = d2{0.0, 0.0};
-        const double f = nr.v[c];
+        double f = nr.v[c];
+        if (inner && f != 0.0) {
+            const SolverState* st = (const SolverState*)(inner + (size_t)c * kStateStride);
+            if (inner_ends_refinement(st->info, st->iters)) f = 0.0;
+        }
         if (f != 0.0) {
             const d2 d = D[i * kp + c];
             *xp = *xp + d2{d.x * f, d.y * f};
@@ -1104,7 +1127,7 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
                             int64_t lda32, const ccg_z* Y, int64_t ldy, ccg_z* X, int64_t ldx,
                             double tol, int32_t maxit, double tol_inner, int32_t maxit_inner,
                             uint32_t flags, void* work, size_t work_bytes, ccg_mixed_result* res,
-                            void* stream)
+                            double* outer_res, void* stream)
 {
     if (n < 0 || n > kMaxNB) return -1;
     if (k < 1 || k > kMaxCols) return -2;
@@ -1129,6 +1152,8 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
         std::memset(&res[j], 0, sizeof res[j]);
         res[j].relres_true = 0.0;
     }
+    if (outer_res)
+        for (int64_t j = 0; j < k * ((int64_t)maxit + 1); ++j) outer_res[j] = __builtin_nan("");
     if (n == 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     const int kk = (int)k;
@@ -1208,6 +1233,7 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
             if (!live[c]) continue;
             const double rel = std::sqrt(nrm[c] / ny2[c]);
             res[c].relres_true = rel;
+            if (outer_res) outer_res[(int64_t)c * ((int64_t)maxit + 1) + outer] = rel;
             if (!std::isfinite(nrm[c])) {
                 res[c].info = 4;
                 live[c] = 0;
@@ -1229,15 +1255,20 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
         rc = run_block(ai, CCG_X0_ZERO, maxit_inner, tol_inner * tol_inner, inner.data(), s, 1);
         if (rc) return rc;
-        km_update<<<elem_blocks(n * k), kBlock, 0, s>>>((d2*)X, ldx, (int)n, kk, kp, D, nr,
-                                                          none);
-        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
         for (int c = 0; c < kk; ++c) {
             if (nr.v[c] == 0.0) continue;
             res[c].outer++;
             res[c].inner_iters += inner[c].iters;
             res[c].matvecs32 += inner[c].matvecs;
+            if (inner_ends_refinement(inner[c].info, inner[c].iters)) {
+                res[c].info = inner[c].info;  // x keeps its value
+                live[c] = 0;
+                nr.v[c] = 0.0;
+            }
         }
+        km_update<<<elem_blocks(n * k), kBlock, 0, s>>>((d2*)X, ldx, (int)n, kk, kp, D, nr,
+                                                          none);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
     return 0;
@@ -1846,7 +1877,12 @@ static int serve_mixed_event(ccg_server* S, ServeReq* r)
         r->outers[c]++;
         r->inner_iters[c] += st.iters;
         r->mv32[c] += st.matvecs;
-        r->mv64[c]++;
+        if (inner_ends_refinement(st.info, st.iters)) {
+            r->info[c] = st.info;  // its correction was not applied
+            r->live[c] = 0;
+        } else {
+            r->mv64[c]++;
+        }
     }
     r->outer++;
     return serve_mixed_decide(S, r, nrm);
@@ -1864,7 +1900,8 @@ static int serve_mixed_outer(ccg_server* S, ServeReq* r)
                             hipMemcpyDeviceToHost, s)) != hipSuccess)
         return (int)e;
     km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp, r->D,
-                                                           r->nr, ColScale{});
+                                                           r->nr, ColScale{},
+                                                           (const char*)r->rec.a.cst);
     gemm(r->Ad, r->ald, (int)r->n, r->Xd, r->k, r->k, r->rec.a.Zp, s);
     km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, r->rec.a.Zp, (int)r->n, r->k,
                                                        kp, r->R);
@@ -2295,10 +2332,11 @@ int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A, int64_t ld
                                 const ccg_c* A32, int64_t lda32, const ccg_z* Y, int64_t ldy,
                                 ccg_z* X, int64_t ldx, double tol, int32_t maxit,
                                 double tol_inner, int32_t maxit_inner, uint32_t flags, void* work,
-                                size_t work_bytes, ccg_mixed_result* res, void* stream)
+                                size_t work_bytes, ccg_mixed_result* res, double* outer_res,
+                                void* stream)
 {
     return ccg::block_mixed_impl(n, k, A, lda, A32, lda32, Y, ldy, X, ldx, tol, maxit, tol_inner,
-                                 maxit_inner, flags, work, work_bytes, res, stream);
+                                 maxit_inner, flags, work, work_bytes, res, outer_res, stream);
 }
 
 // ------------------------------------------------------------- serving ABI

@@ -76,6 +76,25 @@ struct alignas(16) SolverState {
 };
 static_assert(sizeof(SolverState) <= 512, "state block");
 
+// A fresh record: iterating, nothing pending, no scalars yet.
+__device__ __forceinline__ void init_state(SolverState& o, int maxit, double tol2,
+                                           int no_confirm)
+{
+    o.phase = PH_RUN;
+    o.restart = 1;
+    o.info = -1;
+    o.iters = o.matvecs = o.confirms = 0;
+    o.maxit = maxit;
+    o.pending = PK_NONE;
+    o.pending_blocks = 0;
+    o.no_confirm = no_confirm;
+    o.pad1 = o.pad2 = 0;
+    o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
+    o.tol2 = tol2;
+    o.relres_rec = o.relres_true = __builtin_nan("");
+    o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
+}
+
 __device__ __forceinline__ void finish(SolverState& L, int info)
 {
     L.info = info;

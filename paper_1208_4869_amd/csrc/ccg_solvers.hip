@@ -193,24 +193,6 @@ __device__ __forceinline__ void publish(const Args& a, int q, const SolverState&
 
 // --------------------------------------------------------- common kernels
 
-__device__ __forceinline__ void init_state(SolverState& o, int maxit, double tol2,
-                                           int no_confirm)
-{
-    o.phase = PH_RUN;
-    o.restart = 1;
-    o.info = -1;
-    o.iters = o.matvecs = o.confirms = 0;
-    o.maxit = maxit;
-    o.pending = PK_NONE;
-    o.pending_blocks = 0;
-    o.no_confirm = no_confirm;
-    o.pad1 = o.pad2 = 0;
-    o.ny2 = o.thr2 = o.rh2 = o.rr = o.gamma = 0.0;
-    o.tol2 = tol2;
-    o.relres_rec = o.relres_true = __builtin_nan("");
-    o.rho = o.rho_old = o.alpha = o.omega = o.beta = d2{0.0, 0.0};
-}
-
 __global__ void k_init(SolverState* st, int maxit, double tol2, int no_confirm)
 {
     if (threadIdx.x == 0) {
@@ -1179,6 +1161,41 @@ static void launch_sym_role(const Args& a, int& q, hipStream_t s)
     q ^= 1;
 }
 
+// The event log of the calling host thread (ccg_set_event_log), or null.
+static thread_local ccg_event_log* t_event_log = nullptr;
+
+// The CCG_PROD_* kind of a product of role RO.
+template <Role RO>
+static constexpr uint32_t prod_kind()
+{
+    return (RO == ROLE_SETUP_B || RO == ROLE_SETUP_C || RO == ROLE_SETUP_G) ? CCG_PROD_SETUP
+         : RO == ROLE_V ? CCG_PROD_V
+         : RO == ROLE_T ? CCG_PROD_T : RO == ROLE_W ? CCG_PROD_W
+         : RO == ROLE_Q ? CCG_PROD_Q : CCG_PROD_U;
+}
+
+// A dense complex128 A x launch of the solvers, bracketed by a pair of the
+// attached event log's events when it is a sampled launch of a kind the log
+// counts and the log has pairs left.
+template <Role RO>
+static void launch_gemv_logged(const Args& a, int q, hipStream_t s)
+{
+    ccg_event_log* lg = t_event_log;
+    bool rec = false;
+    if (lg && (lg->roles == 0 || (lg->roles & prod_kind<RO>()))) {
+        rec = lg->events && lg->count >= 0 && lg->count < lg->capacity &&
+              (lg->stride <= 1 || lg->seen % lg->stride == 0);
+        lg->seen++;
+    }
+    // a failed record only leaves that pair unset; the solve goes on
+    if (rec) (void)hipEventRecord((hipEvent_t)lg->events[2 * lg->count], s);
+    k_gemv_n_role<RO, d2><<<blocks_n<d2>(a.n), GemvShape<d2>::threads, 0, s>>>(a, q);
+    if (rec) {
+        (void)hipEventRecord((hipEvent_t)lg->events[2 * lg->count + 1], s);
+        lg->count++;
+    }
+}
+
 // A product of role RO: dense (one k_gemv_n_role launch, or the two passes
 // of the upper-triangle product when a.sym is set) or structured.
 template <Role RO, class T, bool S3>
@@ -1193,6 +1210,9 @@ static void launch_product(const Args& a, int& q, hipStream_t s)
             launch_t3_role<RO, 4>(a, q, s);
     } else if (sizeof(T) == sizeof(d2) && a.sym.T > 0) {
         launch_sym_role<RO>(a, q, s);
+    } else if constexpr (sizeof(T) == sizeof(d2)) {
+        launch_gemv_logged<RO>(a, q, s);
+        q ^= 1;
     } else {
         k_gemv_n_role<RO, T><<<blocks_n<T>(a.n), GemvShape<T>::threads, 0, s>>>(a, q);
         q ^= 1;
@@ -1245,7 +1265,6 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
     SyncCtx* sc = nullptr;
     hipError_t e = get_sync(&sc);
     if (e != hipSuccess) return (int)e;
-    const int gN = blocks_n(a.n);
     const int gE = blocks_e(a.n);
     const int gC = a.csh.blocks();
     int q = 0;
@@ -1312,7 +1331,7 @@ static int run_solver(const Args& a, uint32_t flags, int32_t maxit, double tol2,
                 k_cgnr_z2_sym<<<(unsigned)((a.n + kWave - 1) / kWave), kBlock, 0, s>>>(a, flip());
                 k_cgnr_p<<<gE, kBlock, 0, s>>>(a, flip());
             } else if (M == M_CGNR) {
-                k_gemv_n_role<ROLE_W><<<gN, kBlockN, 0, s>>>(f, flip());
+                launch_gemv_logged<ROLE_W>(f, flip(), s);
                 k_cgnr_xr<<<gE, kBlock, 0, s>>>(a, flip());
                 k_cgnr_z1<<<gC, kBlock, 0, s>>>(a, flip());
                 k_cgnr_z2<<<gE, kBlock, 0, s>>>(a, flip());
@@ -1477,6 +1496,57 @@ static int matvec_impl(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg
         hipError_t e2 = hipFreeAsync(part, s);
         if (e == hipSuccess) e = e2;
     }
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+// ------------------------------------------------------------ read stream
+//
+// ccg_read_stream: a measurement aid outside the method -- one pass that
+// reads a buffer with the products' 16-byte nontemporal loads and nothing
+// else, so the HBM read rate the chip delivers to that load pattern can be
+// set beside the products' rates.  Block b reads the b-th slab of
+// CCG_READ_STREAM_SLAB bytes as consecutive 4 KB rows (256 threads x 16 B),
+// kReadUnroll rows in flight per thread -- the contiguous per-block streams
+// of the products; a grid-stride walk with loads spread over the whole
+// buffer measured 10-20% slower.  Every block writes the sum of what it read,
+// so no load can be dropped.
+constexpr int kReadUnroll = 16;
+constexpr int64_t kReadSlab16 = CCG_READ_STREAM_SLAB / 16;
+
+__global__ __launch_bounds__(kBlock) void k_read_stream(const d2* __restrict__ src, int64_t n16,
+                                                        d2* __restrict__ out)
+{
+    __shared__ d2 lds[kMaxWaves];
+    const int64_t b0 = (int64_t)blockIdx.x * kReadSlab16;
+    const int64_t e1 = b0 + kReadSlab16 < n16 ? b0 + kReadSlab16 : n16;
+    int64_t i = b0 + threadIdx.x;
+    d2 acc = d2{0.0, 0.0};
+    for (; i + (kReadUnroll - 1) * kBlock < e1; i += kReadUnroll * kBlock) {
+        d2 v[kReadUnroll];
+#pragma unroll
+        for (int u = 0; u < kReadUnroll; ++u) v[u] = ldnt(src + i + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < kReadUnroll; ++u) acc += v[u];
+    }
+    for (; i < e1; i += kBlock) acc += ldnt(src + i);
+    const d2 tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+static int read_stream_impl(const void* src, size_t bytes, void* out, size_t out_bytes,
+                            void* stream)
+{
+    if (bytes > 0 && !src) return -1;
+    if (bytes % 16 || ((uintptr_t)src & 15)) return -2;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int64_t blocks = (n16 + kReadSlab16 - 1) / kReadSlab16;
+    if (blocks > 0 && (!out || ((uintptr_t)out & 15))) return -3;
+    if (out_bytes < (size_t)blocks * 16) return -4;
+    if (blocks > INT32_MAX) return -2;
+    if (blocks == 0) return 0;
+    k_read_stream<<<(unsigned)blocks, kBlock, 0, (hipStream_t)stream>>>((const d2*)src, n16,
+                                                                         (d2*)out);
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;
 }
 
@@ -1682,7 +1752,7 @@ static MixLayout mix_layout(int64_t n)
 static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, int64_t lda32,
                       const ccg_z* y, ccg_z* x, double tol, int32_t maxit, double tol_inner,
                       int32_t maxit_inner, uint32_t flags, void* work, size_t work_bytes,
-                      ccg_mixed_result* res, void* stream)
+                      ccg_mixed_result* res, double* outer_res, void* stream)
 {
     if (n < 0 || n > kMaxN) return -1;
     if (n > 0 && !A) return -2;
@@ -1702,6 +1772,8 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
     if (!res) return -15;
     std::memset(res, 0, sizeof *res);
     res->relres_true = __builtin_nan("");
+    if (outer_res)
+        for (int32_t j = 0; j <= maxit; ++j) outer_res[j] = __builtin_nan("");
     if (n == 0) {
         res->relres_true = 0.0;
         return 0;
@@ -1764,6 +1836,7 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
         if (rc) return rc;
         if (outer > 0 || !(flags & CCG_X0_ZERO)) res->matvecs64++;
         res->relres_true = std::sqrt(rr / ny2);
+        if (outer_res) outer_res[outer] = res->relres_true;
         if (!std::isfinite(rr)) { res->info = 4; break; }
         if (rr <= thr2) { res->info = 0; break; }
         if (outer >= maxit) { res->info = 1; break; }
@@ -1777,6 +1850,9 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
         res->inner_iters += ir.iters;
         res->matvecs32 += ir.matvecs;
         if (ir.info == 4) { res->info = 4; break; }
+        // a breakdown before the first inner update leaves d = 0: the next
+        // step would repeat this one exactly
+        if ((ir.info == 2 || ir.info == 3) && ir.iters == 0) { res->info = ir.info; break; }
         k_mix_update<<<gE, kBlock, 0, s>>>((int)n, d32, nr, (d2*)x);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
     }
@@ -1982,6 +2058,18 @@ int ccg_matvec_ex(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x
     return ccg::matvec_impl(op, n, A, lda, x, y, work, work_bytes, stream, false);
 }
 
+int ccg_read_stream(const void* src, size_t bytes, void* out, size_t out_bytes, void* stream)
+{
+    return ccg::read_stream_impl(src, bytes, out, out_bytes, stream);
+}
+
+int ccg_set_event_log(ccg_event_log* log)
+{
+    if (log && (log->capacity < 0 || (log->capacity > 0 && !log->events))) return -1;
+    ccg::t_event_log = log;
+    return 0;
+}
+
 int ccg_matvec_noalloc(int op, int64_t n, const ccg_z* A, int64_t lda, const ccg_z* x,
                        ccg_z* y, void* stream)
 {
@@ -2019,10 +2107,11 @@ int ccg_cgnr_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_z* y, ccg_z* x
 int ccg_bicgstab_mixed_ex(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32,
                           int64_t lda32, const ccg_z* y, ccg_z* x, double tol, int32_t maxit,
                           double tol_inner, int32_t maxit_inner, uint32_t flags, void* work,
-                          size_t work_bytes, ccg_mixed_result* res, void* stream)
+                          size_t work_bytes, ccg_mixed_result* res, double* outer_res,
+                          void* stream)
 {
     return ccg::mixed_impl(n, A, lda, A32, lda32, y, x, tol, maxit, tol_inner, maxit_inner,
-                           flags, work, work_bytes, res, stream);
+                           flags, work, work_bytes, res, outer_res, stream);
 }
 
 int ccg_matvec_c64(int64_t n, const ccg_c* A, int64_t lda, const ccg_c* x, ccg_c* y,

@@ -201,7 +201,7 @@ def test_block_mixed_argument_errors_are_rejected_on_the_host(lib):
     assert lib.ccg_matmat_c64(4, 2, d, 4, d, 2, d, 2, d, 8, None) == -10
     assert lib.ccg_matmat_c64(0, 2, None, 1, None, 2, None, 2, None, 0, None) == 0
     res = (_MixedResult * 2)()
-    ok = [4, 2, d, 4, d, 4, d, 2, d, 2, 1e-10, 10, 1e-5, 100, 0, d, big, res, None]
+    ok = [4, 2, d, 4, d, 4, d, 2, d, 2, 1e-10, 10, 1e-5, 100, 0, d, big, res, None, None]
     for pos, bad in ((0, -1), (1, 0), (1, 65), (2, None), (3, 3), (4, None), (5, 3),
                      (6, None), (7, 1), (8, None), (9, 1), (10, 0.0), (11, -1),
                      (12, 1.0), (13, 0), (14, 2), (15, None), (16, 8), (17, None)):
@@ -251,3 +251,53 @@ def test_noalloc_product_rejects_sizes_beyond_its_array_on_the_host(lib):
     assert fn(1, (1 << 30) + 1, dummy, (1 << 30) + 1, dummy, P(512), None) == -2
     # n = 0 is a no-op
     assert fn(1, 0, None, 1, None, None, None) == 0
+
+
+def test_small_batched_argument_errors_on_the_host(lib):
+    """ccg_solve_small_batched rejects every illegal argument before any HIP
+    call (these calls return before touching the device)."""
+    P = ctypes.c_void_p
+    d = P(256)  # never dereferenced
+    fn = lib.ccg_solve_small_batched
+
+    def call(method=2, n=8, batch=3, A=d, lda=8, sA=64, Y=d, sY=8, X=P(4096), sX=8,
+             tol=1e-10, maxit=10, flags=0, res=d):
+        return fn(method, n, batch, A, lda, sA, Y, sY, X, sX, tol, maxit, flags, res, None)
+
+    assert call(method=5) == -1
+    assert call(n=-1) == -2 and call(n=1025, lda=1025, sA=1025 * 1025) == -2
+    assert call(batch=-1) == -3
+    assert call(A=None) == -4
+    assert call(lda=7) == -5
+    assert call(sA=63) == -6
+    assert call(Y=None) == -7
+    assert call(sY=7) == -8
+    assert call(X=None) == -9
+    assert call(sX=7) == -10
+    for tol in (0.0, -1.0, float("nan"), float("inf")):
+        assert call(tol=tol) == -11
+    assert call(maxit=-1) == -12
+    assert call(flags=2) == -13
+    assert call(res=None) == -14
+    assert call(batch=0, A=None, Y=None, X=None, res=None) == 0
+    # one system: its strides are not checked
+    assert call(method=3, batch=1, sA=0, sY=0, sX=0, res=None) == -14
+
+
+def test_read_stream_and_event_log_argument_errors_on_the_host(lib):
+    """The measurement aids reject bad arguments before any HIP call."""
+    from paper_1208_4869_amd.ccg import _EventLog
+    P = ctypes.c_void_p
+    assert lib.ccg_read_stream(None, 16, P(256), 16, None) == -1
+    assert lib.ccg_read_stream(P(256), 24, P(256), 16, None) == -2
+    assert lib.ccg_read_stream(P(264), 16, P(256), 16, None) == -2
+    assert lib.ccg_read_stream(P(256), 16, None, 16, None) == -3
+    assert lib.ccg_read_stream(P(256), 262144 + 16, P(256), 16, None) == -4
+    assert lib.ccg_read_stream(None, 0, None, 0, None) == 0
+    bad = _EventLog(None, 4, 0, 1, 0, 0, 0)
+    assert lib.ccg_set_event_log(ctypes.byref(bad)) == -1
+    neg = _EventLog(None, -1, 0, 1, 0, 0, 0)
+    assert lib.ccg_set_event_log(ctypes.byref(neg)) == -1
+    empty = _EventLog(None, 0, 0, 1, 0, 0, 0)
+    assert lib.ccg_set_event_log(ctypes.byref(empty)) == 0
+    assert lib.ccg_set_event_log(None) == 0

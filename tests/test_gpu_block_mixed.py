@@ -72,13 +72,37 @@ def run_block_mixed(A, Y, X0=None, **kw):
     return X.cpu().numpy(), res
 
 
+def check_against_wide_oracle(orc, A, y, res, label=""):
+    """One column against the oracle of the same refinement (complex64
+    products, complex128 inner vectors, FP64 scalars and refinement): same
+    info, outer steps within one, inner iterations within one per outer step,
+    and the outer residual history ||r_j|| / ||y|| within a factor of two at
+    every check both made while it was above 1e-13 (FP32 rounding moves the
+    inner iterates, so the values agree to a few percent, not bitwise)."""
+    ref = orc.bicgstab_mixed_wide(A, y)
+    msg = "%s: gpu info %d outer %d inner %d | oracle info %d outer %d inner %d" % (
+        label, res.info, res.outer, res.inner_iters, ref.info, ref.outer, ref.inner_iters)
+    assert res.info == ref.info, msg
+    assert abs(res.outer - ref.outer) <= 1, msg
+    assert abs(res.inner_iters - ref.inner_iters) <= max(res.outer, ref.outer), msg
+    g, o = res.outer_res, ref.outer_res
+    both = ~np.isnan(g) & ~np.isnan(o)
+    assert both[0] and g[0] == o[0] == 1.0, msg  # x0 = 0: the first check is ||y|| / ||y||
+    for j in np.nonzero(both)[0]:
+        if min(g[j], o[j]) <= 1e-13:
+            break
+        assert 0.5 <= g[j] / o[j] <= 2.0, msg + " check %d: %.3e vs %.3e" % (j, g[j], o[j])
+    return ref
+
+
 @pytest.mark.parametrize("kind,size,k,cols", [("lattice", 6, 8, None),
                                               ("dense", 256, 16, (0, 7, 15)),
                                               ("lattice", 20, 64, (0, 31, 63))])
 def test_block_mixed_solves(orc, kind, size, k, cols):
     """Every column: true residual <= 1e-10 (host, FP64); sampled columns:
-    forward error within 100x the FP64 oracle's and outer steps within one of
-    the mixed oracle's."""
+    forward error within 100x the FP64 oracle's, and info, outer steps, inner
+    iterations and the outer residual history against the oracle of the same
+    refinement."""
     if kind == "lattice":
         A, Xt, Y = inputs.lattice_system(size, 5, nrhs=k)
     else:
@@ -90,13 +114,29 @@ def test_block_mixed_solves(orc, kind, size, k, cols):
         rel, slack = host_relres(A, X[:, c], Y[:, c])
         assert res[c].info == 0 and rel <= 1e-10 + slack, (c, res[c], rel)
         assert res[c].outer >= 1 and res[c].matvecs32 >= 1
+        assert res[c].matvecs64 == res[c].outer  # x0 = 0: one FP64 residual per step
     for c in (range(k) if cols is None else cols):
         ref64 = orc.bicgstab(A, Y[:, c], tol=1e-10, maxit=1000)
-        refm = orc.bicgstab_mixed(A, Y[:, c])
+        check_against_wide_oracle(orc, A, Y[:, c], res[c], label="%s col %d" % (kind, c))
         fe = np.linalg.norm(X[:, c] - Xt[:, c]) / np.linalg.norm(Xt[:, c])
         fe64 = np.linalg.norm(ref64.x - Xt[:, c]) / np.linalg.norm(Xt[:, c])
         assert fe <= 100 * max(fe64, 1e-13), (c, fe, fe64)
-        assert abs(res[c].outer - refm.outer) <= 1, (c, res[c].outer, refm.outer)
+
+
+def test_block_mixed_inner_breakdown_ends_the_column(orc):
+    """A column whose inner solve breaks down before its first update (the
+    rotation [[0, 1], [-1, 0]] with y = e1: sigma = 0 exactly) ends after
+    one outer step with the inner info 2 and x = 0, as in the oracle, while
+    the other column (y = e1 + i e2 / 3, for which sigma is not zero)
+    converges."""
+    A = np.array([[0, 1], [-1, 0]], dtype=np.complex128)
+    Y = np.array([[1, 1], [0, 1j / 3.0]], dtype=np.complex128)
+    X, res = run_block_mixed(A, Y)
+    ref = orc.bicgstab_mixed_wide(A, Y[:, 0])
+    assert (ref.info, ref.outer, ref.inner_iters) == (2, 1, 0)
+    assert (res[0].info, res[0].outer, res[0].inner_iters) == (2, 1, 0)
+    assert res[0].matvecs64 == 0 and np.all(X[:, 0] == 0)
+    assert res[1].info == 0 and host_relres(A, X[:, 1], Y[:, 1])[0] <= 1.01e-10
 
 
 def test_block_mixed_edges():

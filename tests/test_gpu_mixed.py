@@ -111,3 +111,39 @@ def test_mixed_edges(orc):
     assert r1.info == 0 and r2.info == 0 and r2.outer <= r1.outer
     ref = orc.bicgstab_mixed(A, y, tol_inner=1e-3)
     assert abs(r1.outer - ref.outer) <= 1
+
+
+def test_mixed_inner_breakdown_ends_the_refinement(orc):
+    """An inner breakdown before the first inner update (the rotation
+    [[0, 1], [-1, 0]] with y = e1, and from x0 = (1/2, 1/2): sigma = 0
+    exactly) ends the refinement with info 2 after one step, x as it was --
+    as in the oracle -- instead of repeating the step until the budget."""
+    A = np.array([[0, 1], [-1, 0]], dtype=np.complex128)
+    y = np.array([1, 0], dtype=np.complex128)
+    for x0 in (None, np.array([0.5, 0.5], dtype=np.complex128)):
+        ref = orc.bicgstab_mixed(A, y, x0=x0)
+        x, res = run_mixed(A, y, x0=x0)
+        assert (ref.info, ref.outer, ref.inner_iters) == (2, 1, 0)
+        assert (res.info, res.outer, res.inner_iters) == (2, 1, 0)
+        assert np.array_equal(x, ref.x)
+
+
+@pytest.mark.parametrize("kind,size", [("lattice", 6), ("dense", 256)])
+def test_mixed_outer_history(orc, kind, size):
+    """The outer residual history ||r_j|| / ||y|| against the oracle's: the
+    same number of checks within one, each value within a factor of two while
+    above 1e-13 (FP32 rounding moves the inner iterates a little)."""
+    if kind == "lattice":
+        A, xt, y = inputs.lattice_system(size, 2)
+    else:
+        A, xt, y = inputs.dense_system(size, 61)
+    ref = orc.bicgstab_mixed(A, y)
+    x, res = run_mixed(A, y)
+    g, o = res.outer_res, ref.outer_res
+    assert g[0] == o[0] == 1.0
+    assert abs(int(np.sum(~np.isnan(g))) - int(np.sum(~np.isnan(o)))) <= 1
+    for j in range(len(g)):
+        if np.isnan(g[j]) or np.isnan(o[j]) or min(g[j], o[j]) <= 1e-13:
+            break
+        assert 0.5 <= g[j] / o[j] <= 2.0, (j, g[j], o[j])
+    assert g[res.outer] == res.relres_true
