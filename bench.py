@@ -87,6 +87,11 @@ def parse():
                    help="Poisson arrival rate (requests/s) of the serving leg")
     p.add_argument("--no-sym", action="store_true",
                    help="skip the upper-triangle (complex symmetric) leg")
+    p.add_argument("--no-config0", action="store_true",
+                   help="skip the n = 256 single-solve and 1024-system batch leg")
+    p.add_argument("--headline-only", action="store_true",
+                   help="only the headline BiCGSTAB solves and their product timing "
+                        "(for kernel traces of the headline)")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run a short mix of the kernels for rocprofv3 and exit")
     return p.parse_args()
@@ -104,8 +109,12 @@ def make_inputs():
     return A, x_true, y
 
 
-def time_solves(fn, A, y, x, work, steps, warmup, hist=None, flags=1):
-    """Solves from x0 = 0 (flag 1) plus `flags`; host clock per solve."""
+def time_solves(fn, A, y, x, work, steps, warmup, hist=None, flags=1, event_log=None):
+    """Solves from x0 = 0 (flag 1) plus `flags`; host clock per solve.
+    event_log: a ccg.EventLog attached over the timed solves (it samples
+    their product launches with HIP events on the stream they run on)."""
+    import contextlib
+
     import torch
     res = None
     flags |= 1
@@ -113,13 +122,14 @@ def time_solves(fn, A, y, x, work, steps, warmup, hist=None, flags=1):
         res = fn(A, y, x, TOL, MAXIT, flags=flags, work=work, hist=hist)
     torch.cuda.synchronize()
     lat = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ts = time.perf_counter()
-        res = fn(A, y, x, TOL, MAXIT, flags=flags, work=work, hist=hist)
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    with (event_log if event_log is not None else contextlib.nullcontext()):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            res = fn(A, y, x, TOL, MAXIT, flags=flags, work=work, hist=hist)
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
     return total, np.array(lat), res
 
 
@@ -139,9 +149,9 @@ def time_kernel(launch, reps):
     return s.elapsed_time(e) / 1e3 / reps
 
 
-def cpu_baseline(A, y, budget_s):
-    import oracle
-    orc = oracle.get()
+def _time_oracle(orc, A, y, budget_s):
+    """Complete oracle BiCGSTAB solves of (A, y) until budget_s has passed
+    (at least one, at most 50): (solves/s, count, seconds, last result)."""
     t0 = time.perf_counter()
     k = 0
     res = None
@@ -151,12 +161,103 @@ def cpu_baseline(A, y, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or k >= 50:
             break
-    return {"value": k / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d complete BiCGSTAB solve(s) of the same 20^3 lattice "
-                      "system (n=8000) by the single-threaded C oracle, %.1f s"
-                      % (k, el),
-            "iters": res.iters, "relres_true": res.relres_true,
-            "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+    return k / el, k, el, res
+
+
+PRODUCT_SAMPLE_STRIDE = 7
+
+
+def headline_record(args, total, lat, res, n, relres, fwd):
+    """The contract fields of the JSON line for the headline solves."""
+    return {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "dipole-lattice 20^3, n=8000, dense complex128 "
+                               "A resident in HBM, BiCGSTAB tol 1e-10 from x0=0",
+                   "n": n, "tol": TOL, "maxit": MAXIT, "method": "bicgstab",
+                   "x_seed": X_SEED},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "iters": res.iters,
+        "matvecs": res.matvecs,
+        "relres_true": relres,
+        "fwd_err": fwd,
+    }
+
+
+READ_STREAM_BYTES = 4 << 30
+
+
+def read_stream_peak():
+    """The HBM read rate the chip delivers to a plain streaming read of 4 GiB
+    with the products' 16-byte nontemporal loads (ccg_read_stream), best of
+    10 launches timed with HIP events: the achievable ceiling the product
+    rates are also set against."""
+    import torch
+
+    from paper_1208_4869_amd import ccg
+    buf = torch.ones(READ_STREAM_BYTES // 8, dtype=torch.float64, device="cuda")
+    out = ccg.ccg_read_stream(buf)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(10):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        ccg.ccg_read_stream(buf, out)
+        e.record()
+        e.synchronize()
+        t = s.elapsed_time(e) / 1e3
+        best = t if best is None else min(best, t)
+    del buf
+    torch.cuda.empty_cache()
+    gbs = READ_STREAM_BYTES / best / 1e9
+    log("read stream: %.0f GB/s (%.1f%% of %.0f)" % (gbs, 100 * gbs / HBM_PEAK_GBS,
+                                                    HBM_PEAK_GBS))
+    return gbs
+
+
+def cpu_baseline(A, y, budget_s):
+    """The oracle timed on the host: the one-thread build pinned to one core
+    (taskset-style affinity of this process, restored afterwards), and the
+    OpenMP build of the same source on every core this process may use (the
+    rows of the dense product shared out; the same results bit for bit).
+    Half the budget each."""
+    import oracle
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        v1, k1, el1, res = _time_oracle(oracle.get(), A, y, budget_s / 2)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    omp = oracle.get_omp()
+    threads = omp.threads(len(allowed))
+    vn, kn, eln, resn = _time_oracle(omp, A, y, budget_s / 2)
+    same = bool(np.array_equal(res.x, resn.x))
+    common = {"host_cpu": host_cpu(), "host_threads": os.cpu_count(),
+              "allowed_cpus": len(allowed)}
+    one = {"value": v1, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "%d complete BiCGSTAB solve(s) of the same 20^3 lattice system "
+                     "(n=8000) by the one-thread C oracle pinned to cpu %d, %.1f s"
+                     % (k1, core, el1),
+           "iters": res.iters, "relres_true": res.relres_true, **common}
+    alln = {"value": vn, "unit": "solves/s", "cores": threads, "kind": "oracle (OpenMP build)",
+            "sample": "%d complete solve(s) of the same system by the OpenMP build of the "
+                      "same oracle source on %d threads, %.1f s; solution bit for bit "
+                      "equal to the one-thread build's: %s" % (kn, threads, eln, same),
+            "bitwise_equal_to_one_thread": same, **common}
+    return one, alln
 
 
 def host_cpu():
@@ -306,9 +407,113 @@ def block_leg(A, A_h, steps):
                      "frac": flops / tg / 1e12 / FP64_PEAK_TFLOPS}}
 
 
+CONFIG0_N = 256
+CONFIG0_BATCH = 1024
+
+
+def config0_leg(steps):
+    """The dense n = 256 family (A = 4 I + G / sqrt(n), x_true iid CN(0,1),
+    y = A x_true; seeds 0..1023): single-solve latency of one system (seed 0)
+    through ccg_bicgstab_ex / ccg_cgnr_ex (one kernel per step of the method)
+    and through ccg_solve_small_batched with a batch of one (one workgroup,
+    one launch); then the 1024 seeds solved concurrently by one
+    ccg_solve_small_batched launch per method, timed with HIP events, its
+    algorithmic bytes (16 n^2 per product of every system) against the HBM
+    peak."""
+    import torch
+
+    from paper_1208_4869_amd import ccg, inputs
+    n, B = CONFIG0_N, CONFIG0_BATCH
+    t = time.time()
+    sys_ = [inputs.dense_system(n, s) for s in range(B)]
+    A = torch.from_numpy(np.stack([a for a, _, _ in sys_])).cuda()
+    Y = torch.from_numpy(np.stack([y for _, _, y in sys_])).cuda()
+    Xt = np.stack([xt for _, xt, _ in sys_])
+    torch.cuda.synchronize()
+    log("built %d n=%d systems (%.2f GB of A) in %.1fs" % (B, n, A.numel() * 16 / 1e9,
+                                                          time.time() - t))
+    out = {"workload": "dense n=256 (A = 4I + G/sqrt(n)), seeds 0..%d, tol 1e-10, "
+                       "x0 = 0" % (B - 1), "n": n}
+    A0, y0 = A[0].contiguous(), Y[0].contiguous()
+    # one system through the multi-kernel entry points
+    for name, fn, wsid in (("bicgstab", ccg.ccg_bicgstab_ex, ccg.WS_BICGSTAB),
+                           ("cgnr", ccg.ccg_cgnr_ex, ccg.WS_CGNR)):
+        w = ccg.workspace(wsid, n)
+        x = torch.empty_like(y0)
+        tot, lat, res = time_solves(fn, A0, y0, x, w, steps, 3)
+        out[name + "_single"] = {"entry": "ccg_%s_ex" % name, "solves_per_s": steps / tot,
+                                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                 "iters": res.iters, "matvecs": res.matvecs, "info": res.info}
+    method_ids = (("bicgstab", ccg.WS_BICGSTAB), ("cgnr", ccg.WS_CGNR))
+    # one system, one workgroup: launch + wait per solve
+    res_d = torch.empty(B * 32, dtype=torch.uint8, device="cuda")
+    for name, wsid in method_ids:
+        X1 = torch.empty_like(Y[:1])
+        for _ in range(3):
+            ccg.ccg_solve_small_batched(wsid, A[:1], Y[:1], X1, TOL, MAXIT, ccg.X0_ZERO, res_d)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(steps):
+            ts = time.perf_counter()
+            ccg.ccg_solve_small_batched(wsid, A[:1], Y[:1], X1, TOL, MAXIT, ccg.X0_ZERO, res_d)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+        lat = np.array(lat)
+        r1 = ccg.small_results(res_d, 1)[0]
+        out[name + "_single_small"] = {"entry": "ccg_solve_small_batched, batch 1",
+                                       "solves_per_s": 1.0 / lat.mean(),
+                                       "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                       "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                       "iters": r1.iters, "matvecs": r1.matvecs,
+                                       "info": r1.info}
+    # the whole batch in one launch
+    for name, wsid in method_ids:
+        X = torch.empty_like(Y)
+        ccg.ccg_solve_small_batched(wsid, A, Y, X, TOL, MAXIT, ccg.X0_ZERO, res_d)
+        torch.cuda.synchronize()
+        reps = max(steps // 10, 3)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        wall = []
+        for a, b in ev:
+            ts = time.perf_counter()
+            a.record()
+            ccg.ccg_solve_small_batched(wsid, A, Y, X, TOL, MAXIT, ccg.X0_ZERO, res_d)
+            b.record()
+            b.synchronize()
+            wall.append(time.perf_counter() - ts)
+        dur = np.array([a.elapsed_time(b) / 1e3 for a, b in ev])
+        rs = ccg.small_results(res_d, B)
+        mv = np.array([r.matvecs for r in rs])
+        abytes = float(16.0 * n * n * mv.sum())
+        tk = float(np.median(dur))
+        Xh = X.cpu().numpy()
+        sample = (0, 1, B // 2, B - 1)
+        rel = [float(np.linalg.norm(sys_[b][2] - sys_[b][0] @ Xh[b]) / np.linalg.norm(sys_[b][2]))
+               for b in sample]
+        fe = [float(np.linalg.norm(Xh[b] - Xt[b]) / np.linalg.norm(Xt[b])) for b in sample]
+        out[name + "_batch"] = {
+            "entry": "ccg_solve_small_batched", "batch": B,
+            "kernel": "k_small_%s (one workgroup per system, one launch)" % name,
+            "launch_ms": tk * 1e3, "wall_ms_p50": float(np.percentile(wall, 50) * 1e3),
+            "solves_per_s": B / tk, "solves_per_s_wall": B / float(np.median(wall)),
+            "products": int(mv.sum()), "algorithmic_bytes": abytes,
+            "achieved_gbs": abytes / tk / 1e9, "hbm_frac": abytes / tk / 1e9 / HBM_PEAK_GBS,
+            "all_converged": all(r.info == 0 and r.relres_true <= TOL for r in rs),
+            "iters_range": [int(min(r.iters for r in rs)), int(max(r.iters for r in rs))],
+            "host_relres_sampled_max": max(rel), "fwd_err_sampled_max": max(fe)}
+        log("config 0 %s: batch of %d in %.2f ms (%.0f solves/s, %.0f GB/s of A)" % (
+            name, B, tk * 1e3, B / tk, abytes / tk / 1e9))
+    del A, Y
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_SIZES = (512, 1024, 2048, 4096)
 SERVE_SEED = 2024
 SERVE_POOL_BYTES = 16 << 30
+SERVE_BUDGET_BYTES = 6 << 30  # a pool that binds: the 128 slots would need ~11 GB
 SERVE_TOL_INNER = 1e-5
 
 
@@ -337,7 +542,8 @@ def serve_inputs(nreq):
     return reqs
 
 
-def run_server(reqs, arrivals, mixed=False, tol_inner=SERVE_TOL_INNER):
+def run_server(reqs, arrivals, mixed=False, tol_inner=SERVE_TOL_INNER,
+               pool_bytes=SERVE_POOL_BYTES):
     """Feed reqs to a server at the given arrival times (seconds from the
     start); mixed: FP64 refinement around complex64 inner solves.  Returns
     (makespan, latencies, results, stats)."""
@@ -348,7 +554,7 @@ def run_server(reqs, arrivals, mixed=False, tol_inner=SERVE_TOL_INNER):
     index = {}
     done = 0
     i = 0
-    with ccg.Server(SERVE_POOL_BYTES, max_active=128) as srv:
+    with ccg.Server(pool_bytes, max_active=128) as srv:
         t0 = time.perf_counter()
         while done < N:
             now = time.perf_counter() - t0
@@ -435,6 +641,39 @@ def serve_leg(nreq, rate):
                       "p99_ms": float(np.percentile(lat_s, 99) * 1e3)})
         log("serving at %.0f%% of capacity: p50 %.2f ms p99 %.2f ms" % (
             100 * load, sweep[-1]["p50_ms"], sweep[-1]["p99_ms"]))
+    # a pool that binds: 6 GiB, so admission waits for pool bytes, not for
+    # slots; capacity and Poisson arrivals at 70% of that capacity
+    mk_b, lat_b, res_b, st_b = run_server(reqs, np.zeros(nreq), pool_bytes=SERVE_BUDGET_BYTES)
+    cap_b = nreq / mk_b
+    gb = np.random.default_rng(SERVE_SEED + 20).exponential(1.0 / (0.7 * cap_b), nreq)
+    mk_bp, lat_bp, res_bp, st_bp = run_server(reqs, np.cumsum(gb) - gb[0],
+                                              pool_bytes=SERVE_BUDGET_BYTES)
+    ok = ok and all(a.info == 0 and a.relres_true <= TOL for r in res_bp for a in r)
+    same_b = all(torch.equal(X, Xr) for (_, _, X), Xr in zip(reqs, X_ref))
+    budget = {"pool_bytes": SERVE_BUDGET_BYTES,
+              "capacity_requests_per_s": cap_b,
+              "capacity_admission_waits": st_b["admission_waits"],
+              "capacity_peak_active": st_b["peak_active"],
+              "capacity_pool_peak_bytes": st_b["pool_peak"],
+              "poisson_rate_per_s": 0.7 * cap_b,
+              "poisson_requests_per_s": nreq / mk_bp,
+              "poisson_p50_ms": float(np.percentile(lat_bp, 50) * 1e3),
+              "poisson_p99_ms": float(np.percentile(lat_bp, 99) * 1e3),
+              "poisson_admission_waits": st_bp["admission_waits"],
+              "poisson_peak_active": st_bp["peak_active"],
+              "bitwise_equal_to_alone": bool(same_b)}
+    log("serving in a %d GiB pool: capacity %.0f req/s (%d admission waits); Poisson at "
+        "70%%: p50 %.2f ms p99 %.2f ms" % (SERVE_BUDGET_BYTES >> 30, cap_b,
+                                           st_b["admission_waits"], budget["poisson_p50_ms"],
+                                           budget["poisson_p99_ms"]))
+    # nonsingularity of the realised matrices: sigma_min of the first request
+    # of every size (Gershgorin fails for this family)
+    certs = []
+    for size in SERVE_SIZES:
+        j = next(k for k, (A, _, _) in enumerate(reqs) if A.shape[0] == size)
+        sv = torch.linalg.svdvals(reqs[j][0])
+        certs.append({"request": j, "n": size, "sigma_min": float(sv[-1]),
+                      "sigma_max": float(sv[0])})
     # the mixed-precision variant on the same requests and arrivals
     X64 = [X.clone() for _, _, X in reqs]
     run_server(reqs[:8], np.zeros(8), mixed=True)  # warm-up
@@ -474,6 +713,8 @@ def serve_leg(nreq, rate):
                       "max_rel_diff_vs_fp64_solution": dmax,
                       "ticks_capacity": st_mc["ticks"]},
             "pool_bytes": SERVE_POOL_BYTES,
+            "budget_pool": budget,
+            "sigma_min_certificates": certs,
             "all_converged": ok, "bitwise_equal_to_alone": bool(same)}
 
 
@@ -639,18 +880,49 @@ def main():
         profile_kernels(A, y)
         return
 
-    # --- headline: BiCGSTAB solves/s
+    # --- headline: BiCGSTAB solves/s.  The v = A p products inside the timed
+    # solves (k_gemv_n_role, role v: the dominant kernel, all of its launches
+    # full products) are sampled live with HIP events: every 7th of them
+    # (six per solve, so the sample rotates through the iterations), one
+    # event pair per solve on average.
     x = torch.empty(n, dtype=torch.complex128, device="cuda")
     work = ccg.workspace(ccg.WS_BICGSTAB, n)
+    elog = ccg.EventLog(args.steps + 8, stride=PRODUCT_SAMPLE_STRIDE, roles=ccg.PROD_V)
     log("timing %d BiCGSTAB solves (+%d warm-up)" % (args.steps, args.warmup))
     total, lat, res = time_solves(ccg.ccg_bicgstab_ex, A, y, x, work, args.steps,
-                                  args.warmup)
+                                  args.warmup, event_log=elog)
+    prod_us = np.array(elog.durations()) * 1e6
     xg = x.cpu().numpy()
     relres = float(np.linalg.norm(y_h - A_h @ xg) / np.linalg.norm(y_h))
     fwd = float(np.linalg.norm(xg - x_true) / np.linalg.norm(x_true))
     if res.info != 0 or not relres <= 1.01 * TOL:
         raise SystemExit("BiCGSTAB did not reach the tolerance: info %d relres %.3e"
                          % (res.info, relres))
+    bytes_mv = 16.0 * n * n + 32.0 * n
+    t_in = float(np.mean(prod_us)) * 1e-6
+    gbs_in = bytes_mv / t_in / 1e9
+    log("A x inside the solves: %d samples, mean %.1f us, median %.1f us (%.0f GB/s)"
+        % (len(prod_us), prod_us.mean(), np.median(prod_us), gbs_in))
+    read_gbs = read_stream_peak()
+    trec = measured_traffic()
+    roofline = {"bound": "hbm",
+                "kernel": "k_gemv_n_role, role v (v = A p and the confirming residual) "
+                          "inside the timed BiCGSTAB solves",
+                "achieved": gbs_in, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs_in / HBM_PEAK_GBS,
+                "traffic": trec.get("k_gemv_n_role_traffic_bytes") if trec else None,
+                "launch_us": t_in * 1e6, "launch_us_median": float(np.median(prod_us)),
+                "samples": int(len(prod_us)),
+                "sampling": "HIP events around every %dth role-v product launch of the timed "
+                            "solves, on their stream" % PRODUCT_SAMPLE_STRIDE,
+                "bytes_per_launch": bytes_mv,
+                "measured_read_stream_gbs": read_gbs,
+                "frac_of_measured_read_stream": gbs_in / read_gbs}
+    if args.headline_only:
+        out = headline_record(args, total, lat, res, n, relres, fwd)
+        out["roofline"] = roofline
+        print(json.dumps(out), flush=True)
+        return
 
     # --- CGNR on the same system
     wc = ccg.workspace(ccg.WS_CGNR, n)
@@ -676,7 +948,9 @@ def main():
                     "relres_true": float(np.linalg.norm(y_h - A_h @ xsg)
                                          / np.linalg.norm(y_h))}
 
-    # --- dominant kernel: A x (and A^H x), timed with HIP events
+    # --- the plain A x (ccg_matvec: the same inner loop and launch shape
+    # without the solver's prologue and epilogue) and A^H x, timed with HIP
+    # events over back-to-back launches: secondary figures
     xin = torch.from_numpy(x_true).cuda()
     yout = torch.empty_like(xin)
     wmv = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATVEC_C, n), dtype=torch.uint8,
@@ -684,43 +958,23 @@ def main():
     reps = 50
     tn = time_kernel(lambda: ccg.ccg_matvec(ccg.OP_N, A, xin, yout), reps)
     tc = time_kernel(lambda: ccg.ccg_matvec_ex(ccg.OP_C, A, xin, yout, wmv), reps)
-    bytes_mv = 16.0 * n * n + 32.0 * n
-    trec = measured_traffic()
     gbs_n = bytes_mv / tn / 1e9
     gbs_c = bytes_mv / tc / 1e9
-    log("A x: %.1f us (%.0f GB/s); A^H x: %.1f us (%.0f GB/s)"
+    log("plain A x: %.1f us (%.0f GB/s); A^H x: %.1f us (%.0f GB/s)"
         % (tn * 1e6, gbs_n, tc * 1e6, gbs_c))
+    roofline["plain_kernel"] = {
+        "kernel": "k_gemv_n_plain (ccg_matvec)", "launch_us": tn * 1e6,
+        "achieved": gbs_n, "frac": gbs_n / HBM_PEAK_GBS,
+        "frac_of_measured_read_stream": gbs_n / read_gbs,
+        "traffic": trec.get("k_gemv_n_traffic_bytes") if trec else None,
+        "timing": "HIP events over %d back-to-back launches" % reps}
 
-    out = {
-        "metric": METRIC,
-        "value": args.steps / total,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c128",
-        "data": "synthetic",
-        "config": {"workload": "dipole-lattice 20^3, n=8000, dense complex128 "
-                               "A resident in HBM, BiCGSTAB tol 1e-10 from x0=0",
-                   "n": n, "tol": TOL, "maxit": MAXIT, "method": "bicgstab",
-                   "x_seed": X_SEED},
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "iters": res.iters,
-        "matvecs": res.matvecs,
-        "relres_true": relres,
-        "fwd_err": fwd,
-        "roofline": {"bound": "hbm", "kernel": "k_gemv_n (A x)",
-                     "achieved": gbs_n, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs_n / HBM_PEAK_GBS,
-                     "traffic": trec["k_gemv_n_traffic_bytes"] if trec else None,
-                     "launch_us": tn * 1e6, "bytes_per_launch": bytes_mv},
+    out = headline_record(args, total, lat, res, n, relres, fwd)
+    out.update({
+        "roofline": roofline,
         "matvec_h": {"kernel": "k_gemv_c_band + gather (A^H x)",
                      "achieved_gbs": gbs_c, "frac": gbs_c / HBM_PEAK_GBS,
+                     "frac_of_measured_read_stream": gbs_c / read_gbs,
                      "launch_us": tc * 1e6},
         "cgnr": {"solves_per_s": csteps / ctot,
                  "p50_ms": float(np.percentile(clat, 50) * 1e3),
@@ -728,7 +982,9 @@ def main():
                  "relres_true": crel},
         "cocg": cs["cocg"],
         "cocr": cs["cocr"],
-    }
+    })
+    if not args.no_config0:
+        out["config0"] = config0_leg(max(args.steps * 3, 30))
     if not args.no_sym:
         out["symmetric"] = sym_leg(A, A_h, y, y_h, csteps)
     if not args.no_mixed:
@@ -741,7 +997,8 @@ def main():
         out["serve"] = serve_leg(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (bounded sample, ~%.0f s)" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(A_h, y_h, args.cpu_seconds)
+        out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(
+            A_h, y_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -31,17 +31,29 @@ LIB = os.path.join(BUILD_DIR, "liboracle.so")
 
 X0_ZERO = 1
 
-CFLAGS = ["-O2", "-std=c11", "-Wall", "-Werror=implicit-function-declaration",
+LIB_OMP = os.path.join(BUILD_DIR, "liboracle_omp.so")
+
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas",
+          "-Werror=implicit-function-declaration",
           "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
 
 
-def build(src: str = SRC, out: str = LIB) -> str:
-    """Compile the oracle with gcc into ``out`` (always recompiles)."""
+def build(src: str = SRC, out: str = LIB, openmp: bool = False) -> str:
+    """Compile the oracle with gcc into ``out`` (always recompiles).  openmp:
+    the timing-only build that shares the rows of the dense product among
+    threads (same results bit for bit)."""
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    subprocess.run(["gcc", *CFLAGS, src, "-o", tmp, "-lm"], check=True)
+    extra = ["-fopenmp"] if openmp else []
+    subprocess.run(["gcc", *CFLAGS, *extra, src, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, out)
     return out
+
+
+def build_all() -> None:
+    """Both builds: the one-thread oracle and its OpenMP timing build."""
+    build()
+    build(out=LIB_OMP, openmp=True)
 
 
 class _Stats(ctypes.Structure):
@@ -108,6 +120,8 @@ class Oracle:
         self.lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
+        self.lib.oracle_threads.argtypes = [ctypes.c_int]
+        self.lib.oracle_threads.restype = ctypes.c_int
         self.lib.oracle_matvec_c64.argtypes = [I64, P, I64, P, P]
         self.lib.oracle_matvec_c64.restype = None
         self.lib.oracle_bicgstab_mixed.argtypes = [
@@ -293,6 +307,12 @@ class Oracle:
                               tol=tol, maxit=maxit) for c in cols]
 
 
+    def threads(self, want: int = 0) -> int:
+        """Set (want > 0) and return the thread count of the OpenMP build; 1
+        for the one-thread build."""
+        return int(self.lib.oracle_threads(int(want)))
+
+
 _default: Oracle | None = None
 
 
@@ -301,3 +321,10 @@ def get() -> Oracle:
     if _default is None:
         _default = Oracle()
     return _default
+
+
+def get_omp() -> Oracle:
+    """The OpenMP timing build (built on first use when missing)."""
+    if not os.path.exists(LIB_OMP) or os.path.getmtime(LIB_OMP) < os.path.getmtime(SRC):
+        build(out=LIB_OMP, openmp=True)
+    return Oracle(LIB_OMP)

@@ -50,13 +50,19 @@
  *     t^H t (BiCGSTAB), 4 non-finite value met.
  *
  * Arithmetic: C11 double complex, one thread, every sum a left-to-right loop.
- * Build with -ffp-contract=off so that no multiply-add is fused.
+ * Build with -ffp-contract=off so that no multiply-add is fused.  A second
+ * build of this same file with OpenMP exists for timing on all host cores
+ * only: it splits the rows of the dense product among threads, which leaves
+ * every sum, and so every result, bit for bit as in the one-thread build.
  */
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex zc;
 
@@ -132,11 +138,27 @@ static void zzero(int64_t n, zc* v)
         v[i] = 0.0;
 }
 
+/* Threads the OpenMP build uses from now on (want > 0), and how many it
+ * will use; 1 in the one-thread build. */
+int oracle_threads(int want)
+{
+#ifdef _OPENMP
+    if (want > 0) omp_set_num_threads(want);
+    return omp_get_max_threads();
+#else
+    (void)want;
+    return 1;
+#endif
+}
+
 /* -------------------------------------------------------- matrix products */
 
-/* y = A x : y_i = sum_j A_ij x_j  (the user matvec of the Usage section) */
+/* y = A x : y_i = sum_j A_ij x_j  (the user matvec of the Usage section).
+ * In the OpenMP build (timing only) the rows are shared out among threads;
+ * every row's sum keeps its left-to-right order, so the bits are the same. */
 void oracle_matvec(int64_t n, const zc* A, int64_t lda, const zc* x, zc* y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         zc s = 0.0;
         for (int64_t j = 0; j < n; ++j)

@@ -30,6 +30,18 @@ def test_dense_family_certificate():
         assert 2.0 < smin and smax < 6.5
 
 
+def test_dense_family_certificate_at_the_serving_sizes():
+    """The serving mix draws the same family at n in {512, 1024, 2048, 4096},
+    where Gershgorin fails too: sigma_min from an SVD certifies a sample of
+    seeds at every size (2.6-2.7, far from zero; sigma_max about 5.5)."""
+    for n, seeds in ((512, (0, 1)), (1024, (0, 1)), (2048, (0,)), (4096, (0,))):
+        for seed in seeds:
+            A = inputs.dense_matrix(n, 3000 + n + seed)
+            assert inputs.gershgorin_margin(A) < 0
+            smin, smax = inputs.sigma_extremes(A)
+            assert 2.0 < smin and smax < 6.5, (n, seed, smin, smax)
+
+
 def test_lattice_structure():
     m = 5
     A = inputs.lattice_matrix(m)
