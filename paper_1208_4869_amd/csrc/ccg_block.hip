@@ -75,17 +75,19 @@ static inline int kslice_of(int64_t n)
 // 16w..16w+15 of the tile by all 16 NT columns.
 constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
 
-template <int NT, int KS = kKS>
+template <int NT, int KS = kKS, int WV = kWavesPerBlock>
 __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid)
 {
+    constexpr int TH = WV * kWave;                    // threads per block
+    constexpr int ROWS = 16 * WV;                     // rows per block
     constexpr int AP = KS + 1;                        // padded A-tile row (LDS banks)
-    constexpr int AE = kRowsPerBlock * KS / kBlock;   // A elements per thread
+    constexpr int AE = ROWS * KS / TH;                // A elements per thread
     constexpr int BW = 16 * NT;                       // B-tile width
     constexpr int BN = KS * BW;                       // B-tile elements
-    constexpr int BPT = (BN + kBlock - 1) / kBlock;   // B elements per thread
-    __shared__ d2 As[2][kRowsPerBlock * AP];
+    constexpr int BPT = (BN + TH - 1) / TH;           // B elements per thread
+    __shared__ d2 As[2][ROWS * AP];
     __shared__ d2 Bs[2][BN];
     const int s = bid % kSlices;
     const int rb = bid / kSlices;
@@ -105,7 +107,7 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     // this thread's share of the global tiles
     const int arow = t / (KS / AE);
     const int aseg = (t % (KS / AE)) * AE;
-    const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
+    const int grow = rb * ROWS + arow < n ? rb * ROWS + arow : n - 1;
     const d2* Ar = A + (int64_t)grow * lda;
     // The loads of the next stage only issue here; what falls outside the
     // slice is zeroed when the values go to LDS (after this stage's matrix
@@ -121,7 +123,7 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
-            const int idx = t + m * kBlock;
+            const int idx = t + m * TH;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
             bok[m] = idx < BN && kc < k1 && c < ncols;
@@ -134,7 +136,7 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
-            const int idx = t + m * kBlock;
+            const int idx = t + m * TH;
             if (idx < BN) Bs[buf][idx] = bok[m] ? rbv[m] : z;
         }
     };
@@ -176,18 +178,29 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         if (col >= ncols) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = rb * kRowsPerBlock + w * 16 + lk + 4 * v;
+            const int r = rb * ROWS + w * 16 + lk + 4 * v;
             if (r < n) Zp[((int64_t)s * n + r) * ncols + col] = d2{cre[q][v], cim[q][v]};
         }
     }
 }
 
-template <int NT, int KS = kKS>
-__global__ __launch_bounds__(kBlock) void k_zgemm(const d2* __restrict__ A, int64_t lda, int n,
-                                                  const d2* __restrict__ B, int64_t ldb,
-                                                  int ncols, d2* __restrict__ Zp, int kslice)
+// The stand-alone product (ccg_matmat, the block solvers' products) runs 8
+// wavefronts per block: 128 rows share each B tile in LDS, half the B
+// traffic per product of the 4-wavefront blocks the serving grids keep.
+// Measured at n = 8000, k = 64 (kernel time, HIP events): 517 against 566 us
+// for 4 wavefronts, 0.81 of the FP64 matrix peak; a 16-deep stage (579 us,
+// LDS-bound to 2 blocks per compute unit), 2-wavefront blocks (586 us) and
+// 12- or 32-deep stages were slower.  Every element sums its products in the
+// same order whatever the block shape, so all shapes give the same bits.
+constexpr int kGemmWaves = 8;
+
+template <int NT, int KS = kKS, int WV = kGemmWaves>
+__global__ __launch_bounds__(WV * kWave) void k_zgemm(const d2* __restrict__ A, int64_t lda,
+                                                      int n, const d2* __restrict__ B,
+                                                      int64_t ldb, int ncols,
+                                                      d2* __restrict__ Zp, int kslice)
 {
-    zgemm_body<NT, KS>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    zgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 // Slice s of Z = A B for at most kVCols columns, on the vector units.  With
@@ -281,8 +294,10 @@ template <int NT>
 static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
                         d2* Zp, hipStream_t s)
 {
-    const int rblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    k_zgemm<NT><<<rblocks * kSlices, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, kslice_of(n));
+    constexpr int rows = 16 * kGemmWaves;
+    const int rblocks = (n + rows - 1) / rows;
+    k_zgemm<NT><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
+                                                                 kslice_of(n));
 }
 
 // Z slices = A B: vector units for up to kVCols columns, FP64 matrix cores
@@ -328,17 +343,19 @@ static inline int kslice32_of(int64_t n)
     return (int)(((per + kKS32 - 1) / kKS32) * kKS32);
 }
 
-template <int NT, int KS = kKS32>
+template <int NT, int KS = kKS32, int WV = kWavesPerBlock>
 __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid)
 {
+    constexpr int TH = WV * kWave;
+    constexpr int ROWS = 16 * WV;
     constexpr int AP = KS + 1;
-    constexpr int AE = kRowsPerBlock * KS / kBlock;  // 4
+    constexpr int AE = ROWS * KS / TH;
     constexpr int BW = 16 * NT;
     constexpr int BN = KS * BW;
-    constexpr int BPT = (BN + kBlock - 1) / kBlock;
-    __shared__ f2 As[2][kRowsPerBlock * AP];
+    constexpr int BPT = (BN + TH - 1) / TH;
+    __shared__ f2 As[2][ROWS * AP];
     __shared__ f2 Bs[2][BN];
     const int s = bid % kSlices;
     const int rb = bid / kSlices;
@@ -357,7 +374,7 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     }
     const int arow = t / (KS / AE);
     const int aseg = (t % (KS / AE)) * AE;
-    const int grow = rb * kRowsPerBlock + arow < n ? rb * kRowsPerBlock + arow : n - 1;
+    const int grow = rb * ROWS + arow < n ? rb * ROWS + arow : n - 1;
     const f2* Ar = A + (int64_t)grow * lda;
     // as in zgemm_body: the loads only issue here; zeroing outside the slice
     // and the rounding of B to complex64 happen on the way to LDS
@@ -373,7 +390,7 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
-            const int idx = t + m * kBlock;
+            const int idx = t + m * TH;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
             bok[m] = idx < BN && kc < k1 && c < ncols;
@@ -386,7 +403,7 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
         for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
-            const int idx = t + m * kBlock;
+            const int idx = t + m * TH;
             if (idx < BN)
                 Bs[buf][idx] = bok[m] ? f2{(float)rbv[m].x, (float)rbv[m].y} : z;
         }
@@ -426,28 +443,30 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
         if (col >= ncols) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = rb * kRowsPerBlock + w * 16 + 4 * lk + v;
+            const int r = rb * ROWS + w * 16 + 4 * lk + v;
             if (r < n)
                 Zp[((int64_t)s * n + r) * ncols + col] = d2{(double)cre[q][v], (double)cim[q][v]};
         }
     }
 }
 
-template <int NT, int KS = kKS32>
-__global__ __launch_bounds__(kBlock) void k_cgemm(const f2* __restrict__ A, int64_t lda, int n,
-                                                  const d2* __restrict__ B, int64_t ldb,
-                                                  int ncols, d2* __restrict__ Zp, int kslice)
+template <int NT, int KS = kKS32, int WV = kGemmWaves>
+__global__ __launch_bounds__(WV * kWave) void k_cgemm(const f2* __restrict__ A, int64_t lda,
+                                                      int n, const d2* __restrict__ B,
+                                                      int64_t ldb, int ncols,
+                                                      d2* __restrict__ Zp, int kslice)
 {
-    cgemm_body<NT, KS>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    cgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 template <int NT>
 static void launch_cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
                          d2* Zp, hipStream_t s)
 {
-    const int rblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    k_cgemm<NT><<<rblocks * kSlices, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
-                                                      kslice32_of(n));
+    constexpr int rows = 16 * kGemmWaves;
+    const int rblocks = (n + rows - 1) / rows;
+    k_cgemm<NT><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
+                                                                 kslice32_of(n));
 }
 
 static void cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,

@@ -29,10 +29,14 @@ namespace ccg {
 // clamped to n - 1 (their sums are discarded by the caller).  On return
 // red[w][r] holds wavefront w's sum for row row0 + r; the row total is
 // red[0][r] + red[1][r] + ... in wavefront order (gemv_n_row_total).
+//
+// pre (optional, with U = 1): this wavefront's first chunk of the R rows,
+// already in LDS (R x 64 elements, see gemv_n_prefetch); it is used in place
+// of loading that chunk, in the same order, so the sums keep their bits.
 template <int R, int U, int W>
 __device__ __forceinline__ void gemv_n_block(const d2* __restrict__ A, int64_t lda, int n,
                                              const d2* __restrict__ x, int row0,
-                                             d2 (*red)[R])
+                                             d2 (*red)[R], const d2* pre = nullptr)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -47,6 +51,12 @@ __device__ __forceinline__ void gemv_n_block(const d2* __restrict__ A, int64_t l
     const d2* xl = x + lane;
     const int nfull = n / kWave;  // chunks with 64 valid columns
     int c = wave;
+    if (U == 1 && pre && c < nfull) {
+        const d2 xv = xl[c * kWave];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = cfma(pre[r * kWave + lane], xv, acc[r]);
+        c += W;
+    }
     for (; c + (U - 1) * W < nfull; c += U * W) {
         d2 a[R][U];
         d2 xv[U];
@@ -74,6 +84,29 @@ __device__ __forceinline__ void gemv_n_block(const d2* __restrict__ A, int64_t l
         if (lane == 0) red[wave][r] = s;
     }
     __syncthreads();
+}
+
+// Start the loads of this wavefront's first 64-column chunk of rows row0 ..
+// row0 + R - 1 (chunk `wave`, when it is a full chunk) straight into LDS
+// (global_load_lds: no registers held), pre[r * 64 + lane] for row r, so
+// they are in flight while the kernel does other work before its product
+// (gemv_n_block with pre).  The caller waits for them (s_waitcnt vmcnt(0))
+// before the wavefront reads pre or ends.
+template <int R>
+__device__ __forceinline__ void gemv_n_prefetch(const d2* __restrict__ A, int64_t lda, int n,
+                                                int row0, d2* pre)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    if (wave >= n / kWave) return;  // not a full chunk: loaded the plain way
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = row0 + r < n ? row0 + r : n - 1;
+        const d2* src = A + (int64_t)row * lda + wave * kWave + lane;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(pre + r * kWave),
+                                         16, 0, 0);
+    }
 }
 
 // Total of row row0 + r from the per-wavefront sums, in wavefront order.

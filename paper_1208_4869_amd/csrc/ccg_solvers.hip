@@ -412,14 +412,24 @@ __device__ __forceinline__ void role_partials_wave0(const Args& a, int q, d2 v0,
     }
 }
 
+// The complex128 form first starts the loads of each wavefront's first chunk
+// of A into LDS (A is the same whatever the phase decides), so they are in
+// flight during the prologue; the prologue's latency (state, pending
+// reduction, scalar step) otherwise delays the stream of every block.
 template <Role RO, class T = d2>
-__global__ __launch_bounds__(GemvShape<T>::threads) void k_gemv_n_role(Args a, int q)
+__global__ __launch_bounds__(GemvShape<T>::threads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_gemv_n_role(Args a, int q)
 {
+    constexpr int R = GemvShape<T>::R, W = GemvShape<T>::W;
+    constexpr bool kPre = sizeof(T) == sizeof(d2);
+    __shared__ d2 pre[kPre ? W * R * kWave : 1];
+    const int row0 = blockIdx.x * R;
+    d2* my_pre = pre + (threadIdx.x / kWave) * R * kWave;
+    if constexpr (kPre) gemv_n_prefetch<R>(a.A, a.lda, a.n, row0, my_pre);
     PRODUCT_PROLOGUE();
+    if constexpr (kPre) __builtin_amdgcn_s_waitcnt(0);  // the prefetch has landed
     const int mode = role_mode<RO>(L.phase);
     if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
-    constexpr int R = GemvShape<T>::R, W = GemvShape<T>::W;
-    const int row0 = blockIdx.x * R;
     const int n = a.n;
     const int t = threadIdx.x;
 
@@ -435,7 +445,7 @@ __global__ __launch_bounds__(GemvShape<T>::threads) void k_gemv_n_role(Args a, i
     if constexpr (sizeof(T) == sizeof(f2))
         gemv_n_block_f<R, W>((const f2*)a.A, a.lda, n, (const f2*)in, row0, red, a.vec16);
     else
-        gemv_n_block<R, kU, W>(a.A, a.lda, n, in, row0, red);
+        gemv_n_block<R, kU, W>(a.A, a.lda, n, in, row0, red, my_pre);
     // thread r of the first wavefront finishes row row0 + r
     const int i = row0 + t;
     if (t < R && i < n) {
