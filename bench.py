@@ -46,8 +46,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lattice20.md")
 
 def measured_traffic(which="kernel"):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE record
-    (which = "kernel": the A x kernels; "sym": the upper-triangle product), or
-    None when the hashed kernel sources changed since it was taken."""
+    (which = "role": the A x role kernels inside the solvers; "kernel": the
+    plain products; "sym": the upper-triangle product), or None when that
+    group's hashed kernel sources changed since it was taken."""
     import hashlib
     try:
         line = [ln for ln in open(TRAFFIC_FILE) if ln.startswith("traffic-json:")][0]
@@ -826,12 +827,13 @@ def inputs_cn01(n):
 
 def profile_kernels(A, y):
     """A short, fixed mix for rocprofv3: a device copy of known size (the
-    reference for scaling the HBM byte counters), A x, A^H x, the complex64
-    product on complex64(A), the 64-column product A P, one BiCGSTAB and one
-    CGNR solve."""
+    reference for scaling the HBM byte counters), the read stream, A x, A^H x,
+    the upper-triangle and complex64 products, the 64-column products on
+    FP64 and FP32 matrix cores, one BiCGSTAB and one CGNR solve, and one
+    batched launch of 1024 n = 256 BiCGSTAB solves."""
     import torch
 
-    from paper_1208_4869_amd import ccg
+    from paper_1208_4869_amd import ccg, inputs
     n = A.shape[0]
     src = torch.empty(A.numel() * 2, dtype=torch.float64, device="cuda")
     src.fill_(1.0)
@@ -843,18 +845,30 @@ def profile_kernels(A, y):
     Z = torch.empty_like(P)
     wmm = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATMAT, n, BLOCK_RHS),
                       dtype=torch.uint8, device="cuda")
+    wmm32 = torch.empty(ccg.ccg_workspace_bytes(ccg.WS_MATMAT_C64, n, BLOCK_RHS),
+                        dtype=torch.uint8, device="cuda")
+    rs_out = ccg.ccg_read_stream(src)
     for _ in range(5):
         dst.copy_(src)
+        ccg.ccg_read_stream(src, rs_out)
         ccg.ccg_matvec(ccg.OP_N, A, x)
         ccg.ccg_matvec(ccg.OP_C, A, x)
         ccg.ccg_matvec(ccg.OP_S, A, x)
         ccg.ccg_matvec_c64(A32, x32)
         ccg.ccg_matmat(A, P, Z, work=wmm)
+        ccg.ccg_matmat_c64(A32, P, Z, work=wmm32)
     ccg.ccg_bicgstab_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
     ccg.ccg_cgnr_ex(A, y, torch.empty_like(x), TOL, MAXIT, flags=1)
+    del src, dst, A32
+    sys_ = [inputs.dense_system(CONFIG0_N, s) for s in range(CONFIG0_BATCH)]
+    Ab = torch.from_numpy(np.stack([a for a, _, _ in sys_])).cuda()
+    Yb = torch.from_numpy(np.stack([yy for _, _, yy in sys_])).cuda()
+    Xb = torch.empty_like(Yb)
+    ccg.ccg_solve_small_batched(ccg.WS_BICGSTAB, Ab, Yb, Xb, TOL, MAXIT, ccg.X0_ZERO)
     torch.cuda.synchronize()
-    log("profile mix done: copy %d bytes x5, matvec N/C/S/c64 x5, A P (k=%d) x5, "
-        "1 BiCGSTAB, 1 CGNR" % (src.numel() * 8, BLOCK_RHS))
+    log("profile mix done: copy %d bytes x5, read stream x5, matvec N/C/S/c64 x5, A P "
+        "FP64 and complex64 (k=%d) x5, 1 BiCGSTAB, 1 CGNR, 1 batch of %d n=%d BiCGSTAB"
+        % (A.numel() * 16, BLOCK_RHS, CONFIG0_BATCH, CONFIG0_N))
 
 
 def main():
@@ -905,12 +919,13 @@ def main():
         % (len(prod_us), prod_us.mean(), np.median(prod_us), gbs_in))
     read_gbs = read_stream_peak()
     trec = measured_traffic()
+    trole = measured_traffic("role")
     roofline = {"bound": "hbm",
                 "kernel": "k_gemv_n_role, role v (v = A p and the confirming residual) "
                           "inside the timed BiCGSTAB solves",
                 "achieved": gbs_in, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs_in / HBM_PEAK_GBS,
-                "traffic": trec.get("k_gemv_n_role_traffic_bytes") if trec else None,
+                "traffic": trole["k_gemv_n_role_traffic_bytes"] if trole else None,
                 "launch_us": t_in * 1e6, "launch_us_median": float(np.median(prod_us)),
                 "samples": int(len(prod_us)),
                 "sampling": "HIP events around every %dth role-v product launch of the timed "
