@@ -719,14 +719,17 @@ def serve_leg(nreq, rate):
             "all_converged": ok, "bitwise_equal_to_alone": bool(same)}
 
 
-def t3_bytes(m):
+def t3_bytes(m, even=True):
     """Algorithmic HBM bytes of one structured product: x and y, the kernel
-    transform (M^3), and the two intermediate grids, each written once and
-    read once per direction (G1: M m^2, G2: M^2 m)."""
-    M = 1
+    transform (M^3 points; (M/2 + 1)^2 M for a kernel even in x and y, as
+    the lattice kernel, whose rows of frequencies |kx|, |ky| <= M/2 are the
+    only distinct ones), and the two intermediate grids, each written once
+    and read once per direction (G1: M m^2, G2: M^2 m)."""
+    M = 16
     while M < 2 * m - 1:
         M *= 2
-    return 16.0 * (2 * m ** 3 + M ** 3 + 4 * M * m * m + 4 * M * M * m), M
+    k = (M // 2 + 1) ** 2 * M if even else M ** 3
+    return 16.0 * (2 * m ** 3 + k + 4 * M * m * m + 4 * M * M * m), M
 
 
 def structured_leg(steps):

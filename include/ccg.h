@@ -453,8 +453,12 @@ int ccg_bicgstab_block_mixed_ex(int64_t n, int64_t k, const ccg_z* A,
  * discrete-dipole systems of the Introduction, used through the user's own
  * matrix scheme that the Usage section leaves to the caller's matvec.  The
  * product is a zero-padded 3-D FFT convolution on an M^3 grid (M the
- * smallest power of two >= 2m - 1; 1 <= m <= 128): O(n log n) work and O(n)
- * memory instead of the dense 16 n^2 bytes.
+ * smallest power of two >= max(2m - 1, 16); 1 <= m <= 128): O(n log n) work
+ * and O(n) memory instead of the dense 16 n^2 bytes.  A kernel even in x and
+ * in y (T(-dx, dy, dz) = T(dx, dy, dz) = T(dx, -dy, dz) bit for bit, as the
+ * lattice kernel, a function of |d|) is detected at set-up; its transform is
+ * then kept for the frequencies |kx|, |ky| <= M/2 only, a quarter of the
+ * bytes each product streams for it.
  *
  * ccg_t3_setup: 1 m, 2 table (device, (2m-1)^3 complex128; displacement
  * (dx, dy, dz) at ((dz+m-1)(2m-1) + (dy+m-1))(2m-1) + (dx+m-1); the zero

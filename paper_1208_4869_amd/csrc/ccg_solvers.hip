@@ -466,19 +466,21 @@ void k_gemv_n_role(Args a, int q)
 // (k_t3p_*); the last pass finishes the product and does what k_gemv_n_role
 // does with each element.
 
-template <Role RO, int R>
+template <Role RO, int M>
 __global__ __launch_bounds__(kBlock) void k_t3_x(Args a, int q)
 {
     SOLVER_PROLOGUE();
+    __shared__ d2 tile[T3Shape<M>::T * M];
     const int mode = role_mode<RO>(L.phase);
-    if (mode >= 0 && mode != PH_ZERO) t3_pass_x<R>(a.t3, role_input<RO>(a, mode));
+    if (mode >= 0 && mode != PH_ZERO) t3_pass_x<M>(a.t3, role_input<RO>(a, mode), tile);
     publish(a, q, L, PK_NONE, 0);
 }
 
-template <Role RO, int R>
+template <Role RO, int M>
 __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
 {
     SOLVER_PROLOGUE();
+    __shared__ d2 tile[T3Shape<M>::T * M];
     const int mode = role_mode<RO>(L.phase);
     if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
     if (mode == PH_ZERO) {  // y == 0: x = 0
@@ -487,15 +489,16 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
         publish(a, q, L, PK_ZERO, 0);
         return;
     }
-    d2 v[R];
-    const int line = t3_pass_xi<R>(a.t3, v);
+    const T3Thread<M> th;
+    d2 v[kT3Pts];
+    const int line = t3_pass_xi<M>(a.t3, th, v, tile);
     d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0}, pv2 = d2{0.0, 0.0};
     if (line >= 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int ix = t3_point(r);
+        for (int s = 0; s < kT3Pts / 2; ++s) {  // points < M/2: every ix < m
+            const int ix = th.point(s);
             if (ix < a.t3.m) {
-                const Terms tm = role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[r]);
+                const Terms tm = role_finish<RO, d2>(a, mode, ix + a.t3.m * line, v[s]);
                 pv0 += tm.t0;
                 pv1 += tm.t1;
                 pv2 += tm.t2;
@@ -861,27 +864,42 @@ __global__ __launch_bounds__(kBlock) void k_symv_gather_plain(SymGeom g, int n,
 
 // ------------------------------------------ structured product, plain and set-up
 
-template <int R>
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_x(T3Geom g, const d2* __restrict__ x)
 {
-    t3_pass_x<R>(g, x);
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    t3_pass_x<M>(g, x, tile);
 }
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3p_y(T3Geom g) { t3_pass_y<R>(g); }
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3p_z(T3Geom g) { t3_pass_z<R>(g); }
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3p_yi(T3Geom g) { t3_pass_yi<R>(g); }
-template <int R>
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3p_y(T3Geom g)
+{
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    t3_pass_y<M>(g, tile);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3p_z(T3Geom g)
+{
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    t3_pass_z<M>(g, tile);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3p_yi(T3Geom g)
+{
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    t3_pass_yi<M>(g, tile);
+}
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_xi(T3Geom g, d2* __restrict__ y)
 {
-    d2 v[R];
-    const int line = t3_pass_xi<R>(g, v);
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    const T3Thread<M> th;
+    d2 v[kT3Pts];
+    const int line = t3_pass_xi<M>(g, th, v, tile);
     if (line < 0) return;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int ix = t3_point(r);
-        if (ix < g.m) y[ix + (int64_t)g.m * line] = v[r];
+    for (int s = 0; s < kT3Pts / 2; ++s) {  // points < M/2: every ix < m
+        const int ix = th.point(s);
+        if (ix < g.m) y[ix + g.m * line] = v[s];
     }
 }
 
@@ -905,79 +923,96 @@ __device__ __forceinline__ bool t3_disp(int c, int m, int M, int& d)
     return false;
 }
 
-// Set-up pass 1: lines (y, z) of the wrapped kernel, forward along x ->
-// S[(z M + kx) M + y].  table: (2m-1)^3 values, displacement (dx, dy, dz) at
-// ((dz + m-1)(2m-1) + (dy + m-1))(2m-1) + (dx + m-1).
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3_s1(const d2* __restrict__ table, T3Geom g,
-                                                  d2* __restrict__ S)
+// Whether the kernel table is even in x and in y: T(-dx, dy, dz) and
+// T(dx, -dy, dz) equal T(dx, dy, dz) bit for bit.  k_t3_even_init sets the
+// flag, k_t3_even clears it at any pair that differs.
+__global__ void k_t3_even_init(int* even) { *even = 1; }
+
+__global__ __launch_bounds__(kBlock) void k_t3_even(const d2* __restrict__ table, int m,
+                                                    int* even)
 {
-    const int m = g.m, M = g.M, w = 2 * m - 1;
-    const int line = t3_line();
-    if (line >= M * M) return;
-    const int y = line % M, z = line / M;
+    const int w = 2 * m - 1;
+    const int64_t n = (int64_t)w * w * w;
+    bool odd = false;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int ax = (int)(e % w), ay = (int)((e / w) % w);
+        const int64_t row = e - ax - (int64_t)ay * w;  // (az, 0, 0)
+        const d2 t = table[e];
+        const d2 tx = table[row + (int64_t)ay * w + (w - 1 - ax)];
+        const d2 ty = table[row + (int64_t)(w - 1 - ay) * w + ax];
+        odd |= __builtin_bit_cast(uint64_t, t.x) != __builtin_bit_cast(uint64_t, tx.x) ||
+               __builtin_bit_cast(uint64_t, t.y) != __builtin_bit_cast(uint64_t, tx.y) ||
+               __builtin_bit_cast(uint64_t, t.x) != __builtin_bit_cast(uint64_t, ty.x) ||
+               __builtin_bit_cast(uint64_t, t.y) != __builtin_bit_cast(uint64_t, ty.y);
+    }
+    if (odd) *even = 0;  // every writer writes the same value
+}
+
+// Set-up pass 1: lines y + M z of the wrapped kernel, forward along x ->
+// S1[(z M + kx) M + y].  table: (2m-1)^3 values, displacement (dx, dy, dz) at
+// ((dz + m-1)(2m-1) + (dy + m-1))(2m-1) + (dx + m-1).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3_s1(const d2* __restrict__ table, T3Geom g,
+                                                  d2* __restrict__ S1)
+{
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    const int m = g.m, w = 2 * m - 1;
+    const T3Thread<M> th;  // every line of the M^2 exists (M^2 is a multiple of T)
+    const int y = th.line % M, z = th.line / M;
     int dy = 0, dz = 0;
     const bool yz = t3_disp(y, m, M, dy) && t3_disp(z, m, M, dz);
-    d2 v[R];
+    d2 v[kT3Pts];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int x = t3_point(r);
+    for (int s = 0; s < kT3Pts; ++s) {
         int dx = 0;
-        const bool ok = yz && x < M && t3_disp(x, m, M, dx);
-        v[r] = ok ? table[((int64_t)(dz + m - 1) * w + (dy + m - 1)) * w + (dx + m - 1)]
+        const bool ok = yz && t3_disp(th.point(s), m, M, dx);
+        v[s] = ok ? table[((int64_t)(dz + m - 1) * w + (dy + m - 1)) * w + (dx + m - 1)]
                   : d2{0.0, 0.0};
     }
-    t3_fwd<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int kx = t3_point(r);
-        if (kx < M) S[((int64_t)z * M + kx) * M + y] = v[r];
-    }
+    t3_forward<M, false>(v, th.u, th.il, tile, T3Tw<M>(th.u, g.tw));
+    const T3Strided<M> sd;
+    d2* out = S1 + (sd.line / M) * M * M + sd.line % M;
+    t3_tile_store<M>(th, v, tile, out, M, true);
 }
 
-// Set-up pass 2: lines (kx, z), forward along y -> K[(kx M + ky) M + z]
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3_s2(T3Geom g, const d2* __restrict__ S,
-                                                  d2* __restrict__ K)
+// Set-up pass 2: lines z + M kx, forward along y -> S2[(kx M + ky) M + z]
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3_s2(T3Geom g, const d2* __restrict__ S1,
+                                                  d2* __restrict__ S2)
 {
-    const int M = g.M;
-    const int line = t3_line();
-    if (line >= M * M) return;
-    const int kx = line % M, z = line / M;
-    d2 v[R];
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    const T3Thread<M> th;
+    const d2* in = S1 + ((th.line % M) * M + th.line / M) * M;
+    d2 v[kT3Pts];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int y = t3_point(r);
-        v[r] = y < M ? S[((int64_t)z * M + kx) * M + y] : d2{0.0, 0.0};
-    }
-    t3_fwd<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int ky = t3_point(r);
-        if (ky < M) K[((int64_t)kx * M + ky) * M + z] = v[r];
-    }
+    for (int s = 0; s < kT3Pts; ++s) v[s] = in[th.point(s)];
+    t3_forward<M, false>(v, th.u, th.il, tile, T3Tw<M>(th.u, g.tw));
+    const T3Strided<M> sd;
+    d2* out = S2 + (sd.line / M) * M * M + sd.line % M;
+    t3_tile_store<M>(th, v, tile, out, M, true);
 }
 
-// Set-up pass 3: lines (kx, ky), forward along z, times M^-3 (exact), in place
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_t3_s3(T3Geom g, d2* __restrict__ K, double scale)
+// Set-up pass 3: lines kx M + ky of S2, forward along z, times M^-3 (exact)
+// -> K, in register order, at the row t3_krow gives (a kernel even in x and
+// y: only the lines whose frequencies are both <= M/2).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3_s3(T3Geom g, const d2* __restrict__ S2,
+                                                  d2* __restrict__ K, double scale)
 {
-    const int M = g.M;
-    const int line = t3_line();
-    if (line >= M * M) return;
-    d2* row = K + (int64_t)line * M;
-    d2 v[R];
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    const T3Thread<M> th;
+    const d2* in = S2 + th.line * M;
+    d2 v[kT3Pts];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int z = t3_point(r);
-        v[r] = z < M ? row[z] : d2{0.0, 0.0};
-    }
-    t3_fwd<R>(v, M, g.tw);
+    for (int s = 0; s < kT3Pts; ++s) v[s] = in[th.point(s)];
+    t3_forward<M, false>(v, th.u, th.il, tile, T3Tw<M>(th.u, g.tw));
+    const int qx = th.line / M, qy = th.line % M;
+    const bool even = *g.even != 0;
+    if (even && (t3_freq<M>(qx) > M / 2 || t3_freq<M>(qy) > M / 2)) return;
+    d2* row = K + t3_krow<M>(qx, qy, even) * M;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int kz = t3_point(r);
-        if (kz < M) row[kz] = d2{v[r].x * scale, v[r].y * scale};
-    }
+    for (int s = 0; s < kT3Pts; ++s) row[th.point(s)] = d2{v[s].x * scale, v[s].y * scale};
 }
 
 // ================================================================== host
@@ -1127,9 +1162,26 @@ static int ws_of(int M)
          : M == M_COCG ? CCG_WS_COCG : CCG_WS_COCR;
 }
 
-static inline int t3_blocks(int64_t lines)
+// Padded edges of the structured product: one instantiation per power of two.
+#define T3_DISPATCH(Mv, call)                      \
+    switch (Mv) {                                  \
+    case 16: call(16); break;                      \
+    case 32: call(32); break;                      \
+    case 64: call(64); break;                      \
+    case 128: call(128); break;                    \
+    default: call(256); break;                     \
+    }
+
+// Workgroups of the first and last pass of a product (and so the partial
+// count of a structured solver's product): tiles over the m^2 lines.
+static int t3_edge_tiles(int64_t m)
 {
-    return (int)((lines + kT3LinesPerBlock - 1) / kT3LinesPerBlock);
+    const int M = t3_padded((int)m);
+    int64_t t = 0;
+#define T3_TILES(Mc) t = t3_tiles<Mc>(t3_row((int)m) * m)
+    T3_DISPATCH(M, T3_TILES)
+#undef T3_TILES
+    return (int)(t > 0 ? t : 1);
 }
 
 // The five passes of a structured product of role RO (state copy q in, q
@@ -1138,18 +1190,18 @@ static inline int t3_blocks(int64_t lines)
 // (when the first pass had nothing to transform they work on stale grid
 // data that the last pass then ignores), which spares each of them the
 // dependent load of the state at its start.
-template <Role RO, int R>
+template <Role RO, int M>
 static void launch_t3_role(const Args& a, int& q, hipStream_t s)
 {
-    const int64_t m = a.t3.m, M = a.t3.M;
+    const int64_t m = a.t3.m, mp = a.t3.mp;
     Args b = a;  // only the first pass reports a status word
     b.status = nullptr;
-    k_t3_x<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(a, q);
+    k_t3_x<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(a, q);
     q ^= 1;
-    k_t3p_y<R><<<t3_blocks(M * m), kBlock, 0, s>>>(a.t3);
-    k_t3p_z<R><<<t3_blocks(M * M), kBlock, 0, s>>>(a.t3);
-    k_t3p_yi<R><<<t3_blocks(M * m), kBlock, 0, s>>>(a.t3);
-    k_t3_role<RO, R><<<t3_blocks(m * m), kBlock, 0, s>>>(b, q);
+    k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
+    k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(a.t3);
+    k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
+    k_t3_role<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(b, q);
     q ^= 1;
 }
 
@@ -1212,12 +1264,9 @@ template <Role RO, class T, bool S3>
 static void launch_product(const Args& a, int& q, hipStream_t s)
 {
     if constexpr (S3) {
-        if (a.t3.M <= kWave)
-            launch_t3_role<RO, 1>(a, q, s);
-        else if (a.t3.M == 2 * kWave)
-            launch_t3_role<RO, 2>(a, q, s);
-        else
-            launch_t3_role<RO, 4>(a, q, s);
+#define T3_ROLE(Mc) launch_t3_role<RO, Mc>(a, q, s)
+        T3_DISPATCH(a.t3.M, T3_ROLE)
+#undef T3_ROLE
     } else if (sizeof(T) == sizeof(d2) && a.sym.T > 0) {
         launch_sym_role<RO>(a, q, s);
     } else if constexpr (sizeof(T) == sizeof(d2)) {
@@ -1874,9 +1923,11 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
 
 static constexpr int64_t kT3MaxEdge = kT3MaxM / 2;  // lattice edge m <= 128
 
+// The operator buffer: twiddles | evenness flag | K (M^3 points, or the
+// (M/2 + 1)^2 M of the folded rows) | set-up scratch (M^3).
 struct T3OpLayout {
     int M;
-    size_t tw, K, S, total;
+    size_t tw, even, K, S, total;
 };
 
 static T3OpLayout t3_op_layout(int64_t m)
@@ -1885,17 +1936,18 @@ static T3OpLayout t3_op_layout(int64_t m)
     L.M = t3_padded((int)m);
     const size_t M3 = (size_t)L.M * L.M * L.M;
     L.tw = 0;
-    L.K = align256((size_t)(L.M / 2 > 0 ? L.M / 2 : 1) * sizeof(d2));
+    L.even = align256((size_t)(L.M / 2) * sizeof(d2));
+    L.K = L.even + 256;
     L.S = L.K + align256(M3 * sizeof(d2));
-    L.total = L.S + align256(M3 * sizeof(d2));  // S: set-up scratch
+    L.total = L.S + align256(M3 * sizeof(d2));
     return L;
 }
 
-// Scratch of one product: G1 (M m^2) and G2 (M^2 m).
+// Scratch of one product: G1 (M m mp) and G2 (M^2 mp).
 static size_t t3_grid_bytes(int64_t m)
 {
-    const size_t M = (size_t)t3_padded((int)m);
-    return align256(M * m * m * sizeof(d2)) + align256(M * M * m * sizeof(d2));
+    const size_t M = (size_t)t3_padded((int)m), mp = (size_t)t3_row((int)m);
+    return align256(M * m * mp * sizeof(d2)) + align256(M * M * mp * sizeof(d2));
 }
 
 static T3Geom t3_geom(int64_t m, const void* op, void* grids)
@@ -1904,10 +1956,12 @@ static T3Geom t3_geom(int64_t m, const void* op, void* grids)
     T3Geom g{};
     g.m = (int)m;
     g.M = L.M;
+    g.mp = t3_row((int)m);
     g.tw = (const d2*)((const char*)op + L.tw);
+    g.even = (const int*)((const char*)op + L.even);
     g.K = (const d2*)((const char*)op + L.K);
     g.g1 = (d2*)grids;
-    g.g2 = (d2*)((char*)grids + align256((size_t)L.M * m * m * sizeof(d2)));
+    g.g2 = (d2*)((char*)grids + align256((size_t)L.M * m * g.mp * sizeof(d2)));
     return g;
 }
 
@@ -1915,31 +1969,34 @@ static size_t t3_workspace(int method, int64_t m)
 {
     if (method == CCG_WS_T3_MATVEC) return t3_grid_bytes(m);
     const int64_t n = m * m * m;
-    return layout(method, n, t3_blocks(m * m)).total + t3_grid_bytes(m);
+    return layout(method, n, t3_edge_tiles(m)).total + t3_grid_bytes(m);
 }
 
-template <int R>
+template <int M>
 static void t3_matvec_launch(const T3Geom& g, const d2* x, d2* y, hipStream_t s)
 {
-    const int64_t m = g.m, M = g.M;
-    k_t3p_x<R><<<t3_blocks(m * m), kBlock, 0, s>>>(g, x);
-    k_t3p_y<R><<<t3_blocks(M * m), kBlock, 0, s>>>(g);
-    k_t3p_z<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g);
-    k_t3p_yi<R><<<t3_blocks(M * m), kBlock, 0, s>>>(g);
-    k_t3p_xi<R><<<t3_blocks(m * m), kBlock, 0, s>>>(g, y);
+    const int64_t m = g.m, mp = g.mp;
+    k_t3p_x<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, x);
+    k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
+    k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(g);
+    k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
+    k_t3p_xi<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, y);
 }
 
-template <int R>
+template <int M>
 static void t3_setup_launch(const T3Geom& g, const d2* table, d2* K, d2* S, hipStream_t s)
 {
-    const int64_t M = g.M;
-    k_t3_twiddle<<<(int)((M / 2 + kBlock - 1) / kBlock > 0 ? (M / 2 + kBlock - 1) / kBlock : 1),
-                   kBlock, 0, s>>>((d2*)g.tw, (int)M);
-    k_t3_s1<R><<<t3_blocks(M * M), kBlock, 0, s>>>(table, g, S);
-    k_t3_s2<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g, S, K);
-    int lg = 0;
-    while ((1 << lg) < M) ++lg;
-    k_t3_s3<R><<<t3_blocks(M * M), kBlock, 0, s>>>(g, K, std::ldexp(1.0, -3 * lg));
+    k_t3_twiddle<<<(M / 2 + kBlock - 1) / kBlock, kBlock, 0, s>>>((d2*)g.tw, M);
+    int* even = (int*)g.even;
+    k_t3_even_init<<<1, 1, 0, s>>>(even);
+    const int64_t w = 2 * g.m - 1;
+    const int64_t eb = (w * w * w + kBlock - 1) / kBlock;
+    k_t3_even<<<(int)(eb < 4096 ? eb : 4096), kBlock, 0, s>>>(table, g.m, even);
+    const int tiles = (int)t3_tiles<M>(M * M);
+    // K's region holds pass 1's output until pass 3 writes the transform
+    k_t3_s1<M><<<tiles, kBlock, 0, s>>>(table, g, K);
+    k_t3_s2<M><<<tiles, kBlock, 0, s>>>(g, K, S);
+    k_t3_s3<M><<<tiles, kBlock, 0, s>>>(g, S, K, std::ldexp(1.0, -3 * T3Shape<M>::LG));
 }
 
 static int t3_setup_impl(int64_t m, const ccg_z* table, void* op, size_t op_bytes, void* stream)
@@ -1953,12 +2010,9 @@ static int t3_setup_impl(int64_t m, const ccg_z* table, void* op, size_t op_byte
     T3Geom g = t3_geom(m, op, nullptr);
     d2* K = (d2*)((char*)op + L.K);
     d2* S = (d2*)((char*)op + L.S);
-    if (L.M <= kWave)
-        t3_setup_launch<1>(g, (const d2*)table, K, S, s);
-    else if (L.M == 2 * kWave)
-        t3_setup_launch<2>(g, (const d2*)table, K, S, s);
-    else
-        t3_setup_launch<4>(g, (const d2*)table, K, S, s);
+#define T3_SETUP(Mc) t3_setup_launch<Mc>(g, (const d2*)table, K, S, s)
+    T3_DISPATCH(L.M, T3_SETUP)
+#undef T3_SETUP
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;
 }
@@ -1975,12 +2029,9 @@ static int t3_matvec_impl(int64_t m, const void* op, const ccg_z* x, ccg_z* y, v
     if (work_bytes < t3_grid_bytes(m)) return -6;
     const T3Geom g = t3_geom(m, op, work);
     hipStream_t s = (hipStream_t)stream;
-    if (g.M <= kWave)
-        t3_matvec_launch<1>(g, (const d2*)x, (d2*)y, s);
-    else if (g.M == 2 * kWave)
-        t3_matvec_launch<2>(g, (const d2*)x, (d2*)y, s);
-    else
-        t3_matvec_launch<4>(g, (const d2*)x, (d2*)y, s);
+#define T3_MATVEC(Mc) t3_matvec_launch<Mc>(g, (const d2*)x, (d2*)y, s)
+    T3_DISPATCH(g.M, T3_MATVEC)
+#undef T3_MATVEC
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;
 }
@@ -2007,7 +2058,7 @@ static int t3_solve(int64_t m, const void* op, const ccg_z* y, ccg_z* x, double 
         return 0;
     }
     const int64_t n = m * m * m;
-    const Layout L = layout(method, n, t3_blocks(m * m));
+    const Layout L = layout(method, n, t3_edge_tiles(m));
     // make_args carves the vectors and partial buffers with the default
     // partial count; rebuild them here with the structured one
     Args a = make_args(method, n, nullptr, 1, y, x, work, hist);

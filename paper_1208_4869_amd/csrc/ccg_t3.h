@@ -9,43 +9,115 @@
 // (A x)(p) = sum_q T(p - q) x(q), a linear convolution, which equals the
 // circular convolution on an M^3 grid with M >= 2m - 1 when x is zero-padded
 // and T is wrapped (T(d) stored at d mod M).  Here M is the smallest power of
-// two >= 2m - 1 (at most 256).
+// two >= max(2m - 1, 16) (at most 256).
 //
-// The transforms.  One wavefront transforms one line of M points (lane l
-// holds points l, l + 64, ... for M > 64).  Forward: radix-2 decimation in
-// frequency (natural order in, bit-reversed order out) with twiddles
-// W^t = e^{-2 pi i t / M}; the kernel's transform is produced by the same
-// passes, so the pointwise product is taken in the bit-reversed layout and no
-// reordering pass is needed.  Inverse: decimation in time with conjugate
-// twiddles (bit-reversed in, natural out), which undoes the forward stages
-// exactly up to a factor 2 per stage; the factor M^3 is folded into the
-// kernel's transform at set-up (a power of two: exact).  Pairs at span h < 64
-// are exchanged between lanes with xor shuffles; spans >= 64 are within a
-// lane's registers.
+// The transforms.  A line of M points is held by M/8 threads, 8 points each,
+// and transformed by mixed-radix decimation in frequency: phases of radix 8
+// (the last one of radix 2, 4 or 8 as log2 M dictates).  A phase of radix R
+// on sub-blocks of L points takes, for each offset p1 < L/R of a sub-block,
+// the R points p1 + (L/R) p2, forms their R-point DFT in registers (three,
+// two or one radix-2 stages with constant twiddles), multiplies output k2 by
+// W_L^{p1 k2} (W_L = e^{-2 pi i / L}) and leaves it at p1 + (L/R) k2; the
+// next phase works on the sub-blocks of L/R points so formed.  Between
+// phases the points move through LDS.  The forward transform so ends in a
+// digit-reversed order; every operand of a pointwise product (the kernel's
+// transform is made by the same passes) is in that order, and the inverse
+// transform undoes the phases in reverse order (conjugate twiddles before
+// each inverse R-point DFT), returning natural order, times M.  The factor
+// M^3 of the three inverse transforms is folded into the kernel's transform
+// at set-up (a power of two: exact).
 //
-// Passes of one product (x -> y), each a grid of lines:
-//   X1: lines (iy, iz), forward along x; x zero-padded         -> G1[iz][kx][iy]
-//   X2: lines (kx, iz), forward along y                          -> G2[kx][ky][iz]
-//   X3: lines (kx, ky), forward along z, times K, inverse along z -> G2 (in place)
-//   X4: lines (kx, iz), inverse along y, keep iy < m              -> G1[iz][kx][iy]
-//   X5: lines (iy, iz), inverse along x, keep ix < m              -> y
-// (G1 holds M m^2 points, G2 M^2 m; only the m planes that the zero padding
-// and the final crop leave nonzero are ever transformed.)
+// Tiles.  A workgroup of 256 threads transforms T = 2048 / M whole lines
+// (a line never straddles two wavefronts).  The lines of a tile are
+// consecutive in the pass's line numbering, which is chosen so that the
+// strided side of the pass (the axis being transformed is not the fastest
+// of its array) is consecutive lines at a fixed point: those accesses go
+// through the LDS tile, T neighbouring values per point, while the
+// contiguous side loads or stores each line's run directly.
+//
+// Passes of one product (x -> y); line numberings:
+//   X1: line iy + mp iz,  forward along x; x zero-padded          -> G1[iz][kx][iy]
+//   X2: line iz + mp kx,  forward along y                          -> G2[kx][ky][iz]
+//   X3: line kx M + ky,   forward along z, times K, inverse along z -> G2 (in place)
+//   X4: line iz + mp kx,  inverse along y, keep iy < m              -> G1[iz][kx][iy]
+//   X5: line iy + mp iz,  inverse along x, keep ix < m              -> y
+// (G1 holds M m mp points, G2 M^2 mp, mp = m rounded up to 8 (the lines
+// iy or iz >= m of the numberings are padding and do nothing): only the m
+// planes that the zero padding and the final crop leave nonzero are ever
+// transformed.)  K is stored per
+// line in the order the threads hold it after the forward transform (point
+// s of thread u at s M/8 + u), so that X3 reads it with unit stride.
 #pragma once
 
 #include "ccg_device.h"
 
 namespace ccg {
 
-constexpr int kT3MaxM = 256;     // largest padded grid edge
-constexpr int kT3LinesPerBlock = kBlock / kWave;
+constexpr int kT3MinM = 16;   // smallest padded edge (every phase shape has a swizzle)
+constexpr int kT3MaxM = 256;  // largest padded edge
+constexpr int kT3Pts = 8;     // points per thread
 
-// Padded edge for an m-point lattice edge: the smallest power of two >= 2m - 1.
+// Padded edge for an m-point lattice edge: the smallest power of two
+// >= max(2m - 1, kT3MinM); any such edge gives the same linear convolution.
 __host__ __device__ inline int t3_padded(int m)
 {
-    int M = 1;
+    int M = kT3MinM;
     while (M < 2 * m - 1) M <<= 1;
     return M;
+}
+
+template <int M>
+struct T3Shape {
+    static_assert(M >= kT3MinM && M <= kT3MaxM && (M & (M - 1)) == 0, "padded edge");
+    static constexpr int TPL = M / kT3Pts;   // threads per line
+    static constexpr int T = kBlock / TPL;    // lines per tile
+    static constexpr int LG = M == 16 ? 4 : M == 32 ? 5 : M == 64 ? 6 : M == 128 ? 7 : 8;
+    static constexpr int NPH = LG / 3 + (LG % 3 ? 1 : 0);  // phases
+    static constexpr int radix(int j) { return j < LG / 3 ? 8 : 1 << (LG % 3); }
+    // sub-block length of phase j (every earlier phase has radix 8)
+    static constexpr int sublen(int j) { return M >> (3 * j); }
+};
+
+// Lines of a pass over `lines` lines.
+template <int M>
+constexpr int64_t t3_tiles(int64_t lines)
+{
+    return (lines + T3Shape<M>::T - 1) / T3Shape<M>::T;
+}
+
+__host__ __device__ constexpr int t3_bitrev(int j, int R)
+{
+    return R == 8 ? ((j & 1) << 2) | (j & 2) | ((j >> 2) & 1) : R == 4 ? ((j & 1) << 1) | (j >> 1)
+                                                                        : j;
+}
+
+// Point (position in the line) of slot s of thread u before phase J
+// (natural digit order within the R-point group) and after it (the R-point
+// DFT leaves its outputs in bit-reversed slot order).
+template <int M, int J>
+__device__ __forceinline__ int t3_pos_in(int u, int s)
+{
+    using S = T3Shape<M>;
+    constexpr int R = S::radix(J), L = S::sublen(J), Q = L / R;
+    const int g = u + S::TPL * (s / R);
+    return (g / Q) * L + (g % Q) + Q * (s % R);
+}
+template <int M, int J>
+__device__ __forceinline__ int t3_pos_out(int u, int s)
+{
+    using S = T3Shape<M>;
+    constexpr int R = S::radix(J);
+    return t3_pos_in<M, J>(u, (s / R) * R + t3_bitrev(s % R, R));
+}
+
+// LDS index of point p of line il of a tile: p with its low four bits
+// permuted by higher bits of p and by il, so that each phase's exchange
+// and the tile's strided loads and stores meet few bank conflicts.
+template <int M>
+__device__ __forceinline__ int t3_lds(int il, int p)
+{
+    const int f = (((p >> 4) & 3) ^ (((p >> 5) & 3) << 2) ^ (il << 1)) & 15;
+    return il * M + (p ^ f);
 }
 
 __device__ __forceinline__ d2 cmul_conj(d2 a, d2 w)  // a * conj(w)
@@ -53,231 +125,470 @@ __device__ __forceinline__ d2 cmul_conj(d2 a, d2 w)  // a * conj(w)
     return d2{a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
-__device__ __forceinline__ d2 shfl_xor_d2(d2 v, int mask)
+// a * W_N^t (conj: a * conj(W_N^t)) for the small roots of the in-register
+// DFTs: N in {2, 4, 8}, t < N/2, both constants after unrolling.
+__device__ __forceinline__ d2 t3_wsmall(d2 a, int N, int t, bool conj)
 {
-    return d2{__shfl_xor(v.x, mask, kWave), __shfl_xor(v.y, mask, kWave)};
+    constexpr double c = 0.70710678118654752440;  // sqrt(1/2)
+    const int e = t * (8 / N);  // eighths of a turn
+    if (e == 0) return a;
+    if (e == 2) return conj ? d2{-a.y, a.x} : d2{a.y, -a.x};  // -i (conj: +i)
+    if (e == 1)                                               // (1 - i)/sqrt2 (conj: 1 + i)
+        return conj ? d2{c * (a.x - a.y), c * (a.x + a.y)} : d2{c * (a.x + a.y), c * (a.y - a.x)};
+    // e == 3: (-1 - i)/sqrt2 (conj: -1 + i)
+    return conj ? d2{-c * (a.x + a.y), c * (a.x - a.y)} : d2{c * (a.y - a.x), -c * (a.x + a.y)};
 }
 
-// Lane stages of a transform: spans h = top, top/2, ..., 1 with top =
-// min(M/2, 32): at most six.  Their twiddles are loaded for all stages before
-// the first butterfly (fixed-length loops, unrolled, guarded by h >= 1), so
-// the loads are in flight together instead of one per stage.
-constexpr int kLaneStages = 6;
-
-__device__ __forceinline__ int t3_top(int M) { return M < kWave ? M / 2 : kWave / 2; }
-
-// Forward transform of one line held as R registers per lane (R = M / 64 for
-// M >= 64, else 1 with lanes >= M idle).  tw[t] = e^{-2 pi i t / M}, t < M/2.
+// R-point DFT of slots [b, b + R): radix-2 decimation in frequency, natural
+// order in, bit-reversed order out.
 template <int R>
-__device__ __forceinline__ void t3_fwd(d2 (&v)[R], int M, const d2* __restrict__ tw)
+__device__ __forceinline__ void t3_dft(d2 (&v)[kT3Pts], int b)
 {
-    const int l = threadIdx.x & (kWave - 1);
-    const int top = t3_top(M);
-    d2 w[kLaneStages];
 #pragma unroll
-    for (int i = 0; i < kLaneStages; ++i) {
-        const int h = top >> i;
-        w[i] = h >= 1 ? tw[(l & (h - 1)) * (M / (2 * h))] : d2{1.0, 0.0};
-    }
-    // spans held in registers (h >= 64)
+    for (int h = R / 2; h >= 1; h >>= 1)
 #pragma unroll
-    for (int hr = R / 2; hr >= 1; hr >>= 1) {
-        const int h = hr * kWave;
-        const int step = M / (2 * h);
+        for (int k = 0; k < R; ++k) {
+            if (k & h) continue;
+            const d2 a = v[b + k], c = v[b + k + h];
+            v[b + k] = a + c;
+            v[b + k + h] = t3_wsmall(a - c, 2 * h, k & (h - 1), false);
+        }
+}
+
+// Inverse of t3_dft up to the factor R: bit-reversed in, natural out.
+template <int R>
+__device__ __forceinline__ void t3_idft(d2 (&v)[kT3Pts], int b)
+{
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r & hr) continue;
-            const int e = l + kWave * (r & (hr - 1));  // index within the pair block
-            const d2 a = v[r], b = v[r + hr];
-            v[r] = a + b;
-            v[r + hr] = cmul(a - b, tw[e * step]);
+    for (int h = 1; h <= R / 2; h <<= 1)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k & h) continue;
+            const d2 a = v[b + k], c = t3_wsmall(v[b + k + h], 2 * h, k & (h - 1), true);
+            v[b + k] = a + c;
+            v[b + k + h] = a - c;
+        }
+}
+
+// W_M^t for t < M from the table of W_M^t, t < M/2 (W^{t + M/2} = -W^t).
+template <int M>
+__device__ __forceinline__ d2 t3_tw(const d2* __restrict__ tw, int t)
+{
+    const d2 w = tw[t & (M / 2 - 1)];
+    return (t & (M / 2)) ? d2{-w.x, -w.y} : w;
+}
+
+// Twiddle seeds of a thread: for each phase J with twiddles (every phase but
+// the last, all of radix 8, one group per thread: p1 = u mod L/8), W_L^{p1}
+// and W_L^{4 p1} from the table.  The passes with one transform load them
+// at their start, so that their latency overlaps the data loads; the z pass
+// (two transforms, more live registers) loads them where each phase needs
+// them.
+template <int M>
+__device__ __forceinline__ void t3_seed(int j, int u, const d2* __restrict__ tw, d2& w1, d2& w4)
+{
+    const int L = T3Shape<M>::sublen(j);
+    const int p1 = u % (L / 8);
+    w1 = t3_tw<M>(tw, (M / L) * p1);
+    w4 = t3_tw<M>(tw, (M / L) * p1 * 4);
+}
+
+template <int M, bool kEager = true>
+struct T3Tw {
+    static constexpr int NJ = T3Shape<M>::NPH - 1;
+    d2 w1[kEager ? NJ : 1], w4[kEager ? NJ : 1];
+    const d2* tw;
+    int u;
+    __device__ __forceinline__ T3Tw(int u_, const d2* __restrict__ tw_) : tw(tw_), u(u_)
+    {
+        if constexpr (kEager) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) t3_seed<M>(j, u, tw, w1[j], w4[j]);
         }
     }
-    // spans across lanes
+};
+
+// Twiddles W_L^{p1 k}, k = 1..7, of phase J from its seeds, the others as
+// products (each product adds at most a few units of rounding).
+template <int M, int J, bool kEager>
+__device__ __forceinline__ void t3_twiddles(d2 (&w)[8], const T3Tw<M, kEager>& sd)
+{
+    d2 w1, w4;
+    if constexpr (kEager) {
+        w1 = sd.w1[J];
+        w4 = sd.w4[J];
+    } else {
+        t3_seed<M>(J, sd.u, sd.tw, w1, w4);
+    }
+    const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
+    w[1] = w1;
+    w[2] = w2;
+    w[3] = w3;
+    w[4] = w4;
+    w[5] = cmul(w4, w1);
+    w[6] = cmul(w4, w2);
+    w[7] = cmul(w4, w3);
+}
+
+// Phase J of the forward transform on the registers of thread u.  kHalf:
+// the points >= M/2 are zero (the zero padding: m <= M/2), so in phase 0
+// the first radix-2 stage only copies and twiddles.
+template <int M, int J, bool kHalf, bool kE>
+__device__ __forceinline__ void t3_fphase(d2 (&v)[kT3Pts], const T3Tw<M, kE>& tw)
+{
+    using S = T3Shape<M>;
+    constexpr int R = S::radix(J), L = S::sublen(J);
 #pragma unroll
-    for (int i = 0; i < kLaneStages; ++i) {
-        const int h = top >> i;
-        if (h < 1) break;
-        const bool bottom = (l & h) != 0;
+    for (int i = 0; i < kT3Pts / R; ++i) {
+        if constexpr (kHalf && J == 0) {
+            static_assert(R == 8, "phase 0 has radix 8");
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const d2 pv = shfl_xor_d2(v[r], h);
-            v[r] = bottom ? cmul(pv - v[r], w[i]) : v[r] + pv;
+            for (int k = 0; k < 4; ++k) v[k + 4] = t3_wsmall(v[k], 8, k, false);
+#pragma unroll
+            for (int h = 2; h >= 1; h >>= 1)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (k & h) continue;
+                    const d2 a = v[k], c = v[k + h];
+                    v[k] = a + c;
+                    v[k + h] = t3_wsmall(a - c, 2 * h, k & (h - 1), false);
+                }
+        } else {
+            t3_dft<R>(v, i * R);
+        }
+        if constexpr (L > R) {  // offsets p1 > 0 exist: twiddles W_L^{p1 k2}
+            static_assert(R == 8 && kT3Pts / R == 1, "one radix-8 group per thread");
+            d2 w[8];
+            t3_twiddles<M, J>(w, tw);
+#pragma unroll
+            for (int j = 1; j < R; ++j) v[i * R + j] = cmul(v[i * R + j], w[t3_bitrev(j, R)]);
         }
     }
 }
 
-// Inverse of t3_fwd up to the factor M (bit-reversed in, natural order out).
-template <int R>
-__device__ __forceinline__ void t3_inv(d2 (&v)[R], int M, const d2* __restrict__ tw)
+// Inverse of t3_fphase (up to the factor R).  kHalf: only the points < M/2
+// of phase 0's output are wanted (the crop to m <= M/2).
+template <int M, int J, bool kHalf, bool kE>
+__device__ __forceinline__ void t3_iphase(d2 (&v)[kT3Pts], const T3Tw<M, kE>& tw)
 {
-    const int l = threadIdx.x & (kWave - 1);
-    const int top = t3_top(M);
-    const int nls = top >= 1 ? 32 - __builtin_clz(top) : 0;  // lane stages
-    d2 w[kLaneStages];
+    using S = T3Shape<M>;
+    constexpr int R = S::radix(J), L = S::sublen(J);
 #pragma unroll
-    for (int i = 0; i < kLaneStages; ++i) {
-        const int h = 1 << i;
-        w[i] = i < nls ? tw[(l & (h - 1)) * (M / (2 * h))] : d2{1.0, 0.0};
-    }
+    for (int i = 0; i < kT3Pts / R; ++i) {
+        if constexpr (L > R) {
+            d2 w[8];
+            t3_twiddles<M, J>(w, tw);
 #pragma unroll
-    for (int i = 0; i < kLaneStages; ++i) {
-        if (i >= nls) break;
-        const int h = 1 << i;
-        const bool bottom = (l & h) != 0;
+            for (int j = 1; j < R; ++j)
+                v[i * R + j] = cmul_conj(v[i * R + j], w[t3_bitrev(j, R)]);
+        }
+        if constexpr (kHalf && J == 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const d2 u = bottom ? cmul_conj(v[r], w[i]) : v[r];
-            const d2 pu = shfl_xor_d2(u, h);
-            v[r] = bottom ? pu - u : u + pu;
+            for (int h = 1; h <= 2; h <<= 1)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (k & h) continue;
+                    const d2 a = v[k], c = t3_wsmall(v[k + h], 2 * h, k & (h - 1), true);
+                    v[k] = a + c;
+                    v[k + h] = a - c;
+                }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = v[k] + t3_wsmall(v[k + 4], 8, k, true);
+        } else {
+            t3_idft<R>(v, i * R);
         }
     }
+}
+
+// Store the registers at the points they hold after phase J (output side)
+// or before it (input side), and read them back for another layout.
+template <int M, int J, bool kOut>
+__device__ __forceinline__ void t3_put(const d2 (&v)[kT3Pts], int u, int il, d2* tile)
+{
 #pragma unroll
-    for (int hr = 1; hr <= R / 2; hr <<= 1) {
-        const int h = hr * kWave;
-        const int step = M / (2 * h);
+    for (int s = 0; s < kT3Pts; ++s)
+        tile[t3_lds<M>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))] = v[s];
+}
+template <int M, int J, bool kOut>
+__device__ __forceinline__ void t3_get(d2 (&v)[kT3Pts], int u, int il, const d2* tile)
+{
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r & hr) continue;
-            const int e = l + kWave * (r & (hr - 1));
-            const d2 a = v[r], b = cmul_conj(v[r + hr], tw[e * step]);
-            v[r] = a + b;
-            v[r + hr] = a - b;
-        }
+    for (int s = 0; s < kT3Pts; ++s)
+        v[s] = tile[t3_lds<M>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))];
+}
+
+// Between the phases of a transform the points of a line move between
+// threads of one wavefront only: ordering the LDS accesses within the
+// wavefront suffices (its LDS operations execute in order).
+__device__ __forceinline__ void t3_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward transform: natural order in (slot s of thread u = point u + s M/8),
+// the last phase's output layout out.
+template <int M, bool kHalf, int J = 0, bool kE>
+__device__ __forceinline__ void t3_forward(d2 (&v)[kT3Pts], int u, int il, d2* tile,
+                                           const T3Tw<M, kE>& tw)
+{
+    t3_fphase<M, J, kHalf>(v, tw);
+    if constexpr (J + 1 < T3Shape<M>::NPH) {
+        t3_put<M, J, true>(v, u, il, tile);
+        t3_wave_sync();
+        t3_get<M, J + 1, false>(v, u, il, tile);
+        t3_wave_sync();
+        t3_forward<M, kHalf, J + 1>(v, u, il, tile, tw);
+    }
+}
+
+// Inverse transform (times M): the last forward phase's layout in, natural
+// order out.
+template <int M, bool kHalf, int J = T3Shape<M>::NPH - 1, bool kE>
+__device__ __forceinline__ void t3_inverse(d2 (&v)[kT3Pts], int u, int il, d2* tile,
+                                           const T3Tw<M, kE>& tw)
+{
+    t3_iphase<M, J, kHalf>(v, tw);
+    if constexpr (J > 0) {
+        t3_put<M, J, false>(v, u, il, tile);
+        t3_wave_sync();
+        t3_get<M, J - 1, true>(v, u, il, tile);
+        t3_wave_sync();
+        t3_inverse<M, kHalf, J - 1>(v, u, il, tile, tw);
     }
 }
 
 // Geometry of one structured operator.
 struct T3Geom {
     int m, M;
-    const d2* tw;  // M/2 twiddles
-    const d2* K;   // M^3 kernel transform (bit-reversed layout, scaled by M^-3)
-    d2* g1;        // M m^2
-    d2* g2;        // M^2 m
+    int mp;          // row length of G1 (iy) and G2 (iz): m rounded up to 8
+    const d2* tw;    // M/2 twiddles
+    const int* even; // 1: the kernel is even in x and in y (K holds the folded rows)
+    const d2* K;     // kernel transform, a row of M per line (register order, scaled by M^-3)
+    d2* g1;          // G1[iz][kx][iy]: m M mp points
+    d2* g2;          // G2[kx][ky][iz]: M^2 mp points
 };
 
-// Line of a pass: wavefront w of block b takes line b * 4 + w.
-__device__ __forceinline__ int t3_line()
+// Frequency held at position q of the forward transform's output: the
+// digits of q in the phases' block sizes M/R_0, M/(R_0 R_1), ..., read in
+// reverse order (mixed-radix digit reversal).
+template <int M>
+__device__ __forceinline__ int t3_freq(int q)
 {
-    return blockIdx.x * kT3LinesPerBlock + (int)(threadIdx.x / kWave);
+    using S = T3Shape<M>;
+    int k = 0, mul = 1;
+#pragma unroll
+    for (int j = 0; j < S::NPH; ++j) {
+        const int R = S::radix(j), B = S::sublen(j) / R;
+        k += ((q / B) % R) * mul;
+        mul *= R;
+    }
+    return k;
 }
 
-// Point p of a line held by (lane, register r).
-__device__ __forceinline__ int t3_point(int r) { return (int)(threadIdx.x & (kWave - 1)) + kWave * r; }
-
-// X1: x (n = m^3) -> G1[(iz M + kx) m + iy].  in may be complex128 only.
-template <int R>
-__device__ __forceinline__ void t3_pass_x(const T3Geom& g, const d2* __restrict__ in)
+// Row of K for the z line at positions (qx, qy).  A kernel with
+// T(-dx, dy, dz) = T(dx, dy, dz) = T(dx, -dy, dz) (the lattice kernel, which
+// depends on |d| only) has K(-kx, ky, kz) = K(kx, ky, kz) = K(kx, -ky, kz),
+// so only the rows of frequencies kx, ky in [0, M/2] are kept: (M/2 + 1)^2
+// rows instead of M^2, a quarter of the bytes the z pass streams for K.
+template <int M>
+__device__ __forceinline__ int t3_krow(int qx, int qy, bool even)
 {
-    const int m = g.m, M = g.M;
-    const int line = t3_line();
-    if (line >= m * m) return;
-    const int iy = line % m, iz = line / m;
-    d2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int ix = t3_point(r);
-        v[r] = ix < m ? in[ix + (int64_t)m * (iy + (int64_t)m * iz)] : d2{0.0, 0.0};
-    }
-    t3_fwd<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int kx = t3_point(r);
-        if (kx < M) g.g1[((int64_t)iz * M + kx) * m + iy] = v[r];
-    }
+    if (!even) return qx * M + qy;
+    int fx = t3_freq<M>(qx), fy = t3_freq<M>(qy);
+    fx = fx <= M / 2 ? fx : M - fx;
+    fy = fy <= M / 2 ? fy : M - fy;
+    return fx * (M / 2 + 1) + fy;
 }
 
-// X2: G1 -> G2[(kx M + ky) m + iz]
-template <int R>
-__device__ __forceinline__ void t3_pass_y(const T3Geom& g)
-{
-    const int m = g.m, M = g.M;
-    const int line = t3_line();
-    if (line >= M * m) return;
-    const int kx = line % M, iz = line / M;
-    d2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int iy = t3_point(r);
-        v[r] = iy < m ? g.g1[((int64_t)iz * M + kx) * m + iy] : d2{0.0, 0.0};
-    }
-    t3_fwd<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int ky = t3_point(r);
-        if (ky < M) g.g2[((int64_t)kx * M + ky) * m + iz] = v[r];
-    }
-}
+// Rows of G1 and G2 padded to whole 128-byte lines, so that the T
+// neighbouring values a tile moves per point (T a multiple of 8) never
+// straddle a cache line.
+__host__ __device__ inline int t3_row(int m) { return (m + 7) & ~7; }
 
-// X3: along z: forward, times K, inverse; G2 in place
-template <int R>
-__device__ __forceinline__ void t3_pass_z(const T3Geom& g)
-{
-    const int m = g.m, M = g.M;
-    const int line = t3_line();
-    if (line >= M * M) return;
-    d2* row = g.g2 + (int64_t)line * m;
-    const d2* krow = g.K + (int64_t)line * M;
-    d2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int iz = t3_point(r);
-        v[r] = iz < m ? row[iz] : d2{0.0, 0.0};
+// Thread of a tile pass: line il of the tile, index u within the line.
+// Indices fit in 32 bits: the largest array, K, has 2^24 points.
+template <int M>
+struct T3Thread {
+    int u, il, line;
+    __device__ __forceinline__ T3Thread()
+    {
+        u = (int)threadIdx.x % T3Shape<M>::TPL;
+        il = (int)threadIdx.x / T3Shape<M>::TPL;
+        line = (int)blockIdx.x * T3Shape<M>::T + il;
     }
-    t3_fwd<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int kz = t3_point(r);
-        if (kz < M) v[r] = cmul(v[r], krow[kz]);
-    }
-    t3_inv<R>(v, M, g.tw);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int iz = t3_point(r);
-        if (iz < m) row[iz] = v[r];
-    }
-}
+    // natural point of slot s
+    __device__ __forceinline__ int point(int s) const { return u + T3Shape<M>::TPL * s; }
+};
 
-// X4: G2 -> G1 (inverse along y, keep iy < m)
-template <int R>
-__device__ __forceinline__ void t3_pass_yi(const T3Geom& g)
-{
-    const int m = g.m, M = g.M;
-    const int line = t3_line();
-    if (line >= M * m) return;
-    const int kx = line % M, iz = line / M;
-    d2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int ky = t3_point(r);
-        v[r] = ky < M ? g.g2[((int64_t)kx * M + ky) * m + iz] : d2{0.0, 0.0};
+// The strided side of a tile: thread t moves the points t / T + (256 / T) r
+// of the tile's line t % T (consecutive threads on consecutive lines).
+template <int M>
+struct T3Strided {
+    int line, p0;
+    __device__ __forceinline__ T3Strided()
+    {
+        line = (int)blockIdx.x * T3Shape<M>::T + (int)threadIdx.x % T3Shape<M>::T;
+        p0 = (int)threadIdx.x / T3Shape<M>::T;
     }
-    t3_inv<R>(v, M, g.tw);
+    __device__ __forceinline__ int il() const { return (int)threadIdx.x % T3Shape<M>::T; }
+    static constexpr int kStep = kBlock / T3Shape<M>::T;
+};
+
+// The forward output of every line of the tile through LDS to the strided
+// side: point p of this thread's strided line goes to out[p * stride]
+// (nothing for a padding line: live false).
+template <int M>
+__device__ __forceinline__ void t3_tile_store(const T3Thread<M>& th, const d2 (&v)[kT3Pts],
+                                              d2* tile, d2* out, int stride, bool live)
+{
+    using S = T3Shape<M>;
+    t3_put<M, S::NPH - 1, true>(v, th.u, th.il, tile);
+    __syncthreads();
+    const T3Strided<M> sd;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int iy = t3_point(r);
-        if (iy < m) g.g1[((int64_t)iz * M + kx) * m + iy] = v[r];
+    for (int r = 0; r < kT3Pts; ++r) {
+        const int p = sd.p0 + T3Strided<M>::kStep * r;
+        const d2 val = tile[t3_lds<M>(sd.il(), p)];
+        if (live) out[p * stride] = val;
     }
 }
 
-// X5: G1 -> the product for the points ix < m of line (iy, iz).  Returns the
-// line index (or -1 past the last line); val[r] is the product at point
-// ix = t3_point(r) when ix < m.
-template <int R>
-__device__ __forceinline__ int t3_pass_xi(const T3Geom& g, d2 (&v)[R])
+// The inverse input of every line of the tile from the strided side
+// (in[p * stride]; zeros for a padding line) through LDS.
+template <int M>
+__device__ __forceinline__ void t3_tile_load(const T3Thread<M>& th, d2 (&v)[kT3Pts], d2* tile,
+                                             const d2* in, int stride, bool live)
 {
-    const int m = g.m, M = g.M;
-    const int line = t3_line();
-    const bool live = line < m * m;
-    const int iy = live ? line % m : 0, iz = live ? line / m : 0;
+    using S = T3Shape<M>;
+    const T3Strided<M> sd;
+    d2 w[kT3Pts];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int kx = t3_point(r);
-        v[r] = live && kx < M ? g.g1[((int64_t)iz * M + kx) * m + iy] : d2{0.0, 0.0};
+    for (int r = 0; r < kT3Pts; ++r)
+        w[r] = live ? in[(sd.p0 + T3Strided<M>::kStep * r) * stride] : d2{0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kT3Pts; ++r)
+        tile[t3_lds<M>(sd.il(), sd.p0 + T3Strided<M>::kStep * r)] = w[r];
+    __syncthreads();
+    t3_get<M, S::NPH - 1, true>(v, th.u, th.il, tile);
+    t3_wave_sync();
+}
+
+// X1: x (n = m^3) -> G1[(iz M + kx) mp + iy]; line iy + mp iz (iy < m live).
+template <int M>
+__device__ __forceinline__ void t3_pass_x(const T3Geom g, const d2* __restrict__ in, d2* tile)
+{
+    const int m = g.m, mp = g.mp;
+    const T3Thread<M> th;
+    const T3Tw<M> tw(th.u, g.tw);
+    const int iy = th.line % mp, iz = th.line / mp;
+    const d2* src = in + m * (iy + m * iz);
+    d2 v[kT3Pts] = {};
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {  // points >= M/2 >= m are padding
+        const int ix = th.point(s);
+        if (iz < m && iy < m && ix < m) v[s] = src[ix];
     }
-    // every lane of the wavefront takes part in the shuffles
-    t3_inv<R>(v, M, g.tw);
-    return live ? line : -1;
+    t3_forward<M, true>(v, th.u, th.il, tile, tw);
+    const T3Strided<M> sd;
+    const int oy = sd.line % mp, oz = sd.line / mp;
+    d2* out = g.g1 + oz * M * mp + oy;
+    const bool live = oz < m && oy < m;
+    t3_tile_store<M>(th, v, tile, out, mp, live);
+}
+
+// X2: G1 -> G2[(kx M + ky) mp + iz]; line iz + mp kx (iz < m live).
+template <int M>
+__device__ __forceinline__ void t3_pass_y(const T3Geom g, d2* tile)
+{
+    const int m = g.m, mp = g.mp;
+    const T3Thread<M> th;
+    const T3Tw<M> tw(th.u, g.tw);
+    const int iz = th.line % mp, kx = th.line / mp;
+    const d2* in = g.g1 + (iz * M + kx) * mp;
+    d2 v[kT3Pts] = {};
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int iy = th.point(s);
+        if (kx < M && iz < m && iy < m) v[s] = in[iy];
+    }
+    t3_forward<M, true>(v, th.u, th.il, tile, tw);
+    const T3Strided<M> sd;
+    const int oz = sd.line % mp, ox = sd.line / mp;
+    d2* out = g.g2 + ox * M * mp + oz;
+    const bool live = ox < M && oz < m;
+    t3_tile_store<M>(th, v, tile, out, mp, live);
+}
+
+// X3: along z: forward, times K, inverse; G2 in place; line kx M + ky.
+template <int M>
+__device__ __forceinline__ void t3_pass_z(const T3Geom g, d2* tile)
+{
+    const int m = g.m;
+    const T3Thread<M> th;  // M^2 is a multiple of T: every line exists
+    const T3Tw<M, false> tw(th.u, g.tw);
+    d2* row = g.g2 + th.line * g.mp;
+    const d2* krow = g.K + t3_krow<M>(th.line / M, th.line % M, *g.even != 0) * M;
+    d2 v[kT3Pts] = {};
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int iz = th.point(s);
+        if (iz < m) v[s] = row[iz];
+    }
+    t3_forward<M, true>(v, th.u, th.il, tile, tw);
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s) v[s] = cmul(v[s], krow[th.point(s)]);
+    t3_inverse<M, true>(v, th.u, th.il, tile, tw);
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {  // points < M/2 are the ones kept
+        const int iz = th.point(s);
+        if (iz < m) row[iz] = v[s];
+    }
+}
+
+// X4: G2 -> G1 (inverse along y, keep iy < m); line iz + mp kx (iz < m live).
+template <int M>
+__device__ __forceinline__ void t3_pass_yi(const T3Geom g, d2* tile)
+{
+    const int m = g.m, mp = g.mp;
+    const T3Thread<M> th;
+    const T3Tw<M> tw(th.u, g.tw);
+    const T3Strided<M> sd;
+    const int sz = sd.line % mp, sx = sd.line / mp;
+    const d2* in = g.g2 + sx * M * mp + sz;
+    const bool live = sx < M && sz < m;
+    d2 v[kT3Pts];
+    t3_tile_load<M>(th, v, tile, in, mp, live);
+    t3_inverse<M, true>(v, th.u, th.il, tile, tw);
+    const int iz = th.line % mp, kx = th.line / mp;
+    if (kx >= M || iz >= m) return;
+    d2* out = g.g1 + (iz * M + kx) * mp;
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int iy = th.point(s);
+        if (iy < m) out[iy] = v[s];
+    }
+}
+
+// X5: G1 -> the product for the points ix < m of line iy + mp iz.  Returns
+// the lattice line iy + m iz (or -1 for a padding line or one past the
+// last); v[s], s < 4, is the product at point ix = th.point(s) when ix < m
+// (the other slots hold no output).
+template <int M>
+__device__ __forceinline__ int t3_pass_xi(const T3Geom g, const T3Thread<M>& th,
+                                          d2 (&v)[kT3Pts], d2* tile)
+{
+    const int m = g.m, mp = g.mp;
+    const T3Tw<M> tw(th.u, g.tw);
+    const T3Strided<M> sd;
+    const int sy = sd.line % mp, sz = sd.line / mp;
+    const d2* in = g.g1 + sz * M * mp + sy;
+    const bool live = sz < m && sy < m;
+    t3_tile_load<M>(th, v, tile, in, mp, live);
+    t3_inverse<M, true>(v, th.u, th.il, tile, tw);
+    const int iy = th.line % mp, iz = th.line / mp;
+    return iz < m && iy < m ? iy + m * iz : -1;
 }
 
 }  // namespace ccg
