@@ -509,6 +509,55 @@ __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
     publish(a, q, L, role_kind<RO>(mode), gridDim.x);
 }
 
+// The same roles on small lattices (padded edge <= 64): three launches (the
+// per-plane XY and YX kernels of ccg_t3.h around the z pass).
+template <Role RO, int M>
+__global__ __launch_bounds__(kT3PlaneThreads) void k_t3s_xy_role(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    __shared__ T3PlaneTile<M> tile;
+    __shared__ T3Plane<M> plane;
+    const int mode = role_mode<RO>(L.phase);
+    if (mode >= 0 && mode != PH_ZERO) t3s_xy<M>(a.t3, role_input<RO>(a, mode), tile, plane);
+    publish(a, q, L, PK_NONE, 0);
+}
+
+template <Role RO, int M>
+__global__ __launch_bounds__(kT3PlaneThreads) void k_t3s_yx_role(Args a, int q)
+{
+    SOLVER_PROLOGUE();
+    __shared__ T3PlaneTile<M> tile;
+    __shared__ T3Plane<M> plane;
+    const int mode = role_mode<RO>(L.phase);
+    if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
+    if (mode == PH_ZERO) {  // y == 0: x = 0
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x)
+            a.x[i] = d2{0.0, 0.0};
+        publish(a, q, L, PK_ZERO, 0);
+        return;
+    }
+    d2 v[kT3Pts];
+    const bool live = t3s_yx<M>(a.t3, v, tile, plane);
+    const int m = a.t3.m;
+    const int u = (int)threadIdx.x % T3Shape<M>::TPL, iy = (int)threadIdx.x / T3Shape<M>::TPL;
+    d2 pv0 = d2{0.0, 0.0}, pv1 = d2{0.0, 0.0}, pv2 = d2{0.0, 0.0};
+    if (live) {
+#pragma unroll
+        for (int s = 0; s < kT3Pts / 2; ++s) {
+            const int ix = u + T3Shape<M>::TPL * s;
+            if (ix < m) {
+                const Terms tm =
+                    role_finish<RO, d2>(a, mode, ix + m * (iy + m * (int)blockIdx.x), v[s]);
+                pv0 += tm.t0;
+                pv1 += tm.t1;
+                pv2 += tm.t2;
+            }
+        }
+    }
+    role_partials<RO>(a, q, pv0, pv1, pv2, lds);
+    publish(a, q, L, role_kind<RO>(mode), gridDim.x);
+}
+
 // ------------------------------ upper-triangle products of complex symmetric A
 //
 // The same roles with the product read from the upper triangle (ccg_symv.h):
@@ -903,6 +952,36 @@ __global__ __launch_bounds__(kBlock) void k_t3p_xi(T3Geom g, d2* __restrict__ y)
     }
 }
 
+template <int M>
+__global__ __launch_bounds__(kT3PlaneThreads) void k_t3s_xy(T3Geom g, const d2* __restrict__ x)
+{
+    __shared__ T3PlaneTile<M> tile;
+    __shared__ T3Plane<M> plane;
+    t3s_xy<M>(g, x, tile, plane);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_t3s_z(T3Geom g)
+{
+    __shared__ d2 tile[T3Shape<M>::T * M];
+    t3s_z<M>(g, tile);
+}
+template <int M>
+__global__ __launch_bounds__(kT3PlaneThreads) void k_t3s_yx(T3Geom g, d2* __restrict__ y)
+{
+    __shared__ T3PlaneTile<M> tile;
+    __shared__ T3Plane<M> plane;
+    d2 v[kT3Pts];
+    if (!t3s_yx<M>(g, v, tile, plane)) return;
+    const int m = g.m;
+    const int u = (int)threadIdx.x % T3Shape<M>::TPL, iy = (int)threadIdx.x / T3Shape<M>::TPL;
+    d2* out = y + m * (iy + m * (int)blockIdx.x);
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int ix = u + T3Shape<M>::TPL * s;
+        if (ix < m) out[ix] = v[s];
+    }
+}
+
 // tw[t] = e^{-2 pi i t / M}
 __global__ void k_t3_twiddle(d2* tw, int M)
 {
@@ -1173,12 +1252,13 @@ static int ws_of(int M)
     }
 
 // Workgroups of the first and last pass of a product (and so the partial
-// count of a structured solver's product): tiles over the m^2 lines.
+// count of a structured solver's product): one per z-plane on the
+// three-launch path, else tiles over the lines of the x passes.
 static int t3_edge_tiles(int64_t m)
 {
     const int M = t3_padded((int)m);
     int64_t t = 0;
-#define T3_TILES(Mc) t = t3_tiles<Mc>(t3_row((int)m) * m)
+#define T3_TILES(Mc) t = Mc <= kT3SmallM ? m : t3_tiles<Mc>(t3_row((int)m) * m)
     T3_DISPATCH(M, T3_TILES)
 #undef T3_TILES
     return (int)(t > 0 ? t : 1);
@@ -1196,12 +1276,19 @@ static void launch_t3_role(const Args& a, int& q, hipStream_t s)
     const int64_t m = a.t3.m, mp = a.t3.mp;
     Args b = a;  // only the first pass reports a status word
     b.status = nullptr;
-    k_t3_x<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(a, q);
-    q ^= 1;
-    k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
-    k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(a.t3);
-    k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
-    k_t3_role<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(b, q);
+    if constexpr (M <= kT3SmallM) {
+        k_t3s_xy_role<RO, M><<<(int)m, kT3PlaneThreads, 0, s>>>(a, q);
+        q ^= 1;
+        k_t3s_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(a.t3);
+        k_t3s_yx_role<RO, M><<<(int)m, kT3PlaneThreads, 0, s>>>(b, q);
+    } else {
+        k_t3_x<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(a, q);
+        q ^= 1;
+        k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
+        k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(a.t3);
+        k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(a.t3);
+        k_t3_role<RO, M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(b, q);
+    }
     q ^= 1;
 }
 
@@ -1976,11 +2063,17 @@ template <int M>
 static void t3_matvec_launch(const T3Geom& g, const d2* x, d2* y, hipStream_t s)
 {
     const int64_t m = g.m, mp = g.mp;
-    k_t3p_x<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, x);
-    k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
-    k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(g);
-    k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
-    k_t3p_xi<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, y);
+    if constexpr (M <= kT3SmallM) {
+        k_t3s_xy<M><<<(int)m, kT3PlaneThreads, 0, s>>>(g, x);
+        k_t3s_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(g);
+        k_t3s_yx<M><<<(int)m, kT3PlaneThreads, 0, s>>>(g, y);
+    } else {
+        k_t3p_x<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, x);
+        k_t3p_y<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
+        k_t3p_z<M><<<(int)t3_tiles<M>(M * M), kBlock, 0, s>>>(g);
+        k_t3p_yi<M><<<(int)t3_tiles<M>(mp * M), kBlock, 0, s>>>(g);
+        k_t3p_xi<M><<<(int)t3_tiles<M>(mp * m), kBlock, 0, s>>>(g, y);
+    }
 }
 
 template <int M>

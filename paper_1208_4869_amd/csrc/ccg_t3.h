@@ -436,42 +436,89 @@ struct T3Strided {
     static constexpr int kStep = kBlock / T3Shape<M>::T;
 };
 
-// The forward output of every line of the tile through LDS to the strided
-// side: point p of this thread's strided line goes to out[p * stride]
-// (nothing for a padding line: live false).
-template <int M>
+// The registers of every line of the tile through LDS to the strided side:
+// point p < np of this thread's strided line goes to out[p * stride]
+// (nothing for a padding line: live false).  kNat: the registers hold the
+// natural order (an inverse transform's output), else the forward output.
+template <int M, bool kNat = false>
 __device__ __forceinline__ void t3_tile_store(const T3Thread<M>& th, const d2 (&v)[kT3Pts],
-                                              d2* tile, d2* out, int stride, bool live)
+                                              d2* tile, d2* out, int stride, bool live,
+                                              int np = M)
 {
     using S = T3Shape<M>;
-    t3_put<M, S::NPH - 1, true>(v, th.u, th.il, tile);
+    if constexpr (kNat)
+        t3_put<M, 0, false>(v, th.u, th.il, tile);
+    else
+        t3_put<M, S::NPH - 1, true>(v, th.u, th.il, tile);
     __syncthreads();
     const T3Strided<M> sd;
 #pragma unroll
     for (int r = 0; r < kT3Pts; ++r) {
         const int p = sd.p0 + T3Strided<M>::kStep * r;
         const d2 val = tile[t3_lds<M>(sd.il(), p)];
-        if (live) out[p * stride] = val;
+        if (live && p < np) out[p * stride] = val;
     }
 }
 
-// The inverse input of every line of the tile from the strided side
-// (in[p * stride]; zeros for a padding line) through LDS.
-template <int M>
+// The registers of every line of the tile from the strided side (in[p *
+// stride] for p < np, zeros beyond and for a padding line) through LDS.
+// kNat: natural order (a forward transform's input), else the forward
+// output layout (an inverse transform's input).
+template <int M, bool kNat = false>
 __device__ __forceinline__ void t3_tile_load(const T3Thread<M>& th, d2 (&v)[kT3Pts], d2* tile,
-                                             const d2* in, int stride, bool live)
+                                             const d2* in, int stride, bool live, int np = M)
 {
     using S = T3Shape<M>;
     const T3Strided<M> sd;
     d2 w[kT3Pts];
 #pragma unroll
-    for (int r = 0; r < kT3Pts; ++r)
-        w[r] = live ? in[(sd.p0 + T3Strided<M>::kStep * r) * stride] : d2{0.0, 0.0};
+    for (int r = 0; r < kT3Pts; ++r) {
+        const int p = sd.p0 + T3Strided<M>::kStep * r;
+        w[r] = live && p < np ? in[p * stride] : d2{0.0, 0.0};
+    }
 #pragma unroll
     for (int r = 0; r < kT3Pts; ++r)
         tile[t3_lds<M>(sd.il(), sd.p0 + T3Strided<M>::kStep * r)] = w[r];
     __syncthreads();
-    t3_get<M, S::NPH - 1, true>(v, th.u, th.il, tile);
+    if constexpr (kNat)
+        t3_get<M, 0, false>(v, th.u, th.il, tile);
+    else
+        t3_get<M, S::NPH - 1, true>(v, th.u, th.il, tile);
+    t3_wave_sync();
+}
+
+// A line's forward output to a contiguous run out[0, M) (natural position
+// order, consecutive threads on consecutive points), through the wavefront's
+// own rows of the tile.
+template <int M>
+__device__ __forceinline__ void t3_row_store(const d2 (&v)[kT3Pts], int u, int il, d2* tile,
+                                             d2* out, bool live)
+{
+    t3_put<M, T3Shape<M>::NPH - 1, true>(v, u, il, tile);
+    t3_wave_sync();
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s) {
+        const int p = u + T3Shape<M>::TPL * s;
+        const d2 val = tile[t3_lds<M>(il, p)];
+        if (live) out[p] = val;
+    }
+    t3_wave_sync();
+}
+
+// An inverse transform's input from a contiguous run in[0, M) of forward
+// output, through the wavefront's own rows of the tile.
+template <int M>
+__device__ __forceinline__ void t3_row_load(d2 (&v)[kT3Pts], int u, int il, d2* tile,
+                                            const d2* in, bool live)
+{
+    d2 w[kT3Pts];
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s)
+        w[s] = live ? in[u + T3Shape<M>::TPL * s] : d2{0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s) tile[t3_lds<M>(il, u + T3Shape<M>::TPL * s)] = w[s];
+    t3_wave_sync();
+    t3_get<M, T3Shape<M>::NPH - 1, true>(v, u, il, tile);
     t3_wave_sync();
 }
 
@@ -589,6 +636,118 @@ __device__ __forceinline__ int t3_pass_xi(const T3Geom g, const T3Thread<M>& th,
     t3_inverse<M, true>(v, th.u, th.il, tile, tw);
     const int iy = th.line % mp, iz = th.line / mp;
     return iz < m && iy < m ? iy + m * iz : -1;
+}
+
+// ------------------------------------------------ small lattices (M <= 64)
+//
+// With m <= 32 every pass above is a few microseconds of latency, so the
+// product takes three launches instead of five, one workgroup of 512
+// threads per z-plane for the x and y transforms (each in one round of
+// lines), whose plane stays in LDS:
+//   XY: plane iz: forward along x (m lines), the plane (kx, iy) in LDS,
+//       forward along y (M lines)                        -> G2s[iz][kx][ky]
+//   Z:  lines kx M + ky: forward along z, times K, inverse (the strided
+//       side is iz: loads and stores through the tile)   -> G2s (in place)
+//   YX: plane iz: inverse along y (M lines, keep iy < m), the plane (iy, kx)
+//       in LDS, inverse along x (m lines, keep ix < m)   -> y
+// G2s holds m M^2 points (within the G2 region of the general path).
+
+constexpr int kT3SmallM = 64;      // largest padded edge of the three-launch path
+constexpr int kT3PlaneThreads = 512;  // XY / YX workgroup: every y line of a plane in one round
+
+template <int M>
+struct T3PlaneShape {
+    static constexpr int TL = kT3PlaneThreads / T3Shape<M>::TPL;  // lines per round
+    static_assert(TL >= M, "one round holds the y lines of a plane");
+};
+template <int M>
+using T3PlaneTile = d2[T3PlaneShape<M>::TL * M];
+template <int M>
+using T3Plane = d2[(M / 2) * M];  // m <= M/2 rows of M points
+
+// XY for plane blockIdx.x.
+template <int M>
+__device__ __forceinline__ void t3s_xy(const T3Geom g, const d2* __restrict__ in, d2* tile,
+                                       d2* plane)
+{
+    using S = T3Shape<M>;
+    const int m = g.m, iz = blockIdx.x;
+    const int u = (int)threadIdx.x % S::TPL, il = (int)threadIdx.x / S::TPL;
+    const T3Tw<M> tw(u, g.tw);
+    // x lines iy = il < m
+    d2 v[kT3Pts] = {};
+    const d2* src = in + m * (il + m * iz);
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int ix = u + S::TPL * s;
+        if (il < m && ix < m) v[s] = src[ix];
+    }
+    t3_forward<M, true>(v, u, il, tile, tw);
+    // plane[kx][iy]: row kx of M/2 points
+    if (il < m) {
+#pragma unroll
+        for (int s = 0; s < kT3Pts; ++s)
+            plane[t3_pos_out<M, S::NPH - 1>(u, s) * (M / 2) + il] = v[s];
+    }
+    __syncthreads();
+    // y lines kx = il < M
+    const int kx = il;
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s) v[s] = d2{0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int iy = u + S::TPL * s;
+        if (kx < M && iy < m) v[s] = plane[kx * (M / 2) + iy];
+    }
+    t3_forward<M, true>(v, u, il, tile, tw);
+    t3_row_store<M>(v, u, il, tile, g.g2 + ((int64_t)iz * M + kx) * M, kx < M);
+}
+
+// Z over G2s: line kx M + ky, its points iz < m at stride M^2.
+template <int M>
+__device__ __forceinline__ void t3s_z(const T3Geom g, d2* tile)
+{
+    const int m = g.m;
+    const T3Thread<M> th;  // M^2 is a multiple of T: every line exists
+    const T3Tw<M> tw(th.u, g.tw);
+    const T3Strided<M> sd;
+    d2 v[kT3Pts];
+    t3_tile_load<M, true>(th, v, tile, g.g2 + sd.line, M * M, true, m);
+    t3_forward<M, true>(v, th.u, th.il, tile, tw);
+    const d2* krow = g.K + t3_krow<M>(th.line / M, th.line % M, *g.even != 0) * M;
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s) v[s] = cmul(v[s], krow[th.point(s)]);
+    t3_inverse<M, true>(v, th.u, th.il, tile, tw);
+    t3_wave_sync();
+    t3_tile_store<M, true>(th, v, tile, g.g2 + sd.line, M * M, true, m);
+}
+
+// YX for plane blockIdx.x: leaves the products of plane line iy = il < m
+// in v[s], s < 4, at points ix = u + (M/8) s < m; returns whether the
+// thread holds a line.
+template <int M>
+__device__ __forceinline__ bool t3s_yx(const T3Geom g, d2 (&v)[kT3Pts], d2* tile, d2* plane)
+{
+    using S = T3Shape<M>;
+    const int m = g.m, iz = blockIdx.x;
+    const int u = (int)threadIdx.x % S::TPL, il = (int)threadIdx.x / S::TPL;
+    const T3Tw<M> tw(u, g.tw);
+    // inverse y lines kx = il < M -> plane[iy][kx], iy < m
+    const int kx = il;
+    t3_row_load<M>(v, u, il, tile, g.g2 + ((int64_t)iz * M + kx) * M, kx < M);
+    t3_inverse<M, true>(v, u, il, tile, tw);
+#pragma unroll
+    for (int s = 0; s < kT3Pts / 2; ++s) {
+        const int iy = u + S::TPL * s;
+        if (kx < M && iy < m) plane[iy * M + kx] = v[s];
+    }
+    __syncthreads();
+    // inverse x lines iy = il < m
+#pragma unroll
+    for (int s = 0; s < kT3Pts; ++s)
+        v[s] = il < m ? plane[il * M + t3_pos_out<M, S::NPH - 1>(u, s)] : d2{0.0, 0.0};
+    t3_inverse<M, true>(v, u, il, tile, tw);
+    return il < m;
 }
 
 }  // namespace ccg
