@@ -1111,9 +1111,30 @@ __global__ __launch_bounds__(kBlock) void km_update(d2* __restrict__ X, int64_t 
     }
 }
 
+// Refinement record of a mixed request in the server (device memory): what
+// block_mixed_impl keeps on the host, kept here so that the outer steps run
+// on the device between batched iterations.
+enum MixState { MX_INIT = 0, MX_INNER, MX_FIN };
+
+struct MixRec {
+    double ny2[kMaxCols];   // ||y||^2
+    double nrm[kMaxCols];   // ||r||^2 of the latest FP64 residual
+    double nr[kMaxCols];    // ||r|| of the inner solve now running (0: column sits out)
+    double sc[kMaxCols];    // 1 / ||r|| (0: column sits out)
+    double relres[kMaxCols];
+    int info[kMaxCols], outers[kMaxCols], inner_iters[kMaxCols], mv32[kMaxCols],
+        mv64[kMaxCols], live[kMaxCols], zero[kMaxCols];
+    int state;              // MixState
+    int setup;              // an inner solve starts in this step
+    int zeroing;            // x = 0 in the columns zero[] in this step
+    int outer;              // FP64 residuals after the first
+    int maxit, maxit_inner;
+    double tol, tol_inner2;
+};
+
 struct BMixLayout {
     BLayout inner;
-    size_t R, Ys, D, norms, total;
+    size_t R, Ys, D, norms, mix, total;
 };
 
 static BMixLayout bmix_layout(int64_t n, int k)
@@ -1131,6 +1152,8 @@ static BMixLayout bmix_layout(int64_t n, int k)
     off += mb;
     L.norms = off;
     off += align256(kMaxCols * sizeof(double));
+    L.mix = off;
+    off += align256(sizeof(MixRec));
     L.total = off;
     return L;
 }
@@ -1322,9 +1345,17 @@ struct SlotRec {
     // batched set-up (null when admission copied them)
     const d2 *ysrc, *xsrc;
     int64_t ldys, ldxs;
+    // mixed requests (null mix for FP64 ones): the refinement record, Y and
+    // X (n x k) and R (n x kp) of the outer loop, the blocks of its FP64
+    // residual product [o0, o0 + oG) (slice length kslice64) and of its
+    // column norms [q0, q0 + k)
+    MixRec* mix;
+    const d2* yo;
+    d2 *xo, *ro;
+    int o0, oG, q0, kslice64;
 };
 
-enum RecGrid { RG_COL, RG_MFMA, RG_VALU };
+enum RecGrid { RG_COL, RG_MFMA, RG_VALU, RG_OUT, RG_NORM };
 
 // The record whose blocks of grid `which` contain block b: the last record
 // starting at or before b (records with no blocks in that grid are skipped).
@@ -1334,6 +1365,7 @@ __device__ __forceinline__ int find_rec(const SlotRec* __restrict__ tab, int m, 
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         const int start = which == RG_MFMA ? tab[mid].g0 : which == RG_VALU ? tab[mid].v0
+                        : which == RG_OUT ? tab[mid].o0 : which == RG_NORM ? tab[mid].q0
                         : tab[mid].c0;
         if (start <= b)
             lo = mid;
@@ -1462,7 +1494,10 @@ __global__ __launch_bounds__(kStepThreads) void kv_step(const SlotRec* __restric
     const SlotRec& r = tab[blockIdx.x];
     if (sdone[r.slot]) return;
     const BArgs a = r.a;
-    kb_step_body(a, stage, r.gC, ring ? ring + r.slot : nullptr, ring ? sdone + r.slot : nullptr);
+    // a mixed request's word tells the host when its refinement is over
+    // (ko_decide), not when an inner solve ends
+    kb_step_body(a, stage, r.gC, ring && !r.mix ? ring + r.slot : nullptr,
+                 ring ? sdone + r.slot : nullptr);
 }
 
 // Copy of Y and X (n x k, device sources) into a request's pool matrices
@@ -1496,6 +1531,270 @@ __global__ __launch_bounds__(kMaxCols) void kv_setup_init(const SlotRec* __restr
     if (threadIdx.x == 0) sdone[r.slot] = 0;
     const BArgs a = r.a;
     kb_init_body(a, r.maxit, r.tol2, r.no_confirm);
+}
+
+// ---------------------------------- mixed requests: the outer loop on the device
+//
+// A mixed request runs block_mixed_impl's refinement with x0 = 0, each step
+// of it as a batched kernel over the table, so that no outer step waits for
+// the host.  In every batched iteration, before the inner iteration kernels:
+//   ko_update  x += ||r|| D for the records whose inner solve has ended
+//              (their done word is set), skipping columns whose inner record
+//              ends the refinement
+//   ko_gemm    their FP64 residual product A X (the product gemm() picks)
+//   ko_resid   R = Y - A X (R = Y for a record just admitted)
+//   ko_colnorm ||R[:, c]||^2, one block per column as km_colnorm
+//   ko_decide  one block per record: the inner solve's counts, then per
+//              column converged / outer budget spent / non-finite, the
+//              scales, and the column records of the next inner solve
+//   ko_scale   Ys = R / ||R|| (and x = 0 for a record just admitted)
+//   ko_normy, ko_step (CS_NORMY), ko_setup0, ko_step (CS_SETUP0): the set-up
+//              of the next inner solve, as the batched set-up runs it
+// The arithmetic of each step is block_mixed_impl's, element for element, so
+// a request's x equals the solver run alone bit for bit.
+
+// Which part of the refinement record r takes in this iteration: 1 its first
+// residual (just admitted), 2 an outer step (its inner solve has ended), 0
+// none (inner solve running, or finished).
+__device__ __forceinline__ int mix_turn(const SlotRec& r, const int* sdone)
+{
+    if (!r.mix) return 0;
+    const int st = r.mix->state;
+    return st == MX_INIT ? 1 : (st == MX_INNER && sdone[r.slot]) ? 2 : 0;
+}
+
+// A mixed request's record on admission (one block of kMaxCols threads); the
+// done word stays set until the first inner solve starts.
+__global__ __launch_bounds__(kMaxCols) void ko_init(MixRec* x, int k, int maxit, int maxit_inner,
+                                                    double tol, double tol_inner2, int* sdone)
+{
+    const int c = threadIdx.x;
+    x->ny2[c] = x->nrm[c] = x->nr[c] = x->sc[c] = x->relres[c] = 0.0;
+    x->info[c] = x->outers[c] = x->inner_iters[c] = x->mv32[c] = x->mv64[c] = 0;
+    x->live[c] = c < k ? 1 : 0;
+    x->zero[c] = 0;
+    if (c == 0) {
+        x->state = MX_INIT;
+        x->setup = x->zeroing = 0;
+        x->outer = 0;
+        x->maxit = maxit;
+        x->maxit_inner = maxit_inner;
+        x->tol = tol;
+        x->tol_inner2 = tol_inner2;
+        *sdone = 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void ko_update(const SlotRec* __restrict__ tab, int m,
+                                                    const int* __restrict__ sdone)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    if (mix_turn(r, sdone) != 2) return;
+    const BArgs a = r.a;
+    const MixRec* x = r.mix;
+    const int k = a.k, kp = a.kp;
+    const int64_t total = (int64_t)a.n * k;
+    for (int64_t e = (int64_t)(blockIdx.x - r.c0) * kBlock + threadIdx.x; e < total;
+         e += (int64_t)r.gC * kBlock) {
+        const int64_t i = e / k;
+        const int c = (int)(e - i * k);
+        double f = x->nr[c];
+        if (f != 0.0) {
+            const SolverState& st = col_state(a, c);
+            if (inner_ends_refinement(st.info, st.iters)) f = 0.0;
+        }
+        if (f != 0.0) {
+            d2* xp = r.xo + i * k + c;
+            const d2 d = a.X[i * kp + c];
+            *xp = *xp + d2{d.x * f, d.y * f};
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void ko_gemm(const SlotRec* __restrict__ tab, int m,
+                                                  const int* __restrict__ sdone)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_OUT)];
+    if (r.oG == 0 || mix_turn(r, sdone) != 2) return;
+    const BArgs a = r.a;
+    const int bid = blockIdx.x - r.o0;
+    if (a.k == 1)
+        vgemm_body<1>(a.A, a.lda, a.n, r.xo, 1, 1, a.Zp, r.kslice64, bid);
+    else if (a.k == 2)
+        vgemm_body<2>(a.A, a.lda, a.n, r.xo, 2, 2, a.Zp, r.kslice64, bid);
+    else if (a.k <= kVCols)
+        vgemm_body<4>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp, r.kslice64, bid);
+    else
+        zgemm_body<1>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp, r.kslice64, bid);
+}
+
+__global__ __launch_bounds__(kBlock) void ko_resid(const SlotRec* __restrict__ tab, int m,
+                                                   const int* __restrict__ sdone)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    const int turn = mix_turn(r, sdone);
+    if (!turn) return;
+    const BArgs a = r.a;
+    const int n = a.n, k = a.k, kp = a.kp;
+    const int64_t total = (int64_t)n * kp;
+    for (int64_t e = (int64_t)(blockIdx.x - r.c0) * kBlock + threadIdx.x; e < total;
+         e += (int64_t)r.gC * kBlock) {
+        const int64_t i = e / kp;
+        const int c = (int)(e - i * kp);
+        d2 v = d2{0.0, 0.0};
+        if (c < k) {
+            v = r.yo[i * k + c];
+            if (turn == 2) v = v - slice_sum(a.Zp, n, k, i, c);
+        }
+        r.ro[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void ko_colnorm(const SlotRec* __restrict__ tab, int m,
+                                                     const int* __restrict__ sdone)
+{
+    __shared__ d2 lds[kMaxWaves];
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_NORM)];
+    if (!mix_turn(r, sdone)) return;
+    const int c = blockIdx.x - r.q0;
+    const int n = r.a.n, kp = r.a.kp;
+    d2 acc = d2{0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) acc.x += cabs2(r.ro[(int64_t)i * kp + c]);
+    const d2 tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) r.mix->nrm[c] = tot.x;
+}
+
+// One block of kMaxCols threads per record (thread c: column c).  ring: this
+// iteration's row of host-visible done words.
+__global__ __launch_bounds__(kMaxCols) void ko_decide(const SlotRec* __restrict__ tab, int* sdone,
+                                                      int* ring)
+{
+    __shared__ int act;
+    const SlotRec& r = tab[blockIdx.x];
+    if (!r.mix) return;
+    MixRec* x = r.mix;
+    const int turn = mix_turn(r, sdone);
+    const int c = threadIdx.x;
+    const BArgs a = r.a;
+    if (c == 0) act = 0;
+    __syncthreads();  // every thread has read the state and the done word
+    if (c == 0) x->setup = x->zeroing = 0;
+    if (turn && c < a.k) {
+        if (turn == 1) {  // y's norms (R = y, x0 = 0); x = 0 where y is finite
+            const double v = x->nrm[c];
+            x->ny2[c] = v;
+            if (!__builtin_isfinite(v)) {  // x left as given
+                x->info[c] = 4;
+                x->live[c] = 0;
+            } else {  // y = 0: x = 0, info 0, done
+                x->zero[c] = 1;
+                if (v == 0.0) x->live[c] = 0;
+            }
+        } else if (x->nr[c] != 0.0) {  // the inner solve this column took part in
+            const SolverState& st = col_state(a, c);
+            x->outers[c]++;
+            x->inner_iters[c] += st.iters;
+            x->mv32[c] += st.matvecs;
+            if (inner_ends_refinement(st.info, st.iters)) {
+                x->info[c] = st.info;  // its correction was not applied
+                x->live[c] = 0;
+            } else {
+                x->mv64[c]++;
+            }
+        }
+        const int outer = turn == 1 ? 0 : x->outer + 1;
+        double sc = 0.0, nr = 0.0;
+        if (x->live[c]) {
+            const double nrm = x->nrm[c];
+            const double rel = __builtin_sqrt(nrm / x->ny2[c]);
+            x->relres[c] = rel;
+            if (!__builtin_isfinite(nrm)) {
+                x->info[c] = 4;
+                x->live[c] = 0;
+            } else if (rel <= x->tol) {
+                x->info[c] = 0;
+                x->live[c] = 0;
+            } else if (outer >= x->maxit) {
+                x->info[c] = 1;
+                x->live[c] = 0;
+            } else {
+                nr = __builtin_sqrt(nrm);
+                sc = 1.0 / nr;
+                atomicOr(&act, 1);
+            }
+        }
+        x->sc[c] = sc;
+        x->nr[c] = nr;
+    }
+    __syncthreads();
+    if (turn) {
+        if (act) {  // the next inner solve: column records, done word cleared
+            kb_init_body(a, x->maxit_inner, x->tol_inner2, 1);
+            if (c == 0) {
+                x->setup = 1;
+                x->state = MX_INNER;
+                sdone[r.slot] = 0;
+            }
+        } else if (c == 0) {
+            x->state = MX_FIN;
+        }
+        if (c == 0) {
+            if (turn == 2) x->outer++;
+            x->zeroing = turn == 1;
+        }
+    }
+    __syncthreads();
+    if (c == 0)
+        __hip_atomic_store(ring + r.slot, x->state == MX_FIN ? (int)PH_DONE : (int)PH_RUN,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(kBlock) void ko_scale(const SlotRec* __restrict__ tab, int m)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    if (!r.mix) return;
+    const MixRec* x = r.mix;
+    const BArgs a = r.a;
+    const int k = a.k, kp = a.kp;
+    if (x->setup) {
+        const int64_t total = (int64_t)a.n * kp;
+        for (int64_t e = (int64_t)(blockIdx.x - r.c0) * kBlock + threadIdx.x; e < total;
+             e += (int64_t)r.gC * kBlock) {
+            const double f = x->sc[e % kp];
+            const d2 v = r.ro[e];
+            const_cast<d2*>(a.Y)[e] = d2{v.x * f, v.y * f};
+        }
+    }
+    if (x->zeroing) {
+        const int64_t total = (int64_t)a.n * k;
+        for (int64_t e = (int64_t)(blockIdx.x - r.c0) * kBlock + threadIdx.x; e < total;
+             e += (int64_t)r.gC * kBlock)
+            if (x->zero[e % k]) r.xo[e] = d2{0.0, 0.0};
+    }
+}
+
+// The set-up kernels of the batched set-up, for the records whose next inner
+// solve starts in this iteration.
+__global__ __launch_bounds__(kBlock) void ko_normy(const SlotRec* __restrict__ tab, int m)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    if (!r.mix || !r.mix->setup) return;
+    const BArgs a = r.a;
+    kb_normy_body(a, blockIdx.x - r.c0, r.gC);
+}
+__global__ __launch_bounds__(kBlock) void ko_setup0(const SlotRec* __restrict__ tab, int m)
+{
+    const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_COL)];
+    if (!r.mix || !r.mix->setup) return;
+    const BArgs a = r.a;
+    kb_setup0_body(a, blockIdx.x - r.c0, r.gC);
+}
+__global__ __launch_bounds__(kStepThreads) void ko_step(const SlotRec* __restrict__ tab, int stage)
+{
+    const SlotRec& r = tab[blockIdx.x];
+    if (!r.mix || !r.mix->setup) return;
+    const BArgs a = r.a;
+    kb_step_body(a, stage, r.gC, nullptr);
 }
 
 // First-fit allocator over the pool (offsets and sizes are multiples of 256).
@@ -1557,26 +1856,14 @@ struct ServeReq {
     int64_t ticks = 0, max_ticks = 0, last_tick = -1;
     SlotRec rec{};
     std::vector<ccg_result> res;
-    // mixed precision (FP64 refinement around inner solves on complex64 A)
+    // mixed precision (FP64 refinement around inner solves on complex64 A,
+    // its outer loop run by the ko_* kernels of every batched iteration)
     bool mixed = false;
     double tol_inner = 0.0;
     int32_t maxit_inner = 0;
-    int phase = 0;              // MP_* below; FP64 requests stay in MP_INNER
     int64_t solve_id = 0;       // id of the block solve now iterating
-    bool waiting = false;       // an event of this phase is outstanding
-    int outer = 0;              // FP64 residuals evaluated after the first
-    const d2* Ad = nullptr;     // A as the products read it (the caller's or the pool copy)
-    int64_t ald = 0;
-    d2 *Yd = nullptr, *Xd = nullptr;  // pool copies
-    d2 *R = nullptr, *Ys = nullptr, *D = nullptr;
-    double* norms_d = nullptr;
-    std::vector<double> ny2, relres;
-    std::vector<int> info, outers, inner_iters, mv32, mv64;
-    std::vector<char> live;
-    ColScale nr{};
+    d2* Xd = nullptr;           // pool copy of X
 };
-
-enum MixPhase { MP_INNER = 0, MP_NORMY, MP_RESID };
 
 // Pool bytes of one request: A, Y, X and the block-solver workspace; a mixed
 // request also holds complex64 A and the refinement vectors.
@@ -1631,7 +1918,8 @@ struct ccg_server {
     int tot_c = 0, tot_g = 0, tot_v = 0;
     // copy-out: pinned column records [kMaxActive][kServeCols]
     char* res_h = nullptr;
-    double* norms_h = nullptr;  // pinned column norms of mixed requests
+    ccg::MixRec* mix_h = nullptr;  // pinned refinement records of retiring mixed requests
+    int tot_o = 0, tot_q = 0;      // blocks of the mixed requests' residual products, norms
     hipEvent_t slot_ev[ccg::kMaxActive] = {};
     ccg_server_stats st{};
 };
@@ -1648,27 +1936,9 @@ static int serve_start_solve(ccg_server* S, ServeReq* r, int32_t maxit, double t
     r->rec.tol2 = tol2;
     r->rec.no_confirm = no_confirm;
     r->setup_pending = true;
-    r->phase = MP_INNER;
     r->solve_id = S->next_solve++;
     r->ticks = 0;
     r->max_ticks = 2 * (int64_t)maxit + 4;
-    return 0;
-}
-
-// Enqueue the column norms of M (n x k, ld) into the request's pinned row and
-// record its event.
-static int serve_norms(ccg_server* S, ServeReq* r, const d2* M, int64_t ld)
-{
-    hipStream_t s = S->s;
-    km_colnorm<<<r->k, kBlock, 0, s>>>(M, ld, (int)r->n, r->norms_d);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return (int)e;
-    double* dst = S->norms_h + (size_t)r->slot * kServeCols;
-    if ((e = hipMemcpyAsync(dst, r->norms_d, r->k * sizeof(double), hipMemcpyDeviceToHost,
-                            s)) != hipSuccess)
-        return (int)e;
-    if ((e = hipEventRecord(S->slot_ev[r->slot], s)) != hipSuccess) return (int)e;
-    r->waiting = true;
     return 0;
 }
 
@@ -1729,23 +1999,25 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
     a.Zp = (d2*)(w + L.zp);
     a.cpart = (d2*)(w + L.cpart);
     a.cst = (SolverState*)(w + L.cst);
-    r->Ad = Asrc;
-    r->ald = lda;
-    r->Yd = Y;
     r->Xd = X;
+    r->rec.mix = nullptr;
     if (r->mixed) {
-        // the block solver runs the inner solves A32 D = Ys
+        // the block solver runs the inner solves A32 D = Ys; the outer loop
+        // keeps Y, X and R
         const BMixLayout M = bmix_layout(n, k);
-        r->R = (d2*)(w + M.R);
-        r->Ys = (d2*)(w + M.Ys);
-        r->D = (d2*)(w + M.D);
-        r->norms_d = (double*)(w + M.norms);
         a.A32 = A32;
         a.lda32 = n;
-        a.Y = r->Ys;
+        a.Y = (d2*)(w + M.Ys);
         a.ldy = kp;
-        a.X = r->D;
+        a.X = (d2*)(w + M.D);
         a.ldx = kp;
+        r->rec.mix = (MixRec*)(w + M.mix);
+        r->rec.yo = Y;
+        r->rec.xo = X;
+        r->rec.ro = (d2*)(w + M.R);
+        r->rec.kslice64 = kslice_of(n);
+        r->rec.oG = k <= kVCols ? vgemm_blocks(n)
+                                : (int)((n + kRowsPerBlock - 1) / kRowsPerBlock) * kSlices;
     }
     const size_t row = (size_t)k * sizeof(d2);
     if (!borrow &&
@@ -1785,18 +2057,15 @@ static int serve_admit(ccg_server* S, ServeReq* r, int slot)
     int rc;
     if (r->mixed) {
         km_round<<<elem_blocks(n * n), kBlock, 0, s>>>(Asrc, lda, (int)n, A32);
-        r->ny2.assign(k, 0.0);
-        r->relres.assign(k, 0.0);
-        r->info.assign(k, 0);
-        r->outers.assign(k, 0);
-        r->inner_iters.assign(k, 0);
-        r->mv32.assign(k, 0);
-        r->mv64.assign(k, 0);
-        r->live.assign(k, 1);
-        r->outer = 0;
-        r->phase = MP_NORMY;
-        r->ticks = r->max_ticks = 0;
-        if ((rc = serve_norms(S, r, Y, k))) return rc;
+        ko_init<<<1, kMaxCols, 0, s>>>(r->rec.mix, k, r->maxit, r->maxit_inner, r->tol,
+                                       r->tol_inner * r->tol_inner, S->sdone_d + slot);
+        if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+        // the device ends every inner solve within maxit_inner iterations and
+        // the refinement within maxit outer steps; this bound only guards
+        // against a done word that never arrives
+        r->solve_id = S->next_solve++;
+        r->ticks = 0;
+        r->max_ticks = ((int64_t)r->maxit + 1) * (2 * (int64_t)r->maxit_inner + 6) + 8;
     } else if ((rc = serve_start_solve(S, r, r->maxit, r->tol * r->tol, 0))) {
         return rc;
     }
@@ -1812,7 +2081,11 @@ static int serve_retire(ccg_server* S, ServeReq* r)
     if ((e = hipMemcpy2DAsync(r->X, r->ldx * sizeof(d2), r->Xd, row, row, r->n,
                               hipMemcpyDefault, s)) != hipSuccess)
         return (int)e;
-    if (!r->mixed) {
+    if (r->mixed) {
+        if ((e = hipMemcpyAsync(S->mix_h + r->slot, r->rec.mix, sizeof(MixRec),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return (int)e;
+    } else {
         char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
         if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
                                 hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -1823,139 +2096,28 @@ static int serve_retire(ccg_server* S, ServeReq* r)
     return 0;
 }
 
-// A mixed request whose FP64 residual norms are on the host: decide every
-// column (within tol, outer budget spent, non-finite) and start the inner
-// solve of the others, or retire the request.
-static int serve_mixed_decide(ccg_server* S, ServeReq* r, const double* nrm)
-{
-    hipStream_t s = S->s;
-    ColScale sc{};
-    r->nr = ColScale{};
-    int active = 0;
-    for (int c = 0; c < r->k; ++c) {
-        if (!r->live[c]) continue;
-        const double rel = std::sqrt(nrm[c] / r->ny2[c]);
-        r->relres[c] = rel;
-        if (!std::isfinite(nrm[c])) {
-            r->info[c] = 4;
-            r->live[c] = 0;
-        } else if (rel <= r->tol) {
-            r->info[c] = 0;
-            r->live[c] = 0;
-        } else if (r->outer >= r->maxit) {
-            r->info[c] = 1;
-            r->live[c] = 0;
-        } else {
-            const double v = std::sqrt(nrm[c]);
-            sc.v[c] = 1.0 / v;
-            r->nr.v[c] = v;
-            ++active;
-        }
-    }
-    if (!active) return serve_retire(S, r);
-    const int kp = r->rec.a.kp;
-    km_scale<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->R, (int)r->n, kp, sc, r->Ys);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return (int)e;
-    return serve_start_solve(S, r, r->maxit_inner, r->tol_inner * r->tol_inner, 1);
-}
-
-// A mixed request whose event has completed: the norms of y (first event) or
-// of the FP64 residual after an inner solve.
-static int serve_mixed_event(ccg_server* S, ServeReq* r)
-{
-    hipStream_t s = S->s;
-    const double* nrm = S->norms_h + (size_t)r->slot * kServeCols;
-    const int kp = r->rec.a.kp;
-    if (r->phase == MP_NORMY) {
-        ColScale zero{}, none{};
-        for (int c = 0; c < r->k; ++c) {
-            r->ny2[c] = nrm[c];
-            if (!std::isfinite(nrm[c])) {  // x left as given
-                r->info[c] = 4;
-                r->live[c] = 0;
-            } else {  // x0 = 0 (y = 0: x = 0, info 0, done)
-                zero.v[c] = 1.0;
-                if (nrm[c] == 0.0) r->live[c] = 0;
-            }
-        }
-        km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp,
-                                                               r->D, none, zero);
-        km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, nullptr, (int)r->n, r->k,
-                                                           kp, r->R);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return (int)e;
-        r->phase = MP_RESID;
-        return serve_mixed_decide(S, r, nrm);  // with x0 = 0 the residual is y
-    }
-    // MP_RESID after an inner solve: count it, then decide
-    const char* src = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
-    for (int c = 0; c < r->k; ++c) {
-        if (r->nr.v[c] == 0.0) continue;
-        const SolverState& st = *(const SolverState*)(src + (size_t)c * kStateStride);
-        r->outers[c]++;
-        r->inner_iters[c] += st.iters;
-        r->mv32[c] += st.matvecs;
-        if (inner_ends_refinement(st.info, st.iters)) {
-            r->info[c] = st.info;  // its correction was not applied
-            r->live[c] = 0;
-        } else {
-            r->mv64[c]++;
-        }
-    }
-    r->outer++;
-    return serve_mixed_decide(S, r, nrm);
-}
-
-// An inner solve of mixed request r has ended: x += ||r|| d, then the FP64
-// residual and its column norms (and the inner records, for the counts).
-static int serve_mixed_outer(ccg_server* S, ServeReq* r)
-{
-    hipStream_t s = S->s;
-    const int kp = r->rec.a.kp;
-    char* dst = S->res_h + (size_t)r->slot * kServeCols * kStateStride;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(dst, r->rec.a.cst, (size_t)r->k * kStateStride,
-                            hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return (int)e;
-    km_update<<<elem_blocks(r->n * r->k), kBlock, 0, s>>>(r->Xd, r->k, (int)r->n, r->k, kp, r->D,
-                                                           r->nr, ColScale{},
-                                                           (const char*)r->rec.a.cst);
-    gemm(r->Ad, r->ald, (int)r->n, r->Xd, r->k, r->k, r->rec.a.Zp, s);
-    km_resid<<<elem_blocks(r->n * kp), kBlock, 0, s>>>(r->Yd, r->k, r->rec.a.Zp, (int)r->n, r->k,
-                                                       kp, r->R);
-    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-    r->phase = MP_RESID;
-    return serve_norms(S, r, r->R, kp);
-}
-
-// Requests with an outstanding event: finished copy-outs free their slots and
-// pool blocks; mixed requests whose norms have arrived move on.  wait: block
-// on them.
+// Requests with an outstanding copy-out: finished ones free their slots and
+// pool blocks.  wait: block on them.
 static int serve_collect(ccg_server* S, bool wait)
 {
     for (int q = 0; q < S->max_active; ++q) {
         ServeReq* r = S->slots[q];
-        if (!r || !(r->retiring || r->waiting)) continue;
+        if (!r || !r->retiring) continue;
         hipError_t e = wait ? hipEventSynchronize(S->slot_ev[q]) : hipEventQuery(S->slot_ev[q]);
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) return (int)e;
-        if (r->waiting && !r->retiring) {
-            r->waiting = false;
-            int rc = serve_mixed_event(S, r);
-            if (rc) return rc;
-            continue;
-        }
         r->res.resize(r->k);
         if (r->mixed) {
+            const MixRec& x = S->mix_h[q];
             for (int j = 0; j < r->k; ++j) {
                 ccg_result& o = r->res[j];
-                o.info = r->info[j];
-                o.iters = r->inner_iters[j];
-                o.matvecs = r->mv32[j];
-                o.confirms = r->mv64[j];
-                o.relres_rec = r->relres[j];
-                o.relres_true = r->relres[j];
+                // a column still live here was cut off by the tick guard
+                o.info = x.live[j] && x.state != MX_FIN ? 1 : x.info[j];
+                o.iters = x.inner_iters[j];
+                o.matvecs = x.mv32[j];
+                o.confirms = x.mv64[j];
+                o.relres_rec = x.relres[j];
+                o.relres_true = x.relres[j];
             }
         } else {
             const char* src = S->res_h + (size_t)q * kServeCols * kStateStride;
@@ -1972,7 +2134,6 @@ static int serve_collect(ccg_server* S, bool wait)
         }
         r->state = CCG_REQ_DONE;
         r->retiring = false;
-        r->waiting = false;
         S->finished.push_back(r->ticket);
         S->alloc.release(r->off, r->bytes);
         S->st.pool_used -= r->bytes;
@@ -1982,8 +2143,8 @@ static int serve_collect(ccg_server* S, bool wait)
     return 0;
 }
 
-// Read the done words of tick `seen` (waiting for it): FP64 requests that
-// ended retire, mixed requests whose inner solve ended take an outer step.
+// Read the done words of tick `seen` (waiting for it): requests that ended
+// (a mixed one: its whole refinement) retire.
 static int serve_read_tick(ccg_server* S)
 {
     const int u = (int)(S->seen % kRing);
@@ -1991,15 +2152,13 @@ static int serve_read_tick(ccg_server* S)
     if (e != hipSuccess) return (int)e;
     for (const auto& mt : S->members[u]) {
         ServeReq* r = S->slots[mt.first];
-        // the entry must belong to the request's current solve (a mixed
-        // request starts a new inner solve, with a new id, per outer step)
-        if (!r || r->solve_id != mt.second || r->retiring || r->state != CCG_REQ_RUNNING ||
-            r->phase != MP_INNER)
+        // the entry must belong to the request's current solve
+        if (!r || r->solve_id != mt.second || r->retiring || r->state != CCG_REQ_RUNNING)
             continue;
         const int w = __atomic_load_n(&S->ring_h[u * kMaxActive + mt.first], __ATOMIC_ACQUIRE);
         const bool out_of_budget = r->ticks >= r->max_ticks && r->last_tick == S->seen;
         if (w == PH_DONE || out_of_budget) {
-            int rc = r->mixed ? serve_mixed_outer(S, r) : serve_retire(S, r);
+            int rc = serve_retire(S, r);
             if (rc) return rc;
         }
     }
@@ -2018,20 +2177,28 @@ static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, in
         S->stage_pending[u] = false;
     }
     SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
-    int c = 0, g = 0, v = 0;
+    int c = 0, g = 0, v = 0, o = 0, nq = 0;
     for (size_t i = 0; i < want.size(); ++i) {
         SlotRec rec = S->slots[want[i].first]->rec;
         rec.c0 = c;
         rec.g0 = g;
         rec.v0 = v;
+        rec.o0 = o;
+        rec.q0 = nq;
         c += rec.gC;
         g += rec.gG;
         v += rec.vG;
+        if (rec.mix) {
+            o += rec.oG;
+            nq += rec.a.k;
+        }
         h[i] = rec;
     }
     S->tot_c = c;
     S->tot_g = g;
     S->tot_v = v;
+    S->tot_o = o;
+    S->tot_q = nq;
     S->table = want;
     if (want.empty()) return 0;
     hipError_t e = hipMemcpyAsync(S->tab_d, h, want.size() * sizeof(SlotRec),
@@ -2044,8 +2211,8 @@ static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, in
 
 static bool serve_iterating(const ServeReq* r)
 {
-    return r && r->state == CCG_REQ_RUNNING && !r->retiring && r->phase == MP_INNER &&
-           !r->setup_pending && r->ticks < r->max_ticks;
+    return r && r->state == CCG_REQ_RUNNING && !r->retiring && !r->setup_pending &&
+           r->ticks < r->max_ticks;
 }
 
 // Enqueue the set-up of every solve that starts now, as one batch: a table of
@@ -2143,6 +2310,19 @@ static int serve_step(ccg_server* S)
         const int m = (int)want.size();
         hipStream_t s = S->s;
         const SlotRec* tab = S->tab_d;
+        int* ring = S->ring_d + (size_t)u * kMaxActive;
+        if (any32) {  // the outer steps of the mixed requests, then their inner set-ups
+            ko_update<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+            if (S->tot_o > 0) ko_gemm<<<S->tot_o, kBlock, 0, s>>>(tab, m, S->sdone_d);
+            ko_resid<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
+            ko_colnorm<<<S->tot_q, kBlock, 0, s>>>(tab, m, S->sdone_d);
+            ko_decide<<<m, kMaxCols, 0, s>>>(tab, S->sdone_d, ring);
+            ko_scale<<<S->tot_c, kBlock, 0, s>>>(tab, m);
+            ko_normy<<<S->tot_c, kBlock, 0, s>>>(tab, m);
+            ko_step<<<m, kStepThreads, 0, s>>>(tab, CS_NORMY);
+            ko_setup0<<<S->tot_c, kBlock, 0, s>>>(tab, m);
+            ko_step<<<m, kStepThreads, 0, s>>>(tab, CS_SETUP0);
+        }
         kv_p<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         const int tg = any64 ? S->tot_g : 0;
         const int tv = anyv ? S->tot_v : 0;
@@ -2165,8 +2345,7 @@ static int serve_step(ccg_server* S)
         kv_red2<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
         kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_T, nullptr);
         kv_xr<<<S->tot_c, kBlock, 0, s>>>(tab, m, S->sdone_d);
-        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_XR,
-                                           S->ring_d + (size_t)u * kMaxActive);
+        kv_step<<<m, kStepThreads, 0, s>>>(tab, S->sdone_d, CS_XR, ring);
         if ((e = hipGetLastError()) != hipSuccess) return (int)e;
         if ((e = hipEventRecord(S->tick_ev[u], s)) != hipSuccess) return (int)e;
         S->members[u] = want;
@@ -2408,7 +2587,7 @@ int ccg_server_create(void* pool, size_t pool_bytes, int32_t max_active, void* s
         e = hipHostMalloc((void**)&S->res_h, (size_t)kMaxActive * kServeCols * kStateStride,
                           hipHostMallocDefault);
     if (e == hipSuccess)
-        e = hipHostMalloc((void**)&S->norms_h, (size_t)kMaxActive * kServeCols * sizeof(double),
+        e = hipHostMalloc((void**)&S->mix_h, (size_t)kMaxActive * sizeof(MixRec),
                           hipHostMallocDefault);
     for (int q = 0; q < kRing && e == hipSuccess; ++q) {
         e = hipEventCreateWithFlags(&S->tick_ev[q], hipEventDisableTiming);
@@ -2444,7 +2623,7 @@ int ccg_server_destroy(ccg_server* S)
     if (S->stage_h) keep(hipHostFree(S->stage_h));
     if (S->sstage_h) keep(hipHostFree(S->sstage_h));
     if (S->res_h) keep(hipHostFree(S->res_h));
-    if (S->norms_h) keep(hipHostFree(S->norms_h));
+    if (S->mix_h) keep(hipHostFree(S->mix_h));
     delete S;
     return e == hipSuccess ? 0 : (int)e;
 }

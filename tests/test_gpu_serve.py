@@ -289,13 +289,13 @@ def test_serve_mixed_and_fp64_in_one_mix():
     request equals ccg_bicgstab_block_mixed_ex alone bit for bit, each FP64
     request the block solver alone; a small pool forces waits."""
     import torch
-    specs = [(300, 3, True), (64, 1, False), (513, 8, True), (1024, 2, False),
-             (200, 16, True), (100, 5, False), (1024, 4, True), (7, 2, True)]
+    specs = [(1024, 2, False), (1024, 4, True), (300, 3, True), (64, 1, False),
+             (513, 8, True), (200, 16, True), (100, 5, False), (7, 2, True)]
     reqs = [make_request(n, k, 700 + i) for i, (n, k, _) in enumerate(specs)]
     need = max(ccg.ccg_server_request_bytes(A.shape[0], Y.shape[1], mixed=mx)
                for (A, Y, _), (_, _, mx) in zip(reqs, specs))
     out, held = {}, []
-    with ccg.Server(2 * need, max_active=4) as srv:
+    with ccg.Server(need + need // 4, max_active=4) as srv:
         tickets = []
         for (A, Y, _), (_, _, mx) in zip(reqs, specs):
             n, k = Y.shape
@@ -303,7 +303,9 @@ def test_serve_mixed_and_fp64_in_one_mix():
             tickets.append(srv.submit(dev(A), dev(Y), X, 1e-10, 10 if mx else 1000,
                                       mixed=mx))
             held.append(X)
-            srv.step()
+        # all queued first; the largest request (1024, 4, mixed) fits the pool
+        # only beside small ones, so it waits for the 1024-row FP64 request
+        # admitted before it
         res = srv.run_all(tickets)
         stats = srv.stats()
     assert stats["completed"] == len(reqs) and stats["admission_waits"] > 0
