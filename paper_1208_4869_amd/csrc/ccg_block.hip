@@ -198,8 +198,10 @@ template <int NT, int KS = kKS, int WV = kGemmWaves>
 __global__ __launch_bounds__(WV * kWave) void k_zgemm(const d2* __restrict__ A, int64_t lda,
                                                       int n, const d2* __restrict__ B,
                                                       int64_t ldb, int ncols,
-                                                      d2* __restrict__ Zp, int kslice)
+                                                      d2* __restrict__ Zp, int kslice,
+                                                      const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     zgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
@@ -255,11 +257,15 @@ __device__ __forceinline__ void vgemm_body(const d2* __restrict__ A, int64_t lda
     }
 }
 
+// skip (device word, or null): when set, a solver has no column left that
+// needs this product and the launch does nothing.
 template <int KP>
 __global__ __launch_bounds__(kBlock) void k_vgemm(const d2* __restrict__ A, int64_t lda, int n,
                                                   const d2* __restrict__ B, int64_t ldb,
-                                                  int ncols, d2* __restrict__ Zp, int kslice)
+                                                  int ncols, d2* __restrict__ Zp, int kslice,
+                                                  const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     vgemm_body<KP>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
@@ -292,34 +298,34 @@ __global__ __launch_bounds__(kBlock) void k_zgemm_sum(const d2* __restrict__ Zp,
 
 template <int NT>
 static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
-                        d2* Zp, hipStream_t s)
+                        d2* Zp, hipStream_t s, const int* skip)
 {
     constexpr int rows = 16 * kGemmWaves;
     const int rblocks = (n + rows - 1) / rows;
     k_zgemm<NT><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
-                                                                 kslice_of(n));
+                                                                 kslice_of(n), skip);
 }
 
 // Z slices = A B: vector units for up to kVCols columns, FP64 matrix cores
 // beyond.
 static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,
-                 hipStream_t s)
+                 hipStream_t s, const int* skip = nullptr)
 {
     if (ncols <= kVCols) {
         const int g = vgemm_blocks(n), ks = kslice_of(n);
         if (ncols == 1)
-            k_vgemm<1><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+            k_vgemm<1><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks, skip);
         else if (ncols == 2)
-            k_vgemm<2><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+            k_vgemm<2><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks, skip);
         else
-            k_vgemm<4><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks);
+            k_vgemm<4><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks, skip);
         return;
     }
     switch ((ncols + 15) / 16) {
-    case 1: launch_gemm<1>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    case 2: launch_gemm<2>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    case 3: launch_gemm<3>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    default: launch_gemm<4>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    case 1: launch_gemm<1>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    case 2: launch_gemm<2>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    case 3: launch_gemm<3>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    default: launch_gemm<4>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
     }
 }
 
@@ -454,29 +460,31 @@ template <int NT, int KS = kKS32, int WV = kGemmWaves>
 __global__ __launch_bounds__(WV * kWave) void k_cgemm(const f2* __restrict__ A, int64_t lda,
                                                       int n, const d2* __restrict__ B,
                                                       int64_t ldb, int ncols,
-                                                      d2* __restrict__ Zp, int kslice)
+                                                      d2* __restrict__ Zp, int kslice,
+                                                      const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     cgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 template <int NT>
 static void launch_cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
-                         d2* Zp, hipStream_t s)
+                         d2* Zp, hipStream_t s, const int* skip)
 {
     constexpr int rows = 16 * kGemmWaves;
     const int rblocks = (n + rows - 1) / rows;
     k_cgemm<NT><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
-                                                                 kslice32_of(n));
+                                                                 kslice32_of(n), skip);
 }
 
 static void cgemm(const f2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,
-                  hipStream_t s)
+                  hipStream_t s, const int* skip = nullptr)
 {
     switch ((ncols + 15) / 16) {
-    case 1: launch_cgemm<1>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    case 2: launch_cgemm<2>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    case 3: launch_cgemm<3>(A, lda, n, B, ldb, ncols, Zp, s); break;
-    default: launch_cgemm<4>(A, lda, n, B, ldb, ncols, Zp, s); break;
+    case 1: launch_cgemm<1>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    case 2: launch_cgemm<2>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    case 3: launch_cgemm<3>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
+    default: launch_cgemm<4>(A, lda, n, B, ldb, ncols, Zp, s, skip); break;
     }
 }
 
@@ -506,6 +514,7 @@ struct BArgs {
     SolverState* cst;                // kp records
     const f2* A32;                   // complex64 A: products on FP32 matrix cores
     int64_t lda32;
+    int* done;                       // solve alone: set once every column has finished
 };
 
 constexpr size_t kStateStride = 256;
@@ -550,6 +559,7 @@ __device__ __forceinline__ void kb_init_body(const BArgs& a, int maxit, double t
                                              int no_confirm)
 {
     const int j = threadIdx.x;
+    if (j == 0 && a.done) *a.done = 0;
     if (j >= a.kp) return;
     SolverState o;
     const bool real_col = j < a.k;
@@ -840,7 +850,7 @@ __device__ __forceinline__ void kb_xr_body(const BArgs& a, int bid, int nblk)
 __global__ __launch_bounds__(kStepThreads) void kb_step(BArgs a, int stage, int nparts,
                                                        int* ring_slot)
 {
-    kb_step_body(a, stage, nparts, ring_slot);
+    kb_step_body(a, stage, nparts, ring_slot, a.done);
 }
 __global__ __launch_bounds__(kBlock) void kb_normy(BArgs a) { kb_normy_body(a, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(kBlock) void kb_setup0(BArgs a) { kb_setup0_body(a, blockIdx.x, gridDim.x); }
@@ -869,7 +879,7 @@ static int col_blocks(int64_t n, int kp)
 }
 
 struct BLayout {
-    size_t cst, cpart, mats, zp, total;
+    size_t cst, done, cpart, mats, zp, total;
     size_t mat_bytes;
 };
 
@@ -880,6 +890,8 @@ static BLayout block_layout(int64_t n, int k)
     size_t off = 0;
     L.cst = off;
     off += align256(kStateStride * kMaxCols);
+    L.done = off;
+    off += 256;
     L.cpart = off;
     off += align256((size_t)kColBlocks * kp * 2 * sizeof(d2));
     L.mat_bytes = align256((size_t)(n > 0 ? n : 1) * kp * sizeof(d2));
@@ -896,9 +908,9 @@ static BLayout block_layout(int64_t n, int k)
 static void block_product(const BArgs& a, const d2* B, hipStream_t s)
 {
     if (a.A32)
-        cgemm(a.A32, a.lda32, a.n, B, a.kp, a.kp, a.Zp, s);
+        cgemm(a.A32, a.lda32, a.n, B, a.kp, a.kp, a.Zp, s, a.done);
     else
-        gemm(a.A, a.lda, a.n, B, a.kp, a.kp, a.Zp, s);
+        gemm(a.A, a.lda, a.n, B, a.kp, a.kp, a.Zp, s, a.done);
 }
 
 static int run_block(const BArgs& a, uint32_t flags, int32_t maxit, double tol2,
@@ -1009,6 +1021,7 @@ static int block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda, const ccg
     a.Zp = (d2*)(base + L.zp);
     a.cpart = (d2*)(base + L.cpart);
     a.cst = (SolverState*)(base + L.cst);
+    a.done = (int*)(base + L.done);
     return run_block(a, flags, maxit, tol * tol, res, (hipStream_t)stream);
 }
 
@@ -1224,6 +1237,7 @@ static int block_mixed_impl(int64_t n, int64_t k, const ccg_z* A, int64_t lda, c
     ai.Zp = (d2*)(base + L.inner.zp);
     ai.cpart = (d2*)(base + L.inner.cpart);
     ai.cst = (SolverState*)(base + L.inner.cst);
+    ai.done = (int*)(base + L.inner.done);
 
     hipError_t e;
     std::vector<double> nrm(kk), ny2(kk);
