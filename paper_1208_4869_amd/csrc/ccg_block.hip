@@ -73,22 +73,44 @@ static inline int kslice_of(int64_t n)
 // per stage; the global loads of the next stage are in flight while the
 // matrix cores work on the current one.  Wavefront w multiplies rows
 // 16w..16w+15 of the tile by all 16 NT columns.
+//
+// kHalf (NT = 1, ncols <= 8): the 16 columns of the matrix-core tile hold the
+// real parts (columns 0-7) and the imaginary parts (8-15) of the 8 complex
+// columns of B, so each 4-deep step takes two real products (Re A and Im A
+// times that tile) instead of four on a half-empty tile; lane c and lane
+// c + 8 then combine Re Z = Re A Re B - Im A Im B and Im Z = Re A Im B +
+// Im A Re B.  The serving products of 5 to 8 columns are HBM bound with it
+// rather than bound by the padded matrix-core work.
 constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
+constexpr int kHalfCols = 8;  // widest product of the packed form
 
-template <int NT, int KS = kKS, int WV = kWavesPerBlock>
+// LDS of one zgemm_body shape: two A tiles and two B tiles (the caller
+// declares it, so that a kernel with several shapes holds the largest once).
+template <int NT, int KS = kKS, int WV = kWavesPerBlock, bool kHalf = false>
+struct ZgemmLds {
+    static constexpr int ROWS = 16 * WV;                    // rows per block
+    static constexpr int AP = KS + 1;                       // padded A-tile row (LDS banks)
+    static constexpr int BW = kHalf ? kHalfCols : 16 * NT;  // B-tile width
+    static constexpr int BN = KS * BW;                      // B-tile elements
+    static constexpr int size = 2 * ROWS * AP + 2 * BN;     // d2 elements
+};
+
+template <int NT, int KS = kKS, int WV = kWavesPerBlock, bool kHalf = false>
 __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
-                                           d2* __restrict__ Zp, int kslice, int bid)
+                                           d2* __restrict__ Zp, int kslice, int bid, d2* lds)
 {
+    static_assert(!kHalf || NT == 1, "the packed form has one tile");
+    using LD = ZgemmLds<NT, KS, WV, kHalf>;
     constexpr int TH = WV * kWave;                    // threads per block
-    constexpr int ROWS = 16 * WV;                     // rows per block
-    constexpr int AP = KS + 1;                        // padded A-tile row (LDS banks)
+    constexpr int ROWS = LD::ROWS;
+    constexpr int AP = LD::AP;
     constexpr int AE = ROWS * KS / TH;                // A elements per thread
-    constexpr int BW = 16 * NT;                       // B-tile width
-    constexpr int BN = KS * BW;                       // B-tile elements
+    constexpr int BW = LD::BW;
+    constexpr int BN = LD::BN;
     constexpr int BPT = (BN + TH - 1) / TH;           // B elements per thread
-    __shared__ d2 As[2][ROWS * AP];
-    __shared__ d2 Bs[2][BN];
+    d2(*As)[ROWS * AP] = reinterpret_cast<d2(*)[ROWS * AP]>(lds);
+    d2(*Bs)[BN] = reinterpret_cast<d2(*)[BN]>(lds + 2 * ROWS * AP);
     const int s = bid % kSlices;
     const int rb = bid / kSlices;
     const int t = threadIdx.x;
@@ -152,18 +174,26 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
 #pragma unroll
         for (int ks = 0; ks < KS; ks += 4) {
             const d2 a = As[cur][(w * 16 + li) * AP + ks + lk];
-            d2 b[NT];
+            if constexpr (kHalf) {
+                // cre: Re A x [Re B | Im B], cim: Im A x [Re B | Im B]
+                const d2 bb = Bs[cur][(ks + lk) * BW + (li & (kHalfCols - 1))];
+                const double bp = li < kHalfCols ? bb.x : bb.y;
+                cre[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bp, cre[0], 0, 0, 0);
+                cim[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bp, cim[0], 0, 0, 0);
+            } else {
+                d2 b[NT];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
+                for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].x, cre[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].y, cim[q], 0, 0, 0);
-            }
+                for (int q = 0; q < NT; ++q) {
+                    cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].x, cre[q], 0, 0, 0);
+                    cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].y, cim[q], 0, 0, 0);
+                }
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[q].y, cre[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[q].x, cim[q], 0, 0, 0);
+                for (int q = 0; q < NT; ++q) {
+                    cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[q].y, cre[q], 0, 0, 0);
+                    cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[q].x, cim[q], 0, 0, 0);
+                }
             }
         }
         if (st + 1 < nst) lstore(cur ^ 1);
@@ -172,6 +202,16 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     // result register v of a lane holds row lk + 4 v of the wavefront's 16-row
     // tile, column li (the v_mfma_f64_16x16x4f64 result layout; the
     // integer-input product tests pin it)
+    if constexpr (kHalf) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double d1 = cre[0][v], d2v = cim[0][v];
+            const double o1 = __shfl_xor(d1, kHalfCols, kWave), o2 = __shfl_xor(d2v, kHalfCols, kWave);
+            const int r = rb * ROWS + w * 16 + lk + 4 * v;
+            if (li < ncols && r < n) Zp[((int64_t)s * n + r) * ncols + li] = d2{d1 - o2, o1 + d2v};
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         const int col = 16 * q + li;
@@ -194,15 +234,16 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
 // same order whatever the block shape, so all shapes give the same bits.
 constexpr int kGemmWaves = 8;
 
-template <int NT, int KS = kKS, int WV = kGemmWaves>
+template <int NT, int KS = kKS, int WV = kGemmWaves, bool kHalf = false>
 __global__ __launch_bounds__(WV * kWave) void k_zgemm(const d2* __restrict__ A, int64_t lda,
                                                       int n, const d2* __restrict__ B,
                                                       int64_t ldb, int ncols,
                                                       d2* __restrict__ Zp, int kslice,
                                                       const int* __restrict__ skip)
 {
+    __shared__ d2 lds[ZgemmLds<NT, KS, WV, kHalf>::size];
     if (skip && *skip) return;
-    zgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    zgemm_body<NT, KS, WV, kHalf>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x, lds);
 }
 
 // Slice s of Z = A B for at most kVCols columns, on the vector units.  With
@@ -296,18 +337,18 @@ __global__ __launch_bounds__(kBlock) void k_zgemm_sum(const d2* __restrict__ Zp,
     }
 }
 
-template <int NT>
+template <int NT, bool kHalf = false>
 static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
                         d2* Zp, hipStream_t s, const int* skip)
 {
     constexpr int rows = 16 * kGemmWaves;
     const int rblocks = (n + rows - 1) / rows;
-    k_zgemm<NT><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(A, lda, n, B, ldb, ncols, Zp,
-                                                                 kslice_of(n), skip);
+    k_zgemm<NT, kKS, kGemmWaves, kHalf><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(
+        A, lda, n, B, ldb, ncols, Zp, kslice_of(n), skip);
 }
 
 // Z slices = A B: vector units for up to kVCols columns, FP64 matrix cores
-// beyond.
+// beyond (the packed form up to kHalfCols columns).
 static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols, d2* Zp,
                  hipStream_t s, const int* skip = nullptr)
 {
@@ -319,6 +360,10 @@ static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int 
             k_vgemm<2><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks, skip);
         else
             k_vgemm<4><<<g, kBlock, 0, s>>>(A, lda, n, B, ldb, ncols, Zp, ks, skip);
+        return;
+    }
+    if (ncols <= kHalfCols) {
+        launch_gemm<1, true>(A, lda, n, B, ldb, ncols, Zp, s, skip);
         return;
     }
     switch ((ncols + 15) / 16) {
@@ -1415,11 +1460,16 @@ SERVE_COL_KERNEL(xr)
 __global__ __launch_bounds__(kBlock) void kv_gemm(const SlotRec* __restrict__ tab, int m,
                                                   const int* __restrict__ sdone, int use_s)
 {
+    __shared__ d2 zl[ZgemmLds<1>::size];  // the larger of the two forms
     const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_MFMA)];
     if (sdone[r.slot] || r.a.A32 || r.gG == 0) return;
     const BArgs a = r.a;
-    zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
-                  blockIdx.x - r.g0);
+    if (a.kp <= kHalfCols)
+        zgemm_body<1, kKS, kWavesPerBlock, true>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp,
+                                                 a.Zp, r.kslice, blockIdx.x - r.g0, zl);
+    else
+        zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
+                      blockIdx.x - r.g0, zl);
 }
 
 // The FP64 requests of at most kVCols columns: the vector-unit product, as
@@ -1465,12 +1515,18 @@ __global__ __launch_bounds__(kBlock) void kv_prod(const SlotRec* __restrict__ ta
                                                   const int* __restrict__ sdone, int use_s,
                                                   int tot_g)
 {
+    __shared__ d2 zl[ZgemmLds<1>::size];
     const int b = blockIdx.x;
     if (b < tot_g) {
         const SlotRec& r = tab[find_rec(tab, m, b, RG_MFMA)];
         if (sdone[r.slot] || r.a.A32 || r.gG == 0) return;
         const BArgs a = r.a;
-        zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice, b - r.g0);
+        if (a.kp <= kHalfCols)
+            zgemm_body<1, kKS, kWavesPerBlock, true>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp,
+                                                     a.kp, a.Zp, r.kslice, b - r.g0, zl);
+        else
+            zgemm_body<1>(a.A, a.lda, a.n, use_s ? a.S : a.B, a.kp, a.kp, a.Zp, r.kslice,
+                          b - r.g0, zl);
         return;
     }
     const int bv = b - tot_g;
@@ -1628,6 +1684,7 @@ __global__ __launch_bounds__(kBlock) void ko_update(const SlotRec* __restrict__ 
 __global__ __launch_bounds__(kBlock) void ko_gemm(const SlotRec* __restrict__ tab, int m,
                                                   const int* __restrict__ sdone)
 {
+    __shared__ d2 zl[ZgemmLds<1>::size];
     const SlotRec& r = tab[find_rec(tab, m, blockIdx.x, RG_OUT)];
     if (r.oG == 0 || mix_turn(r, sdone) != 2) return;
     const BArgs a = r.a;
@@ -1638,8 +1695,11 @@ __global__ __launch_bounds__(kBlock) void ko_gemm(const SlotRec* __restrict__ ta
         vgemm_body<2>(a.A, a.lda, a.n, r.xo, 2, 2, a.Zp, r.kslice64, bid);
     else if (a.k <= kVCols)
         vgemm_body<4>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp, r.kslice64, bid);
+    else if (a.k <= kHalfCols)
+        zgemm_body<1, kKS, kWavesPerBlock, true>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp,
+                                                 r.kslice64, bid, zl);
     else
-        zgemm_body<1>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp, r.kslice64, bid);
+        zgemm_body<1>(a.A, a.lda, a.n, r.xo, a.k, a.k, a.Zp, r.kslice64, bid, zl);
 }
 
 __global__ __launch_bounds__(kBlock) void ko_resid(const SlotRec* __restrict__ tab, int m,

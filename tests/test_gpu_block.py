@@ -17,18 +17,20 @@ def int_block(n, k, seed, bound=1024):
 
 
 @pytest.mark.parametrize("n,k", [(1, 1), (5, 3), (64, 16), (65, 17), (130, 64),
-                                 (257, 33), (200, 70), (1000, 64)])
+                                 (257, 33), (200, 70), (1000, 64),
+                                 (67, 5), (130, 8), (1000, 6), (3, 7)])
 def test_matmat_integer_bitwise(orc, n, k):
     """Gaussian-integer inputs: exact in any summation order, so the matrix-core
     product equals the oracle's column products bit for bit (this also fixes
-    the MFMA operand and result lane layout)."""
+    the MFMA operand and result lane layout; 5 to 8 columns take the packed
+    form, real and imaginary parts of B in one 16-wide tile)."""
     A = inputs.gaussian_integer_matrix(n, n, bound=1024)
     B = int_block(n, k, n + k)
     Z = ccg.ccg_matmat(dev(A), dev(B)).cpu().numpy()
     assert np.array_equal(Z, orc.matmat(A, B))
 
 
-@pytest.mark.parametrize("n,k", [(7, 5), (300, 64), (1031, 40)])
+@pytest.mark.parametrize("n,k", [(7, 5), (300, 64), (1031, 40), (513, 8)])
 def test_matmat_random_bound_and_layout(orc, n, k):
     rng = np.random.default_rng(n)
     A = inputs.cn01(rng, (n, n))
