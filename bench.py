@@ -741,18 +741,23 @@ def structured_leg(steps):
 
     from paper_1208_4869_amd import ccg, inputs
     out = {"products": [], "solves": []}
-    for m in (20, 26, 64, 100):
-        op = ccg.T3Operator(m, inputs.lattice_table(m))
+    for m, kind in ((20, "lattice"), (26, "lattice"), (64, "lattice"), (100, "lattice"),
+                    (100, "general")):
+        if kind == "lattice":  # even in x and y: the folded kernel transform
+            table = inputs.lattice_table(m)
+        else:  # no symmetry: the full kernel transform
+            table = inputs.cn01(np.random.default_rng(100 + m), (2 * m - 1) ** 3)
+        op = ccg.T3Operator(m, table)
         x = torch.from_numpy(inputs.cn01(np.random.default_rng(m), m ** 3)).cuda()
         y = torch.empty_like(x)
         work = op.workspace(ccg.WS_T3_MATVEC)
         t = time_kernel(lambda: op.matvec(x, y, work), 20)
-        b, M = t3_bytes(m)
-        out["products"].append({"m": m, "n": m ** 3, "M": M, "us": t * 1e6,
-                                "bytes": b, "gbs": b / t / 1e9,
+        b, M = t3_bytes(m, even=kind == "lattice")
+        out["products"].append({"m": m, "n": m ** 3, "M": M, "table": kind, "us": t * 1e6,
+                                "bytes": b, "gbs": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS,
                                 "dense_bytes": 16.0 * m ** 6})
-        log("structured product m=%d (n=%d, M=%d): %.1f us, %.0f GB/s of %.3g bytes"
-            % (m, m ** 3, M, t * 1e6, b / t / 1e9, b))
+        log("structured product m=%d (n=%d, M=%d, %s kernel): %.1f us, %.0f GB/s of %.3g bytes"
+            % (m, m ** 3, M, kind, t * 1e6, b / t / 1e9, b))
         del op, work
     for m, seed in ((LATTICE_M, X_SEED), (26, 2), (64, 3)):
         op = ccg.T3Operator(m, inputs.lattice_table(m))
@@ -868,9 +873,23 @@ def profile_kernels(A, y):
     Yb = torch.from_numpy(np.stack([yy for _, _, yy in sys_])).cuda()
     Xb = torch.empty_like(Yb)
     ccg.ccg_solve_small_batched(ccg.WS_BICGSTAB, Ab, Yb, Xb, TOL, MAXIT, ccg.X0_ZERO)
+    del Ab, Yb, Xb
+    # structured products at m = 100 (lattice kernel: folded transform; a
+    # general kernel: the full one) and m = 20 (three-launch path)
+    for m, table in ((100, inputs.lattice_table(100)),
+                     (100, inputs.cn01(np.random.default_rng(200), 199 ** 3)),
+                     (20, inputs.lattice_table(20))):
+        op = ccg.T3Operator(m, table)
+        xs = torch.from_numpy(inputs.cn01(np.random.default_rng(m), m ** 3)).cuda()
+        ys = torch.empty_like(xs)
+        wk = op.workspace(ccg.WS_T3_MATVEC)
+        for _ in range(5):
+            op.matvec(xs, ys, wk)
+        del op, wk
     torch.cuda.synchronize()
     log("profile mix done: copy %d bytes x5, read stream x5, matvec N/C/S/c64 x5, A P "
-        "FP64 and complex64 (k=%d) x5, 1 BiCGSTAB, 1 CGNR, 1 batch of %d n=%d BiCGSTAB"
+        "FP64 and complex64 (k=%d) x5, 1 BiCGSTAB, 1 CGNR, 1 batch of %d n=%d BiCGSTAB, "
+        "structured products x5 (m = 100 lattice and general kernels, m = 20)"
         % (A.numel() * 16, BLOCK_RHS, CONFIG0_BATCH, CONFIG0_N))
 
 

@@ -208,10 +208,18 @@ struct T3Tw {
     }
 };
 
-// Twiddles W_L^{p1 k}, k = 1..7, of phase J from its seeds, the others as
-// products (each product adds at most a few units of rounding).
-template <int M, int J, bool kEager>
-__device__ __forceinline__ void t3_twiddles(d2 (&w)[8], const T3Tw<M, kEager>& sd)
+// v[bitrev(k)] times W_L^{p1 k} (kConj: its conjugate), k = 1..7, for phase
+// J: W_L^{p1} and W_L^{4 p1} from the seeds, the others as their products
+// (each product adds at most a few units of rounding), each applied as soon
+// as it is formed so that few stay live.
+template <bool kConj>
+__device__ __forceinline__ void t3_tmul(d2& x, d2 w)
+{
+    x = kConj ? cmul_conj(x, w) : cmul(x, w);
+}
+
+template <int M, int J, bool kConj, bool kEager>
+__device__ __forceinline__ void t3_twiddle(d2 (&v)[kT3Pts], const T3Tw<M, kEager>& sd)
 {
     d2 w1, w4;
     if constexpr (kEager) {
@@ -220,14 +228,15 @@ __device__ __forceinline__ void t3_twiddles(d2 (&w)[8], const T3Tw<M, kEager>& s
     } else {
         t3_seed<M>(J, sd.u, sd.tw, w1, w4);
     }
-    const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
-    w[1] = w1;
-    w[2] = w2;
-    w[3] = w3;
-    w[4] = w4;
-    w[5] = cmul(w4, w1);
-    w[6] = cmul(w4, w2);
-    w[7] = cmul(w4, w3);
+    t3_tmul<kConj>(v[t3_bitrev(1, 8)], w1);
+    const d2 w2 = cmul(w1, w1);
+    t3_tmul<kConj>(v[t3_bitrev(2, 8)], w2);
+    const d2 w3 = cmul(w1, w2);
+    t3_tmul<kConj>(v[t3_bitrev(3, 8)], w3);
+    t3_tmul<kConj>(v[t3_bitrev(4, 8)], w4);
+    t3_tmul<kConj>(v[t3_bitrev(5, 8)], cmul(w4, w1));
+    t3_tmul<kConj>(v[t3_bitrev(6, 8)], cmul(w4, w2));
+    t3_tmul<kConj>(v[t3_bitrev(7, 8)], cmul(w4, w3));
 }
 
 // Phase J of the forward transform on the registers of thread u.  kHalf:
@@ -258,10 +267,7 @@ __device__ __forceinline__ void t3_fphase(d2 (&v)[kT3Pts], const T3Tw<M, kE>& tw
         }
         if constexpr (L > R) {  // offsets p1 > 0 exist: twiddles W_L^{p1 k2}
             static_assert(R == 8 && kT3Pts / R == 1, "one radix-8 group per thread");
-            d2 w[8];
-            t3_twiddles<M, J>(w, tw);
-#pragma unroll
-            for (int j = 1; j < R; ++j) v[i * R + j] = cmul(v[i * R + j], w[t3_bitrev(j, R)]);
+            t3_twiddle<M, J, false>(v, tw);
         }
     }
 }
@@ -275,13 +281,7 @@ __device__ __forceinline__ void t3_iphase(d2 (&v)[kT3Pts], const T3Tw<M, kE>& tw
     constexpr int R = S::radix(J), L = S::sublen(J);
 #pragma unroll
     for (int i = 0; i < kT3Pts / R; ++i) {
-        if constexpr (L > R) {
-            d2 w[8];
-            t3_twiddles<M, J>(w, tw);
-#pragma unroll
-            for (int j = 1; j < R; ++j)
-                v[i * R + j] = cmul_conj(v[i * R + j], w[t3_bitrev(j, R)]);
-        }
+        if constexpr (L > R) t3_twiddle<M, J, true>(v, tw);
         if constexpr (kHalf && J == 0) {
 #pragma unroll
             for (int h = 1; h <= 2; h <<= 1)
