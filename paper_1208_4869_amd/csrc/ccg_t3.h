@@ -387,6 +387,28 @@ __device__ __forceinline__ int t3_freq(int q)
     return k;
 }
 
+// Position holding frequency k (the inverse of t3_freq).
+template <int M>
+__device__ __forceinline__ int t3_pos(int k)
+{
+    using S = T3Shape<M>;
+    int q = 0;
+#pragma unroll
+    for (int j = 0; j < S::NPH; ++j) {
+        const int R = S::radix(j);
+        q += (k % R) * (S::sublen(j) / R);
+        k /= R;
+    }
+    return q;
+}
+
+// Frequencies in mirror-pair order: 0, M/2, 1, M - 1, 2, M - 2, ...
+template <int M>
+__device__ __forceinline__ int t3_mirror_seq(int a)
+{
+    return a == 0 ? 0 : a == 1 ? M / 2 : (a & 1) ? M - (a >> 1) : (a >> 1);
+}
+
 // Row of K for the z line at positions (qx, qy).  A kernel with
 // T(-dx, dy, dz) = T(dx, dy, dz) = T(dx, -dy, dz) (the lattice kernel, which
 // depends on |d| only) has K(-kx, ky, kz) = K(kx, ky, kz) = K(kx, -ky, kz),
@@ -568,15 +590,26 @@ __device__ __forceinline__ void t3_pass_y(const T3Geom g, d2* tile)
     t3_tile_store<M>(th, v, tile, out, mp, live);
 }
 
-// X3: along z: forward, times K, inverse; G2 in place; line kx M + ky.
+// X3: along z: forward, times K, inverse; G2 in place; line kx M + ky.  For
+// a kernel even in x and y the lines are taken in frequency order with each
+// frequency beside its mirror (t3_mirror_seq), so that the up to four lines
+// sharing a folded K row run in one workgroup (the mirror in y: the next
+// line) or M lines later (the mirror in x: a workgroup M / T later, on the
+// same XCD), and the row is read from HBM about once.
 template <int M>
 __device__ __forceinline__ void t3_pass_z(const T3Geom g, d2* tile)
 {
     const int m = g.m;
     const T3Thread<M> th;  // M^2 is a multiple of T: every line exists
     const T3Tw<M, false> tw(th.u, g.tw);
-    d2* row = g.g2 + th.line * g.mp;
-    const d2* krow = g.K + t3_krow<M>(th.line / M, th.line % M, *g.even != 0) * M;
+    const bool even = *g.even != 0;
+    int qx = th.line / M, qy = th.line % M;
+    if (even) {
+        qx = t3_pos<M>(t3_mirror_seq<M>(qx));
+        qy = t3_pos<M>(t3_mirror_seq<M>(qy));
+    }
+    d2* row = g.g2 + (qx * M + qy) * g.mp;
+    const d2* krow = g.K + t3_krow<M>(qx, qy, even) * M;
     d2 v[kT3Pts] = {};
 #pragma unroll
     for (int s = 0; s < kT3Pts / 2; ++s) {
