@@ -30,6 +30,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <unordered_map>
@@ -2251,9 +2252,16 @@ static int serve_upload_table(ccg_server* S, const std::vector<std::pair<int, in
         S->stage_pending[u] = false;
     }
     SlotRec* h = S->stage_h + (size_t)u * kMaxActive;
+    // the device table lists the largest systems first: every batched grid
+    // then ends with the smallest blocks, and its tail is short
+    std::vector<int> order(want.size());
+    for (size_t i = 0; i < want.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
+        return S->slots[want[p].first]->n > S->slots[want[q].first]->n;
+    });
     int c = 0, g = 0, v = 0, o = 0, nq = 0;
     for (size_t i = 0; i < want.size(); ++i) {
-        SlotRec rec = S->slots[want[i].first]->rec;
+        SlotRec rec = S->slots[want[order[i]].first]->rec;
         rec.c0 = c;
         rec.g0 = g;
         rec.v0 = v;
