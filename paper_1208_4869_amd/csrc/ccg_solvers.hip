@@ -1942,21 +1942,6 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
     in.x = (d2*)d32;
     in.vec16 = rows16(A32, lda32);  // the inner vectors are 256-byte aligned
 
-    auto residual_norm2 = [&](bool x_zero, double* rr) -> int {
-        if (x_zero)
-            k_mix_copy<<<gE, kBlock, 0, s>>>((int)n, (const d2*)y, (d2*)x, r64, part);
-        else
-            k_mix_resid<<<gN, kBlockN, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x,
-                                               (const d2*)y, r64, part);
-        k_mix_total<<<1, kBlock, 0, s>>>(part, x_zero ? gE : gN, tot);
-        d2 h;
-        if ((e = hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
-            return (int)e;
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
-        *rr = h.x;
-        return 0;
-    };
-
     // ||y||^2
     k_mix_norm<<<gE, kBlock, 0, s>>>((int)n, (const d2*)y, part);
     k_mix_total<<<1, kBlock, 0, s>>>(part, gE, tot);
@@ -1975,6 +1960,26 @@ static int mixed_impl(int64_t n, const ccg_z* A, int64_t lda, const ccg_c* A32, 
         res->relres_true = 0.0;
         return 0;
     }
+    auto residual_norm2 = [&](bool x_zero, double* rr) -> int {
+        if (x_zero) {
+            // r = y, x = 0: ||r||^2 is ||y||^2, summed by the same blocks in
+            // the same order as k_mix_norm did above (the same bits), so no
+            // second round trip to the host
+            k_mix_copy<<<gE, kBlock, 0, s>>>((int)n, (const d2*)y, (d2*)x, r64, part);
+            *rr = ny2;
+            return (int)hipGetLastError();
+        }
+        k_mix_resid<<<gN, kBlockN, 0, s>>>((const d2*)A, lda, (int)n, (const d2*)x,
+                                           (const d2*)y, r64, part);
+        k_mix_total<<<1, kBlock, 0, s>>>(part, gN, tot);
+        d2 h;
+        if ((e = hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return (int)e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return (int)e;
+        *rr = h.x;
+        return 0;
+    };
+
     const double thr2 = tol * tol * ny2;
     for (int outer = 0;; ++outer) {
         double rr = 0.0;
