@@ -928,7 +928,7 @@ __global__ __launch_bounds__(kBlock) void k_t3p_y(T3Geom g)
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_z(T3Geom g)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M, true>()];
     t3_pass_z<M>(g, tile);
 }
 template <int M>

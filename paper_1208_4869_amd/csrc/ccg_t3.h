@@ -110,14 +110,27 @@ __device__ __forceinline__ int t3_pos_out(int u, int s)
     return t3_pos_in<M, J>(u, (s / R) * R + t3_bitrev(s % R, R));
 }
 
-// LDS index of point p of line il of a tile: p with its low four bits
-// permuted by higher bits of p and by il, so that each phase's exchange
-// and the tile's strided loads and stores meet few bank conflicts.
-template <int M>
+// LDS index of point p of line il of a tile.  Default layout: p with its
+// low four bits permuted by higher bits of p and by il, so that each
+// phase's exchange and the tile's strided loads and stores (consecutive
+// threads on consecutive lines) meet few bank conflicts.  kPad (a pass with
+// exchanges only, the z pass): one point of padding after every 16, rows of
+// M + M/16 points, which keeps the exchanges within two-way conflicts and
+// makes every slot's index the thread's base plus a constant (an immediate
+// offset of the LDS instruction) instead of a per-slot permutation.
+template <int M, bool kPad = false>
 __device__ __forceinline__ int t3_lds(int il, int p)
 {
+    if constexpr (kPad) return il * (M + M / 16) + p + (p >> 4);
     const int f = (((p >> 4) & 3) ^ (((p >> 5) & 3) << 2) ^ (il << 1)) & 15;
     return il * M + (p ^ f);
+}
+
+// Points of an LDS tile of T lines in either layout.
+template <int M, bool kPad = false>
+constexpr int t3_tile_pts()
+{
+    return T3Shape<M>::T * (kPad ? M + M / 16 : M);
 }
 
 __device__ __forceinline__ d2 cmul_conj(d2 a, d2 w)  // a * conj(w)
@@ -302,19 +315,19 @@ __device__ __forceinline__ void t3_iphase(d2 (&v)[kT3Pts], const T3Tw<M, kE>& tw
 
 // Store the registers at the points they hold after phase J (output side)
 // or before it (input side), and read them back for another layout.
-template <int M, int J, bool kOut>
+template <int M, int J, bool kOut, bool kPad = false>
 __device__ __forceinline__ void t3_put(const d2 (&v)[kT3Pts], int u, int il, d2* tile)
 {
 #pragma unroll
     for (int s = 0; s < kT3Pts; ++s)
-        tile[t3_lds<M>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))] = v[s];
+        tile[t3_lds<M, kPad>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))] = v[s];
 }
-template <int M, int J, bool kOut>
+template <int M, int J, bool kOut, bool kPad = false>
 __device__ __forceinline__ void t3_get(d2 (&v)[kT3Pts], int u, int il, const d2* tile)
 {
 #pragma unroll
     for (int s = 0; s < kT3Pts; ++s)
-        v[s] = tile[t3_lds<M>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))];
+        v[s] = tile[t3_lds<M, kPad>(il, kOut ? t3_pos_out<M, J>(u, s) : t3_pos_in<M, J>(u, s))];
 }
 
 // Between the phases of a transform the points of a line move between
@@ -329,33 +342,33 @@ __device__ __forceinline__ void t3_wave_sync()
 
 // Forward transform: natural order in (slot s of thread u = point u + s M/8),
 // the last phase's output layout out.
-template <int M, bool kHalf, int J = 0, bool kE>
+template <int M, bool kHalf, int J = 0, bool kE, bool kPad = false>
 __device__ __forceinline__ void t3_forward(d2 (&v)[kT3Pts], int u, int il, d2* tile,
                                            const T3Tw<M, kE>& tw)
 {
     t3_fphase<M, J, kHalf>(v, tw);
     if constexpr (J + 1 < T3Shape<M>::NPH) {
-        t3_put<M, J, true>(v, u, il, tile);
+        t3_put<M, J, true, kPad>(v, u, il, tile);
         t3_wave_sync();
-        t3_get<M, J + 1, false>(v, u, il, tile);
+        t3_get<M, J + 1, false, kPad>(v, u, il, tile);
         t3_wave_sync();
-        t3_forward<M, kHalf, J + 1>(v, u, il, tile, tw);
+        t3_forward<M, kHalf, J + 1, kE, kPad>(v, u, il, tile, tw);
     }
 }
 
 // Inverse transform (times M): the last forward phase's layout in, natural
 // order out.
-template <int M, bool kHalf, int J = T3Shape<M>::NPH - 1, bool kE>
+template <int M, bool kHalf, int J = T3Shape<M>::NPH - 1, bool kE, bool kPad = false>
 __device__ __forceinline__ void t3_inverse(d2 (&v)[kT3Pts], int u, int il, d2* tile,
                                            const T3Tw<M, kE>& tw)
 {
     t3_iphase<M, J, kHalf>(v, tw);
     if constexpr (J > 0) {
-        t3_put<M, J, false>(v, u, il, tile);
+        t3_put<M, J, false, kPad>(v, u, il, tile);
         t3_wave_sync();
-        t3_get<M, J - 1, true>(v, u, il, tile);
+        t3_get<M, J - 1, true, kPad>(v, u, il, tile);
         t3_wave_sync();
-        t3_inverse<M, kHalf, J - 1>(v, u, il, tile, tw);
+        t3_inverse<M, kHalf, J - 1, kE, kPad>(v, u, il, tile, tw);
     }
 }
 
@@ -610,16 +623,19 @@ __device__ __forceinline__ void t3_pass_z(const T3Geom g, d2* tile)
     }
     d2* row = g.g2 + (qx * M + qy) * g.mp;
     const d2* krow = g.K + t3_krow<M>(qx, qy, even) * M;
-    d2 v[kT3Pts] = {};
+    d2 v[kT3Pts];
 #pragma unroll
-    for (int s = 0; s < kT3Pts / 2; ++s) {
+    for (int s = 0; s < kT3Pts / 2; ++s) {  // a clamped load and a select: no branch
         const int iz = th.point(s);
-        if (iz < m) v[s] = row[iz];
+        const d2 val = row[iz < m ? iz : m - 1];
+        v[s] = iz < m ? val : d2{0.0, 0.0};
     }
-    t3_forward<M, true>(v, th.u, th.il, tile, tw);
+#pragma unroll
+    for (int s = kT3Pts / 2; s < kT3Pts; ++s) v[s] = d2{0.0, 0.0};
+    t3_forward<M, true, 0, false, true>(v, th.u, th.il, tile, tw);
 #pragma unroll
     for (int s = 0; s < kT3Pts; ++s) v[s] = cmul(v[s], krow[th.point(s)]);
-    t3_inverse<M, true>(v, th.u, th.il, tile, tw);
+    t3_inverse<M, true, T3Shape<M>::NPH - 1, false, true>(v, th.u, th.il, tile, tw);
 #pragma unroll
     for (int s = 0; s < kT3Pts / 2; ++s) {  // points < M/2 are the ones kept
         const int iz = th.point(s);
