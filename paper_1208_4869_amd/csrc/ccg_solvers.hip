@@ -470,7 +470,7 @@ template <Role RO, int M>
 __global__ __launch_bounds__(kBlock) void k_t3_x(Args a, int q)
 {
     SOLVER_PROLOGUE();
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const int mode = role_mode<RO>(L.phase);
     if (mode >= 0 && mode != PH_ZERO) t3_pass_x<M>(a.t3, role_input<RO>(a, mode), tile);
     publish(a, q, L, PK_NONE, 0);
@@ -480,7 +480,7 @@ template <Role RO, int M>
 __global__ __launch_bounds__(kBlock) void k_t3_role(Args a, int q)
 {
     SOLVER_PROLOGUE();
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const int mode = role_mode<RO>(L.phase);
     if (mode < 0) { publish(a, q, L, PK_NONE, 0); return; }
     if (mode == PH_ZERO) {  // y == 0: x = 0
@@ -916,31 +916,31 @@ __global__ __launch_bounds__(kBlock) void k_symv_gather_plain(SymGeom g, int n,
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_x(T3Geom g, const d2* __restrict__ x)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     t3_pass_x<M>(g, x, tile);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_y(T3Geom g)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     t3_pass_y<M>(g, tile);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_z(T3Geom g)
 {
-    __shared__ d2 tile[t3_tile_pts<M, true>()];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     t3_pass_z<M>(g, tile);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_yi(T3Geom g)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     t3_pass_yi<M>(g, tile);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3p_xi(T3Geom g, d2* __restrict__ y)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const T3Thread<M> th;
     d2 v[kT3Pts];
     const int line = t3_pass_xi<M>(g, th, v, tile);
@@ -962,7 +962,7 @@ __global__ __launch_bounds__(kT3PlaneThreads) void k_t3s_xy(T3Geom g, const d2* 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3s_z(T3Geom g)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     t3s_z<M>(g, tile);
 }
 template <int M>
@@ -1035,7 +1035,7 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3_s1(const d2* __restrict__ table, T3Geom g,
                                                   d2* __restrict__ S1)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const int m = g.m, w = 2 * m - 1;
     const T3Thread<M> th;  // every line of the M^2 exists (M^2 is a multiple of T)
     const int y = th.line % M, z = th.line / M;
@@ -1060,7 +1060,7 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3_s2(T3Geom g, const d2* __restrict__ S1,
                                                   d2* __restrict__ S2)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const T3Thread<M> th;
     const d2* in = S1 + ((th.line % M) * M + th.line / M) * M;
     d2 v[kT3Pts];
@@ -1079,7 +1079,7 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void k_t3_s3(T3Geom g, const d2* __restrict__ S2,
                                                   d2* __restrict__ K, double scale)
 {
-    __shared__ d2 tile[T3Shape<M>::T * M];
+    __shared__ d2 tile[t3_tile_pts<M>()];
     const T3Thread<M> th;
     const d2* in = S2 + th.line * M;
     d2 v[kT3Pts];

@@ -110,27 +110,27 @@ __device__ __forceinline__ int t3_pos_out(int u, int s)
     return t3_pos_in<M, J>(u, (s / R) * R + t3_bitrev(s % R, R));
 }
 
-// LDS index of point p of line il of a tile.  Default layout: p with its
-// low four bits permuted by higher bits of p and by il, so that each
-// phase's exchange and the tile's strided loads and stores (consecutive
-// threads on consecutive lines) meet few bank conflicts.  kPad (a pass with
-// exchanges only, the z pass): one point of padding after every 16, rows of
-// M + M/16 points, which keeps the exchanges within two-way conflicts and
-// makes every slot's index the thread's base plus a constant (an immediate
-// offset of the LDS instruction) instead of a per-slot permutation.
+// LDS index of point p of line il of a tile; a line's row holds M + M/16
+// points in both layouts, so that a wavefront's rows are its own in either.
+// kPad (the exchanges between phases): one point of padding after every 16,
+// which keeps them within two-way bank conflicts and makes every slot's
+// index the thread's base plus a constant (an immediate offset of the LDS
+// instruction).  Otherwise (the tile's strided loads and stores, consecutive
+// threads on consecutive lines): p with its low four bits permuted by higher
+// bits of p and by il, which spreads the lines over the banks.
 template <int M, bool kPad = false>
 __device__ __forceinline__ int t3_lds(int il, int p)
 {
     if constexpr (kPad) return il * (M + M / 16) + p + (p >> 4);
     const int f = (((p >> 4) & 3) ^ (((p >> 5) & 3) << 2) ^ (il << 1)) & 15;
-    return il * M + (p ^ f);
+    return il * (M + M / 16) + (p ^ f);
 }
 
-// Points of an LDS tile of T lines in either layout.
-template <int M, bool kPad = false>
+// Points of the LDS tile of T lines.
+template <int M>
 constexpr int t3_tile_pts()
 {
-    return T3Shape<M>::T * (kPad ? M + M / 16 : M);
+    return T3Shape<M>::T * (M + M / 16);
 }
 
 __device__ __forceinline__ d2 cmul_conj(d2 a, d2 w)  // a * conj(w)
@@ -342,7 +342,7 @@ __device__ __forceinline__ void t3_wave_sync()
 
 // Forward transform: natural order in (slot s of thread u = point u + s M/8),
 // the last phase's output layout out.
-template <int M, bool kHalf, int J = 0, bool kE, bool kPad = false>
+template <int M, bool kHalf, int J = 0, bool kE, bool kPad = true>
 __device__ __forceinline__ void t3_forward(d2 (&v)[kT3Pts], int u, int il, d2* tile,
                                            const T3Tw<M, kE>& tw)
 {
@@ -358,7 +358,7 @@ __device__ __forceinline__ void t3_forward(d2 (&v)[kT3Pts], int u, int il, d2* t
 
 // Inverse transform (times M): the last forward phase's layout in, natural
 // order out.
-template <int M, bool kHalf, int J = T3Shape<M>::NPH - 1, bool kE, bool kPad = false>
+template <int M, bool kHalf, int J = T3Shape<M>::NPH - 1, bool kE, bool kPad = true>
 __device__ __forceinline__ void t3_inverse(d2 (&v)[kT3Pts], int u, int il, d2* tile,
                                            const T3Tw<M, kE>& tw)
 {
@@ -710,7 +710,7 @@ struct T3PlaneShape {
     static_assert(TL >= M, "one round holds the y lines of a plane");
 };
 template <int M>
-using T3PlaneTile = d2[T3PlaneShape<M>::TL * M];
+using T3PlaneTile = d2[T3PlaneShape<M>::TL * (M + M / 16)];
 template <int M>
 using T3Plane = d2[(M / 2) * M];  // m <= M/2 rows of M points
 
