@@ -84,6 +84,24 @@ static inline int kslice_of(int64_t n)
 // rather than bound by the padded matrix-core work.
 constexpr int kKS = 8;  // k per LDS stage (a multiple of the 4-deep MFMA step)
 constexpr int kHalfCols = 8;  // widest product of the packed form
+// Stages whose global loads are in flight at once in the packed form: its
+// products are HBM bound (8 to 16 flops per byte of A), and one stage ahead
+// (two A elements per thread per barrier) leaves HBM mostly idle.  The ring
+// holds the loaded values in registers; each stage stores one slot to LDS,
+// waits at the barrier, issues the loads of the stage kHalfRing ahead into
+// that slot and multiplies.  Measured through ccg_matmat with 4-wavefront
+// blocks (6 / 8 columns, HIP events): n = 4096 50.4 / 49.4 us against 61.6 /
+// 59.3 for one stage ahead with 8-wavefront blocks, n = 2048 19.0 / 19.4
+// against 24.8 / 25.2; an 8-deep ring was slower than 4 (53.1 / 51.2 at
+// n = 4096: more registers, fewer blocks per compute unit).  Above
+// kHalfRingMaxN the stand-alone product keeps the one-stage form, which was
+// faster there (n = 8000: 180.7 against 189.0 us).  The serving grids keep
+// the one-stage form: they batch many requests, so many blocks per compute
+// unit are in flight anyway, and their capacity did not change with a ring of
+// 4 or 8 (within the 3% spread between boxes).  The matrix-core steps are the
+// same in every form, so are the bits.
+constexpr int kHalfRing = 4;
+constexpr int kHalfRingMaxN = 4096;
 
 // LDS of one zgemm_body shape: two A tiles and two B tiles (the caller
 // declares it, so that a kernel with several shapes holds the largest once).
@@ -96,7 +114,7 @@ struct ZgemmLds {
     static constexpr int size = 2 * ROWS * AP + 2 * BN;     // d2 elements
 };
 
-template <int NT, int KS = kKS, int WV = kWavesPerBlock, bool kHalf = false>
+template <int NT, int KS = kKS, int WV = kWavesPerBlock, bool kHalf = false, int PF = 1>
 __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid, d2* lds)
@@ -132,46 +150,39 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     const int aseg = (t % (KS / AE)) * AE;
     const int grow = rb * ROWS + arow < n ? rb * ROWS + arow : n - 1;
     const d2* Ar = A + (int64_t)grow * lda;
-    // The loads of the next stage only issue here; what falls outside the
-    // slice is zeroed when the values go to LDS (after this stage's matrix
-    // products), so nothing waits for the loads before the products.
-    d2 ra[AE], rbv[BPT];
-    bool aok[AE], bok[BPT];
-    auto gload = [&](int kk) {
+    // The loads of a stage only issue here; what falls outside the slice is
+    // zeroed when the values go to LDS (after other stages' matrix products),
+    // so nothing waits for the loads before the products.  Slot j of the ring
+    // holds the loads of stages j, j + PF, j + 2 PF, ...
+    d2 ra[PF][AE], rbv[PF][BPT];
+    bool aok[PF][AE], bok[PF][BPT];
+    auto gload = [&](int j, int kk) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int kc = kk + aseg + e;
-            aok[e] = kc < k1;
-            ra[e] = Ar[kc < n ? kc : n - 1];
+            aok[j][e] = kc < k1;
+            ra[j][e] = Ar[kc < k1 ? kc : k0];
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * TH;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
-            bok[m] = idx < BN && kc < k1 && c < ncols;
-            rbv[m] = B[(int64_t)(bok[m] ? kc : k0) * ldb + (bok[m] ? c : 0)];
+            bok[j][m] = idx < BN && kc < k1 && c < ncols;
+            rbv[j][m] = B[(int64_t)(bok[j][m] ? kc : k0) * ldb + (bok[j][m] ? c : 0)];
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int j, int buf) {
         const d2 z = d2{0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[j][e] ? ra[j][e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * TH;
-            if (idx < BN) Bs[buf][idx] = bok[m] ? rbv[m] : z;
+            if (idx < BN) Bs[buf][idx] = bok[j][m] ? rbv[j][m] : z;
         }
     };
-    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
-    if (nst > 0) {
-        gload(k0);
-        lstore(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-        const int cur = st & 1;
-        if (st + 1 < nst) gload(k0 + (st + 1) * KS);
+    auto mstage = [&](int cur) {
 #pragma unroll
         for (int ks = 0; ks < KS; ks += 4) {
             const d2 a = As[cur][(w * 16 + li) * AP + ks + lk];
@@ -197,8 +208,46 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
                 }
             }
         }
-        if (st + 1 < nst) lstore(cur ^ 1);
+    };
+    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
+    if constexpr (PF == 1) {
+        // next stage's loads in flight during this stage's products; one
+        // barrier per stage
+        if (nst > 0) {
+            gload(0, k0);
+            lstore(0, 0);
+        }
         __syncthreads();
+        for (int st = 0; st < nst; ++st) {
+            const int cur = st & 1;
+            if (st + 1 < nst) gload(0, k0 + (st + 1) * KS);
+            mstage(cur);
+            if (st + 1 < nst) lstore(0, cur ^ 1);
+            __syncthreads();
+        }
+    } else {
+        // PF stages in flight.  Stage st stores slot st mod PF into LDS
+        // buffer st mod 2 (whose previous contents, stage st - 2, every
+        // wavefront has multiplied before the barrier of stage st - 1),
+        // waits at the barrier, refills the slot with stage st + PF and
+        // multiplies.  Every slot is loaded and stored in each group of PF
+        // stages, also past the slice (those loads re-read its first
+        // columns and are zeroed), so the compiler's count of the loads in
+        // flight stays exact and a store waits only for its own slot; only
+        // the products stop at the last stage (nst is the same in the whole
+        // block).
+#pragma unroll
+        for (int j = 0; j < PF; ++j) gload(j, k0 + j * KS);
+        for (int st0 = 0; st0 < nst; st0 += PF) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int st = st0 + j;
+                lstore(j, st & 1);
+                __syncthreads();
+                gload(j, k0 + (st + PF) * KS);
+                if (st < nst) mstage(st & 1);
+            }
+        }
     }
     // result register v of a lane holds row lk + 4 v of the wavefront's 16-row
     // tile, column li (the v_mfma_f64_16x16x4f64 result layout; the
@@ -235,7 +284,7 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
 // same order whatever the block shape, so all shapes give the same bits.
 constexpr int kGemmWaves = 8;
 
-template <int NT, int KS = kKS, int WV = kGemmWaves, bool kHalf = false>
+template <int NT, int KS = kKS, int WV = kGemmWaves, bool kHalf = false, int PF = 1>
 __global__ __launch_bounds__(WV * kWave) void k_zgemm(const d2* __restrict__ A, int64_t lda,
                                                       int n, const d2* __restrict__ B,
                                                       int64_t ldb, int ncols,
@@ -244,7 +293,7 @@ __global__ __launch_bounds__(WV * kWave) void k_zgemm(const d2* __restrict__ A, 
 {
     __shared__ d2 lds[ZgemmLds<NT, KS, WV, kHalf>::size];
     if (skip && *skip) return;
-    zgemm_body<NT, KS, WV, kHalf>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x, lds);
+    zgemm_body<NT, KS, WV, kHalf, PF>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x, lds);
 }
 
 // Slice s of Z = A B for at most kVCols columns, on the vector units.  With
@@ -342,9 +391,19 @@ template <int NT, bool kHalf = false>
 static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int ncols,
                         d2* Zp, hipStream_t s, const int* skip)
 {
+    if constexpr (kHalf) {
+        if (n <= kHalfRingMaxN) {  // the packed form's ring
+            constexpr int rows = 16 * kWavesPerBlock;
+            const int rblocks = (n + rows - 1) / rows;
+            k_zgemm<NT, kKS, kWavesPerBlock, kHalf, kHalfRing>
+                <<<rblocks * kSlices, kWavesPerBlock * kWave, 0, s>>>(A, lda, n, B, ldb, ncols,
+                                                                      Zp, kslice_of(n), skip);
+            return;
+        }
+    }
     constexpr int rows = 16 * kGemmWaves;
     const int rblocks = (n + rows - 1) / rows;
-    k_zgemm<NT, kKS, kGemmWaves, kHalf><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(
+    k_zgemm<NT, kKS, kGemmWaves, kHalf, 1><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(
         A, lda, n, B, ldb, ncols, Zp, kslice_of(n), skip);
 }
 
