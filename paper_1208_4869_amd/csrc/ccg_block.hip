@@ -232,20 +232,23 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         // waits at the barrier, refills the slot with stage st + PF and
         // multiplies.  Every slot is loaded and stored in each group of PF
         // stages, also past the slice (those loads re-read its first
-        // columns and are zeroed), so the compiler's count of the loads in
-        // flight stays exact and a store waits only for its own slot; only
-        // the products stop at the last stage (nst is the same in the whole
-        // block).
+        // columns, k0 < k1 <= n, and are zeroed), so the compiler's count of
+        // the loads in flight stays exact and a store waits only for its own
+        // slot; only the products stop at the last stage.  An empty slice
+        // (k0 >= n: small n) loads nothing and stores its zero sums.  nst is
+        // the same in the whole block.
+        if (nst > 0) {
 #pragma unroll
-        for (int j = 0; j < PF; ++j) gload(j, k0 + j * KS);
-        for (int st0 = 0; st0 < nst; st0 += PF) {
+            for (int j = 0; j < PF; ++j) gload(j, k0 + j * KS);
+            for (int st0 = 0; st0 < nst; st0 += PF) {
 #pragma unroll
-            for (int j = 0; j < PF; ++j) {
-                const int st = st0 + j;
-                lstore(j, st & 1);
-                __syncthreads();
-                gload(j, k0 + (st + PF) * KS);
-                if (st < nst) mstage(st & 1);
+                for (int j = 0; j < PF; ++j) {
+                    const int st = st0 + j;
+                    lstore(j, st & 1);
+                    __syncthreads();
+                    gload(j, k0 + (st + PF) * KS);
+                    if (st < nst) mstage(st & 1);
+                }
             }
         }
     }
