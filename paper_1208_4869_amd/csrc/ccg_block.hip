@@ -75,6 +75,19 @@ static inline int kslice_of(int64_t n)
 // matrix cores work on the current one.  Wavefront w multiplies rows
 // 16w..16w+15 of the tile by all 16 NT columns.
 //
+// Each complex product takes three real matrix-core products rather than
+// four (the 3M method): with P1 = Re A Re B, P2 = Im A Im B and
+// P3 = (Re A + Im A)(Re B + Im B) accumulated over the slice, Re Z = P1 - P2
+// and Im Z = (P3 - P1) - P2.  It does a quarter less matrix-core work; its
+// error is bounded normwise like the four-product form's (Higham, SIAM J.
+// Matrix Anal. Appl. 13, 1992), about three times the unit roundoff times
+// |A| |B| for the imaginary part instead of two, and it is exact on Gaussian
+// integers of moderate size.  At n = 8000, k = 64 (20 back-to-back launches
+// through ccg_matmat, HIP events, A/B on one box): 543 - 553 us against
+// 609 - 612 us; splitting the 64 columns over two wavefronts per 16 rows
+// (half the accumulators, two blocks per compute unit) or 16-deep stages
+// measured the same.
+//
 // kHalf (NT = 1, ncols <= 8): the 16 columns of the matrix-core tile hold the
 // real parts (columns 0-7) and the imaginary parts (8-15) of the 8 complex
 // columns of B, so each 4-deep step takes two real products (Re A and Im A
@@ -139,11 +152,15 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
     const int lk = lane >> 4;  // k within the 4-deep MFMA step
     const int k0 = s * kslice;
     const int k1 = k0 + kslice < n ? k0 + kslice : n;
-    d4 cre[NT], cim[NT];
+    // kHalf: cre = Re A x [Re B | Im B], cim = Im A x [Re B | Im B].  Else the
+    // three real products of each complex one: cre = Re A Re B, cim =
+    // Im A Im B, c3 = (Re A + Im A)(Re B + Im B).
+    d4 cre[NT], cim[NT], c3[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         cre[q] = d4{0.0, 0.0, 0.0, 0.0};
         cim[q] = d4{0.0, 0.0, 0.0, 0.0};
+        c3[q] = d4{0.0, 0.0, 0.0, 0.0};
     }
     // this thread's share of the global tiles
     const int arow = t / (KS / AE);
@@ -196,15 +213,13 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
                 d2 b[NT];
 #pragma unroll
                 for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
+                const double as = a.x + a.y;
 #pragma unroll
                 for (int q = 0; q < NT; ++q) {
                     cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].x, cre[q], 0, 0, 0);
-                    cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[q].y, cim[q], 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b[q].y, cre[q], 0, 0, 0);
-                    cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[q].x, cim[q], 0, 0, 0);
+                    cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[q].y, cim[q], 0, 0, 0);
+                    c3[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, b[q].x + b[q].y, c3[q], 0, 0,
+                                                                 0);
                 }
             }
         }
@@ -265,6 +280,7 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
         }
         return;
     }
+    // Re = Re A Re B - Im A Im B, Im = (c3 - Re A Re B) - Im A Im B
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         const int col = 16 * q + li;
@@ -272,7 +288,9 @@ __device__ __forceinline__ void zgemm_body(const d2* __restrict__ A, int64_t lda
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = rb * ROWS + w * 16 + lk + 4 * v;
-            if (r < n) Zp[((int64_t)s * n + r) * ncols + col] = d2{cre[q][v], cim[q][v]};
+            if (r < n)
+                Zp[((int64_t)s * n + r) * ncols + col] =
+                    d2{cre[q][v] - cim[q][v], (c3[q][v] - cre[q][v]) - cim[q][v]};
         }
     }
 }
