@@ -422,9 +422,16 @@ static void launch_gemm(const d2* A, int64_t lda, int n, const d2* B, int64_t ld
             return;
         }
     }
+    // 49 - 64 columns: the 3M accumulators leave one 8-wavefront block per
+    // compute unit, whose waves waited on their loads 27% of their cycles
+    // with one stage ahead; two stages ahead (the ring of the packed form,
+    // same occupancy) took n = 8000 from 544 - 548 to 533 - 535 us (four: no
+    // better).  Narrower products keep two blocks per compute unit and one
+    // stage.
+    constexpr int PF = (!kHalf && NT == 4) ? 2 : 1;
     constexpr int rows = 16 * kGemmWaves;
     const int rblocks = (n + rows - 1) / rows;
-    k_zgemm<NT, kKS, kGemmWaves, kHalf, 1><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(
+    k_zgemm<NT, kKS, kGemmWaves, kHalf, PF><<<rblocks * kSlices, kGemmWaves * kWave, 0, s>>>(
         A, lda, n, B, ldb, ncols, Zp, kslice_of(n), skip);
 }
 
