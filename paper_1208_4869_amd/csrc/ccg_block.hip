@@ -68,12 +68,13 @@ static inline int kslice_of(int64_t n)
 // Slice s of Z = A B: Zp[s][i][c] = sum over k in slice s of A[i][k] B[k][c],
 // for i < n, c < ncols (ncols <= 16 NT).
 //
-// The block stages tiles of A (64 rows x kKS) and B (kKS x 16 NT) through LDS,
-// double buffered, with coalesced loads (each thread fetches two consecutive
-// elements of an A row; a wavefront covers 16 rows x 128 bytes), one barrier
-// per stage; the global loads of the next stage are in flight while the
-// matrix cores work on the current one.  Wavefront w multiplies rows
-// 16w..16w+15 of the tile by all 16 NT columns.
+// The block stages tiles of A (16 WV rows x kKS) and B (kKS x 16 NT) through
+// LDS, double buffered, with coalesced loads (each thread fetches two
+// consecutive elements of an A row; a wavefront covers 16 rows x 128 bytes),
+// one barrier per stage; the global loads of the next PF stages are in flight
+// while the matrix cores work on the current one (PF = 1 except for the
+// products that launch_gemm gives a ring, below).  Wavefront w multiplies
+// rows 16w..16w+15 of the tile by all 16 NT columns.
 //
 // Each complex product takes three real matrix-core products rather than
 // four (the 3M method): with P1 = Re A Re B, P2 = Im A Im B and
