@@ -30,8 +30,13 @@ def test_matmat_integer_bitwise(orc, n, k):
     assert np.array_equal(Z, orc.matmat(A, B))
 
 
-@pytest.mark.parametrize("n,k", [(7, 5), (300, 64), (1031, 40), (513, 8)])
+@pytest.mark.parametrize("n,k", [(7, 5), (300, 64), (1031, 40), (513, 8), (100, 12),
+                                 (257, 20)])
 def test_matmat_random_bound_and_layout(orc, n, k):
+    """Random inputs against the oracle within 4 gamma_{n+2} |A| |B| (the
+    three-real-product form's bound is about 3 u |A| |B| per element for the
+    imaginary part), every column-tile count: 5 and 8 columns packed, 12, 20,
+    40 and 64 on one to four tiles."""
     rng = np.random.default_rng(n)
     A = inputs.cn01(rng, (n, n))
     Bbig = inputs.cn01(rng, (n, k + 3))
