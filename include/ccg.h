@@ -367,7 +367,11 @@ int ccg_round_c64(int64_t rows, int64_t cols, const ccg_z* src, int64_t lds,
  * (element (i, c) at B[i*ldb + c], ldb >= k; same for Z).  The user matvec of
  * the Usage section applied to k vectors; on FP64 matrix cores
  * (v_mfma_f64_16x16x4f64), FP64 accumulation in a fixed order (reproducible
- * bit for bit).  Columns are processed 64 at a time.  B and Z must not
+ * bit for bit).  Beyond 8 columns each complex product is formed from three
+ * real ones (Re A Re B, Im A Im B, (Re A + Im A)(Re B + Im B)): every element
+ * is within about 3 (n + 2) u |A| |B| of the exact product, u = 2^-53, and
+ * exact on Gaussian integers of moderate size.  Columns are processed 64 at a
+ * time.  B and Z must not
  * overlap.  Asynchronous; ccg_matmat takes a stream-ordered scratch of
  * ccg_workspace_bytes(CCG_WS_MATMAT, n, k) bytes, ccg_matmat_ex takes it from
  * the caller (256-byte aligned).
@@ -407,10 +411,10 @@ int ccg_bicgstab_block_ex(int64_t n, int64_t k, const ccg_z* A, int64_t lda,
 /*
  * Z = A32 B with A32 complex64 (the copy made by ccg_round_c64), B and Z
  * complex128 n x k row-major: B is rounded to complex64 as it is read, the
- * products accumulate in FP32 on the FP32 matrix cores
- * (v_mfma_f32_16x16x4f32), each of the 8 K-slices is widened to FP64 and the
- * slices are added in FP64 in a fixed order.  The product of the mixed block
- * solver below.  Arguments: 1 n, 2 k, 3 A32, 4 lda32, 5 B, 6 ldb, 7 Z, 8 ldz,
+ * products (three real ones per complex one, as in ccg_matmat) accumulate in
+ * FP32 on the FP32 matrix cores (v_mfma_f32_16x16x4f32), each of the 8
+ * K-slices is widened to FP64 and the slices are added in FP64 in a fixed
+ * order.  The product of the mixed block solver below.  Arguments: 1 n, 2 k, 3 A32, 4 lda32, 5 B, 6 ldb, 7 Z, 8 ldz,
  * 9 work (256-byte aligned, >= ccg_workspace_bytes(CCG_WS_MATMAT_C64, n, k)),
  * 10 work_bytes, 11 stream.  Asynchronous.
  */
