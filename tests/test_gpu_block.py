@@ -54,6 +54,22 @@ def test_matmat_random_bound_and_layout(orc, n, k):
     assert np.array_equal(Z2, Zg[:, :k])  # fixed summation order
 
 
+@pytest.mark.parametrize("k", [12, 64])
+def test_matmat_cancellation_bound(orc, k):
+    """Real parts six orders above the imaginary ones: the three-real-product
+    form recovers Im Z as (P3 - P1) - P2 from terms of the size of the real
+    parts, so its error is bounded normwise (by |A| |B|) and not relative to
+    |Im Z|; the elementwise bound of the other product tests still holds."""
+    rng = np.random.default_rng(99 + k)
+    n = 700
+    A = rng.standard_normal((n, n)) + 1e-6j * rng.standard_normal((n, n))
+    B = rng.standard_normal((n, k)) + 1e-6j * rng.standard_normal((n, k))
+    Z = ccg.ccg_matmat(dev(A), dev(B)).cpu().numpy()
+    ref = orc.matmat(A, B)
+    bound = 4 * gamma(n + 2) * (np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(Z - ref) <= bound)
+
+
 def check_block(orc, A, Xt, Y, cols_oracle=None, tol=1e-10, maxit=1000):
     n, k = Y.shape
     Ad, Yd = dev(A), dev(Y)
