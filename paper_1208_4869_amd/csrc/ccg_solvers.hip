@@ -607,19 +607,27 @@ __global__ __launch_bounds__(kBlock) void k_sym_role(Args a, int q)
 template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 {
-    SOLVER_PROLOGUE();
-    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     T* s = (T*)a.s;
     const T* r = (const T*)a.r;
     const T* v = (const T*)a.v;
     const T* rh = (const T*)a.rh;
+    // The thread's first element's operands do not depend on the pending
+    // step: their loads are in flight during the prologue's state load.
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 zero = d2{0.0, 0.0};
+    const d2 v_0 = i0 < a.n ? ldv(v, i0) : zero;
+    const d2 r_0 = i0 < a.n ? ldv(r, i0) : zero;
+    const d2 rh_0 = i0 < a.n ? ldv(rh, i0) : zero;
+    SOLVER_PROLOGUE();
+    if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     const d2 nal = d2{-L.alpha.x, -L.alpha.y};
-    d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        stv(s, i, cfma(nal, ldv(v, i), ldv(r, i)));
+    d2 v0 = zero, v1 = zero;
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        stv(s, i, cfma(nal, first ? v_0 : ldv(v, i), first ? r_0 : ldv(r, i)));
         const d2 si = ldv(s, i);
         v0.x += cabs2(si);
-        v1 = cfma_conj(ldv(rh, i), si, v1);
+        v1 = cfma_conj(first ? rh_0 : ldv(rh, i), si, v1);
     }
     write_partials(v0, v1, a.part[q ^ 1], lds);
     publish(a, q, L, PK_S2, gridDim.x);
@@ -631,30 +639,40 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
 template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_xrp(Args a, int q)
 {
-    SOLVER_PROLOGUE();
-    const int ph = L.phase;
-    if (ph != PH_RUN && ph != PH_HALF) { publish(a, q, L, PK_NONE, 0); return; }
     T* x = (T*)a.x;
     T* r = (T*)a.r;
     T* p = (T*)a.p;
     const T* s = (const T*)a.s;
     const T* tv = (const T*)a.t;
     const T* v = (const T*)a.v;
+    // as in k_bicg_s: the first element's operands load during the prologue
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 zero = d2{0.0, 0.0};
+    const bool in0 = i0 < a.n;
+    const d2 p_0 = in0 ? ldv(p, i0) : zero;
+    const d2 x_0 = in0 ? ldv(x, i0) : zero;
+    const d2 s_0 = in0 ? ldv(s, i0) : zero;
+    const d2 t_0 = in0 ? ldv(tv, i0) : zero;
+    const d2 v_0 = in0 ? ldv(v, i0) : zero;
+    SOLVER_PROLOGUE();
+    const int ph = L.phase;
+    if (ph != PH_RUN && ph != PH_HALF) { publish(a, q, L, PK_NONE, 0); return; }
     const d2 alpha = L.alpha;
     const d2 omega = L.omega;
     const d2 beta = L.beta;
     const d2 nom = d2{-omega.x, -omega.y};
-    d2 v0 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 pi = ldv(p, i);
-        d2 xi = cfma(alpha, pi, ldv(x, i));
+    d2 v0 = zero;
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        const d2 pi = first ? p_0 : ldv(p, i);
+        d2 xi = cfma(alpha, pi, first ? x_0 : ldv(x, i));
         if (ph == PH_RUN) {
-            const d2 si = ldv(s, i);
+            const d2 si = first ? s_0 : ldv(s, i);
             xi = cfma(omega, si, xi);
-            stv(r, i, cfma(nom, ldv(tv, i), si));
+            stv(r, i, cfma(nom, first ? t_0 : ldv(tv, i), si));
             const d2 ri = ldv(r, i);
             v0.x += cabs2(ri);
-            const d2 d = cfma(nom, ldv(v, i), pi);  // p - omega v
+            const d2 d = cfma(nom, first ? v_0 : ldv(v, i), pi);  // p - omega v
             stv(p, i, cfma(beta, d, ri));
         }
         stv(x, i, xi);
