@@ -603,6 +603,14 @@ __global__ __launch_bounds__(kBlock) void k_sym_role(Args a, int q)
 
 // ------------------------------------------------------- BiCGSTAB vectors
 
+// The vector kernels load the operands of a thread's first element before
+// their prologue: they do not depend on the pending step, so their latency
+// overlaps the prologue's state and partial loads.
+__device__ __forceinline__ d2 first_ld(const d2* v, int i0, int n)
+{
+    return i0 < n ? v[i0] : d2{0.0, 0.0};
+}
+
 // s = r - alpha v, ||s||^2, r^H s
 template <class T = d2>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
@@ -611,8 +619,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Args a, int q)
     const T* r = (const T*)a.r;
     const T* v = (const T*)a.v;
     const T* rh = (const T*)a.rh;
-    // The thread's first element's operands do not depend on the pending
-    // step: their loads are in flight during the prologue's state load.
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
     const d2 zero = d2{0.0, 0.0};
     const d2 v_0 = i0 < a.n ? ldv(v, i0) : zero;
@@ -645,7 +651,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xrp(Args a, int q)
     const T* s = (const T*)a.s;
     const T* tv = (const T*)a.t;
     const T* v = (const T*)a.v;
-    // as in k_bicg_s: the first element's operands load during the prologue
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
     const d2 zero = d2{0.0, 0.0};
     const bool in0 = i0 < a.n;
@@ -687,17 +692,21 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xrp(Args a, int q)
 // x += alpha p, r -= alpha w, ||r||^2
 __global__ __launch_bounds__(kBlock) void k_cgnr_xr(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 p_0 = first_ld(a.p, i0, a.n), w_0 = first_ld(a.w, i0, a.n);
+    const d2 x_0 = first_ld(a.x, i0, a.n), r_0 = first_ld(a.r, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     const double al = L.alpha.x;
     d2 v0 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 pi = a.p[i];
-        const d2 wi = a.w[i];
-        d2 xi = a.x[i];
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        const d2 pi = first ? p_0 : a.p[i];
+        const d2 wi = first ? w_0 : a.w[i];
+        d2 xi = first ? x_0 : a.x[i];
         xi.x = __builtin_fma(al, pi.x, xi.x);
         xi.y = __builtin_fma(al, pi.y, xi.y);
-        d2 ri = a.r[i];
+        d2 ri = first ? r_0 : a.r[i];
         ri.x = __builtin_fma(-al, wi.x, ri.x);
         ri.y = __builtin_fma(-al, wi.y, ri.y);
         a.x[i] = xi;
@@ -766,16 +775,19 @@ __global__ __launch_bounds__(kBlock) void k_cgnr_z2_sym(Args a, int q)
 // p = z (new direction) or p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 z_0 = first_ld(a.z, i0, a.n), p_0 = first_ld(a.p, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase == PH_RUN) {
         const bool fresh = L.restart != 0;
         const double beta = L.beta.x;
-        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-            const d2 zi = a.z[i];
+        for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+            const bool first = i == i0;
+            const d2 zi = first ? z_0 : a.z[i];
             if (fresh) {
                 a.p[i] = zi;
             } else {
-                d2 pi = a.p[i];
+                d2 pi = first ? p_0 : a.p[i];
                 pi.x = __builtin_fma(beta, pi.x, zi.x);
                 pi.y = __builtin_fma(beta, pi.y, zi.y);
                 a.p[i] = pi;
@@ -791,13 +803,16 @@ __global__ __launch_bounds__(kBlock) void k_cgnr_p(Args a, int q)
 // COCG: p = r (new direction) or p = r + beta p
 __global__ __launch_bounds__(kBlock) void k_cocg_p(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 r_0 = first_ld(a.r, i0, a.n), p_0 = first_ld(a.p, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase == PH_RUN || L.phase == PH_RESTART) {
         const bool fresh = L.restart != 0;
         const d2 beta = L.beta;
-        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-            const d2 ri = a.r[i];
-            a.p[i] = fresh ? ri : cfma(beta, a.p[i], ri);
+        for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+            const bool first = i == i0;
+            const d2 ri = first ? r_0 : a.r[i];
+            a.p[i] = fresh ? ri : cfma(beta, first ? p_0 : a.p[i], ri);
         }
     }
     publish(a, q, L, PK_NONE, 0);
@@ -806,14 +821,18 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(Args a, int q)
 // COCG: x += alpha p, r -= alpha q, ||r||^2, (r, r)
 __global__ __launch_bounds__(kBlock) void k_cocg_xr(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 p_0 = first_ld(a.p, i0, a.n), x_0 = first_ld(a.x, i0, a.n);
+    const d2 v_0 = first_ld(a.v, i0, a.n), r_0 = first_ld(a.r, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     const d2 alpha = L.alpha;
     const d2 nal = d2{-alpha.x, -alpha.y};
     d2 v0 = d2{0.0, 0.0}, v1 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        a.x[i] = cfma(alpha, a.p[i], a.x[i]);
-        const d2 ri = cfma(nal, a.v[i], a.r[i]);
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        a.x[i] = cfma(alpha, first ? p_0 : a.p[i], first ? x_0 : a.x[i]);
+        const d2 ri = cfma(nal, first ? v_0 : a.v[i], first ? r_0 : a.r[i]);
         a.r[i] = ri;
         v0.x += cabs2(ri);
         v1 = cfma(ri, ri, v1);
@@ -826,21 +845,25 @@ __global__ __launch_bounds__(kBlock) void k_cocg_xr(Args a, int q)
 // (w, w)
 __global__ __launch_bounds__(kBlock) void k_cocr_pw(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 r_0 = first_ld(a.r, i0, a.n), u_0 = first_ld(a.z, i0, a.n);
+    const d2 p_0 = first_ld(a.p, i0, a.n), w_0 = first_ld(a.w, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     const bool fresh = L.restart != 0;
     const d2 beta = L.beta;
     d2 v0 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        const d2 ri = a.r[i];
-        const d2 ui = a.z[i];
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        const d2 ri = first ? r_0 : a.r[i];
+        const d2 ui = first ? u_0 : a.z[i];
         d2 pi, wi;
         if (fresh) {
             pi = ri;
             wi = ui;
         } else {
-            pi = cfma(beta, a.p[i], ri);
-            wi = cfma(beta, a.w[i], ui);
+            pi = cfma(beta, first ? p_0 : a.p[i], ri);
+            wi = cfma(beta, first ? w_0 : a.w[i], ui);
         }
         a.p[i] = pi;
         a.w[i] = wi;
@@ -853,14 +876,18 @@ __global__ __launch_bounds__(kBlock) void k_cocr_pw(Args a, int q)
 // COCR: x += alpha p, r -= alpha w, ||r||^2
 __global__ __launch_bounds__(kBlock) void k_cocr_xr(Args a, int q)
 {
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    const d2 p_0 = first_ld(a.p, i0, a.n), x_0 = first_ld(a.x, i0, a.n);
+    const d2 w_0 = first_ld(a.w, i0, a.n), r_0 = first_ld(a.r, i0, a.n);
     SOLVER_PROLOGUE();
     if (L.phase != PH_RUN) { publish(a, q, L, PK_NONE, 0); return; }
     const d2 alpha = L.alpha;
     const d2 nal = d2{-alpha.x, -alpha.y};
     d2 v0 = d2{0.0, 0.0};
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock) {
-        a.x[i] = cfma(alpha, a.p[i], a.x[i]);
-        const d2 ri = cfma(nal, a.w[i], a.r[i]);
+    for (int i = i0; i < a.n; i += gridDim.x * kBlock) {
+        const bool first = i == i0;
+        a.x[i] = cfma(alpha, first ? p_0 : a.p[i], first ? x_0 : a.x[i]);
+        const d2 ri = cfma(nal, first ? w_0 : a.w[i], first ? r_0 : a.r[i]);
         a.r[i] = ri;
         v0.x += cabs2(ri);
     }
