@@ -484,7 +484,7 @@ static inline int kslice32_of(int64_t n)
     return (int)(((per + kKS32 - 1) / kKS32) * kKS32);
 }
 
-template <int NT, int KS = kKS32, int WV = kWavesPerBlock>
+template <int NT, int KS = kKS32, int WV = kWavesPerBlock, int PF = 1>
 __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda, int n,
                                            const d2* __restrict__ B, int64_t ldb, int ncols,
                                            d2* __restrict__ Zp, int kslice, int bid)
@@ -520,45 +520,37 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     const f2* Ar = A + (int64_t)grow * lda;
     // as in zgemm_body: the loads only issue here; zeroing outside the slice
     // and the rounding of B to complex64 happen on the way to LDS
-    f2 ra[AE];
-    d2 rbv[BPT];
-    bool aok[AE], bok[BPT];
-    auto gload = [&](int kk) {
+    f2 ra[PF][AE];
+    d2 rbv[PF][BPT];
+    bool aok[PF][AE], bok[PF][BPT];
+    auto gload = [&](int j, int kk) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int kc = kk + aseg + e;
-            aok[e] = kc < k1;
-            ra[e] = Ar[kc < n ? kc : n - 1];
+            aok[j][e] = kc < k1;
+            ra[j][e] = Ar[kc < k1 ? kc : k0];
         }
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * TH;
             const int kc = kk + idx / BW;
             const int c = idx % BW;
-            bok[m] = idx < BN && kc < k1 && c < ncols;
-            rbv[m] = B[(int64_t)(bok[m] ? kc : k0) * ldb + (bok[m] ? c : 0)];
+            bok[j][m] = idx < BN && kc < k1 && c < ncols;
+            rbv[j][m] = B[(int64_t)(bok[j][m] ? kc : k0) * ldb + (bok[j][m] ? c : 0)];
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int j, int buf) {
         const f2 z = f2{0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[e] ? ra[e] : z;
+        for (int e = 0; e < AE; ++e) As[buf][arow * AP + aseg + e] = aok[j][e] ? ra[j][e] : z;
 #pragma unroll
         for (int m = 0; m < BPT; ++m) {
             const int idx = t + m * TH;
             if (idx < BN)
-                Bs[buf][idx] = bok[m] ? f2{(float)rbv[m].x, (float)rbv[m].y} : z;
+                Bs[buf][idx] = bok[j][m] ? f2{(float)rbv[j][m].x, (float)rbv[j][m].y} : z;
         }
     };
-    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
-    if (nst > 0) {
-        gload(k0);
-        lstore(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-        const int cur = st & 1;
-        if (st + 1 < nst) gload(k0 + (st + 1) * KS);
+    auto mstage = [&](int cur) {
 #pragma unroll
         for (int ks = 0; ks < KS; ks += 4) {
             const f2 a = As[cur][(w * 16 + li) * AP + ks + lk];
@@ -573,8 +565,34 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
                 c3[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b[q].x + b[q].y, c3[q], 0, 0, 0);
             }
         }
-        if (st + 1 < nst) lstore(cur ^ 1);
+    };
+    const int nst = k1 > k0 ? (k1 - k0 + KS - 1) / KS : 0;
+    if constexpr (PF == 1) {
+        if (nst > 0) {
+            gload(0, k0);
+            lstore(0, 0);
+        }
         __syncthreads();
+        for (int st = 0; st < nst; ++st) {
+            const int cur = st & 1;
+            if (st + 1 < nst) gload(0, k0 + (st + 1) * KS);
+            mstage(cur);
+            if (st + 1 < nst) lstore(0, cur ^ 1);
+            __syncthreads();
+        }
+    } else if (nst > 0) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) gload(j, k0 + j * KS);
+        for (int st0 = 0; st0 < nst; st0 += PF) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int st = st0 + j;
+                lstore(j, st & 1);
+                __syncthreads();
+                gload(j, k0 + (st + PF) * KS);
+                if (st < nst) mstage(st & 1);
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
@@ -591,7 +609,11 @@ __device__ __forceinline__ void cgemm_body(const f2* __restrict__ A, int64_t lda
     }
 }
 
-template <int NT, int KS = kKS32, int WV = kGemmWaves>
+// 49 - 64 columns keep two stages of loads in flight (the ring of
+// zgemm_body): with three real products per complex one the FP32 matrix-core
+// work per stage is short, and n = 8000, k = 64 took 309 - 312 against
+// 316 - 318 us (A/B on one box).  Same steps, same bits.
+template <int NT, int KS = kKS32, int WV = kGemmWaves, int PF = (NT == 4 ? 2 : 1)>
 __global__ __launch_bounds__(WV * kWave) void k_cgemm(const f2* __restrict__ A, int64_t lda,
                                                       int n, const d2* __restrict__ B,
                                                       int64_t ldb, int ncols,
@@ -599,7 +621,7 @@ __global__ __launch_bounds__(WV * kWave) void k_cgemm(const f2* __restrict__ A, 
                                                       const int* __restrict__ skip)
 {
     if (skip && *skip) return;
-    cgemm_body<NT, KS, WV>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
+    cgemm_body<NT, KS, WV, PF>(A, lda, n, B, ldb, ncols, Zp, kslice, blockIdx.x);
 }
 
 template <int NT>
