@@ -345,23 +345,57 @@ def ccg_read_stream(src, out=None, stream=None):
     return out
 
 
+# hipEventDisableSystemFence: recording the event does no system-scope
+# cache writeback and invalidation, which HIP recommends for events used only
+# for timing (the fence would also delay the product the pair brackets).
+_HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000
+
+
+def _hip(lib, name, argtypes):
+    """A HIP runtime function looked up through the library's handle, so it
+    is the runtime the library (and torch) already use."""
+    f = getattr(lib, name)
+    f.argtypes = argtypes
+    f.restype = ctypes.c_int
+    return f
+
+
 class EventLog:
     """Pairs of timing events recorded by the library around the dense
     complex128 products of the solves this host thread runs while attached
-    (ccg_set_event_log); durations() gives each product's time in seconds."""
+    (ccg_set_event_log); durations() gives each product's time in seconds.
+    The events are HIP events created with hipEventDisableSystemFence."""
 
     def __init__(self, capacity: int, stride: int = 1, roles: int = 0):
-        torch = _torch()
-        self.pairs = [(torch.cuda.Event(enable_timing=True),
-                       torch.cuda.Event(enable_timing=True)) for _ in range(capacity)]
-        for a, b in self.pairs:  # torch creates its events on first record
-            a.record()
-            b.record()
-        torch.cuda.synchronize()
-        self._arr = (ctypes.c_void_p * (2 * capacity))(
-            *[e.cuda_event for pair in self.pairs for e in pair])
+        lib = load()
+        create = _hip(lib, "hipEventCreateWithFlags",
+                      [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint])
+        self._elapsed = _hip(lib, "hipEventElapsedTime",
+                             [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p])
+        self._destroy = _hip(lib, "hipEventDestroy", [ctypes.c_void_p])
+        self._events = []
+        for _ in range(2 * max(int(capacity), 0)):
+            e = ctypes.c_void_p()
+            rc = create(ctypes.byref(e), _HIP_EVENT_DISABLE_SYSTEM_FENCE)
+            if rc != 0:
+                self.close()
+                raise CcgError("hipEventCreateWithFlags failed (%d)" % rc)
+            self._events.append(e.value)
+        self._arr = (ctypes.c_void_p * len(self._events))(*self._events)
         self._log = _EventLog(ctypes.cast(self._arr, ctypes.POINTER(ctypes.c_void_p)),
                               capacity, 0, int(stride), 0, int(roles), 0)
+
+    def close(self):
+        """Destroy the events (after the recorded work has completed)."""
+        for e in getattr(self, "_events", []):
+            self._destroy(ctypes.c_void_p(e))
+        self._events = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __enter__(self):
         self._log.count = 0
@@ -382,7 +416,15 @@ class EventLog:
 
     def durations(self):
         _torch().cuda.synchronize()
-        return [a.elapsed_time(b) / 1e3 for a, b in self.pairs[:self.count]]
+        out = []
+        for i in range(self.count):
+            ms = ctypes.c_float()
+            rc = self._elapsed(ctypes.byref(ms), ctypes.c_void_p(self._events[2 * i]),
+                               ctypes.c_void_p(self._events[2 * i + 1]))
+            if rc != 0:
+                raise CcgError("hipEventElapsedTime failed (%d)" % rc)
+            out.append(ms.value / 1e3)
+        return out
 
 
 def _short(name, A, y, x, tol, maxit, stream):
